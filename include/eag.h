@@ -1,0 +1,303 @@
+/*
+ * eag.h - C ABI of the MI355X (gfx950) surfel ray/path tracing library.
+ *
+ * Scope: ray tracing through a scene of 2D Gaussian surfels as defined in
+ * "EAG-PT: Emission-Aware Gaussians and Path Tracing for Diffuse Indoor
+ * Scene Reconstruction and Editing" (arXiv 2601.23065):
+ *   - the surfel and its response              Sec. 3.1, Eq. 1
+ *   - front-to-back compositing of traced
+ *     quantities {N, D, R, E, P}               Sec. 3.1, Eq. 2-3
+ *   - light bouncing from X = O + Dt w          Sec. 3.1 "Light Bouncing"
+ *   - single-bounce emission-aware render      Sec. 3.3, Eq. 5-7
+ *     and its gradient (Stage 1 objective)     Sec. 3.3, Eq. 8
+ *   - multi-bounce path tracing                Sec. 3.4, Eq. 9
+ *   - scene edits (relighting, recolouring)    Sec. 1 and Sec. 5 results
+ *
+ * Conventions for every call:
+ *   - Plain C. No exceptions cross the boundary; every entry point returns
+ *     an eag_status and, on failure, sets a thread-local message readable
+ *     with eag_last_error().
+ *   - "device" pointers are HIP device memory on the current device, owned
+ *     by the caller (the Python binding allocates them as torch tensors).
+ *     "host" pointers are ordinary host memory. The library never calls
+ *     hipMalloc/hipFree; every buffer it needs is a caller-provided
+ *     workspace whose size a *_bytes query returns.
+ *   - Every compute call is asynchronous on the given HIP stream
+ *     (hipStream_t passed as void*; NULL = default stream) unless stated.
+ *     Input buffers must stay alive until the stream reaches the call.
+ *   - Asynchronous device faults surface as EAG_ERR_DEVICE from a later
+ *     call; host-side validation errors return EAG_ERR_INVALID_ARGUMENT and
+ *     launch nothing.
+ *   - Arrays are component-major (structure of arrays) float32:
+ *     a "[3][n]" array holds x[0..n), then y[0..n), then z[0..n).
+ */
+#ifndef EAG_H
+#define EAG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EAG_ABI_VERSION 1u
+
+typedef enum {
+  EAG_OK = 0,
+  EAG_NOT_READY = 1,
+  EAG_ERR_INVALID_ARGUMENT = -1,
+  EAG_ERR_WORKSPACE_TOO_SMALL = -2,
+  EAG_ERR_OUT_OF_BUDGET = -3,
+  EAG_ERR_DEVICE = -4,
+  EAG_ERR_CANCELLED = -5,
+  EAG_ERR_UNKNOWN_TICKET = -6,
+  EAG_ERR_INTERNAL = -7
+} eag_status;
+
+/* Message of the last non-OK status returned on this thread (never NULL). */
+const char* eag_last_error(void);
+uint32_t eag_abi_version(void);
+
+/* ------------------------------------------------------------------------
+ * Scene: n surfels, borrowed device arrays (Sec. 3.1: centre p, tangent
+ * scales s_u, s_v, orientation quaternion q, opacity sigma; Eq. 3: linear
+ * radiance r, emissive term e in [0,1], diffuse albedo rho).
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  int64_t n;                 /* number of surfels, 1 <= n <= 2^23            */
+  const float* pos;          /* device [3][n] centre p                        */
+  const float* rot;          /* device [4][n] quaternion (w,x,y,z), |q| > 0   */
+  const float* scale;        /* device [2][n] s_u, s_v > 0                    */
+  const float* opacity;      /* device [n] sigma in [0,1); 0 = deleted        */
+  const float* albedo;       /* device [3][n] rho                             */
+  const float* radiance;     /* device [3][n] r (emission / radiance cache)   */
+  const float* emissive;     /* device [n] e                                  */
+} eag_surfels;
+
+/* Gradients with the same shapes as the inputs; accumulated with +=, the
+ * caller zeroes them. The emissive term e receives no gradient (it enters the
+ * single-bounce map only through the threshold of Eq. 5). */
+typedef struct {
+  float* pos;                /* device [3][n] */
+  float* rot;                /* device [4][n] (w.r.t. the unnormalised q) */
+  float* scale;              /* device [2][n] */
+  float* opacity;            /* device [n]    */
+  float* albedo;             /* device [3][n] */
+  float* radiance;           /* device [3][n] */
+} eag_surfel_grads;
+
+/* Pinhole camera with vertical field of view; image row 0 is the top. */
+typedef struct {
+  float eye[3], look_at[3], up[3];
+  float vfov_deg;            /* (0, 180) */
+  int32_t width, height;     /* >= 1 */
+} eag_camera;
+
+enum {
+  EAG_JITTER = 1u,               /* jitter camera rays inside the pixel (Philox segment word 0xffffffff) */
+  EAG_ADDITIVE_EMISSION = 2u,    /* test mode: L_o = L_e + L_r at every hit (first line of Eq. 5)       */
+  EAG_DETACH_BOUNCE = 4u         /* adjoint: hold bounce origin X and direction w' constant             */
+};
+
+/* Parameters of tracing and rendering. eag_default_params fills the
+ * defaults in brackets. */
+typedef struct {
+  int32_t spp;              /* samples per pixel [4] (Eq. 7 and Eq. 9 n_spp)                 */
+  int32_t max_depth;        /* max diffuse reflections per path [5] (Eq. 9 bounce limit);   */
+                            /* a path traces at most max_depth + 1 segments, <= 64           */
+  int32_t rr_start;         /* Russian roulette once depth >= rr_start; 0 = off [3]           */
+  float tau_E;              /* emitter threshold on composited E [0.1] (Eq. 5)                */
+  float T_min;              /* compositing stops after T < T_min [1e-4] (Sec. 3.1)            */
+  float t_min;              /* minimum hit distance [1e-3]                                    */
+  float k_sigma;            /* accept iff u^2+v^2 <= k_sigma^2 [3]                            */
+  float depth_quantum;      /* order key floor(t/dq) then surfel index [2^-13]; must be 0 or  */
+                            /* a power of two; 0 = exact (t, index) order (n <= 65536)        */
+  int32_t kbuf;             /* k-buffer depth, must be 16                                     */
+  uint32_t camera_id;       /* 4th Philox counter word (camera c of a batch uses id + c)      */
+  uint64_t seed;            /* Philox key [0]                                                 */
+  uint32_t flags;           /* EAG_* flags [0]                                                */
+  uint32_t reserved;
+} eag_trace_params;
+
+void eag_default_params(eag_trace_params* p);
+
+/* ------------------------------------------------------------------------
+ * Acceleration structure: a linear BVH over the surfels' k_sigma ellipse
+ * bounds (63-bit Morton order, Karras hierarchy). The paper's implementation
+ * uses an OptiX acceleration structure (Sec. 5 "Implementation Details");
+ * gfx950 has no ray-tracing units, so this one is built and traversed by
+ * hand-written kernels.
+ *
+ * The BVH stores a snapshot of the geometry (p, q, s, sigma) taken at build
+ * or refit time; renders read geometry from it and attributes (rho, r, e)
+ * from the eag_surfels passed to each call. After changing geometry, call
+ * eag_refit_bvh (same n, same topology) or rebuild.
+ * ------------------------------------------------------------------------ */
+typedef struct eag_bvh eag_bvh;   /* opaque host handle; node storage is in caller memory */
+
+typedef struct {
+  int64_t n;                 /* surfels                              */
+  int32_t max_depth;         /* deepest leaf (root = 0)              */
+  int32_t root;              /* root reference (>= 0 internal node; <0: leaf ~ref) */
+  float lo[3], hi[3];        /* scene bounds of the surfel boxes     */
+  const void* nodes;         /* device: (n-1) internal nodes, 64 B each:  */
+                             /*   float lo0[3], hi0[3], lo1[3], hi1[3]; int32 child0, child1, pad[2] */
+                             /*   child >= 0: internal node, child < 0: leaf at sorted position ~child */
+  const void* records;       /* device: n geometry records, 64 B each, in sorted (Morton) order */
+  const int32_t* perm;       /* device [n]: sorted position -> surfel index */
+} eag_bvh_info;
+
+size_t eag_bvh_bytes(int64_t n);
+size_t eag_build_workspace_bytes(int64_t n);
+/* Build. Synchronises `stream` once at the end to read back depth and bounds.
+ * bvh_mem: device, >= eag_bvh_bytes(n), 256-B aligned, owned by the caller and
+ * referenced by the handle until eag_bvh_destroy. ws: device scratch, only
+ * used during the call. */
+eag_status eag_build_bvh(const eag_surfels* s, void* bvh_mem, size_t bvh_bytes,
+                         void* ws, size_t ws_bytes, void* stream, eag_bvh** out);
+/* Recompute frames, records and node bounds after a geometry edit that keeps
+ * n; topology is kept (Morton order of the build). Synchronises `stream`. */
+eag_status eag_refit_bvh(eag_bvh* bvh, const eag_surfels* s, void* ws, size_t ws_bytes, void* stream);
+eag_status eag_bvh_get_info(const eag_bvh* bvh, eag_bvh_info* out);
+void eag_bvh_destroy(eag_bvh* bvh);
+
+/* ------------------------------------------------------------------------
+ * Tracing (Sec. 3.1, Eq. 1-3): blend every surfel on each ray front to back
+ * through a 16-entry k-buffer, in order of the key (floor(t/dq), index),
+ * stopping after the first hit with T < T_min.
+ * ------------------------------------------------------------------------ */
+size_t eag_trace_workspace_bytes(int64_t n_surfels);
+/* origins, dirs: device [3][n_rays], dirs unit length.
+ * out: device [12][n_rays] = Nt(3), Dt, R(3), E, P(3), A (Nt = N/|N|, Dt = D/A;
+ *      all zero for a miss).
+ * hit_idx: nullable device [n_rays][max_hits] surfel indices in blending order;
+ * hit_count: nullable device [n_rays] number of blended hits (may exceed
+ * max_hits; only the first max_hits are written). */
+eag_status eag_trace_rays(const eag_bvh* bvh, const eag_surfels* s, const eag_trace_params* p,
+                          int64_t n_rays, const float* origins, const float* dirs, float* out,
+                          int32_t* hit_idx, int32_t* hit_count, int32_t max_hits,
+                          void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Single-bounce emission-aware render (Sec. 3.3, Eq. 5-7): per pixel, the
+ * camera segment through the pixel centre gives (Nt, Dt, R, E, P, A); a miss
+ * renders 0, E > tau_E renders R, otherwise P * (1/spp) sum_s R(w'_s) with w'_s
+ * cosine-sampled about Nt from X = O + Dt w (Philox counter (pixel, s, 0,
+ * camera_id + c)). Secondary segments blend r without an emitter test (the
+ * radiance cache).
+ * ------------------------------------------------------------------------ */
+#define EAG_FWD_PIXEL_FLOATS 16
+/* Floats of forward state kept for the backward pass:
+ * n_cams*H*W*(EAG_FWD_PIXEL_FLOATS + 3*spp). */
+int64_t eag_fwd_state_floats(const eag_camera* cams, int32_t n_cams, const eag_trace_params* p);
+size_t eag_render_workspace_bytes(int64_t n_surfels, const eag_camera* cams, int32_t n_cams,
+                                  const eag_trace_params* p);
+/* cams: host [n_cams], all the same width and height.
+ * rgb: device [n_cams][H][W][3].
+ * fwd_state: nullable device buffer of eag_fwd_state_floats() floats. */
+eag_status eag_render_single_bounce(const eag_bvh* bvh, const eag_surfels* s, const eag_camera* cams,
+                                    int32_t n_cams, const eag_trace_params* p, float* rgb, float* fwd_state,
+                                    void* ws, size_t ws_bytes, void* stream);
+/* Exact reverse of eag_render_single_bounce with every discrete decision of
+ * the forward pass held fixed (hit sets, order, stopping hit, normal signs,
+ * emitter branch); includes the chain through X (via Dt) and w' (via Nt and
+ * the hemisphere frame) unless EAG_DETACH_BOUNCE. Hit lists are recomputed,
+ * not stored. dL_drgb: device [n_cams][H][W][3]; fwd_state from the forward
+ * call with the same arguments. Gradients are accumulated into `grads` with
+ * float atomics. */
+eag_status eag_single_bounce_backward(const eag_bvh* bvh, const eag_surfels* s, const eag_camera* cams,
+                                      int32_t n_cams, const eag_trace_params* p, const float* dL_drgb,
+                                      const float* fwd_state, const eag_surfel_grads* grads,
+                                      void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Multi-bounce path tracing (Sec. 3.4, Eq. 9) in a persistent wavefront
+ * kernel. Per path: miss -> 0; E > tau_E -> add beta*R and stop; depth ==
+ * max_depth -> discard; else beta *= P, cosine-sample w' (Philox counter
+ * (pixel, sample, depth, camera_id)), continue from X; Russian roulette when
+ * the new depth >= rr_start: q = min(0.95, max beta), survive iff u2 < q,
+ * beta /= q.
+ * accum: device int64 [H][W][3] running sums in fixed point (value *
+ * EAG_ACCUM_SCALE, rounded to nearest); the sums are independent of launch
+ * order and of how samples are split across calls. Samples
+ * [sample_begin, sample_begin + sample_count) are added.
+ * counters: nullable device uint64 [5] += {segments traced, paths started,
+ * k-buffer rounds, candidate surfel tests, blended hits}.
+ * ------------------------------------------------------------------------ */
+#define EAG_ACCUM_SCALE 4294967296.0 /* 2^32 */
+size_t eag_path_trace_workspace_bytes(int64_t n_surfels);
+eag_status eag_path_trace(const eag_bvh* bvh, const eag_surfels* s, const eag_camera* cam,
+                          const eag_trace_params* p, uint32_t sample_begin, uint32_t sample_count,
+                          int64_t* accum, uint64_t* counters, void* ws, size_t ws_bytes, void* stream);
+/* rgb[i] = accum[i] / (EAG_ACCUM_SCALE * total_spp) for i < 3*n_pixels (device arrays). */
+eag_status eag_accum_resolve(const int64_t* accum, int64_t n_pixels, int32_t total_spp, float* rgb,
+                             void* stream);
+
+/* ------------------------------------------------------------------------
+ * Scene edits (the paper's relighting and material edits, Sec. 1, Sec. 5).
+ * Attribute edits write the caller's arrays in place and need no refit.
+ * ------------------------------------------------------------------------ */
+enum {
+  EAG_EDIT_SET_RADIANCE = 1,    /* r[i] = value[0..2]                         */
+  EAG_EDIT_SCALE_RADIANCE = 2,  /* r[i] *= value[0..2] (0 switches lights off) */
+  EAG_EDIT_SET_ALBEDO = 3,      /* rho[i] = value[0..2]                       */
+  EAG_EDIT_SET_EMISSIVE = 4     /* e[i] = value[0]                            */
+};
+typedef struct {
+  int32_t kind;
+  const int32_t* idx;           /* device [count] surfel indices, each < n */
+  int64_t count;
+  float value[3];
+} eag_edit;
+typedef struct {
+  int64_t n;
+  float* albedo;                /* device [3][n] */
+  float* radiance;              /* device [3][n] */
+  float* emissive;              /* device [n]    */
+} eag_surfel_attrs;
+eag_status eag_apply_edit(const eag_edit* e, const eag_surfel_attrs* a, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Serving: a resident scene answering path-tracing requests with continuous
+ * batching. A host scheduler thread admits requests while their fixed-point
+ * accumulators fit the arena and a slot is free, and each launch of the
+ * multi-request persistent kernel draws paths from every live request, so
+ * requests that arrive while others run join the next launch. Edits are
+ * ordered with respect to later submits: each request renders the scene
+ * version current at its submit; attribute edits create a new version
+ * (copy-on-write attributes), geometry is shared.
+ * ------------------------------------------------------------------------ */
+typedef struct eag_server eag_server;
+typedef struct {
+  void* arena;                  /* device memory owned by the caller            */
+  size_t arena_bytes;
+  int32_t max_live_requests;    /* slots, 1..64                                 */
+  int64_t paths_per_launch;     /* work quantum of one launch (all live requests) */
+  void* stream;                 /* stream the server launches on                */
+} eag_server_config;
+typedef struct {
+  eag_camera cam;
+  eag_trace_params params;      /* spp, max_depth, rr_start, seed, camera_id ... */
+  float* out_rgb;               /* device [H][W][3], written when done           */
+} eag_request;
+typedef struct {
+  int32_t status;               /* EAG_OK, EAG_NOT_READY, or an error          */
+  uint32_t scene_version;
+  double t_submit, t_admit, t_done;   /* seconds, host monotonic clock           */
+  uint64_t paths;
+} eag_result;
+/* Bytes of arena needed for a scene of n surfels with `versions` attribute versions. */
+size_t eag_serve_arena_bytes(int64_t n, int32_t versions, size_t request_bytes);
+/* Copies the scene into the arena and builds the BVH (synchronous). */
+eag_status eag_serve_create(const eag_surfels* s, const eag_server_config* cfg, eag_server** out);
+eag_status eag_serve_submit(eag_server* srv, const eag_request* req, uint64_t* ticket);  /* non-blocking */
+eag_status eag_serve_edit(eag_server* srv, const eag_edit* e, uint64_t* ticket);        /* idx: host */
+eag_status eag_serve_poll(eag_server* srv, uint64_t ticket, eag_result* out);           /* non-blocking */
+eag_status eag_serve_cancel(eag_server* srv, uint64_t ticket);
+eag_status eag_serve_destroy(eag_server* srv);  /* drains, stops the scheduler thread */
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EAG_H */

@@ -1,0 +1,289 @@
+"""Python binding of the surfel tracing library: torch tensors for device
+memory and streams, the C ABI for every computation.
+
+All tensors passed in are float32 CUDA (HIP) tensors in the component-major
+layouts of include/eag.h. Nothing here computes on the scene: a missing or
+failing library raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass, fields
+
+import torch
+
+from . import _lib as L
+
+_GEOM = ("pos", "rot", "scale", "opacity")
+_ATTR = ("albedo", "radiance", "emissive")
+_SHAPES = {"pos": 3, "rot": 4, "scale": 2, "opacity": 0, "albedo": 3, "radiance": 3, "emissive": 0}
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+def _bytes(nbytes, device):
+    return torch.empty(max(int(nbytes), 256) + 256, dtype=torch.uint8, device=device)
+
+
+def _aligned(buf):
+    """256-byte aligned view start of a uint8 buffer."""
+    p = buf.data_ptr()
+    off = (-p) % 256
+    return C.c_void_p(p + off), buf.numel() - off
+
+
+@dataclass
+class Params:
+    """Mirror of eag_trace_params (defaults = eag_default_params)."""
+    spp: int = 4
+    max_depth: int = 5
+    rr_start: int = 3
+    tau_E: float = 0.1
+    T_min: float = 1e-4
+    t_min: float = 1e-3
+    k_sigma: float = 3.0
+    depth_quantum: float = 2.0 ** -13
+    kbuf: int = 16
+    camera_id: int = 0
+    seed: int = 0
+    flags: int = 0
+
+    def c(self):
+        p = L.TraceParams()
+        for f in fields(self):
+            setattr(p, f.name, getattr(self, f.name))
+        return p
+
+
+def camera_struct(cam):
+    """cam: object with eye, look_at, up, vfov_deg, width, height."""
+    c = L.Camera()
+    c.eye[:] = [float(v) for v in cam.eye]
+    c.look_at[:] = [float(v) for v in cam.look_at]
+    c.up[:] = [float(v) for v in cam.up]
+    c.vfov_deg = float(cam.vfov_deg)
+    c.width = int(cam.width)
+    c.height = int(cam.height)
+    return c
+
+
+class Scene:
+    """Device-resident surfel arrays (float32, component-major)."""
+
+    def __init__(self, arrays: dict, device="cuda"):
+        self.t = {}
+        n = None
+        for k in _GEOM + _ATTR:
+            v = torch.as_tensor(arrays[k], dtype=torch.float32).to(device).contiguous()
+            if _SHAPES[k]:
+                assert v.dim() == 2 and v.shape[0] == _SHAPES[k], (k, tuple(v.shape))
+                m = v.shape[1]
+            else:
+                assert v.dim() == 1, k
+                m = v.shape[0]
+            n = m if n is None else n
+            assert m == n, f"{k} has {m} surfels, expected {n}"
+            self.t[k] = v
+        self.n = n
+        self.device = torch.device(device)
+
+    def __getattr__(self, k):
+        t = self.__dict__.get("t", {})
+        if k in t:
+            return t[k]
+        raise AttributeError(k)
+
+    def c(self, overrides: dict | None = None):
+        s = L.Surfels()
+        s.n = self.n
+        for k in _GEOM + _ATTR:
+            setattr(s, k, _ptr((overrides or {}).get(k, self.t[k])))
+        return s
+
+    def attrs_c(self):
+        a = L.SurfelAttrs()
+        a.n = self.n
+        a.albedo, a.radiance, a.emissive = _ptr(self.t["albedo"]), _ptr(self.t["radiance"]), _ptr(self.t["emissive"])
+        return a
+
+
+class BVH:
+    """Linear BVH over a Scene; owns its device memory as a torch tensor."""
+
+    def __init__(self, scene: Scene, stream=None):
+        lib = L.load()
+        self.scene = scene
+        n = scene.n
+        self.mem = _bytes(lib.eag_bvh_bytes(n), scene.device)
+        ws = _bytes(lib.eag_build_workspace_bytes(n), scene.device)
+        h = C.c_void_p()
+        mp, mb = _aligned(self.mem)
+        wp, wb = _aligned(ws)
+        sc = scene.c()
+        L.check(lib.eag_build_bvh(C.byref(sc), mp, mb, wp, wb, _stream(stream), C.byref(h)))
+        self.h = h
+        self._ws = ws
+
+    def refit(self, scene: Scene | None = None, stream=None):
+        lib = L.load()
+        scene = scene or self.scene
+        wp, wb = _aligned(self._ws)
+        sc = scene.c()
+        L.check(lib.eag_refit_bvh(self.h, C.byref(sc), wp, wb, _stream(stream)))
+
+    def info(self):
+        i = L.BvhInfo()
+        L.check(L.load().eag_bvh_get_info(self.h, C.byref(i)))
+        return i
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                L.load().eag_bvh_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+
+def trace_rays(bvh: BVH, scene: Scene, params: Params, origins, dirs, max_hits: int = 0, stream=None):
+    """origins, dirs: [3, M] float32 device tensors. Returns out [12, M]
+    (Nt, Dt, R, E, P, A) and, if max_hits > 0, (hit_idx [M, max_hits],
+    hit_count [M])."""
+    lib = L.load()
+    m = origins.shape[1]
+    dev = scene.device
+    out = torch.empty((12, m), dtype=torch.float32, device=dev)
+    hits = torch.full((m, max(max_hits, 1)), -1, dtype=torch.int32, device=dev) if max_hits > 0 else None
+    cnt = torch.zeros(m, dtype=torch.int32, device=dev) if max_hits > 0 else None
+    ws = _bytes(lib.eag_trace_workspace_bytes(scene.n), dev)
+    wp, wb = _aligned(ws)
+    p = params.c()
+    sc = scene.c()
+    L.check(lib.eag_trace_rays(bvh.h, C.byref(sc), C.byref(p), m, _ptr(origins.contiguous()),
+                               _ptr(dirs.contiguous()), _ptr(out), _ptr(hits), _ptr(cnt), max_hits, wp, wb,
+                               _stream(stream)))
+    return (out, hits, cnt) if max_hits > 0 else out
+
+
+def _cams(cams):
+    arr = (L.Camera * len(cams))()
+    for i, c in enumerate(cams):
+        arr[i] = camera_struct(c)
+    return arr
+
+
+def render_single_bounce(bvh: BVH, scene: Scene, cams, params: Params, keep_state: bool = False, stream=None,
+                         overrides=None):
+    """Returns rgb [n_cams, H, W, 3] and, if keep_state, the forward state."""
+    lib = L.load()
+    ca = _cams(cams)
+    p = params.c()
+    H, W = cams[0].height, cams[0].width
+    dev = scene.device
+    rgb = torch.empty((len(cams), H, W, 3), dtype=torch.float32, device=dev)
+    state = None
+    if keep_state:
+        state = torch.empty(lib.eag_fwd_state_floats(ca, len(cams), C.byref(p)), dtype=torch.float32, device=dev)
+    ws = _bytes(lib.eag_render_workspace_bytes(scene.n, ca, len(cams), C.byref(p)), dev)
+    wp, wb = _aligned(ws)
+    sc = scene.c(overrides)
+    L.check(lib.eag_render_single_bounce(bvh.h, C.byref(sc), ca, len(cams), C.byref(p), _ptr(rgb), _ptr(state),
+                                         wp, wb, _stream(stream)))
+    return (rgb, state) if keep_state else rgb
+
+
+def single_bounce_backward(bvh: BVH, scene: Scene, cams, params: Params, dL_drgb, state, grads: dict | None = None,
+                           stream=None, overrides=None):
+    """Accumulates gradients into `grads` (zeroed tensors are created if
+    None) and returns them."""
+    lib = L.load()
+    ca = _cams(cams)
+    p = params.c()
+    dev = scene.device
+    if grads is None:
+        grads = {k: torch.zeros_like(scene.t[k]) for k in ("pos", "rot", "scale", "opacity", "albedo", "radiance")}
+    g = L.SurfelGrads()
+    for k in ("pos", "rot", "scale", "opacity", "albedo", "radiance"):
+        setattr(g, k, _ptr(grads[k]))
+    ws = _bytes(lib.eag_render_workspace_bytes(scene.n, ca, len(cams), C.byref(p)), dev)
+    wp, wb = _aligned(ws)
+    sc = scene.c(overrides)
+    L.check(lib.eag_single_bounce_backward(bvh.h, C.byref(sc), ca, len(cams), C.byref(p),
+                                           _ptr(dL_drgb.contiguous()), _ptr(state), C.byref(g), wp, wb,
+                                           _stream(stream)))
+    return grads
+
+
+class SingleBounceRender(torch.autograd.Function):
+    """Differentiable single-bounce render: forward and backward both run in
+    the HIP library; the BVH must match the geometry passed in (build or
+    refit it outside)."""
+
+    @staticmethod
+    def forward(ctx, pos, rot, scale, opacity, albedo, radiance, emissive, bvh, scene, cams, params):
+        ov = dict(pos=pos.detach(), rot=rot.detach(), scale=scale.detach(), opacity=opacity.detach(),
+                  albedo=albedo.detach(), radiance=radiance.detach(), emissive=emissive.detach())
+        rgb, state = render_single_bounce(bvh, scene, cams, params, keep_state=True, overrides=ov)
+        ctx.save_for_backward(state)
+        ctx.extra = (bvh, scene, cams, params, ov)
+        return rgb
+
+    @staticmethod
+    def backward(ctx, d_rgb):
+        (state,) = ctx.saved_tensors
+        bvh, scene, cams, params, ov = ctx.extra
+        grads = {k: torch.zeros_like(ov[k]) for k in ("pos", "rot", "scale", "opacity", "albedo", "radiance")}
+        single_bounce_backward(bvh, scene, cams, params, d_rgb, state, grads, overrides=ov)
+        return (grads["pos"], grads["rot"], grads["scale"], grads["opacity"], grads["albedo"], grads["radiance"],
+                None, None, None, None, None)
+
+
+def path_trace(bvh: BVH, scene: Scene, cam, params: Params, sample_begin: int = 0, sample_count: int | None = None,
+               accum=None, counters=None, stream=None, ws=None):
+    """Adds samples [sample_begin, sample_begin + sample_count) into the int64
+    fixed-point accumulator [H, W, 3] (created if None) and returns it."""
+    lib = L.load()
+    dev = scene.device
+    sample_count = params.spp if sample_count is None else sample_count
+    if accum is None:
+        accum = torch.zeros((cam.height, cam.width, 3), dtype=torch.int64, device=dev)
+    if ws is None:
+        ws = _bytes(lib.eag_path_trace_workspace_bytes(scene.n), dev)
+    wp, wb = _aligned(ws)
+    c = camera_struct(cam)
+    p = params.c()
+    sc = scene.c()
+    L.check(lib.eag_path_trace(bvh.h, C.byref(sc), C.byref(c), C.byref(p), sample_begin, sample_count, _ptr(accum),
+                               _ptr(counters), wp, wb, _stream(stream)))
+    return accum
+
+
+def path_trace_workspace(scene: Scene):
+    return _bytes(L.load().eag_path_trace_workspace_bytes(scene.n), scene.device)
+
+
+def resolve(accum, total_spp: int, stream=None):
+    """float32 image [H, W, 3] = accum / (2^32 * total_spp)."""
+    rgb = torch.empty(accum.shape, dtype=torch.float32, device=accum.device)
+    L.check(L.load().eag_accum_resolve(_ptr(accum), accum.numel() // 3, int(total_spp), _ptr(rgb), _stream(stream)))
+    return rgb
+
+
+def apply_edit(scene: Scene, kind: int, idx, value, stream=None):
+    """In-place attribute edit of the scene's arrays; idx: int32 device tensor."""
+    e = L.Edit()
+    e.kind = int(kind)
+    idx = idx.to(torch.int32).contiguous()
+    e.idx = _ptr(idx)
+    e.count = idx.numel()
+    vals = list(value) + [0.0] * (3 - len(list(value)))
+    e.value[:] = [float(v) for v in vals[:3]]
+    a = scene.attrs_c()
+    L.check(L.load().eag_apply_edit(C.byref(e), C.byref(a), _stream(stream)))

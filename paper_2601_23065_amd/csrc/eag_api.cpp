@@ -1,0 +1,442 @@
+// C ABI of the library: argument validation, workspace carving and error
+// conversion. Every entry point catches everything and returns a status.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "eag_internal.h"
+#include "eag_render.h"
+
+namespace eag {
+
+namespace {
+thread_local std::string g_last_error;
+
+eag_status set_error(eag_status s, const std::string& m) {
+  g_last_error = m;
+  return s;
+}
+
+template <class F>
+eag_status guarded(F&& f) {
+  try {
+    f();
+    return EAG_OK;
+  } catch (const Error& e) {
+    return set_error(e.status, e.msg);
+  } catch (const std::bad_alloc&) {
+    return set_error(EAG_ERR_INTERNAL, "host allocation failed");
+  } catch (...) {
+    return set_error(EAG_ERR_INTERNAL, "unexpected exception");
+  }
+}
+
+int bits_for(int64_t n) {
+  int b = 1;
+  while ((int64_t(1) << b) < n) ++b;
+  return b;
+}
+
+bool is_pow2_or_zero(float x) {
+  if (x == 0.0f) return true;
+  if (!(x > 0.0f) || !std::isfinite(x)) return false;
+  int e = 0;
+  return std::frexp(x, &e) == 0.5f;
+}
+}  // namespace
+
+void fail(eag_status s, const std::string& msg) { throw Error{s, msg}; }
+
+void check_hip(hipError_t e, const char* what) {
+  if (e != hipSuccess) fail(EAG_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+void validate_params(const eag_trace_params* p) {
+  if (!p) fail(EAG_ERR_INVALID_ARGUMENT, "params is null");
+  if (p->kbuf != KBUF) fail(EAG_ERR_INVALID_ARGUMENT, "kbuf must be 16");
+  if (p->spp < 1) fail(EAG_ERR_INVALID_ARGUMENT, "spp must be >= 1");
+  if (p->max_depth < 0 || p->max_depth > 64) fail(EAG_ERR_INVALID_ARGUMENT, "max_depth must be in [0, 64]");
+  if (p->rr_start < 0) fail(EAG_ERR_INVALID_ARGUMENT, "rr_start must be >= 0");
+  if (!(p->T_min > 0.0f && p->T_min < 1.0f)) fail(EAG_ERR_INVALID_ARGUMENT, "T_min must be in (0, 1)");
+  if (!(p->t_min >= 0.0f) || !std::isfinite(p->t_min)) fail(EAG_ERR_INVALID_ARGUMENT, "t_min must be >= 0");
+  if (!(p->k_sigma > 0.0f) || !std::isfinite(p->k_sigma)) fail(EAG_ERR_INVALID_ARGUMENT, "k_sigma must be > 0");
+  if (!std::isfinite(p->tau_E)) fail(EAG_ERR_INVALID_ARGUMENT, "tau_E must be finite");
+  if (!is_pow2_or_zero(p->depth_quantum))
+    fail(EAG_ERR_INVALID_ARGUMENT, "depth_quantum must be 0 or a power of two");
+}
+
+TraceSetup trace_setup(const eag_bvh* b, const eag_trace_params* p, float t_max_needed) {
+  TraceSetup ts;
+  ts.idx_bits = b->idx_bits;
+  const int bucket_bits = 64 - 2 * ts.idx_bits;
+  if (p->depth_quantum == 0.0f) {
+    if (bucket_bits < 32) fail(EAG_ERR_INVALID_ARGUMENT, "depth_quantum = 0 (exact t order) needs n <= 65536");
+    ts.max_bucket = 0xffffffffu;
+    ts.inv_dq = 0.0f;
+  } else {
+    ts.max_bucket = bucket_bits >= 32 ? 0xffffffffu : ((1u << bucket_bits) - 1u);
+    ts.inv_dq = 1.0f / p->depth_quantum;
+    const double t_rep = (double)ts.max_bucket * (double)p->depth_quantum;
+    if ((double)t_max_needed >= t_rep)
+      fail(EAG_ERR_INVALID_ARGUMENT, "scene too deep for the order key at this depth_quantum and surfel count "
+                                     "(raise depth_quantum)");
+  }
+  if (b->max_depth > STACK_SIZE) fail(EAG_ERR_INTERNAL, "BVH deeper than the traversal stack");
+  return ts;
+}
+
+CamDev make_cam(const eag_camera& c, uint32_t id) {
+  if (c.width < 1 || c.height < 1) fail(EAG_ERR_INVALID_ARGUMENT, "camera size must be >= 1");
+  if ((int64_t)c.width * c.height > (int64_t(1) << 31)) fail(EAG_ERR_INVALID_ARGUMENT, "camera too large");
+  if (!(c.vfov_deg > 0.0f && c.vfov_deg < 180.0f)) fail(EAG_ERR_INVALID_ARGUMENT, "vfov must be in (0, 180)");
+  double e[3], f[3], u[3];
+  for (int a = 0; a < 3; ++a) {
+    e[a] = c.eye[a];
+    f[a] = (double)c.look_at[a] - c.eye[a];
+    u[a] = c.up[a];
+  }
+  const double fl = std::sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+  if (!(fl > 0)) fail(EAG_ERR_INVALID_ARGUMENT, "camera eye equals look_at");
+  for (double& v : f) v /= fl;
+  double r[3] = {f[1] * u[2] - f[2] * u[1], f[2] * u[0] - f[0] * u[2], f[0] * u[1] - f[1] * u[0]};
+  const double rl = std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+  if (!(rl > 1e-12)) fail(EAG_ERR_INVALID_ARGUMENT, "camera up is parallel to the view direction");
+  for (double& v : r) v /= rl;
+  const double up2[3] = {r[1] * f[2] - r[2] * f[1], r[2] * f[0] - r[0] * f[2], r[0] * f[1] - r[1] * f[0]};
+  const double th = std::tan(c.vfov_deg * M_PI / 360.0);
+  const double aspect = (double)c.width / (double)c.height;
+  CamDev d;
+  for (int a = 0; a < 3; ++a) {
+    d.eye[a] = (float)e[a];
+    d.right[a] = (float)(r[a] * th * aspect);
+    d.up[a] = (float)(up2[a] * th);
+    d.fwd[a] = (float)f[a];
+  }
+  d.width = c.width;
+  d.height = c.height;
+  d.id = id;
+  d.pad = 0;
+  return d;
+}
+
+// Longest distance a ray of this camera can travel inside the scene box.
+float camera_t_max(const eag_bvh* b, const eag_camera& c) {
+  double d2 = 0, diag2 = 0;
+  for (int a = 0; a < 3; ++a) {
+    const double lo = b->lo[a], hi = b->hi[a], e = c.eye[a];
+    const double far = std::fmax(std::fabs(e - lo), std::fabs(e - hi));
+    d2 += far * far;
+    diag2 += (hi - lo) * (hi - lo);
+  }
+  return (float)(std::sqrt(d2) + std::sqrt(diag2));
+}
+
+float scene_t_max(const eag_bvh* b) {
+  double diag2 = 0;
+  for (int a = 0; a < 3; ++a) diag2 += (double)(b->hi[a] - b->lo[a]) * (b->hi[a] - b->lo[a]);
+  return (float)std::sqrt(diag2);
+}
+
+}  // namespace eag
+
+using namespace eag;
+
+namespace {
+
+// Render / trace workspace: attribute records plus per-call buffers.
+struct RenderWs {
+  Attr* attrs;
+  float* state;
+  float* r1;
+  unsigned long long* work;
+  size_t bytes;
+};
+
+RenderWs render_ws(void* base, int64_t n, int64_t n_pix, int64_t spp, bool own_state) {
+  Carver c(base, ~size_t(0));
+  RenderWs w;
+  w.attrs = c.take<Attr>(n);
+  w.state = own_state ? c.take<float>(n_pix * EAG_FWD_PIXEL_FLOATS) : nullptr;
+  w.r1 = own_state ? c.take<float>(n_pix * spp * 3) : nullptr;
+  w.work = c.take<unsigned long long>(8);
+  w.bytes = c.bytes();
+  return w;
+}
+
+void check_cams(const eag_camera* cams, int32_t n_cams) {
+  if (!cams || n_cams < 1) fail(EAG_ERR_INVALID_ARGUMENT, "need at least one camera");
+  for (int i = 1; i < n_cams; ++i)
+    if (cams[i].width != cams[0].width || cams[i].height != cams[0].height)
+      fail(EAG_ERR_INVALID_ARGUMENT, "all cameras of a batch must have the same size");
+}
+
+void check_bvh(const eag_bvh* b, const eag_surfels* s) {
+  if (!b) fail(EAG_ERR_INVALID_ARGUMENT, "bvh is null");
+  validate_surfels(s);
+  if (s->n != b->n) fail(EAG_ERR_INVALID_ARGUMENT, "surfel count differs from the BVH's");
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* eag_last_error(void) { return g_last_error.c_str(); }
+uint32_t eag_abi_version(void) { return EAG_ABI_VERSION; }
+
+void eag_default_params(eag_trace_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->spp = 4;
+  p->max_depth = 5;
+  p->rr_start = 3;
+  p->tau_E = 0.1f;
+  p->T_min = 1e-4f;
+  p->t_min = 1e-3f;
+  p->k_sigma = 3.0f;
+  p->depth_quantum = 1.0f / 8192.0f;
+  p->kbuf = 16;
+  p->camera_id = 0;
+  p->seed = 0;
+  p->flags = 0;
+}
+
+size_t eag_bvh_bytes(int64_t n) { return n < 1 ? 0 : bvh_layout(nullptr, n).bytes; }
+
+size_t eag_build_workspace_bytes(int64_t n) {
+  if (n < 1) return 0;
+  try {
+    return build_ws_bytes(n);
+  } catch (...) {
+    return 0;
+  }
+}
+
+eag_status eag_build_bvh(const eag_surfels* s, void* bvh_mem, size_t bvh_bytes, void* ws, size_t ws_bytes,
+                         void* stream, eag_bvh** out) {
+  return guarded([&] {
+    validate_surfels(s);
+    if (!out) fail(EAG_ERR_INVALID_ARGUMENT, "out is null");
+    if (!bvh_mem || !ws) fail(EAG_ERR_INVALID_ARGUMENT, "bvh_mem and ws must be device buffers");
+    if ((reinterpret_cast<uintptr_t>(bvh_mem) & 255) || (reinterpret_cast<uintptr_t>(ws) & 255))
+      fail(EAG_ERR_INVALID_ARGUMENT, "bvh_mem and ws must be 256-byte aligned");
+    const BvhLayout l = bvh_layout(bvh_mem, s->n);
+    if (bvh_bytes < l.bytes) fail(EAG_ERR_WORKSPACE_TOO_SMALL, "bvh_mem too small");
+    eag_bvh* b = new eag_bvh();
+    b->n = s->n;
+    b->idx_bits = bits_for(s->n);
+    b->mem = bvh_mem;
+    b->mem_bytes = bvh_bytes;
+    b->hdr = l.hdr;
+    b->nodes = l.nodes;
+    b->recs = l.recs;
+    b->perm = l.perm;
+    b->leaf_parent = l.leaf_parent;
+    b->node_parent = l.node_parent;
+    try {
+      build_bvh(s, b, ws, ws_bytes, static_cast<hipStream_t>(stream));
+    } catch (...) {
+      delete b;
+      throw;
+    }
+    if (b->max_depth > STACK_SIZE) {
+      delete b;
+      fail(EAG_ERR_INTERNAL, "BVH deeper than the traversal stack");
+    }
+    *out = b;
+  });
+}
+
+eag_status eag_refit_bvh(eag_bvh* b, const eag_surfels* s, void* ws, size_t ws_bytes, void* stream) {
+  return guarded([&] {
+    check_bvh(b, s);
+    if (!ws) fail(EAG_ERR_INVALID_ARGUMENT, "ws is null");
+    refit_bvh(s, b, ws, ws_bytes, static_cast<hipStream_t>(stream));
+  });
+}
+
+eag_status eag_bvh_get_info(const eag_bvh* b, eag_bvh_info* out) {
+  return guarded([&] {
+    if (!b || !out) fail(EAG_ERR_INVALID_ARGUMENT, "null argument");
+    out->n = b->n;
+    out->max_depth = b->max_depth;
+    out->root = b->root;
+    for (int a = 0; a < 3; ++a) {
+      out->lo[a] = b->lo[a];
+      out->hi[a] = b->hi[a];
+    }
+    out->nodes = b->nodes;
+    out->records = b->recs;
+    out->perm = b->perm;
+  });
+}
+
+void eag_bvh_destroy(eag_bvh* b) { delete b; }
+
+size_t eag_trace_workspace_bytes(int64_t n) { return n < 1 ? 0 : render_ws(nullptr, n, 0, 0, false).bytes; }
+
+eag_status eag_trace_rays(const eag_bvh* b, const eag_surfels* s, const eag_trace_params* p, int64_t n_rays,
+                          const float* origins, const float* dirs, float* out, int32_t* hit_idx, int32_t* hit_count,
+                          int32_t max_hits, void* ws, size_t ws_bytes, void* stream) {
+  return guarded([&] {
+    check_bvh(b, s);
+    validate_params(p);
+    if (n_rays < 0) fail(EAG_ERR_INVALID_ARGUMENT, "n_rays < 0");
+    if (n_rays > 0 && (!origins || !dirs || !out)) fail(EAG_ERR_INVALID_ARGUMENT, "ray or output pointer is null");
+    if (hit_idx && max_hits < 1) fail(EAG_ERR_INVALID_ARGUMENT, "max_hits must be >= 1 with hit_idx");
+    const RenderWs w = render_ws(ws, b->n, 0, 0, false);
+    if (!ws || ws_bytes < w.bytes) fail(EAG_ERR_WORKSPACE_TOO_SMALL, "trace workspace too small");
+    if (n_rays == 0) return;
+    // rays may start anywhere: allow the key range for a ray from far outside
+    double far = 0;
+    for (int a = 0; a < 3; ++a) far = std::fmax(far, std::fmax(std::fabs(b->lo[a]), std::fabs(b->hi[a])));
+    const TraceSetup ts = trace_setup(b, p, (float)(4.0 * far + scene_t_max(b)));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    pack_attrs(s, b, w.attrs, st);
+    launch_trace_rays(b, w.attrs, p, ts, n_rays, origins, dirs, out, hit_idx, hit_count, max_hits, st);
+  });
+}
+
+int64_t eag_fwd_state_floats(const eag_camera* cams, int32_t n_cams, const eag_trace_params* p) {
+  if (!cams || n_cams < 1 || !p || p->spp < 1) return 0;
+  const int64_t np = (int64_t)cams[0].width * cams[0].height * n_cams;
+  return np * (EAG_FWD_PIXEL_FLOATS + 3 * (int64_t)p->spp);
+}
+
+size_t eag_render_workspace_bytes(int64_t n, const eag_camera* cams, int32_t n_cams, const eag_trace_params* p) {
+  if (n < 1 || !cams || n_cams < 1 || !p || p->spp < 1) return 0;
+  const int64_t np = (int64_t)cams[0].width * cams[0].height * n_cams;
+  return render_ws(nullptr, n, np, p->spp, true).bytes;
+}
+
+eag_status eag_render_single_bounce(const eag_bvh* b, const eag_surfels* s, const eag_camera* cams, int32_t n_cams,
+                                    const eag_trace_params* p, float* rgb, float* fwd_state, void* ws,
+                                    size_t ws_bytes, void* stream) {
+  return guarded([&] {
+    check_bvh(b, s);
+    validate_params(p);
+    check_cams(cams, n_cams);
+    if (!rgb) fail(EAG_ERR_INVALID_ARGUMENT, "rgb is null");
+    const int64_t hw = (int64_t)cams[0].width * cams[0].height;
+    const int64_t np = hw * n_cams;
+    const RenderWs w = render_ws(ws, b->n, np, p->spp, true);
+    if (!ws || ws_bytes < w.bytes) fail(EAG_ERR_WORKSPACE_TOO_SMALL, "render workspace too small");
+    float t_max = scene_t_max(b);
+    for (int i = 0; i < n_cams; ++i) t_max = std::fmax(t_max, camera_t_max(b, cams[i]));
+    const TraceSetup ts = trace_setup(b, p, t_max);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    pack_attrs(s, b, w.attrs, st);
+    const TraceCtx tc = make_ctx(b, w.attrs, p, ts);
+    float* state = fwd_state ? fwd_state : w.state;
+    float* r1 = fwd_state ? fwd_state + np * EAG_FWD_PIXEL_FLOATS : w.r1;
+    SbParams sp;
+    sp.spp = p->spp;
+    sp.flags = p->flags;
+    sp.k0 = (uint32_t)(p->seed & 0xffffffffu);
+    sp.k1 = (uint32_t)(p->seed >> 32);
+    sp.tau_E = p->tau_E;
+    for (int c0 = 0; c0 < n_cams; c0 += MAX_CAMS_PER_LAUNCH) {
+      const int nc = std::min(MAX_CAMS_PER_LAUNCH, n_cams - c0);
+      CamBatch cb;
+      std::memset(&cb, 0, sizeof(cb));
+      for (int i = 0; i < nc; ++i) cb.c[i] = make_cam(cams[c0 + i], p->camera_id + (uint32_t)(c0 + i));
+      launch_single_bounce(tc, cb, hw, nc, sp, state + c0 * hw * EAG_FWD_PIXEL_FLOATS, r1 + c0 * hw * p->spp * 3,
+                           rgb + c0 * hw * 3, st);
+    }
+  });
+}
+
+eag_status eag_single_bounce_backward(const eag_bvh* b, const eag_surfels* s, const eag_camera* cams, int32_t n_cams,
+                                      const eag_trace_params* p, const float* dL_drgb, const float* fwd_state,
+                                      const eag_surfel_grads* grads, void* ws, size_t ws_bytes, void* stream) {
+  return guarded([&] {
+    check_bvh(b, s);
+    validate_params(p);
+    check_cams(cams, n_cams);
+    if (!dL_drgb || !fwd_state || !grads) fail(EAG_ERR_INVALID_ARGUMENT, "null argument");
+    if (!grads->pos || !grads->rot || !grads->scale || !grads->opacity || !grads->albedo || !grads->radiance)
+      fail(EAG_ERR_INVALID_ARGUMENT, "a gradient pointer is null");
+    const int64_t hw = (int64_t)cams[0].width * cams[0].height;
+    const int64_t np = hw * n_cams;
+    const RenderWs w = render_ws(ws, b->n, np, p->spp, true);
+    if (!ws || ws_bytes < w.bytes) fail(EAG_ERR_WORKSPACE_TOO_SMALL, "render workspace too small");
+    float t_max = scene_t_max(b);
+    for (int i = 0; i < n_cams; ++i) t_max = std::fmax(t_max, camera_t_max(b, cams[i]));
+    const TraceSetup ts = trace_setup(b, p, t_max);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    pack_attrs(s, b, w.attrs, st);
+    const TraceCtx tc = make_ctx(b, w.attrs, p, ts);
+    SbParams sp;
+    sp.spp = p->spp;
+    sp.flags = p->flags;
+    sp.k0 = (uint32_t)(p->seed & 0xffffffffu);
+    sp.k1 = (uint32_t)(p->seed >> 32);
+    sp.tau_E = p->tau_E;
+    const float* r1 = fwd_state + np * EAG_FWD_PIXEL_FLOATS;
+    for (int c0 = 0; c0 < n_cams; c0 += MAX_CAMS_PER_LAUNCH) {
+      const int nc = std::min(MAX_CAMS_PER_LAUNCH, n_cams - c0);
+      CamBatch cb;
+      std::memset(&cb, 0, sizeof(cb));
+      for (int i = 0; i < nc; ++i) cb.c[i] = make_cam(cams[c0 + i], p->camera_id + (uint32_t)(c0 + i));
+      launch_single_bounce_backward(tc, *s, cb, hw, nc, sp, fwd_state + c0 * hw * EAG_FWD_PIXEL_FLOATS,
+                                    r1 + c0 * hw * p->spp * 3, dL_drgb + c0 * hw * 3, *grads, w.state, st);
+    }
+  });
+}
+
+size_t eag_path_trace_workspace_bytes(int64_t n) { return n < 1 ? 0 : render_ws(nullptr, n, 0, 0, false).bytes; }
+
+eag_status eag_path_trace(const eag_bvh* b, const eag_surfels* s, const eag_camera* cam, const eag_trace_params* p,
+                          uint32_t sample_begin, uint32_t sample_count, int64_t* accum, uint64_t* counters, void* ws,
+                          size_t ws_bytes, void* stream) {
+  return guarded([&] {
+    check_bvh(b, s);
+    validate_params(p);
+    if (!cam || !accum) fail(EAG_ERR_INVALID_ARGUMENT, "null argument");
+    if ((uint64_t)sample_begin + sample_count > 0xffffffffull) fail(EAG_ERR_INVALID_ARGUMENT, "sample range overflow");
+    const RenderWs w = render_ws(ws, b->n, 0, 0, false);
+    if (!ws || ws_bytes < w.bytes) fail(EAG_ERR_WORKSPACE_TOO_SMALL, "path-trace workspace too small");
+    const CamDev cd = make_cam(*cam, p->camera_id);
+    const TraceSetup ts = trace_setup(b, p, std::fmax(scene_t_max(b), camera_t_max(b, *cam)));
+    if (sample_count == 0) return;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    pack_attrs(s, b, w.attrs, st);
+    const TraceCtx tc = make_ctx(b, w.attrs, p, ts);
+    PtParams pp;
+    pp.max_depth = p->max_depth;
+    pp.rr_start = p->rr_start;
+    pp.flags = p->flags;
+    pp.k0 = (uint32_t)(p->seed & 0xffffffffu);
+    pp.k1 = (uint32_t)(p->seed >> 32);
+    pp.tau_E = p->tau_E;
+    pp.sample_begin = sample_begin;
+    pp.sample_count = sample_count;
+    pp.tiles_x = (cam->width + 7) / 8;
+    pp.tile_pixels = (int64_t)pp.tiles_x * ((cam->height + 7) / 8) * 64;
+    launch_path_trace(tc, cd, pp, accum, w.work, reinterpret_cast<unsigned long long*>(counters), st);
+  });
+}
+
+eag_status eag_accum_resolve(const int64_t* accum, int64_t n_pixels, int32_t total_spp, float* rgb, void* stream) {
+  return guarded([&] {
+    if (!accum || !rgb || n_pixels < 0 || total_spp < 1) fail(EAG_ERR_INVALID_ARGUMENT, "bad resolve arguments");
+    if (n_pixels == 0) return;
+    launch_accum_resolve(accum, n_pixels * 3, 1.0 / (EAG_ACCUM_SCALE * (double)total_spp), rgb,
+                         static_cast<hipStream_t>(stream));
+  });
+}
+
+eag_status eag_apply_edit(const eag_edit* e, const eag_surfel_attrs* a, void* stream) {
+  return guarded([&] {
+    if (!e || !a) fail(EAG_ERR_INVALID_ARGUMENT, "null argument");
+    if (a->n < 1 || !a->albedo || !a->radiance || !a->emissive) fail(EAG_ERR_INVALID_ARGUMENT, "bad attribute arrays");
+    if (e->count < 0 || (e->count > 0 && !e->idx)) fail(EAG_ERR_INVALID_ARGUMENT, "bad edit index list");
+    if (e->kind < EAG_EDIT_SET_RADIANCE || e->kind > EAG_EDIT_SET_EMISSIVE) fail(EAG_ERR_INVALID_ARGUMENT, "bad edit kind");
+    if (e->count == 0) return;
+    launch_apply_edit(*e, *a, static_cast<hipStream_t>(stream));
+  });
+}
+
+}  // extern "C"

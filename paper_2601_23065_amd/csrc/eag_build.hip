@@ -1,0 +1,399 @@
+// Linear BVH build and refit over 2D Gaussian surfels.
+//
+// 1. frames and k_sigma-ellipse boxes of every surfel (the surfel of
+//    Sec. 3.1: centre p, tangent axes t_u, t_v from the normalised
+//    quaternion, scales s_u, s_v), and the scene bounds;
+// 2. 63-bit Morton codes of the centres, radix-sorted with rocPRIM;
+// 3. Karras' radix-tree construction (one thread per internal node, ties of
+//    equal codes broken by sorted position);
+// 4. geometry records in sorted order (one 64-B record per surfel);
+// 5. bottom-up box propagation with per-node arrival counters;
+// 6. the deepest leaf, which bounds the traversal stack.
+#include <hip/hip_runtime.h>
+#include <rocprim/device/device_radix_sort.hpp>
+
+#include "eag_device.h"
+#include "eag_internal.h"
+
+namespace eag {
+
+namespace {
+
+__device__ __forceinline__ uint32_t fenc(float f) {
+  const uint32_t b = __float_as_uint(f);
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__host__ __device__ __forceinline__ float fdec(uint32_t e) {
+  const uint32_t b = (e & 0x80000000u) ? (e & 0x7fffffffu) : ~e;
+  float f;
+  __builtin_memcpy(&f, &b, 4);
+  return f;
+}
+
+struct Frame {
+  V3 tu, tv, n;
+};
+__device__ __forceinline__ Frame frame_of(const float* rot, int64_t n, int64_t i) {
+  float w = rot[i], x = rot[n + i], y = rot[2 * n + i], z = rot[3 * n + i];
+  const float inv = 1.0f / sqrtf(w * w + x * x + y * y + z * z);
+  w *= inv; x *= inv; y *= inv; z *= inv;
+  Frame f;
+  f.tu = v3(1.0f - 2.0f * (y * y + z * z), 2.0f * (x * y + w * z), 2.0f * (x * z - w * y));
+  f.tv = v3(2.0f * (x * y - w * z), 1.0f - 2.0f * (x * x + z * z), 2.0f * (y * z + w * x));
+  f.n = cross(f.tu, f.tv);
+  return f;
+}
+
+__global__ void k_init_header(BvhHeader* h) {
+  if (threadIdx.x < 3) {
+    h->plo[threadIdx.x] = 0xffffffffu;
+    h->phi[threadIdx.x] = 0u;
+    h->blo[threadIdx.x] = 0xffffffffu;
+    h->bhi[threadIdx.x] = 0u;
+  }
+  if (threadIdx.x == 0) h->max_depth = 0;
+}
+
+// Box of the k_sigma ellipse: half extent along axis a is
+// k * sqrt((s_u t_u,a)^2 + (s_v t_v,a)^2), padded so that float32 rounding in
+// the surfel test can never place an accepted hit outside its box.
+__global__ void k_boxes(eag_surfels s, float k, float* box, BvhHeader* h) {
+  const int64_t n = s.n;
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  float plo[3] = {__builtin_inff(), __builtin_inff(), __builtin_inff()};
+  float phi[3] = {-__builtin_inff(), -__builtin_inff(), -__builtin_inff()};
+  float blo[3] = {__builtin_inff(), __builtin_inff(), __builtin_inff()};
+  float bhi[3] = {-__builtin_inff(), -__builtin_inff(), -__builtin_inff()};
+  if (i < n) {
+    const Frame f = frame_of(s.rot, n, i);
+    const float su = s.scale[i], sv = s.scale[n + i];
+    const float p[3] = {s.pos[i], s.pos[n + i], s.pos[2 * n + i]};
+    const float pad = 2e-5f * (1.0f + fmaxf(fmaxf(fabsf(p[0]), fabsf(p[1])), fabsf(p[2])));
+    const float tu[3] = {f.tu.x, f.tu.y, f.tu.z}, tv[3] = {f.tv.x, f.tv.y, f.tv.z};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const float e = k * sqrtf((su * tu[a]) * (su * tu[a]) + (sv * tv[a]) * (sv * tv[a])) + pad;
+      box[a * n + i] = p[a] - e;
+      box[(3 + a) * n + i] = p[a] + e;
+      plo[a] = phi[a] = p[a];
+      blo[a] = p[a] - e;
+      bhi[a] = p[a] + e;
+    }
+  }
+  // block reduction of the bounds, then one atomic per block and component
+  __shared__ float red[12][256];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    red[a][threadIdx.x] = plo[a];
+    red[3 + a][threadIdx.x] = phi[a];
+    red[6 + a][threadIdx.x] = blo[a];
+    red[9 + a][threadIdx.x] = bhi[a];
+  }
+  __syncthreads();
+  for (int s2 = blockDim.x / 2; s2 > 0; s2 >>= 1) {
+    if (threadIdx.x < s2) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        red[a][threadIdx.x] = fminf(red[a][threadIdx.x], red[a][threadIdx.x + s2]);
+        red[3 + a][threadIdx.x] = fmaxf(red[3 + a][threadIdx.x], red[3 + a][threadIdx.x + s2]);
+        red[6 + a][threadIdx.x] = fminf(red[6 + a][threadIdx.x], red[6 + a][threadIdx.x + s2]);
+        red[9 + a][threadIdx.x] = fmaxf(red[9 + a][threadIdx.x], red[9 + a][threadIdx.x + s2]);
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 3) {
+    const int a = threadIdx.x;
+    atomicMin(&h->plo[a], fenc(red[a][0]));
+    atomicMax(&h->phi[a], fenc(red[3 + a][0]));
+    atomicMin(&h->blo[a], fenc(red[6 + a][0]));
+    atomicMax(&h->bhi[a], fenc(red[9 + a][0]));
+  }
+}
+
+__device__ __forceinline__ uint64_t spread3(uint32_t a) {
+  uint64_t x = a & 0x1fffffu;
+  x = (x | x << 32) & 0x1f00000000ffffull;
+  x = (x | x << 16) & 0x1f0000ff0000ffull;
+  x = (x | x << 8) & 0x100f00f00f00f00full;
+  x = (x | x << 4) & 0x10c30c30c30c30c3ull;
+  x = (x | x << 2) & 0x1249249249249249ull;
+  return x;
+}
+
+__global__ void k_morton(eag_surfels s, const BvhHeader* h, uint64_t* codes, uint32_t* ids) {
+  const int64_t n = s.n;
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t q[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float lo = fdec(h->plo[a]), hi = fdec(h->phi[a]);
+    const float ext = hi - lo;
+    float x = ext > 0.0f ? (s.pos[a * n + i] - lo) / ext : 0.0f;
+    x = fminf(fmaxf(x, 0.0f), 1.0f);
+    q[a] = min((uint32_t)(x * 2097152.0f), 2097151u);
+  }
+  codes[i] = (spread3(q[0]) << 2) | (spread3(q[1]) << 1) | spread3(q[2]);
+  ids[i] = (uint32_t)i;
+}
+
+__device__ __forceinline__ int common_prefix(const uint64_t* c, int n, int i, int j) {
+  if (j < 0 || j >= n) return -1;
+  const uint64_t a = c[i], b = c[j];
+  if (a == b) return 64 + __clz((uint32_t)(i ^ j));
+  return __clzll(a ^ b);
+}
+
+// Karras (HPG 2012), Algorithm for one internal node i of n-1.
+__global__ void k_karras(const uint64_t* c, int n, Node* nodes, int32_t* leaf_parent, int32_t* node_parent) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n - 1) return;
+  const int d = (common_prefix(c, n, i, i + 1) - common_prefix(c, n, i, i - 1)) >= 0 ? 1 : -1;
+  const int dmin = common_prefix(c, n, i, i - d);
+  int lmax = 2;
+  while (common_prefix(c, n, i, i + lmax * d) > dmin) lmax *= 2;
+  int l = 0;
+  for (int t = lmax / 2; t >= 1; t /= 2)
+    if (common_prefix(c, n, i, i + (l + t) * d) > dmin) l += t;
+  const int j = i + l * d;
+  const int dnode = common_prefix(c, n, i, j);
+  int s = 0;
+  for (int div = 2;; div *= 2) {
+    const int t = (l + div - 1) / div;
+    if (common_prefix(c, n, i, i + (s + t) * d) > dnode) s += t;
+    if (t <= 1) break;
+  }
+  const int g = i + s * d + min(d, 0);
+  const int lo = min(i, j), hi = max(i, j);
+  const int left = (lo == g) ? ~g : g;
+  const int right = (hi == g + 1) ? ~(g + 1) : (g + 1);
+  nodes[i].d = make_int4(left, right, 0, 0);
+  if (left < 0) leaf_parent[~left] = i; else node_parent[left] = i;
+  if (right < 0) leaf_parent[~right] = i; else node_parent[right] = i;
+  if (i == 0) node_parent[0] = -1;
+}
+
+__global__ void k_records(eag_surfels s, const int32_t* perm, Record* recs) {
+  const int64_t n = s.n;
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const int64_t i = perm[j];
+  const Frame f = frame_of(s.rot, n, i);
+  const float su = s.scale[i], sv = s.scale[n + i];
+  const float isu = 1.0f / su, isv = 1.0f / sv;
+  float4* r = reinterpret_cast<float4*>(recs + j);
+  r[0] = make_float4(s.pos[i], s.pos[n + i], s.pos[2 * n + i], s.opacity[i]);
+  r[1] = make_float4(f.n.x, f.n.y, f.n.z, __uint_as_float((uint32_t)i));
+  r[2] = make_float4(f.tu.x * isu, f.tu.y * isu, f.tu.z * isu, su);
+  r[3] = make_float4(f.tv.x * isv, f.tv.y * isv, f.tv.z * isv, sv);
+}
+
+__global__ void k_zero_i32(int32_t* p, int64_t n) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+__device__ __forceinline__ float aload(const float* p) {
+  return __uint_as_float(__hip_atomic_load(reinterpret_cast<const uint32_t*>(p), __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT));
+}
+
+__device__ __forceinline__ void put_box(Node* nd, int slot, const float* lo, const float* hi) {
+  float* f = reinterpret_cast<float*>(nd);
+  const int o = slot * 6;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    __hip_atomic_store(reinterpret_cast<uint32_t*>(f + o + a), __float_as_uint(lo[a]), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(reinterpret_cast<uint32_t*>(f + o + 3 + a), __float_as_uint(hi[a]), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// Bottom-up: each leaf writes its box into its parent's slot; the second of
+// the two children to arrive at a node forms the union and moves up.
+__global__ void k_bottom_up(int64_t n, const float* box, const int32_t* perm, Node* nodes,
+                            const int32_t* leaf_parent, const int32_t* node_parent, int32_t* visits) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const int64_t i = perm[j];
+  float lo[3], hi[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = box[a * n + i];
+    hi[a] = box[(3 + a) * n + i];
+  }
+  int child = ~(int)j;
+  int p = leaf_parent[j];
+  while (p >= 0) {
+    Node* nd = nodes + p;
+    const int slot = (nd->d.x == child) ? 0 : 1;
+    put_box(nd, slot, lo, hi);
+    __threadfence();
+    const int old = atomicAdd(&visits[p], 1);
+    if (old == 0) return;
+    __threadfence();
+    const float* f = reinterpret_cast<const float*>(nd);
+    const int o = (1 - slot) * 6;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = fminf(lo[a], aload(f + o + a));
+      hi[a] = fmaxf(hi[a], aload(f + o + 3 + a));
+    }
+    child = p;
+    p = node_parent[p];
+  }
+}
+
+__global__ void k_depth(int64_t n, const int32_t* leaf_parent, const int32_t* node_parent, BvhHeader* h) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  int d = 0;
+  int p = leaf_parent[j];
+  while (p >= 0) {
+    ++d;
+    p = node_parent[p];
+  }
+  atomicMax(&h->max_depth, d);
+}
+
+__global__ void k_attrs(eag_surfels s, const int32_t* perm, Attr* attrs) {
+  const int64_t n = s.n;
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const int64_t i = perm[j];
+  float4* a = reinterpret_cast<float4*>(attrs + j);
+  a[0] = make_float4(s.albedo[i], s.albedo[n + i], s.albedo[2 * n + i], s.emissive[i]);
+  a[1] = make_float4(s.radiance[i], s.radiance[n + i], s.radiance[2 * n + i], 0.0f);
+}
+
+inline unsigned blocks(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
+
+struct BuildWs {
+  float* box;
+  uint64_t* codes_in;
+  uint64_t* codes_out;
+  uint32_t* ids_in;
+  int32_t* visits;
+  void* sort_tmp;
+  size_t sort_bytes;
+  size_t bytes;
+};
+
+size_t sort_tmp_bytes(int64_t n) {
+  size_t b = 0;
+  hipError_t e = rocprim::radix_sort_pairs(nullptr, b, (uint64_t*)nullptr, (uint64_t*)nullptr, (uint32_t*)nullptr,
+                                           (uint32_t*)nullptr, (size_t)n, 0, 63, (hipStream_t)0);
+  check_hip(e, "radix_sort_pairs size query");
+  return b;
+}
+
+BuildWs build_ws(void* base, int64_t n) {
+  Carver c(base, ~size_t(0));
+  BuildWs w;
+  w.box = c.take<float>(6 * n);
+  w.codes_in = c.take<uint64_t>(n);
+  w.codes_out = c.take<uint64_t>(n);
+  w.ids_in = c.take<uint32_t>(n);
+  w.visits = c.take<int32_t>(n);
+  w.sort_bytes = sort_tmp_bytes(n);
+  w.sort_tmp = c.take<char>(w.sort_bytes);
+  w.bytes = c.bytes();
+  return w;
+}
+
+void read_back(eag_bvh* b, hipStream_t st) {
+  BvhHeader h;
+  check_hip(hipMemcpyAsync(&h, b->hdr, sizeof(h), hipMemcpyDeviceToHost, st), "header copy");
+  check_hip(hipStreamSynchronize(st), "build sync");
+  for (int a = 0; a < 3; ++a) {
+    b->lo[a] = fdec(h.blo[a]);
+    b->hi[a] = fdec(h.bhi[a]);
+  }
+  b->max_depth = h.max_depth;
+}
+
+}  // namespace
+
+BvhLayout bvh_layout(void* base, int64_t n) {
+  Carver c(base, ~size_t(0));
+  BvhLayout l;
+  l.hdr = c.take<BvhHeader>(1);
+  l.nodes = c.take<Node>(n > 1 ? n - 1 : 1);
+  l.recs = c.take<Record>(n);
+  l.perm = c.take<int32_t>(n);
+  l.leaf_parent = c.take<int32_t>(n);
+  l.node_parent = c.take<int32_t>(n > 1 ? n - 1 : 1);
+  l.bytes = c.bytes();
+  return l;
+}
+
+size_t build_ws_bytes(int64_t n) { return build_ws(nullptr, n).bytes; }
+
+void validate_surfels(const eag_surfels* s) {
+  if (!s) fail(EAG_ERR_INVALID_ARGUMENT, "surfels is null");
+  if (s->n < 1 || s->n > (int64_t(1) << 23)) fail(EAG_ERR_INVALID_ARGUMENT, "surfel count must be in [1, 2^23]");
+  if (!s->pos || !s->rot || !s->scale || !s->opacity || !s->albedo || !s->radiance || !s->emissive)
+    fail(EAG_ERR_INVALID_ARGUMENT, "a surfel array pointer is null");
+}
+
+static void geometry_pass(const eag_surfels* s, eag_bvh* b, const BuildWs& w, hipStream_t st) {
+  const int64_t n = s->n;
+  hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, st, b->hdr);
+  hipLaunchKernelGGL(k_boxes, dim3(blocks(n)), dim3(256), 0, st, *s, 3.0f, w.box, b->hdr);
+}
+
+void build_bvh(const eag_surfels* s, eag_bvh* b, void* ws, size_t ws_bytes, hipStream_t st) {
+  const int64_t n = s->n;
+  BuildWs w = build_ws(ws, n);
+  if (ws_bytes < w.bytes) fail(EAG_ERR_WORKSPACE_TOO_SMALL, "build workspace too small");
+  geometry_pass(s, b, w, st);
+  hipLaunchKernelGGL(k_morton, dim3(blocks(n)), dim3(256), 0, st, *s, b->hdr, w.codes_in, w.ids_in);
+  size_t sb = w.sort_bytes;
+  check_hip(rocprim::radix_sort_pairs(w.sort_tmp, sb, w.codes_in, w.codes_out, w.ids_in,
+                                      reinterpret_cast<uint32_t*>(b->perm), (size_t)n, 0, 63, st),
+            "radix_sort_pairs");
+  if (n > 1) {
+    hipLaunchKernelGGL(k_karras, dim3(blocks(n - 1)), dim3(256), 0, st, w.codes_out, (int)n, b->nodes,
+                       b->leaf_parent, b->node_parent);
+  } else {
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, b->leaf_parent, (int64_t)1);
+  }
+  hipLaunchKernelGGL(k_records, dim3(blocks(n)), dim3(256), 0, st, *s, b->perm, b->recs);
+  if (n > 1) {
+    hipLaunchKernelGGL(k_zero_i32, dim3(blocks(n)), dim3(256), 0, st, w.visits, n);
+    hipLaunchKernelGGL(k_bottom_up, dim3(blocks(n)), dim3(256), 0, st, n, w.box, b->perm, b->nodes,
+                       b->leaf_parent, b->node_parent, w.visits);
+    hipLaunchKernelGGL(k_depth, dim3(blocks(n)), dim3(256), 0, st, n, b->leaf_parent, b->node_parent, b->hdr);
+  }
+  check_hip(hipGetLastError(), "build launch");
+  b->root = n > 1 ? 0 : ~0;
+  read_back(b, st);
+}
+
+void refit_bvh(const eag_surfels* s, eag_bvh* b, void* ws, size_t ws_bytes, hipStream_t st) {
+  const int64_t n = s->n;
+  BuildWs w = build_ws(ws, n);
+  if (ws_bytes < w.bytes) fail(EAG_ERR_WORKSPACE_TOO_SMALL, "refit workspace too small");
+  BvhHeader* h = b->hdr;
+  // bounds are recomputed; max_depth is kept since the topology is unchanged
+  hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, st, h);
+  hipLaunchKernelGGL(k_boxes, dim3(blocks(n)), dim3(256), 0, st, *s, 3.0f, w.box, h);
+  hipLaunchKernelGGL(k_records, dim3(blocks(n)), dim3(256), 0, st, *s, b->perm, b->recs);
+  if (n > 1) {
+    hipLaunchKernelGGL(k_zero_i32, dim3(blocks(n)), dim3(256), 0, st, w.visits, n);
+    hipLaunchKernelGGL(k_bottom_up, dim3(blocks(n)), dim3(256), 0, st, n, w.box, b->perm, b->nodes,
+                       b->leaf_parent, b->node_parent, w.visits);
+  }
+  check_hip(hipGetLastError(), "refit launch");
+  const int32_t depth = b->max_depth;
+  read_back(b, st);
+  b->max_depth = depth;
+}
+
+void pack_attrs(const eag_surfels* s, const eag_bvh* b, Attr* attrs, hipStream_t st) {
+  hipLaunchKernelGGL(k_attrs, dim3(blocks(s->n)), dim3(256), 0, st, *s, b->perm, attrs);
+}
+
+}  // namespace eag

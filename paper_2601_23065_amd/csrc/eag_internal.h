@@ -1,0 +1,108 @@
+// Host-side internals shared by the library's translation units: the BVH
+// handle, memory carving helpers, launch wrappers and error plumbing.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/eag.h"
+
+namespace eag {
+
+struct Node;
+struct Record;
+struct Attr;
+struct CamDev;
+
+// Thrown inside the library, converted to a status at the C boundary.
+struct Error {
+  eag_status status;
+  std::string msg;
+};
+[[noreturn]] void fail(eag_status s, const std::string& msg);
+void check_hip(hipError_t e, const char* what);
+
+inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+// Sequential carving of a caller-provided buffer into aligned pieces.
+struct Carver {
+  char* base;
+  size_t used = 0;
+  size_t cap;
+  Carver(void* p, size_t c) : base(static_cast<char*>(p)), cap(c) {}
+  template <class T>
+  T* take(size_t count) {
+    size_t off = align_up(used);
+    used = off + count * sizeof(T);
+    return base ? reinterpret_cast<T*>(base + off) : nullptr;
+  }
+  size_t bytes() const { return align_up(used); }
+};
+
+// Device-side header of a BVH allocation.
+struct BvhHeader {
+  uint32_t plo[3], phi[3];   // ordered-uint encoded centre bounds (Morton frame)
+  uint32_t blo[3], bhi[3];   // ordered-uint encoded box bounds
+  int32_t max_depth;
+  int32_t pad[3];
+};
+
+}  // namespace eag
+
+struct eag_bvh {
+  int64_t n;
+  int32_t idx_bits;
+  int32_t max_depth;
+  int32_t root;
+  float lo[3], hi[3];
+  void* mem;
+  size_t mem_bytes;
+  eag::BvhHeader* hdr;
+  eag::Node* nodes;
+  eag::Record* recs;
+  int32_t* perm;
+  int32_t* leaf_parent;
+  int32_t* node_parent;
+};
+
+namespace eag {
+
+// Pieces of a BVH allocation of n surfels (base may be null to size it).
+struct BvhLayout {
+  BvhHeader* hdr;
+  Node* nodes;
+  Record* recs;
+  int32_t* perm;
+  int32_t* leaf_parent;
+  int32_t* node_parent;
+  size_t bytes;
+};
+BvhLayout bvh_layout(void* base, int64_t n);
+
+size_t build_ws_bytes(int64_t n);
+void validate_surfels(const eag_surfels* s);
+void build_bvh(const eag_surfels* s, eag_bvh* b, void* ws, size_t ws_bytes, hipStream_t st);
+void refit_bvh(const eag_surfels* s, eag_bvh* b, void* ws, size_t ws_bytes, hipStream_t st);
+
+// Attribute records in sorted order (rho, e, r), refreshed by every render call.
+void pack_attrs(const eag_surfels* s, const eag_bvh* b, Attr* attrs, hipStream_t st);
+
+// Trace context parameters derived from a BVH and trace params.
+struct TraceSetup {
+  int32_t idx_bits;
+  uint32_t max_bucket;
+  float inv_dq;
+};
+TraceSetup trace_setup(const eag_bvh* b, const eag_trace_params* p, float t_max_needed);
+void validate_params(const eag_trace_params* p);
+CamDev make_cam(const eag_camera& c, uint32_t id);
+float camera_t_max(const eag_bvh* b, const eag_camera& c);
+
+void launch_trace_rays(const eag_bvh* b, const Attr* attrs, const eag_trace_params* p, const TraceSetup& ts,
+                       int64_t n_rays, const float* o, const float* d, float* out, int32_t* hit_idx,
+                       int32_t* hit_count, int32_t max_hits, hipStream_t st);
+
+}  // namespace eag

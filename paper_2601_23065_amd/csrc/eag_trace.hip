@@ -1,0 +1,65 @@
+// Tracing of caller-supplied rays (Sec. 3.1, Eq. 1-3): one thread per ray,
+// multi-round k-buffer traversal and front-to-back blending, output of the
+// normalised traced quantities and, optionally, the blended hit list.
+#include "eag_device.h"
+#include "eag_internal.h"
+
+namespace eag {
+
+namespace {
+
+__global__ void __launch_bounds__(256) k_trace_rays(TraceCtx tc, int64_t n_rays, const float* o, const float* d,
+                                                    float* out, int32_t* hit_idx, int32_t* hit_count,
+                                                    int32_t max_hits) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n_rays) return;
+  const V3 O = v3(o[i], o[n_rays + i], o[2 * n_rays + i]);
+  const V3 W = v3(d[i], d[n_rays + i], d[2 * n_rays + i]);
+  int32_t* hl = hit_idx ? hit_idx + i * (int64_t)max_hits : nullptr;
+  const SegOut s = trace_segment<Q_ALL>(tc, O, W, hl, max_hits);
+  const float A = 1.0f - s.T;
+  float v[12];
+  if (s.nhits > 0 && A > 0.0f) {
+    const float il = 1.0f / sqrtf(dot(s.N, s.N));
+    v[0] = s.N.x * il; v[1] = s.N.y * il; v[2] = s.N.z * il;
+    v[3] = s.D / A;
+  } else {
+    v[0] = v[1] = v[2] = v[3] = 0.0f;
+  }
+  v[4] = s.R.x; v[5] = s.R.y; v[6] = s.R.z;
+  v[7] = s.E;
+  v[8] = s.P.x; v[9] = s.P.y; v[10] = s.P.z;
+  v[11] = s.nhits > 0 ? A : 0.0f;
+#pragma unroll
+  for (int k = 0; k < 12; ++k) out[k * n_rays + i] = v[k];
+  if (hit_count) hit_count[i] = s.nhits;
+}
+
+}  // namespace
+
+TraceCtx make_ctx(const eag_bvh* b, const Attr* attrs, const eag_trace_params* p, const TraceSetup& ts) {
+  TraceCtx tc;
+  tc.nodes = b->nodes;
+  tc.recs = b->recs;
+  tc.attrs = attrs;
+  tc.root = b->root;
+  tc.idx_bits = ts.idx_bits;
+  tc.max_bucket = ts.max_bucket;
+  tc.inv_dq = ts.inv_dq;
+  tc.t_min = p->t_min;
+  tc.k2 = p->k_sigma * p->k_sigma;
+  tc.T_min = p->T_min;
+  return tc;
+}
+
+void launch_trace_rays(const eag_bvh* b, const Attr* attrs, const eag_trace_params* p, const TraceSetup& ts,
+                       int64_t n_rays, const float* o, const float* d, float* out, int32_t* hit_idx,
+                       int32_t* hit_count, int32_t max_hits, hipStream_t st) {
+  const TraceCtx tc = make_ctx(b, attrs, p, ts);
+  const unsigned g = (unsigned)((n_rays + 255) / 256);
+  hipLaunchKernelGGL(k_trace_rays, dim3(g), dim3(256), 0, st, tc, n_rays, o, d, out, hit_idx, hit_count,
+                     max_hits);
+  check_hip(hipGetLastError(), "trace_rays launch");
+}
+
+}  // namespace eag

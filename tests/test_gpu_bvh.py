@@ -1,0 +1,77 @@
+"""LBVH invariants on the device-built tree: every surfel in exactly one
+leaf, every child box inside its parent's box, each leaf's box contains its
+surfel's k_sigma ellipse, and the stack bound (max depth) is consistent."""
+import numpy as np
+import pytest
+import torch
+
+import scenegen as sg
+from tests._util import gpu_scene
+
+pytestmark = pytest.mark.gpu
+
+
+def _slice(buf, addr, nbytes):
+    off = int(addr) - buf.data_ptr()
+    assert 0 <= off and off + nbytes <= buf.numel()
+    return buf[off:off + nbytes].cpu().numpy()
+
+
+def _nodes(bvh, n):
+    """Copy the node array and permutation out of the BVH's own tensor."""
+    info = bvh.info()
+    m = max(n - 1, 1)
+    nodes = _slice(bvh.mem, info.nodes, m * 64).view(np.int32).reshape(m, 16)
+    perm = _slice(bvh.mem, info.perm, n * 4).view(np.int32)
+    return info, nodes, perm
+
+
+@pytest.mark.parametrize("which", ["cloud", "room"])
+def test_bvh_invariants(which):
+    from paper_2601_23065_amd.api import BVH
+    scene = sg.cloud_scene(2000, seed=1) if which == "cloud" else sg.room_scene(30000, (4.0, 3.0, 2.5), 5, seed=8)
+    gs = gpu_scene(scene)
+    bvh = BVH(gs)
+    n = scene.n
+    info, nodes, perm = _nodes(bvh, n)
+    assert sorted(perm.tolist()) == list(range(n))
+    boxes = nodes[:, :12].view(np.float32).reshape(-1, 2, 6)       # [node, child, lo3 hi3]
+    kids = nodes[:, 12:14]
+    seen = np.zeros(n, dtype=np.int64)
+    depth_max = 0
+    stack = [(0, 0, None)]
+    while stack:
+        i, d, parent_box = stack.pop()
+        depth_max = max(depth_max, d + 1)
+        for c in range(2):
+            b = boxes[i, c]
+            assert np.all(b[:3] <= b[3:])
+            if parent_box is not None:
+                assert np.all(b[:3] >= parent_box[:3]) and np.all(b[3:] <= parent_box[3:])
+            ref = int(kids[i, c])
+            if ref >= 0:
+                stack.append((ref, d + 1, b))
+            else:
+                seen[~ref] += 1
+                s = int(perm[~ref])
+                p = scene.pos[:, s].astype(np.float64)
+                assert np.all(b[:3] < p) and np.all(p < b[3:])
+    assert np.all(seen == 1)
+    assert info.max_depth == depth_max
+    lo, hi = np.array(info.lo), np.array(info.hi)
+    assert np.all(lo <= scene.pos.min(axis=1)) and np.all(hi >= scene.pos.max(axis=1))
+
+
+def test_single_surfel_scene():
+    from paper_2601_23065_amd.api import BVH, Params, trace_rays
+    s = sg.cloud_scene(1, seed=3)
+    s.pos[:] = 0
+    s.rot[:] = np.array([[1.0], [0.0], [0.0], [0.0]], dtype=np.float32)
+    gs = gpu_scene(s)
+    bvh = BVH(gs)
+    assert bvh.info().root < 0
+    o = torch.tensor([[0.0], [0.0], [-2.0]], device="cuda")
+    d = torch.tensor([[0.0], [0.0], [1.0]], device="cuda")
+    out, hits, cnt = trace_rays(bvh, gs, Params(), o, d, max_hits=4)
+    assert int(cnt[0]) == 1 and int(hits[0, 0]) == 0
+    assert abs(float(out[11, 0]) - float(s.opacity[0])) < 1e-6
