@@ -34,6 +34,10 @@ ALGO_BYTES_PER_HIT = 68
 ALGO_BYTES_PER_SEGMENT = 96
 
 
+def _log(msg):
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
 def _oracle_worker(args):
     import oracle.render as R
     pixels, samples = args
@@ -77,6 +81,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--surfels", type=int, default=1_000_000)
+    ap.add_argument("--spp", type=int, default=None, help="override the workload's 64 spp (diagnostics only)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
@@ -90,10 +95,12 @@ def main():
 
     scene, cams, cfg = sg.config(3, n_override=args.surfels if args.surfels != 1_000_000 else None)
     cam = cams[0]
-    params = Params(spp=cfg["spp"], max_depth=cfg["max_depth"], rr_start=cfg["rr_start"], seed=0, camera_id=0)
+    params = Params(spp=args.spp or cfg["spp"], max_depth=cfg["max_depth"], rr_start=cfg["rr_start"], seed=0,
+                    camera_id=0)
+    _log(f"scene ready: {scene.n} surfels, {cam.width}x{cam.height}, {params.spp} spp")
     gs = Scene(scene.arrays())
     ws = path_trace_workspace(gs)
-    counters = torch.zeros(5, dtype=torch.int64, device="cuda")
+    counters = torch.zeros(6, dtype=torch.int64, device="cuda")
     stream = torch.cuda.current_stream()
 
     def step():
@@ -105,20 +112,25 @@ def main():
         img = resolve(acc, params.spp)
         return img, (ev0, ev1)
 
-    for _ in range(args.warmup):
+    for i in range(args.warmup):
         step()
+        torch.cuda.synchronize()
+        _log(f"warmup step {i} done")
     torch.cuda.synchronize()
     counters.zero_()
     evs = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for i in range(args.steps):
         img, ev = step()
         evs.append(ev)
+        if args.steps > 1:
+            _log(f"step {i} issued")
     torch.cuda.synchronize()
+    _log("timed steps done")
     wall = time.perf_counter() - t0
     c = counters.cpu().numpy().astype(np.float64)
-    segments, paths, rounds, tests, blended = (c[i] / args.steps for i in range(5))
+    segments, paths, rounds, tests, blended, visits = (c[i] / args.steps for i in range(6))
     pt_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
     ms_per_step = wall / args.steps * 1e3
     value = segments / (ms_per_step * 1e-3) / 1e6
@@ -146,11 +158,13 @@ def main():
                      "frac": round(achieved / PEAK_HBM_GBS, 5), "traffic": None},
         "detail": {"segments_per_step": segments, "paths_per_step": paths, "kbuf_rounds_per_segment":
                    round(rounds / max(segments, 1), 3), "candidate_tests_per_segment": round(tests / max(segments, 1), 2),
+                   "nodes_visited_per_segment": round(visits / max(segments, 1), 2),
                    "blended_hits_per_segment": round(blended / max(segments, 1), 3),
                    "pt_kernel_ms": round(pt_ms, 3), "paths_per_s": round(paths / (ms_per_step * 1e-3), 1),
                    "image_mean": float(img.mean())},
     }
     if not args.no_cpu:
+        _log("oracle CPU baseline")
         rec["cpu_baseline"] = cpu_baseline(scene, cam, params)
     print(json.dumps(rec))
 

@@ -168,15 +168,18 @@ void eag_bvh_destroy(eag_bvh* bvh);
  * stopping after the first hit with T < T_min.
  * ------------------------------------------------------------------------ */
 size_t eag_trace_workspace_bytes(int64_t n_surfels);
-/* origins, dirs: device [3][n_rays], dirs unit length.
+/* origins, dirs: device double [3][n_rays], dirs unit length (the tracer's
+ * ray geometry is double precision throughout).
  * out: device [12][n_rays] = Nt(3), Dt, R(3), E, P(3), A (Nt = N/|N|, Dt = D/A;
  *      all zero for a miss).
  * hit_idx: nullable device [n_rays][max_hits] surfel indices in blending order;
  * hit_count: nullable device [n_rays] number of blended hits (may exceed
- * max_hits; only the first max_hits are written). */
+ * max_hits; only the first max_hits are written).
+ * stats: nullable device [n_rays][3] traversal statistics per ray: k-buffer
+ * rounds, candidate surfel tests, internal nodes visited. */
 eag_status eag_trace_rays(const eag_bvh* bvh, const eag_surfels* s, const eag_trace_params* p,
-                          int64_t n_rays, const float* origins, const float* dirs, float* out,
-                          int32_t* hit_idx, int32_t* hit_count, int32_t max_hits,
+                          int64_t n_rays, const double* origins, const double* dirs, float* out,
+                          int32_t* hit_idx, int32_t* hit_count, int32_t max_hits, int32_t* stats,
                           void* ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
@@ -187,9 +190,12 @@ eag_status eag_trace_rays(const eag_bvh* bvh, const eag_surfels* s, const eag_tr
  * camera_id + c)). Secondary segments blend r without an emitter test (the
  * radiance cache).
  * ------------------------------------------------------------------------ */
-#define EAG_FWD_PIXEL_FLOATS 16
-/* Floats of forward state kept for the backward pass:
- * n_cams*H*W*(EAG_FWD_PIXEL_FLOATS + 3*spp). */
+/* Forward state kept for the backward pass: per pixel EAG_FWD_PIXEL_FLOATS
+ * floats (as doubles: Nt(3), Dt, |N|, A, R(3), P(3); then float E and the
+ * branch 0 miss / 1 emitter / 2 reflect, and two pad floats), followed by
+ * the R of every secondary sample as doubles [n_cams][H][W][spp][3].
+ * Total floats: n_cams*H*W*(EAG_FWD_PIXEL_FLOATS + 6*spp). */
+#define EAG_FWD_PIXEL_FLOATS 28
 int64_t eag_fwd_state_floats(const eag_camera* cams, int32_t n_cams, const eag_trace_params* p);
 size_t eag_render_workspace_bytes(int64_t n_surfels, const eag_camera* cams, int32_t n_cams,
                                   const eag_trace_params* p);
@@ -222,8 +228,8 @@ eag_status eag_single_bounce_backward(const eag_bvh* bvh, const eag_surfels* s, 
  * EAG_ACCUM_SCALE, rounded to nearest); the sums are independent of launch
  * order and of how samples are split across calls. Samples
  * [sample_begin, sample_begin + sample_count) are added.
- * counters: nullable device uint64 [5] += {segments traced, paths started,
- * k-buffer rounds, candidate surfel tests, blended hits}.
+ * counters: nullable device uint64 [6] += {segments traced, paths started,
+ * k-buffer rounds, candidate surfel tests, blended hits, BVH nodes visited}.
  * ------------------------------------------------------------------------ */
 #define EAG_ACCUM_SCALE 4294967296.0 /* 2^32 */
 size_t eag_path_trace_workspace_bytes(int64_t n_surfels);

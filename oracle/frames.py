@@ -5,7 +5,8 @@
   convention), and its normal is t_u x t_v (Sec. 3.1, Eq. 1 and the traced
   normal of Eq. 3). Pinned by closed-form rotations (tests/test_oracle_frames).
 * camera_rays: pinhole camera with vertical field of view through pixel
-  centres, row 0 at the top. The camera basis is fwd = normalize(look_at -
+  centres, row 0 at the top. Eye, look-at, up and field of view are float32
+  values (the camera record), upcast exactly. The camera basis is fwd = normalize(look_at -
   eye), right = normalize(fwd x up), up' = right x fwd. Pinned by
   symmetry and angle checks.
 * hemisphere_frame / cosine_direction: the paper samples the new direction in
@@ -32,11 +33,16 @@ def quat_frames(rot):
     return tu, tv, n
 
 
+def _f32(v):
+    """Camera parameters are float32 values (the renderers' camera record)."""
+    return np.asarray(v, dtype=np.float32).astype(np.float64)
+
+
 def camera_basis(cam):
-    eye = np.asarray(cam.eye, dtype=np.float64)
-    fwd = np.asarray(cam.look_at, dtype=np.float64) - eye
+    eye = _f32(cam.eye)
+    fwd = _f32(cam.look_at) - eye
     fwd /= np.linalg.norm(fwd)
-    right = np.cross(fwd, np.asarray(cam.up, dtype=np.float64))
+    right = np.cross(fwd, _f32(cam.up))
     right /= np.linalg.norm(right)
     up = np.cross(right, fwd)
     return eye, right, up, fwd
@@ -50,7 +56,7 @@ def camera_rays(cam, px, py, jitter=None):
     px = np.asarray(px, dtype=np.float64)
     py = np.asarray(py, dtype=np.float64)
     ox, oy = (0.5, 0.5) if jitter is None else jitter
-    tan_h = np.tan(np.deg2rad(cam.vfov_deg) * 0.5)
+    tan_h = np.tan(np.deg2rad(float(_f32(cam.vfov_deg))) * 0.5)
     aspect = cam.width / cam.height
     nx = (2.0 * (px + ox) / cam.width - 1.0) * tan_h * aspect
     ny = (1.0 - 2.0 * (py + oy) / cam.height) * tan_h

@@ -28,7 +28,7 @@ import numpy as np
 
 from . import philox
 from .frames import camera_rays, cosine_direction
-from .tracer import Scene64, trace, F_RR, KAPPA, U32
+from .tracer import Scene64, trace, F_RR, UF32
 
 JITTER_SEGMENT = 0xFFFFFFFF
 
@@ -172,8 +172,8 @@ def path_trace(scene, cam, prm, pixels=None, samples=None, keep_segments=False):
             if prm.rr_start > 0 and k + 1 >= prm.rr_start:
                 q = np.minimum(0.95, beta[ps].max(axis=1))
                 keep = u2 < q
-                # margin: the float32 throughput carries ~(segments * 64) ulps
-                close = np.abs(u2 - q) <= q * (k + 1) * 64 * KAPPA * U32 + 1e-7
+                # margin: a float32 throughput carries a few ulps per product
+                close = np.abs(u2 - q) <= q * (k + 1) * 8 * UF32 + 1e-7
                 flags[ps[close]] |= F_RR
                 beta[ps[keep]] /= q[keep][:, None]
             for jj, j in enumerate(refl):

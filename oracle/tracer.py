@@ -25,22 +25,26 @@ V = A v, transmittance independent of order, split associativity), and a
 pure-Python per-ray loop on tiny scenes.
 
 Decision margins. Besides the exact result, each segment carries flag bits
-for decisions that a float32 evaluation of the same definition may take
-differently: a surfel near its acceptance rim or near t_min, a key near a
-bucket edge, transmittance near T_min at the stopping hit, E near tau_E, a
-nearly empty segment and a near-singular hemisphere frame. Each margin is an
-error bound built from a float32 rounding model (unit roundoff 2^-24 times
-a safety factor KAPPA, times the magnitudes involved) plus the propagated
-error of the ray's own origin and direction, which the renderers carry from
-segment to segment. Flagged segments are excluded from bit-exact
-comparisons and counted.
+for decisions that another evaluation of the same definition, with
+different rounding, may take differently: a surfel near its acceptance rim
+or near t_min, a key near a bucket edge, transmittance near T_min at the
+stopping hit, E near tau_E, a nearly empty segment and a near-singular
+hemisphere frame. Each margin is an error bound built from a rounding model
+(unit roundoff UGEOM for ray geometry, which a float32 evaluation would
+set to 2^-24 and a double-precision one to 2^-53, times a safety factor
+KAPPA, times the magnitudes involved; UF32 for quantities kept in float32),
+plus the propagated error of the ray's own origin and direction, which the
+renderers carry from segment to segment. Flagged segments are excluded from
+bit-exact comparisons and counted.
 """
 import numpy as np
 
 from .frames import quat_frames, hemisphere_frame
 
-U32 = 2.0 ** -24
-KAPPA = 2.0
+UGEOM = 2.0 ** -53      # ray geometry evaluated in double precision
+UF32 = 2.0 ** -24       # quantities stored in float32 (E against tau_E, throughput)
+KAPPA = 64.0
+U32 = UGEOM
 
 F_RIM, F_TMIN, F_BUCKET, F_TERM, F_EMIT, F_THIN, F_FRAME, F_PAR, F_RR = (1 << i for i in range(9))
 FLAG_NAMES = {F_RIM: "rim", F_TMIN: "tmin", F_BUCKET: "bucket", F_TERM: "term", F_EMIT: "emit",
@@ -68,7 +72,7 @@ class Scene64:
 class Segment:
     """Result of tracing one ray segment."""
     __slots__ = ("hits", "t", "alpha", "n_acc", "N", "D", "R", "E", "P", "A", "Nt", "Dt", "Nlen",
-                 "T", "flags", "eX", "ew", "mlen")
+                 "T", "flags", "eX", "ew", "mlen", "O", "W")
 
     def __init__(self):
         self.hits = np.zeros(0, dtype=np.int64)
@@ -89,6 +93,8 @@ class Segment:
         self.eX = 0.0
         self.ew = 0.0
         self.mlen = 1.0
+        self.O = None
+        self.W = None
 
     @property
     def hit(self) -> bool:
@@ -155,6 +161,7 @@ def _trace_batch(sc, O, W, prm, eO, ew, seg_k):
     res = []
     for b in range(O.shape[0]):
         seg = Segment()
+        seg.O, seg.W = O[b], W[b]
         idx = np.nonzero(acc[b])[0]
         flags = (F_RIM if rim[b] else 0) | (F_TMIN if tmin[b] else 0) | (F_PAR if par[b] else 0)
         if idx.size == 0:
@@ -229,7 +236,7 @@ def _trace_batch(sc, O, W, prm, eO, ew, seg_k):
         elif abs(np.log(max(T[m], 1e-300)) - lnTmin) <= dlnT:
             flags |= F_TERM
         dw = ea + np.concatenate([[0.0], np.cumsum(lt)[:-1]])
-        dE = float(np.sum(wts * sc.e[hi] * dw)) + KAPPA * U32
+        dE = float(np.sum(wts * sc.e[hi] * dw)) + 4 * UF32 * max(seg.E, prm.tau_E)
         if abs(seg.E - prm.tau_E) <= dE:
             flags |= F_EMIT
         if seg.A < 1e-4:

@@ -14,7 +14,7 @@ STATUS_NAMES = {0: "EAG_OK", 1: "EAG_NOT_READY", -1: "EAG_ERR_INVALID_ARGUMENT",
 
 JITTER, ADDITIVE_EMISSION, DETACH_BOUNCE = 1, 2, 4
 EDIT_SET_RADIANCE, EDIT_SCALE_RADIANCE, EDIT_SET_ALBEDO, EDIT_SET_EMISSIVE = 1, 2, 3, 4
-FWD_PIXEL_FLOATS = 16
+FWD_PIXEL_FLOATS = 28
 ACCUM_SCALE = 4294967296.0
 
 vp = C.c_void_p
@@ -81,7 +81,7 @@ SIGNATURES = {
     "eag_bvh_get_info": (C.c_int, [vp, P(BvhInfo)]),
     "eag_bvh_destroy": (None, [vp]),
     "eag_trace_workspace_bytes": (C.c_size_t, [C.c_int64]),
-    "eag_trace_rays": (C.c_int, [vp, P(Surfels), P(TraceParams), C.c_int64, vp, vp, vp, vp, vp, C.c_int32, vp,
+    "eag_trace_rays": (C.c_int, [vp, P(Surfels), P(TraceParams), C.c_int64, vp, vp, vp, vp, vp, C.c_int32, vp, vp,
                                  C.c_size_t, vp]),
     "eag_fwd_state_floats": (C.c_int64, [P(Camera), C.c_int32, P(TraceParams)]),
     "eag_render_workspace_bytes": (C.c_size_t, [C.c_int64, P(Camera), C.c_int32, P(TraceParams)]),

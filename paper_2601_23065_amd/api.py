@@ -152,10 +152,12 @@ class BVH:
             pass
 
 
-def trace_rays(bvh: BVH, scene: Scene, params: Params, origins, dirs, max_hits: int = 0, stream=None):
+def trace_rays(bvh: BVH, scene: Scene, params: Params, origins, dirs, max_hits: int = 0, stream=None,
+               stats=None):
     """origins, dirs: [3, M] float32 device tensors. Returns out [12, M]
     (Nt, Dt, R, E, P, A) and, if max_hits > 0, (hit_idx [M, max_hits],
-    hit_count [M])."""
+    hit_count [M]). stats: optional int32 [M, 3] device tensor receiving
+    (k-buffer rounds, candidate tests, nodes visited) per ray."""
     lib = L.load()
     m = origins.shape[1]
     dev = scene.device
@@ -166,9 +168,11 @@ def trace_rays(bvh: BVH, scene: Scene, params: Params, origins, dirs, max_hits: 
     wp, wb = _aligned(ws)
     p = params.c()
     sc = scene.c()
-    L.check(lib.eag_trace_rays(bvh.h, C.byref(sc), C.byref(p), m, _ptr(origins.contiguous()),
-                               _ptr(dirs.contiguous()), _ptr(out), _ptr(hits), _ptr(cnt), max_hits, wp, wb,
-                               _stream(stream)))
+    origins = origins.to(torch.float64).contiguous()
+    dirs = dirs.to(torch.float64).contiguous()
+    L.check(lib.eag_trace_rays(bvh.h, C.byref(sc), C.byref(p), m, _ptr(origins),
+                               _ptr(dirs), _ptr(out), _ptr(hits), _ptr(cnt), max_hits, _ptr(stats),
+                               wp, wb, _stream(stream)))
     return (out, hits, cnt) if max_hits > 0 else out
 
 

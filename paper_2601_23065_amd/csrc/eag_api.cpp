@@ -49,6 +49,7 @@ bool is_pow2_or_zero(float x) {
 }  // namespace
 
 void fail(eag_status s, const std::string& msg) { throw Error{s, msg}; }
+void set_last_error(const std::string& msg) { g_last_error = msg; }
 
 void check_hip(hipError_t e, const char* what) {
   if (e != hipSuccess) fail(EAG_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
@@ -75,10 +76,10 @@ TraceSetup trace_setup(const eag_bvh* b, const eag_trace_params* p, float t_max_
   if (p->depth_quantum == 0.0f) {
     if (bucket_bits < 32) fail(EAG_ERR_INVALID_ARGUMENT, "depth_quantum = 0 (exact t order) needs n <= 65536");
     ts.max_bucket = 0xffffffffu;
-    ts.inv_dq = 0.0f;
+    ts.inv_dq = 0.0;
   } else {
     ts.max_bucket = bucket_bits >= 32 ? 0xffffffffu : ((1u << bucket_bits) - 1u);
-    ts.inv_dq = 1.0f / p->depth_quantum;
+    ts.inv_dq = 1.0 / (double)p->depth_quantum;
     const double t_rep = (double)ts.max_bucket * (double)p->depth_quantum;
     if ((double)t_max_needed >= t_rep)
       fail(EAG_ERR_INVALID_ARGUMENT, "scene too deep for the order key at this depth_quantum and surfel count "
@@ -110,10 +111,10 @@ CamDev make_cam(const eag_camera& c, uint32_t id) {
   const double aspect = (double)c.width / (double)c.height;
   CamDev d;
   for (int a = 0; a < 3; ++a) {
-    d.eye[a] = (float)e[a];
-    d.right[a] = (float)(r[a] * th * aspect);
-    d.up[a] = (float)(up2[a] * th);
-    d.fwd[a] = (float)f[a];
+    d.eye[a] = e[a];
+    d.right[a] = r[a] * th * aspect;
+    d.up[a] = up2[a] * th;
+    d.fwd[a] = f[a];
   }
   d.width = c.width;
   d.height = c.height;
@@ -150,7 +151,9 @@ namespace {
 struct RenderWs {
   Attr* attrs;
   float* state;
-  float* r1;
+  double* r1;
+  float* adj;                 // per-sample dL/dX, dL/dNt of the adjoint
+  double* gacc;               // double gradient accumulators of the adjoint
   unsigned long long* work;
   size_t bytes;
 };
@@ -160,7 +163,9 @@ RenderWs render_ws(void* base, int64_t n, int64_t n_pix, int64_t spp, bool own_s
   RenderWs w;
   w.attrs = c.take<Attr>(n);
   w.state = own_state ? c.take<float>(n_pix * EAG_FWD_PIXEL_FLOATS) : nullptr;
-  w.r1 = own_state ? c.take<float>(n_pix * spp * 3) : nullptr;
+  w.r1 = own_state ? c.take<double>(n_pix * spp * 3) : nullptr;
+  w.adj = own_state ? c.take<float>(n_pix * spp * 12) : nullptr;   // 6 doubles per sample
+  w.gacc = own_state ? c.take<double>(grad_accum_doubles(n)) : nullptr;
   w.work = c.take<unsigned long long>(8);
   w.bytes = c.bytes();
   return w;
@@ -278,8 +283,8 @@ void eag_bvh_destroy(eag_bvh* b) { delete b; }
 size_t eag_trace_workspace_bytes(int64_t n) { return n < 1 ? 0 : render_ws(nullptr, n, 0, 0, false).bytes; }
 
 eag_status eag_trace_rays(const eag_bvh* b, const eag_surfels* s, const eag_trace_params* p, int64_t n_rays,
-                          const float* origins, const float* dirs, float* out, int32_t* hit_idx, int32_t* hit_count,
-                          int32_t max_hits, void* ws, size_t ws_bytes, void* stream) {
+                          const double* origins, const double* dirs, float* out, int32_t* hit_idx, int32_t* hit_count,
+                          int32_t max_hits, int32_t* stats, void* ws, size_t ws_bytes, void* stream) {
   return guarded([&] {
     check_bvh(b, s);
     validate_params(p);
@@ -295,14 +300,14 @@ eag_status eag_trace_rays(const eag_bvh* b, const eag_surfels* s, const eag_trac
     const TraceSetup ts = trace_setup(b, p, (float)(4.0 * far + scene_t_max(b)));
     hipStream_t st = static_cast<hipStream_t>(stream);
     pack_attrs(s, b, w.attrs, st);
-    launch_trace_rays(b, w.attrs, p, ts, n_rays, origins, dirs, out, hit_idx, hit_count, max_hits, st);
+    launch_trace_rays(b, w.attrs, p, ts, n_rays, origins, dirs, out, hit_idx, hit_count, max_hits, stats, st);
   });
 }
 
 int64_t eag_fwd_state_floats(const eag_camera* cams, int32_t n_cams, const eag_trace_params* p) {
   if (!cams || n_cams < 1 || !p || p->spp < 1) return 0;
   const int64_t np = (int64_t)cams[0].width * cams[0].height * n_cams;
-  return np * (EAG_FWD_PIXEL_FLOATS + 3 * (int64_t)p->spp);
+  return np * (EAG_FWD_PIXEL_FLOATS + 6 * (int64_t)p->spp);
 }
 
 size_t eag_render_workspace_bytes(int64_t n, const eag_camera* cams, int32_t n_cams, const eag_trace_params* p) {
@@ -330,7 +335,7 @@ eag_status eag_render_single_bounce(const eag_bvh* b, const eag_surfels* s, cons
     pack_attrs(s, b, w.attrs, st);
     const TraceCtx tc = make_ctx(b, w.attrs, p, ts);
     float* state = fwd_state ? fwd_state : w.state;
-    float* r1 = fwd_state ? fwd_state + np * EAG_FWD_PIXEL_FLOATS : w.r1;
+    double* r1 = fwd_state ? reinterpret_cast<double*>(fwd_state + np * EAG_FWD_PIXEL_FLOATS) : w.r1;
     SbParams sp;
     sp.spp = p->spp;
     sp.flags = p->flags;
@@ -374,15 +379,17 @@ eag_status eag_single_bounce_backward(const eag_bvh* b, const eag_surfels* s, co
     sp.k0 = (uint32_t)(p->seed & 0xffffffffu);
     sp.k1 = (uint32_t)(p->seed >> 32);
     sp.tau_E = p->tau_E;
-    const float* r1 = fwd_state + np * EAG_FWD_PIXEL_FLOATS;
+    const double* r1 = reinterpret_cast<const double*>(fwd_state + np * EAG_FWD_PIXEL_FLOATS);
+    launch_grad_zero(w.gacc, b->n, st);
     for (int c0 = 0; c0 < n_cams; c0 += MAX_CAMS_PER_LAUNCH) {
       const int nc = std::min(MAX_CAMS_PER_LAUNCH, n_cams - c0);
       CamBatch cb;
       std::memset(&cb, 0, sizeof(cb));
       for (int i = 0; i < nc; ++i) cb.c[i] = make_cam(cams[c0 + i], p->camera_id + (uint32_t)(c0 + i));
       launch_single_bounce_backward(tc, *s, cb, hw, nc, sp, fwd_state + c0 * hw * EAG_FWD_PIXEL_FLOATS,
-                                    r1 + c0 * hw * p->spp * 3, dL_drgb + c0 * hw * 3, *grads, w.state, st);
+                                    r1 + c0 * hw * p->spp * 3, dL_drgb + c0 * hw * 3, w.gacc, w.adj, st);
     }
+    launch_grad_finalize(w.gacc, b->n, *grads, st);
   });
 }
 
@@ -404,18 +411,26 @@ eag_status eag_path_trace(const eag_bvh* b, const eag_surfels* s, const eag_came
     hipStream_t st = static_cast<hipStream_t>(stream);
     pack_attrs(s, b, w.attrs, st);
     const TraceCtx tc = make_ctx(b, w.attrs, p, ts);
-    PtParams pp;
-    pp.max_depth = p->max_depth;
-    pp.rr_start = p->rr_start;
-    pp.flags = p->flags;
-    pp.k0 = (uint32_t)(p->seed & 0xffffffffu);
-    pp.k1 = (uint32_t)(p->seed >> 32);
-    pp.tau_E = p->tau_E;
-    pp.sample_begin = sample_begin;
-    pp.sample_count = sample_count;
-    pp.tiles_x = (cam->width + 7) / 8;
-    pp.tile_pixels = (int64_t)pp.tiles_x * ((cam->height + 7) / 8) * 64;
-    launch_path_trace(tc, cd, pp, accum, w.work, reinterpret_cast<unsigned long long*>(counters), st);
+    PtLaunch L;
+    std::memset(&L, 0, sizeof(L));
+    PtSlot& S = L.s[0];
+    S.cam = cd;
+    S.accum = accum;
+    S.attrs = w.attrs;
+    S.work_begin = 0;
+    S.tiles_x = (cam->width + 7) / 8;
+    S.tile_pixels = (int64_t)S.tiles_x * ((cam->height + 7) / 8) * 64;
+    S.global_end = (int64_t)sample_count * S.tile_pixels;
+    S.sample_begin = sample_begin;
+    S.max_depth = p->max_depth;
+    S.rr_start = p->rr_start;
+    S.flags = p->flags;
+    S.k0 = (uint32_t)(p->seed & 0xffffffffu);
+    S.k1 = (uint32_t)(p->seed >> 32);
+    S.tau_E = p->tau_E;
+    L.n_slots = 1;
+    L.n_work = S.global_end;
+    launch_path_trace(tc, L, w.work, reinterpret_cast<unsigned long long*>(counters), st);
   });
 }
 

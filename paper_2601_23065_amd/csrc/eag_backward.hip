@@ -1,14 +1,316 @@
-// Single-bounce adjoint (placeholder until the adjoint kernels land).
+// Single-bounce adjoint (reverse of Sec. 3.3, Eq. 7; the gradient the Stage-1
+// objective of Eq. 8 needs, extended to every surfel parameter but e).
+//
+// Hit lists are recomputed, not stored: each kernel re-traces its segment
+// with the forward's exact code, so the k-buffer visits the same hits
+// in the same order, and reverses the blending on the fly. For a blended
+// quantity V = sum_i T_{i-1} alpha_i v_i,
+//   dV/dalpha_j = T_{j-1} v_j - (V - V_{<=j}) / (1 - alpha_j),
+// where the suffix V - V_{<=j} comes from the forward's stored total minus
+// the running prefix; A = 1 - T_m adds T_m / (1 - alpha_j).
+//
+// k_sb_bwd_secondary  one thread per (pixel, sample) of reflecting pixels:
+//   upstream dR1 = P * dL / spp; per hit: radiance gradient, alpha -> opacity,
+//   tangent-plane coordinates -> centre, quaternion, scales, and the ray's
+//   origin X and direction w'. Writes dL/dX and dL/dNt (through the
+//   hemisphere frame) per sample.
+// k_sb_bwd_camera     one thread per pixel: gathers its samples' dX, dNt in
+//   order, maps them to dN, dD, dA through Nt = N/|N| and Dt = D/A, adds dP =
+//   dL * mean R1 (or dR = dL for emitter pixels) and reverses the camera
+//   segment.
+// Gradients are scattered with double atomics into a workspace accumulator
+// and added to the caller's float arrays at the end.
 #include "eag_device.h"
 #include "eag_internal.h"
 #include "eag_render.h"
 
 namespace eag {
 
-void launch_single_bounce_backward(const TraceCtx&, const eag_surfels&, const CamBatch&, int64_t, int32_t,
-                                   const SbParams&, const float*, const float*, const float*,
-                                   const eag_surfel_grads&, float*, hipStream_t) {
-  fail(EAG_ERR_INTERNAL, "single-bounce backward is not available in this build");
+namespace {
+
+// Gradient accumulators: double precision in the workspace (component-major,
+// pos[3] rot[4] scale[2] opacity albedo[3] radiance[3] = 16 rows of n), so
+// that sums of many opposing contributions keep their small results; they
+// are added to the caller's float arrays once at the end.
+constexpr int GRAD_ROWS = 16;
+struct GradPtrs {
+  double* pos;
+  double* rot;
+  double* scale;
+  double* opacity;
+  double* albedo;
+  double* radiance;
+  int64_t n;
+};
+
+__device__ __forceinline__ void atomic_add3(double* base, int64_t n, int64_t i, D3 v) {
+  atomicAdd(base + i, v.x);
+  atomicAdd(base + n + i, v.y);
+  atomicAdd(base + 2 * n + i, v.z);
+}
+
+// Chain of one hit's opacity-term gradient g_alpha, distance gradient g_t and
+// normal gradient g_n into the surfel's centre, quaternion, scales and opacity
+// (atomics), and into the ray origin and direction (accumulated in gO, gW).
+// Double precision, like the forward geometry.
+__device__ void chain_hit(const Geo& ge, const GradPtrs& gp, uint32_t idx, D3 O, D3 W, double t, double g_alpha,
+                          double g_t, D3 g_n, bool ray_grad, D3& gO, D3& gW) {
+  const int64_t n = gp.n;
+  const D3 d = ge.p - O;
+  const double den = dot(W, ge.n);
+  const D3 y = d3(t * W.x - d.x, t * W.y - d.y, t * W.z - d.z);
+  const double u = dot(y, ge.tu) / ge.su, v = dot(y, ge.tv) / ge.sv;
+  const double g = exp(-0.5 * (u * u + v * v));
+  // alpha = sigma g, g = exp(-(u^2+v^2)/2)
+  const double g_sigma = g_alpha * g;
+  const double g_q2 = -0.5 * g * (g_alpha * ge.sigma);
+  const double gu = 2.0 * u * g_q2, gv = 2.0 * v * g_q2;
+  // u = y.t_u / s_u, v = y.t_v / s_v
+  const D3 gy = (gu / ge.su) * ge.tu + (gv / ge.sv) * ge.tv;
+  // y = t W - d, t = (d.n) / (W.n)
+  const double gt = g_t + dot(gy, W);
+  const double gnum = gt / den, gden = -gt * t / den;
+  const D3 gd = gnum * ge.n - gy;
+  const D3 gn = g_n + gnum * d + gden * W;
+  if (ray_grad) {
+    gW = gW + t * gy + gden * ge.n;
+    gO = gO - gd;
+  }
+  // t_u, t_v: through u, v and n = t_u x t_v
+  const D3 gtu = (gu / ge.su) * y + cross(ge.tv, gn);
+  const D3 gtv = (gv / ge.sv) * y + cross(gn, ge.tu);
+  const double gsu = -gu * u / ge.su;
+  const double gsv = -gv * v / ge.sv;
+  const double qw = ge.qw, qx = ge.qx, qy = ge.qy, qz = ge.qz;
+  const double gqw = 2.0 * (gtu.y * qz - gtu.z * qy - gtv.x * qz + gtv.z * qx);
+  const double gqx = 2.0 * (gtu.y * qy + gtu.z * qz + gtv.x * qy - 2.0 * gtv.y * qx + gtv.z * qw);
+  const double gqy = 2.0 * (-2.0 * gtu.x * qy + gtu.y * qx - gtu.z * qw + gtv.x * qx + gtv.z * qz);
+  const double gqz = 2.0 * (-2.0 * gtu.x * qz + gtu.y * qw + gtu.z * qx - gtv.x * qw - 2.0 * gtv.y * qz + gtv.z * qy);
+  // q_hat = q / |q|
+  const double proj = qw * gqw + qx * gqx + qy * gqy + qz * gqz;
+  atomicAdd(gp.rot + idx, (gqw - qw * proj) * ge.iq);
+  atomicAdd(gp.rot + n + idx, (gqx - qx * proj) * ge.iq);
+  atomicAdd(gp.rot + 2 * n + idx, (gqy - qy * proj) * ge.iq);
+  atomicAdd(gp.rot + 3 * n + idx, (gqz - qz * proj) * ge.iq);
+  atomic_add3(gp.pos, n, idx, gd);
+  atomicAdd(gp.scale + idx, gsu);
+  atomicAdd(gp.scale + n + idx, gsv);
+  atomicAdd(gp.opacity + idx, g_sigma);
+}
+
+// Secondary segment: only R1 = sum w r is used.
+struct SecondaryAdj {
+  const TraceCtx* tc;
+  const float* rot;
+  GradPtrs gp;
+  D3 O, W;
+  D3 gR1;
+  double G;          // gR1 . R1 (the forward total)
+  double prefix;
+  bool ray_grad;
+  D3 gO, gW;
+  __device__ void operator()(uint32_t pos, double t, double alpha, double w, double Tb) {
+    const Record r = load_record(tc->recs, pos);
+    const uint32_t idx = rec_index(r);
+    const Geo ge = surfel_geo(r);
+    const float4 rr = tc->attrs[pos].r;
+    const double c = gR1.x * rr.x + gR1.y * rr.y + gR1.z * rr.z;
+    prefix += w * c;
+    const double g_alpha = Tb * c - (G - prefix) / (1.0 - alpha);
+    atomic_add3(gp.radiance, gp.n, idx, w * gR1);
+    chain_hit(ge, gp, idx, O, W, t, g_alpha, 0.0, d3(0.0, 0.0, 0.0), ray_grad, gO, gW);
+  }
+};
+
+// Camera segment: N, D, R (emitter pixels), P (reflecting pixels), A.
+struct CameraAdj {
+  const TraceCtx* tc;
+  const float* rot;
+  GradPtrs gp;
+  D3 O, W;
+  D3 gN, gR, gP;
+  double gD, gA, Tm, G, prefix;
+  bool has_R, has_P;
+  __device__ void operator()(uint32_t pos, double t, double alpha, double w, double Tb) {
+    const Record r = load_record(tc->recs, pos);
+    const uint32_t idx = rec_index(r);
+    const Geo ge = surfel_geo(r);
+    const Attr at = tc->attrs[pos];
+    const D3 nn = ge.n;
+    const double sgn = dot(W, nn) > 0.0 ? -1.0 : 1.0;   // n' = sgn n faces the origin
+    const D3 rho = d3(at.rho_e.x, at.rho_e.y, at.rho_e.z), rad = d3(at.r.x, at.r.y, at.r.z);
+    const double c = sgn * dot(gN, nn) + gD * t + dot(gR, rad) + dot(gP, rho);
+    prefix += w * c;
+    const double g_alpha = Tb * c - (G - prefix - gA * Tm) / (1.0 - alpha);
+    if (has_R) atomic_add3(gp.radiance, gp.n, idx, w * gR);
+    if (has_P) atomic_add3(gp.albedo, gp.n, idx, w * gP);
+    D3 dummyO = d3(0.0, 0.0, 0.0), dummyW = d3(0.0, 0.0, 0.0);
+    chain_hit(ge, gp, idx, O, W, t, g_alpha, w * gD, (sgn * w) * gN, false, dummyO, dummyW);
+  }
+};
+
+__global__ void __launch_bounds__(256) k_sb_bwd_secondary(TraceCtx tc, const CamBatch cams, int64_t hw,
+                                                          int32_t n_cams, SbParams sp, const float* state,
+                                                          const double* r1, const float* dL, const float* rot,
+                                                          GradPtrs gp, double* adj) {
+  const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t S = sp.spp;
+  if (tid >= hw * n_cams * S) return;
+  const int64_t g = tid / S;
+  const uint32_t s = (uint32_t)(tid % S);
+  const FwdState st = load_state(state + g * EAG_FWD_PIXEL_FLOATS);
+  double out[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (st.branch == 2.0f) {
+    const CamDev& c = cams.c[g / hw];
+    const uint32_t pix = (uint32_t)(g % hw);
+    const D3 Wc = pixel_dir(c, pix, 0, sp.flags, sp.k0, sp.k1);
+    const D3 X = d3(c.eye[0] + st.Dt * Wc.x, c.eye[1] + st.Dt * Wc.y, c.eye[2] + st.Dt * Wc.z);
+    const D3 Nt = st.Nt;
+    const uint4 w4 = philox(make_uint4(pix, s, 0u, c.id), sp.k0, sp.k1);
+    const double u0 = to_unit(w4.x), u1 = to_unit(w4.y);
+    const D3 Wd = cosine_dir(Nt, u0, u1);
+    const double inv = 1.0 / (double)S;
+    SecondaryAdj a;
+    a.tc = &tc;
+    a.rot = rot;
+    a.gp = gp;
+    a.O = X;
+    a.W = Wd;
+    a.gR1 = d3(st.P.x * dL[g * 3 + 0] * inv, st.P.y * dL[g * 3 + 1] * inv, st.P.z * dL[g * 3 + 2] * inv);
+    const double* R1 = r1 + (g * S + s) * 3;
+    a.G = a.gR1.x * R1[0] + a.gR1.y * R1[1] + a.gR1.z * R1[2];
+    a.prefix = 0.0;
+    a.ray_grad = !(sp.flags & EAG_DETACH_BOUNCE);
+    a.gO = d3(0.0, 0.0, 0.0);
+    a.gW = d3(0.0, 0.0, 0.0);
+    trace_segment_cb<Q_RADIANCE, true>(tc, X, Wd, a);
+    if (a.ray_grad) {
+      // w' = c1 b1 + c2 b2 + c3 Nt, b1 = m / |m|, m = h - (h.Nt) Nt, b2 = Nt x b1
+      const D3 h = d3(HX, HY, HZ);
+      const double hn = dot(h, Nt);
+      const D3 m = h - hn * Nt;
+      const double ml = sqrt(dot(m, m));
+      const D3 b1 = (1.0 / ml) * m;
+      const double rr = sqrt(u0);
+      double sn, cs;
+      sincos(TWO_PI * u1, &sn, &cs);
+      const double c1 = rr * cs, c2 = rr * sn, c3 = sqrt(1.0 - u0);
+      const D3 gw = a.gW;
+      const D3 gb2 = c2 * gw;
+      const D3 gb1 = c1 * gw + cross(gb2, Nt);
+      D3 gNt = c3 * gw + cross(b1, gb2);
+      const D3 gm = (1.0 / ml) * (gb1 - dot(b1, gb1) * b1);
+      gNt = gNt - hn * gm - dot(gm, Nt) * h;
+      out[0] = a.gO.x; out[1] = a.gO.y; out[2] = a.gO.z;
+      out[3] = gNt.x; out[4] = gNt.y; out[5] = gNt.z;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 6; ++k) adj[tid * 6 + k] = out[k];
+}
+
+__global__ void __launch_bounds__(256) k_sb_bwd_camera(TraceCtx tc, const CamBatch cams, int64_t hw, int32_t n_cams,
+                                                       SbParams sp, const float* state, const double* r1,
+                                                       const double* adj, const float* dL, const float* rot,
+                                                       GradPtrs gp) {
+  const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (g >= hw * n_cams) return;
+  const FwdState st = load_state(state + g * EAG_FWD_PIXEL_FLOATS);
+  if (st.branch == 0.0f) return;
+  const CamDev& c = cams.c[g / hw];
+  const uint32_t pix = (uint32_t)(g % hw);
+  const D3 W = pixel_dir(c, pix, 0, sp.flags, sp.k0, sp.k1);
+  const D3 dl = d3(dL[g * 3 + 0], dL[g * 3 + 1], dL[g * 3 + 2]);
+  CameraAdj a;
+  a.tc = &tc;
+  a.rot = rot;
+  a.gp = gp;
+  a.O = d3(c.eye[0], c.eye[1], c.eye[2]);
+  a.W = W;
+  a.gN = d3(0.0, 0.0, 0.0);
+  a.gR = d3(0.0, 0.0, 0.0);
+  a.gP = d3(0.0, 0.0, 0.0);
+  a.gD = 0.0;
+  a.gA = 0.0;
+  a.Tm = 1.0 - st.A;
+  a.has_R = st.branch == 1.0f;
+  a.has_P = st.branch == 2.0f;
+  const D3 R = st.R, P = st.P;
+  if (a.has_R) {
+    a.gR = dl;
+    a.G = dot(dl, R);
+  } else {
+    const int S = sp.spp;
+    double m0 = 0.0, m1 = 0.0, m2 = 0.0;
+    D3 gX = d3(0.0, 0.0, 0.0), gNt = d3(0.0, 0.0, 0.0);
+    for (int s = 0; s < S; ++s) {
+      const double* q = r1 + (g * S + s) * 3;
+      m0 += q[0];
+      m1 += q[1];
+      m2 += q[2];
+      const double* ad = adj + (g * S + s) * 6;
+      gX = gX + d3(ad[0], ad[1], ad[2]);
+      gNt = gNt + d3(ad[3], ad[4], ad[5]);
+    }
+    const double inv = 1.0 / (double)S;
+    a.gP = d3(dl.x * (m0 * inv), dl.y * (m1 * inv), dl.z * (m2 * inv));
+    // X = O + Dt W; Nt = N / |N|; Dt = D / A
+    const double gDt = dot(gX, W);
+    a.gN = (1.0 / st.Nlen) * (gNt - dot(st.Nt, gNt) * st.Nt);
+    a.gD = gDt / st.A;
+    a.gA = -gDt * st.Dt / st.A;
+    a.G = dot(a.gN, st.Nlen * st.Nt) + a.gD * (st.Dt * st.A) + dot(a.gP, P);
+  }
+  a.prefix = 0.0;
+  trace_segment_cb<Q_ALL, true>(tc, a.O, W, a);
+}
+
+__global__ void k_zero_f64(double* p, int64_t n) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0;
+}
+
+__global__ void k_grad_finalize(const double* acc, int64_t n, eag_surfel_grads g) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n * GRAD_ROWS) return;
+  const int64_t row = i / n, j = i - row * n;
+  float* dst;
+  if (row < 3) dst = g.pos + row * n;
+  else if (row < 7) dst = g.rot + (row - 3) * n;
+  else if (row < 9) dst = g.scale + (row - 7) * n;
+  else if (row < 10) dst = g.opacity;
+  else if (row < 13) dst = g.albedo + (row - 10) * n;
+  else dst = g.radiance + (row - 13) * n;
+  dst[j] += (float)acc[i];
+}
+
+}  // namespace
+
+size_t grad_accum_doubles(int64_t n) { return (size_t)n * GRAD_ROWS; }
+
+void launch_single_bounce_backward(const TraceCtx& tc, const eag_surfels& s, const CamBatch& cams, int64_t hw,
+                                   int32_t n_cams, const SbParams& sp, const float* state, const double* r1,
+                                   const float* dL, double* gacc, float* scratch, hipStream_t st) {
+  const int64_t n = s.n;
+  GradPtrs gp{gacc, gacc + 3 * n, gacc + 7 * n, gacc + 9 * n, gacc + 10 * n, gacc + 13 * n, n};
+  const int64_t np = hw * n_cams;
+  const int64_t ns = np * sp.spp;
+  hipLaunchKernelGGL(k_sb_bwd_secondary, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, st, tc, cams, hw, n_cams,
+                     sp, state, r1, dL, s.rot, gp, reinterpret_cast<double*>(scratch));
+  hipLaunchKernelGGL(k_sb_bwd_camera, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, st, tc, cams, hw, n_cams, sp,
+                     state, r1, reinterpret_cast<const double*>(scratch), dL, s.rot, gp);
+  check_hip(hipGetLastError(), "single-bounce backward launch");
+}
+
+void launch_grad_zero(double* gacc, int64_t n, hipStream_t st) {
+  const int64_t m = n * GRAD_ROWS;
+  hipLaunchKernelGGL(k_zero_f64, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, gacc, m);
+}
+
+void launch_grad_finalize(const double* gacc, int64_t n, const eag_surfel_grads& g, hipStream_t st) {
+  const int64_t m = n * GRAD_ROWS;
+  hipLaunchKernelGGL(k_grad_finalize, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, gacc, n, g);
+  check_hip(hipGetLastError(), "gradient finalize launch");
 }
 
 }  // namespace eag

@@ -31,15 +31,15 @@ __host__ __device__ __forceinline__ float fdec(uint32_t e) {
 }
 
 struct Frame {
-  V3 tu, tv, n;
+  D3 tu, tv, n;
 };
 __device__ __forceinline__ Frame frame_of(const float* rot, int64_t n, int64_t i) {
-  float w = rot[i], x = rot[n + i], y = rot[2 * n + i], z = rot[3 * n + i];
-  const float inv = 1.0f / sqrtf(w * w + x * x + y * y + z * z);
+  double w = rot[i], x = rot[n + i], y = rot[2 * n + i], z = rot[3 * n + i];
+  const double inv = 1.0 / sqrt(w * w + x * x + y * y + z * z);
   w *= inv; x *= inv; y *= inv; z *= inv;
   Frame f;
-  f.tu = v3(1.0f - 2.0f * (y * y + z * z), 2.0f * (x * y + w * z), 2.0f * (x * z - w * y));
-  f.tv = v3(2.0f * (x * y - w * z), 1.0f - 2.0f * (x * x + z * z), 2.0f * (y * z + w * x));
+  f.tu = d3(1.0 - 2.0 * (y * y + z * z), 2.0 * (x * y + w * z), 2.0 * (x * z - w * y));
+  f.tv = d3(2.0 * (x * y - w * z), 1.0 - 2.0 * (x * x + z * z), 2.0 * (y * z + w * x));
   f.n = cross(f.tu, f.tv);
   return f;
 }
@@ -66,13 +66,13 @@ __global__ void k_boxes(eag_surfels s, float k, float* box, BvhHeader* h) {
   float bhi[3] = {-__builtin_inff(), -__builtin_inff(), -__builtin_inff()};
   if (i < n) {
     const Frame f = frame_of(s.rot, n, i);
-    const float su = s.scale[i], sv = s.scale[n + i];
+    const double su = s.scale[i], sv = s.scale[n + i];
     const float p[3] = {s.pos[i], s.pos[n + i], s.pos[2 * n + i]};
     const float pad = 2e-5f * (1.0f + fmaxf(fmaxf(fabsf(p[0]), fabsf(p[1])), fabsf(p[2])));
-    const float tu[3] = {f.tu.x, f.tu.y, f.tu.z}, tv[3] = {f.tv.x, f.tv.y, f.tv.z};
+    const double tu[3] = {f.tu.x, f.tu.y, f.tu.z}, tv[3] = {f.tv.x, f.tv.y, f.tv.z};
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      const float e = k * sqrtf((su * tu[a]) * (su * tu[a]) + (sv * tv[a]) * (sv * tv[a])) + pad;
+      const float e = (float)(k * sqrt((su * tu[a]) * (su * tu[a]) + (sv * tv[a]) * (sv * tv[a]))) + pad;
       box[a * n + i] = p[a] - e;
       box[(3 + a) * n + i] = p[a] + e;
       plo[a] = phi[a] = p[a];
@@ -179,14 +179,10 @@ __global__ void k_records(eag_surfels s, const int32_t* perm, Record* recs) {
   const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (j >= n) return;
   const int64_t i = perm[j];
-  const Frame f = frame_of(s.rot, n, i);
-  const float su = s.scale[i], sv = s.scale[n + i];
-  const float isu = 1.0f / su, isv = 1.0f / sv;
   float4* r = reinterpret_cast<float4*>(recs + j);
   r[0] = make_float4(s.pos[i], s.pos[n + i], s.pos[2 * n + i], s.opacity[i]);
-  r[1] = make_float4(f.n.x, f.n.y, f.n.z, __uint_as_float((uint32_t)i));
-  r[2] = make_float4(f.tu.x * isu, f.tu.y * isu, f.tu.z * isu, su);
-  r[3] = make_float4(f.tv.x * isv, f.tv.y * isv, f.tv.z * isv, sv);
+  r[1] = make_float4(s.rot[i], s.rot[n + i], s.rot[2 * n + i], s.rot[3 * n + i]);
+  r[2] = make_float4(s.scale[i], s.scale[n + i], __uint_as_float((uint32_t)i), 0.0f);
 }
 
 __global__ void k_zero_i32(int32_t* p, int64_t n) {

@@ -7,6 +7,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace eag {
 
 constexpr int KBUF = 16;          // k-buffer depth
@@ -25,14 +27,15 @@ struct __align__(16) Node {
   int4 d;     // child0 child1 - -
 };
 
-// Geometry record of one surfel in sorted order, 64 B (one float4 load each):
-//   p.x p.y p.z sigma | n.x n.y n.z index | a_u.x a_u.y a_u.z s_u | a_v.x a_v.y a_v.z s_v
-// with n = t_u x t_v, a_u = t_u / s_u, a_v = t_v / s_v, index = original surfel index.
+// Geometry record of one surfel in sorted order, 48 B (three float4 loads):
+//   p.x p.y p.z sigma | q.w q.x q.y q.z | s_u s_v index -
+// with q the caller's (unnormalised) quaternion and index the original surfel
+// index. Frames are derived in double precision at use (surfel_geo), so the
+// tracer sees exactly the float32 inputs, like the float64 definition.
 struct __align__(16) Record {
   float4 p_sigma;
-  float4 n_idx;
-  float4 au;
-  float4 av;
+  float4 q;
+  float4 s_idx;
 };
 
 // Attributes of one surfel in sorted order, 32 B: rho.xyz e | r.xyz -
@@ -71,43 +74,53 @@ __device__ __forceinline__ V3 cross(V3 a, V3 b) {
   return V3{a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
 }
 
-// Pinhole camera prepared on the host (double precision, rounded once):
-// ray direction = normalize(dx * right + dy * up + fwd) with
-// dx = 2 (x + ox) / W - 1, dy = 1 - 2 (y + oy) / H; right and up are
-// pre-scaled by tan(vfov/2) * W/H and tan(vfov/2).
+// double-precision vectors for ray geometry
+struct D3 { double x, y, z; };
+__device__ __forceinline__ D3 d3(double x, double y, double z) { return D3{x, y, z}; }
+__device__ __forceinline__ D3 operator+(D3 a, D3 b) { return D3{a.x + b.x, a.y + b.y, a.z + b.z}; }
+__device__ __forceinline__ D3 operator-(D3 a, D3 b) { return D3{a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ __forceinline__ D3 operator*(double s, D3 a) { return D3{s * a.x, s * a.y, s * a.z}; }
+__device__ __forceinline__ double dot(D3 a, D3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ D3 cross(D3 a, D3 b) {
+  return D3{a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+
+// Pinhole camera prepared on the host in double precision: ray direction =
+// normalize(dx * right + dy * up + fwd) with dx = 2 (x + ox) / W - 1,
+// dy = 1 - 2 (y + oy) / H; right and up are pre-scaled by tan(vfov/2) * W/H
+// and tan(vfov/2).
 struct CamDev {
-  float eye[3], right[3], up[3], fwd[3];
+  double eye[3], right[3], up[3], fwd[3];
   int32_t width, height;
   uint32_t id;
   int32_t pad;
 };
 
-__device__ __forceinline__ V3 camera_dir(const CamDev& c, int px, int py, float ox, float oy) {
-  const float dx = 2.0f * ((float)px + ox) / (float)c.width - 1.0f;
-  const float dy = 1.0f - 2.0f * ((float)py + oy) / (float)c.height;
-  V3 d = v3(dx * c.right[0] + dy * c.up[0] + c.fwd[0], dx * c.right[1] + dy * c.up[1] + c.fwd[1],
+__device__ __forceinline__ D3 camera_dir(const CamDev& c, int px, int py, double ox, double oy) {
+  const double dx = 2.0 * ((double)px + ox) / (double)c.width - 1.0;
+  const double dy = 1.0 - 2.0 * ((double)py + oy) / (double)c.height;
+  D3 d = d3(dx * c.right[0] + dy * c.up[0] + c.fwd[0], dx * c.right[1] + dy * c.up[1] + c.fwd[1],
             dx * c.right[2] + dy * c.up[2] + c.fwd[2]);
-  const float inv = 1.0f / sqrtf(dot(d, d));
-  return inv * d;
+  return (1.0 / sqrt(dot(d, d))) * d;
 }
 
 // Hemisphere frame: Gram-Schmidt of the fixed helper h = (1,2,3)/sqrt(14)
 // against the unit normal n: b1 = normalize(h - (h.n) n), b2 = n x b1.
 // Cosine-weighted direction (Malley): r = sqrt(u0), phi = 2 pi u1,
 // w' = r cos(phi) b1 + r sin(phi) b2 + sqrt(1 - u0) n.
-constexpr float HX = 0.2672612419124244f, HY = 0.5345224838248488f, HZ = 0.8017837257372732f;
+constexpr double HX = 0.2672612419124244, HY = 0.5345224838248488, HZ = 0.8017837257372732;
+constexpr double TWO_PI = 6.283185307179586;
 
-__device__ __forceinline__ V3 cosine_dir(V3 n, float u0, float u1) {
-  const float hn = HX * n.x + HY * n.y + HZ * n.z;
-  V3 m = v3(HX - hn * n.x, HY - hn * n.y, HZ - hn * n.z);
-  const float il = 1.0f / sqrtf(dot(m, m));
-  const V3 b1 = il * m;
-  const V3 b2 = cross(n, b1);
-  const float r = sqrtf(u0);
-  float s, c;
-  sincosf(6.283185307179586f * u1, &s, &c);
-  const float z = sqrtf(1.0f - u0);
-  return v3(r * c * b1.x + r * s * b2.x + z * n.x, r * c * b1.y + r * s * b2.y + z * n.y,
+__device__ __forceinline__ D3 cosine_dir(D3 n, double u0, double u1) {
+  const double hn = HX * n.x + HY * n.y + HZ * n.z;
+  const D3 m = d3(HX - hn * n.x, HY - hn * n.y, HZ - hn * n.z);
+  const D3 b1 = (1.0 / sqrt(dot(m, m))) * m;
+  const D3 b2 = cross(n, b1);
+  const double r = sqrt(u0);
+  double s, c;
+  sincos(TWO_PI * u1, &s, &c);
+  const double z = sqrt(1.0 - u0);
+  return d3(r * c * b1.x + r * s * b2.x + z * n.x, r * c * b1.y + r * s * b2.y + z * n.y,
             r * c * b1.z + r * s * b2.z + z * n.z);
 }
 
@@ -125,19 +138,19 @@ struct TraceCtx {
   int32_t root;            // >= 0: internal node index; < 0: single leaf ~root
   int32_t idx_bits;        // bits of an index (both index fields)
   uint32_t max_bucket;     // largest representable bucket
-  float inv_dq;            // 1 / dq, or 0 for exact-t keys
-  float t_min;
-  float k2;                // k_sigma^2
-  float T_min;
+  double inv_dq;           // 1 / dq, or 0 for exact-t keys
+  double t_min;
+  double k2;               // k_sigma^2
+  double T_min;
 };
 
-__device__ __forceinline__ uint64_t make_key(const TraceCtx& tc, float t, uint32_t idx, uint32_t pos) {
+__device__ __forceinline__ uint64_t make_key(const TraceCtx& tc, double t, uint32_t idx, uint32_t pos) {
   uint32_t bucket;
-  if (tc.inv_dq > 0.0f) {
-    const float b = floorf(t * tc.inv_dq);
-    bucket = b >= (float)tc.max_bucket ? tc.max_bucket : (uint32_t)b;
+  if (tc.inv_dq > 0.0) {
+    const double b = floor(t * tc.inv_dq);
+    bucket = b >= (double)tc.max_bucket ? tc.max_bucket : (uint32_t)b;
   } else {
-    bucket = __float_as_uint(t);
+    bucket = __float_as_uint((float)t);
   }
   return ((uint64_t)bucket << (2 * tc.idx_bits)) | ((uint64_t)idx << tc.idx_bits) | (uint64_t)pos;
 }
@@ -147,64 +160,113 @@ __device__ __forceinline__ uint32_t key_pos(const TraceCtx& tc, uint64_t k) {
 __device__ __forceinline__ uint32_t key_idx(const TraceCtx& tc, uint64_t k) {
   return (uint32_t)((k >> tc.idx_bits) & ((1ull << tc.idx_bits) - 1));
 }
-// smallest t that can carry the given key's bucket (for culling), conservative
+// smallest t that can carry the given key's bucket (for culling)
 __device__ __forceinline__ float key_tlo(const TraceCtx& tc, uint64_t k) {
   const uint32_t b = (uint32_t)(k >> (2 * tc.idx_bits));
-  if (tc.inv_dq > 0.0f) return (float)b / tc.inv_dq;
+  if (tc.inv_dq > 0.0) return (float)((double)b / tc.inv_dq);
   return __uint_as_float(b);
 }
 // largest t whose bucket does not exceed the key's bucket
 __device__ __forceinline__ float key_thi(const TraceCtx& tc, uint64_t k) {
   const uint32_t b = (uint32_t)(k >> (2 * tc.idx_bits));
-  if (tc.inv_dq > 0.0f) return (float)(b + 1u) / tc.inv_dq;
+  if (tc.inv_dq > 0.0) return (float)((double)(b + 1u) / tc.inv_dq);
   return __uint_as_float(b);
 }
 
 // ---------------------------------------------------------------------------
-// Ray-surfel test on the tangent plane (Eq. 1): returns true and (t, alpha)
-// when accepted.
+// Ray-surfel test on the tangent plane (Eq. 1), in double precision: the
+// local coordinates come from a difference of nearly equal distances, and
+// float32 there would cost ~1e-5 in u at room scale, which the bounce point
+// and direction then amplify.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ bool surfel_test(const Record& r, V3 O, V3 W, float t_min, float k2, float& t,
-                                            float& alpha) {
-  const V3 d = v3(r.p_sigma.x - O.x, r.p_sigma.y - O.y, r.p_sigma.z - O.z);
-  const V3 n = v3(r.n_idx.x, r.n_idx.y, r.n_idx.z);
-  const float den = dot(W, n);
-  const float num = dot(d, n);
-  if (!(fabsf(den) > 1e-12f) || !(r.p_sigma.w > 0.0f)) return false;
-  t = num / den;
-  if (!(t > t_min)) return false;
-  const V3 y = v3(t * W.x - d.x, t * W.y - d.y, t * W.z - d.z);
-  const float u = y.x * r.au.x + y.y * r.au.y + y.z * r.au.z;
-  const float v = y.x * r.av.x + y.y * r.av.y + y.z * r.av.z;
-  const float q2 = u * u + v * v;
-  if (!(q2 <= k2)) return false;
-  alpha = r.p_sigma.w * expf(-0.5f * q2);
-  return true;
-}
-
 __device__ __forceinline__ Record load_record(const Record* recs, uint32_t pos) {
   const float4* p = reinterpret_cast<const float4*>(recs + pos);
   Record r;
   r.p_sigma = p[0];
-  r.n_idx = p[1];
-  r.au = p[2];
-  r.av = p[3];
+  r.q = p[1];
+  r.s_idx = p[2];
   return r;
+}
+
+__device__ __forceinline__ uint32_t rec_index(const Record& r) { return __float_as_uint(r.s_idx.z); }
+
+// A surfel's geometry in double precision (Sec. 3.1): centre p, tangent axes
+// t_u, t_v = the first two columns of the rotation of q / |q|, normal
+// n = t_u x t_v, scales.
+struct Geo {
+  D3 p, tu, tv, n;
+  double su, sv, sigma;
+  double qw, qx, qy, qz, iq;   // unit quaternion and 1 / |q|
+};
+
+__device__ __forceinline__ Geo surfel_geo(const Record& r) {
+  Geo g;
+  g.p = d3(r.p_sigma.x, r.p_sigma.y, r.p_sigma.z);
+  g.sigma = r.p_sigma.w;
+  double w = r.q.x, x = r.q.y, y = r.q.z, z = r.q.w;
+  g.iq = 1.0 / sqrt(w * w + x * x + y * y + z * z);
+  w *= g.iq; x *= g.iq; y *= g.iq; z *= g.iq;
+  g.qw = w; g.qx = x; g.qy = y; g.qz = z;
+  g.tu = d3(1.0 - 2.0 * (y * y + z * z), 2.0 * (x * y + w * z), 2.0 * (x * z - w * y));
+  g.tv = d3(2.0 * (x * y - w * z), 1.0 - 2.0 * (x * x + z * z), 2.0 * (y * z + w * x));
+  g.n = cross(g.tu, g.tv);
+  g.su = r.s_idx.x;
+  g.sv = r.s_idx.y;
+  return g;
+}
+
+// Returns true and (t, q2 = u^2 + v^2) when the ray meets the surfel's
+// k_sigma ellipse beyond t_min: den = W.n, t = ((p - O).n) / den,
+// y = O + t W - p, u = y.t_u / s_u, v = y.t_v / s_v.
+__device__ __forceinline__ bool surfel_test(const Geo& g, D3 O, D3 W, double t_min, double k2, double& t,
+                                            double& q2) {
+  const D3 d = g.p - O;
+  const double den = dot(W, g.n);
+  if (!(fabs(den) > 1e-12) || !(g.sigma > 0.0)) return false;
+  t = dot(d, g.n) / den;
+  if (!(t > t_min)) return false;
+  const D3 y = d3(t * W.x - d.x, t * W.y - d.y, t * W.z - d.z);
+  const double u = dot(y, g.tu) / g.su;
+  const double v = dot(y, g.tv) / g.sv;
+  q2 = u * u + v * v;
+  return q2 <= k2;
+}
+
+// The same test straight from a record, computing the frame piecewise so
+// that few double values are live at once (the traversal's inner loop).
+__device__ __forceinline__ bool record_test(const Record& r, D3 O, D3 W, double t_min, double k2, double& t) {
+  if (!(r.p_sigma.w > 0.0f)) return false;
+  double w = r.q.x, x = r.q.y, y = r.q.z, z = r.q.w;
+  const double iq = 1.0 / sqrt(w * w + x * x + y * y + z * z);
+  w *= iq; x *= iq; y *= iq; z *= iq;
+  const D3 tu = d3(1.0 - 2.0 * (y * y + z * z), 2.0 * (x * y + w * z), 2.0 * (x * z - w * y));
+  const D3 tv = d3(2.0 * (x * y - w * z), 1.0 - 2.0 * (x * x + z * z), 2.0 * (y * z + w * x));
+  const D3 n = cross(tu, tv);
+  const double den = dot(W, n);
+  if (!(fabs(den) > 1e-12)) return false;
+  const D3 d = d3((double)r.p_sigma.x - O.x, (double)r.p_sigma.y - O.y, (double)r.p_sigma.z - O.z);
+  t = dot(d, n) / den;
+  if (!(t > t_min)) return false;
+  const D3 yv = d3(t * W.x - d.x, t * W.y - d.y, t * W.z - d.z);
+  const double u = dot(yv, tu) / (double)r.s_idx.x;
+  const double v = dot(yv, tv) / (double)r.s_idx.y;
+  return u * u + v * v <= k2;
 }
 
 // ---------------------------------------------------------------------------
 // Segment result: the traced quantities of Eq. 3 before normalisation.
 // ---------------------------------------------------------------------------
 struct SegOut {
-  V3 N;
-  float D;
-  V3 R;
-  float E;
-  V3 P;
-  float T;
+  D3 N;
+  double D;
+  D3 R;
+  double E;
+  D3 P;
+  double T;
   int32_t nhits;
   int32_t rounds;
   int32_t tests;
+  int32_t visits;
 };
 
 enum { Q_ALL = 0, Q_RADIANCE = 1 };
@@ -216,55 +278,98 @@ __device__ __forceinline__ float slab(float lx, float ly, float lz, float hx, fl
   const float ay = (ly - O.y) * iW.y, by = (hy - O.y) * iW.y;
   const float az = (lz - O.z) * iW.z, bz = (hz - O.z) * iW.z;
   const float tn = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), fmaxf(fminf(az, bz), tlo));
-  // widen the exit by 2*gamma(3) so that rounding never rejects a box the ray touches
-  const float tf = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), fminf(fmaxf(az, bz), thi)) * 1.0000004f;
+  // widen the exit so that rounding (and the float32 copy of the ray) never
+  // rejects a box the ray touches
+  const float tf = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), fminf(fmaxf(az, bz), thi)) * 1.000002f + 1e-6f;
   return tn <= tf ? tn : __builtin_inff();
+}
+
+// No per-hit callback (forward passes).
+struct NoHit {
+  __device__ __forceinline__ void operator()(uint32_t, double, double, double, double) const {}
+};
+
+// Traversal stack: the top STACK_LDS entries of every lane live in LDS,
+// strided by the thread index so that a wave's pushes hit distinct banks;
+// deeper entries (rare) spill to a private array.
+constexpr int STACK_LDS = 24;
+constexpr int TRACE_BLOCK = 256;   // every tracing kernel runs 256-thread blocks
+
+struct TravStack {
+  int* lds;        // this lane's column: lds[i * TRACE_BLOCK]
+  int ovf[STACK_SIZE - STACK_LDS];
+  int sp;
+  __device__ __forceinline__ void push(int v) {
+    if (sp < STACK_LDS) lds[sp * TRACE_BLOCK] = v;
+    else ovf[sp - STACK_LDS] = v;
+    ++sp;
+  }
+  __device__ __forceinline__ int pop() {
+    --sp;
+    return sp < STACK_LDS ? lds[sp * TRACE_BLOCK] : ovf[sp - STACK_LDS];
+  }
+};
+
+// Accept a candidate key into the sorted k-buffer (ascending; empty = ~0).
+__device__ __forceinline__ void kbuf_insert(uint64_t (&kk)[KBUF], uint64_t key) {
+  int p = 0;
+#pragma unroll
+  for (int j = 0; j < KBUF; ++j) p += (kk[j] < key) ? 1 : 0;
+#pragma unroll
+  for (int j = KBUF - 1; j > 0; --j) kk[j] = (j > p) ? kk[j - 1] : (j == p ? key : kk[j]);
+  kk[0] = (p == 0) ? key : kk[0];
 }
 
 // One ray segment: multi-round k-buffer traversal and front-to-back blending.
 // Round r collects the KBUF smallest keys strictly greater than the last key
 // blended in round r-1, blends them in order, and stops the segment after the
 // first hit with T < T_min, or when a round returns fewer than KBUF hits.
-// If hit_out is non-null, up to max_hits blended surfel indices are written.
-template <int QMODE>
-__device__ SegOut trace_segment(const TraceCtx& tc, V3 O, V3 W, int32_t* hit_out = nullptr, int max_hits = 0) {
+// on_hit(pos, t, alpha, w, T_before) is called for every blended hit, in
+// blending order. If hit_out is non-null, up to max_hits blended surfel
+// indices are written. Must be called from a TRACE_BLOCK-thread block.
+// QMODE: Q_ALL blends every quantity, Q_RADIANCE only r. DACC: accumulate
+// R, E, P in double (the single-bounce render, whose adjoint subtracts
+// running prefixes from these totals) or in float (path tracing).
+template <int QMODE, bool DACC, class HitFn>
+__device__ SegOut trace_segment_cb(const TraceCtx& tc, D3 O, D3 W, HitFn& on_hit, int32_t* hit_out = nullptr,
+                                   int max_hits = 0) {
+  __shared__ int s_stack[STACK_LDS * TRACE_BLOCK];
+  TravStack st;
+  st.lds = s_stack + threadIdx.x;
   SegOut o;
-  o.N = v3(0.f, 0.f, 0.f);
-  o.D = 0.f;
-  o.R = v3(0.f, 0.f, 0.f);
-  o.E = 0.f;
-  o.P = v3(0.f, 0.f, 0.f);
-  o.T = 1.0f;
+  o.N = d3(0.0, 0.0, 0.0);
+  o.D = 0.0;
+  o.T = 1.0;
   o.nhits = 0;
   o.rounds = 0;
   o.tests = 0;
-  const V3 iW = v3(1.0f / (fabsf(W.x) > 1e-30f ? W.x : copysignf(1e-30f, W.x)),
-                   1.0f / (fabsf(W.y) > 1e-30f ? W.y : copysignf(1e-30f, W.y)),
-                   1.0f / (fabsf(W.z) > 1e-30f ? W.z : copysignf(1e-30f, W.z)));
-  uint64_t last = 0;            // keys must exceed this (0 is below every valid key: t > 0)
+  o.visits = 0;
+  using Acc = typename std::conditional<DACC, double, float>::type;
+  Acc R0 = 0, R1 = 0, R2 = 0, E = 0, P0 = 0, P1 = 0, P2 = 0;
+  const V3 Of = v3((float)O.x, (float)O.y, (float)O.z);
+  const float wx = (float)W.x, wy = (float)W.y, wz = (float)W.z;
+  const V3 iW = v3(1.0f / (fabsf(wx) > 1e-30f ? wx : copysignf(1e-30f, wx)),
+                   1.0f / (fabsf(wy) > 1e-30f ? wy : copysignf(1e-30f, wy)),
+                   1.0f / (fabsf(wz) > 1e-30f ? wz : copysignf(1e-30f, wz)));
+  uint64_t last = 0;            // keys must exceed this once have_last
   bool have_last = false;
   float t_floor = 0.0f;         // boxes ending before this cannot hold a key > last
   bool done = false;
   while (!done) {
     uint64_t kk[KBUF];
-    float kt[KBUF], ka[KBUF];
 #pragma unroll
-    for (int j = 0; j < KBUF; ++j) { kk[j] = ~0ull; kt[j] = 0.f; ka[j] = 0.f; }
+    for (int j = 0; j < KBUF; ++j) kk[j] = ~0ull;
     int cnt = 0;
     float t_cut = __builtin_inff();   // boxes entered after this cannot hold a key < kk[KBUF-1]
-
-    int stack[STACK_SIZE];
-    float stack_t[STACK_SIZE];
-    int sp = 0;
+    const float tlo0 = fmaxf((float)tc.t_min, t_floor) * 0.99999f - 1e-6f;
+    st.sp = 0;
     int ref = tc.root;
-    const float tlo0 = fmaxf(tc.t_min, t_floor) * 0.99999f - 1e-7f;
     while (true) {
       if (ref >= 0) {
+        ++o.visits;
         const Node nd = tc.nodes[ref];
-        const float thi = t_cut;
-        const float tlo = tlo0;
-        float e0 = slab(nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y, O, iW, tlo, thi);
-        float e1 = slab(nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w, O, iW, tlo, thi);
+        const float e0 = slab(nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y, Of, iW, tlo0, t_cut);
+        const float e1 = slab(nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w, Of, iW, tlo0, t_cut);
         const int c0 = nd.d.x, c1 = nd.d.y;
         // leaf children are tested right away
 #pragma unroll
@@ -274,42 +379,26 @@ __device__ SegOut trace_segment(const TraceCtx& tc, V3 O, V3 W, int32_t* hit_out
           if (c < 0 && e < __builtin_inff()) {
             const uint32_t pos = (uint32_t)(~c);
             const Record r = load_record(tc.recs, pos);
-            float t, a;
+            double t;
             ++o.tests;
-            if (surfel_test(r, O, W, tc.t_min, tc.k2, t, a)) {
-              const uint64_t key = make_key(tc, t, __float_as_uint(r.n_idx.w), pos);
+            if (record_test(r, O, W, tc.t_min, tc.k2, t)) {
+              const uint64_t key = make_key(tc, t, rec_index(r), pos);
               if ((!have_last || key > last) && key < kk[KBUF - 1]) {
-                uint64_t ck = key;
-                float ct = t, ca = a;
-#pragma unroll
-                for (int j = 0; j < KBUF; ++j) {
-                  const bool sw = ck < kk[j];
-                  const uint64_t tk = kk[j];
-                  const float tt = kt[j], ta = ka[j];
-                  kk[j] = sw ? ck : tk;
-                  kt[j] = sw ? ct : tt;
-                  ka[j] = sw ? ca : ta;
-                  ck = sw ? tk : ck;
-                  ct = sw ? tt : ct;
-                  ca = sw ? ta : ca;
-                }
+                kbuf_insert(kk, key);
                 if (++cnt >= KBUF) {
                   cnt = KBUF;
-                  t_cut = key_thi(tc, kk[KBUF - 1]) * 1.000001f + 1e-6f;
+                  t_cut = key_thi(tc, kk[KBUF - 1]) * 1.000002f + 1e-6f;
                 }
               }
             }
           }
         }
-        const bool h0 = c0 >= 0 && e0 <= t_cut;
-        const bool h1 = c1 >= 0 && e1 <= t_cut;
+        // a missed box reports +inf, which must not pass an infinite cut
+        const bool h0 = c0 >= 0 && e0 < __builtin_inff() && e0 <= t_cut;
+        const bool h1 = c1 >= 0 && e1 < __builtin_inff() && e1 <= t_cut;
         if (h0 && h1) {
           const bool first0 = e0 <= e1;
-          if (sp < STACK_SIZE) {
-            stack[sp] = first0 ? c1 : c0;
-            stack_t[sp] = first0 ? e1 : e0;
-            ++sp;
-          }
+          st.push(first0 ? c1 : c0);
           ref = first0 ? c0 : c1;
           continue;
         }
@@ -319,65 +408,77 @@ __device__ SegOut trace_segment(const TraceCtx& tc, V3 O, V3 W, int32_t* hit_out
         // the whole scene is one surfel
         const uint32_t pos = (uint32_t)(~ref);
         const Record r = load_record(tc.recs, pos);
-        float t, a;
+        double t;
         ++o.tests;
-        if (surfel_test(r, O, W, tc.t_min, tc.k2, t, a)) {
-          const uint64_t key = make_key(tc, t, __float_as_uint(r.n_idx.w), pos);
-          if (!have_last || key > last) { kk[0] = key; kt[0] = t; ka[0] = a; cnt = 1; }
+        if (record_test(r, O, W, tc.t_min, tc.k2, t)) {
+          const uint64_t key = make_key(tc, t, rec_index(r), pos);
+          if (!have_last || key > last) { kk[0] = key; cnt = 1; }
         }
       }
-      // pop, skipping entries that the tightened cut now excludes
-      bool got = false;
-      while (sp > 0) {
-        --sp;
-        if (stack_t[sp] <= t_cut) { ref = stack[sp]; got = true; break; }
-      }
-      if (!got) break;
+      if (st.sp == 0) break;
+      ref = st.pop();
     }
     ++o.rounds;
 
-    // blend this round's hits in key order
+    // blend this round's hits in key order (the buffer is shifted down one
+    // entry per hit, which keeps its indexing static); t and alpha are
+    // recomputed from the record with the same double-precision test
+    const uint64_t round_last = kk[KBUF - 1];
+    for (int j = 0; j < cnt && !done; ++j) {
+      const uint64_t key = kk[0];
 #pragma unroll
-    for (int j = 0; j < KBUF; ++j) {
-      if (j < cnt && !done) {
-        const uint32_t pos = key_pos(tc, kk[j]);
-        const float a = ka[j];
-        const float w = o.T * a;
-        if (QMODE == Q_ALL) {
-          const float4 nr = reinterpret_cast<const float4*>(tc.recs + pos)[1];
-          const float s = (W.x * nr.x + W.y * nr.y + W.z * nr.z) > 0.0f ? -w : w;  // n' faces the origin
-          o.N.x += s * nr.x;
-          o.N.y += s * nr.y;
-          o.N.z += s * nr.z;
-          o.D += w * kt[j];
-          const Attr at = tc.attrs[pos];
-          o.P.x += w * at.rho_e.x;
-          o.P.y += w * at.rho_e.y;
-          o.P.z += w * at.rho_e.z;
-          o.E += w * at.rho_e.w;
-          o.R.x += w * at.r.x;
-          o.R.y += w * at.r.y;
-          o.R.z += w * at.r.z;
-        } else {
-          const float4 r = tc.attrs[pos].r;
-          o.R.x += w * r.x;
-          o.R.y += w * r.y;
-          o.R.z += w * r.z;
-        }
-        if (hit_out && o.nhits < max_hits) hit_out[o.nhits] = (int32_t)key_idx(tc, kk[j]);
-        ++o.nhits;
-        o.T *= (1.0f - a);
-        if (o.T < tc.T_min) done = true;
+      for (int m = 0; m < KBUF - 1; ++m) kk[m] = kk[m + 1];
+      const uint32_t pos = key_pos(tc, key);
+      const Geo ge = surfel_geo(load_record(tc.recs, pos));
+      double t = 0.0, q2 = 0.0;
+      surfel_test(ge, O, W, -1e300, 1e300, t, q2);
+      const double a = ge.sigma * exp(-0.5 * q2);
+      const double w = o.T * a;
+      const Acc wf = (Acc)w;
+      if (QMODE == Q_ALL) {
+        const double sw = dot(W, ge.n) > 0.0 ? -w : w;  // n' faces the origin
+        o.N.x += sw * ge.n.x;
+        o.N.y += sw * ge.n.y;
+        o.N.z += sw * ge.n.z;
+        o.D += w * t;
+        const Attr at = tc.attrs[pos];
+        P0 += wf * at.rho_e.x;
+        P1 += wf * at.rho_e.y;
+        P2 += wf * at.rho_e.z;
+        E += wf * at.rho_e.w;
+        R0 += wf * at.r.x;
+        R1 += wf * at.r.y;
+        R2 += wf * at.r.z;
+      } else {
+        const float4 rr = tc.attrs[pos].r;
+        R0 += wf * rr.x;
+        R1 += wf * rr.y;
+        R2 += wf * rr.z;
       }
+      if (hit_out && o.nhits < max_hits) hit_out[o.nhits] = (int32_t)key_idx(tc, key);
+      on_hit(pos, t, a, w, o.T);
+      ++o.nhits;
+      o.T *= (1.0 - a);
+      if (o.T < tc.T_min) done = true;
     }
     if (cnt < KBUF) done = true;
     if (!done) {
-      last = kk[KBUF - 1];
+      last = round_last;
       have_last = true;
       t_floor = key_tlo(tc, last);
     }
   }
+  o.R = d3(R0, R1, R2);
+  o.E = E;
+  o.P = d3(P0, P1, P2);
   return o;
+}
+
+template <int QMODE, bool DACC = false>
+__device__ __forceinline__ SegOut trace_segment(const TraceCtx& tc, D3 O, D3 W, int32_t* hit_out = nullptr,
+                                                int max_hits = 0) {
+  NoHit nh;
+  return trace_segment_cb<QMODE, DACC>(tc, O, W, nh, hit_out, max_hits);
 }
 
 }  // namespace eag

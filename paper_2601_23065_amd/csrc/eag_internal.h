@@ -23,6 +23,7 @@ struct Error {
   std::string msg;
 };
 [[noreturn]] void fail(eag_status s, const std::string& msg);
+void set_last_error(const std::string& msg);
 void check_hip(hipError_t e, const char* what);
 
 inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
@@ -94,7 +95,7 @@ void pack_attrs(const eag_surfels* s, const eag_bvh* b, Attr* attrs, hipStream_t
 struct TraceSetup {
   int32_t idx_bits;
   uint32_t max_bucket;
-  float inv_dq;
+  double inv_dq;
 };
 TraceSetup trace_setup(const eag_bvh* b, const eag_trace_params* p, float t_max_needed);
 void validate_params(const eag_trace_params* p);
@@ -102,7 +103,7 @@ CamDev make_cam(const eag_camera& c, uint32_t id);
 float camera_t_max(const eag_bvh* b, const eag_camera& c);
 
 void launch_trace_rays(const eag_bvh* b, const Attr* attrs, const eag_trace_params* p, const TraceSetup& ts,
-                       int64_t n_rays, const float* o, const float* d, float* out, int32_t* hit_idx,
-                       int32_t* hit_count, int32_t max_hits, hipStream_t st);
+                       int64_t n_rays, const double* o, const double* d, float* out, int32_t* hit_idx,
+                       int32_t* hit_count, int32_t max_hits, int32_t* stats, hipStream_t st);
 
 }  // namespace eag

@@ -12,6 +12,9 @@
 // X = O + Dt w, and Russian roulette (q = min(0.95, max beta), survive iff
 // u2 < q, beta /= q) applies once the new depth reaches rr_start.
 // A wave exits when the counter is exhausted and all its lanes are idle.
+// One launch can serve several requests (slots), each with its own camera,
+// parameters, accumulator and scene version; the server uses this to batch
+// requests that are live at the same time.
 //
 // Work items are sample-major over 8x8 pixel tiles, so a wave's first
 // segments are spatially coherent. Contributions are added to int64 fixed
@@ -25,8 +28,6 @@ namespace eag {
 
 namespace {
 
-constexpr uint32_t JITTER_SEGMENT = 0xffffffffu;
-
 __device__ __forceinline__ void add_fixed(int64_t* acc, float v) {
   if (v != 0.0f) {
     const long long q = (long long)rint((double)v * EAG_ACCUM_SCALE);
@@ -34,19 +35,18 @@ __device__ __forceinline__ void add_fixed(int64_t* acc, float v) {
   }
 }
 
-__global__ void __launch_bounds__(256) k_path_trace(TraceCtx tc, CamDev cam, PtParams pp, int64_t* accum,
-                                                    unsigned long long* work_counter,
+__global__ void __launch_bounds__(256) k_path_trace(TraceCtx tc, PtLaunch L, unsigned long long* work_counter,
                                                     unsigned long long* counters) {
   const int lane = (int)(threadIdx.x & 63);
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  const int64_t n_work = (int64_t)pp.sample_count * pp.tile_pixels;
-  const int W_img = cam.width, H_img = cam.height;
 
   bool alive = false;
+  int slot = 0;
   uint32_t pix = 0, sample = 0;
   int depth = 0;
-  V3 O = v3(0.f, 0.f, 0.f), Wd = v3(0.f, 0.f, 1.f), beta = v3(1.f, 1.f, 1.f);
-  unsigned long long n_rounds = 0, n_tests = 0, n_paths = 0, n_hits = 0;
+  D3 O = d3(0.0, 0.0, 0.0), Wd = d3(0.0, 0.0, 1.0);
+  V3 beta = v3(1.f, 1.f, 1.f);
+  unsigned long long n_rounds = 0, n_tests = 0, n_paths = 0, n_hits = 0, n_visits = 0;
 
   while (true) {
     // ---- refill idle lanes from the global work counter
@@ -59,24 +59,23 @@ __global__ void __launch_bounds__(256) k_path_trace(TraceCtx tc, CamDev cam, PtP
       base = __shfl(base, leader);
       if (need) {
         const int64_t wid = (int64_t)base + __popcll(idle & lt_mask);
-        if (wid < n_work) {
-          const int64_t s_rel = wid / pp.tile_pixels;
-          const int64_t tp = wid - s_rel * pp.tile_pixels;
+        if (wid < L.n_work) {
+          int k = 0;
+          while (k < L.n_slots - 1 && wid >= L.s[k].global_end) ++k;
+          const PtSlot& S = L.s[k];
+          const int64_t item = S.work_begin + (wid - (k ? L.s[k - 1].global_end : 0));
+          const int64_t s_rel = item / S.tile_pixels;
+          const int64_t tp = item - s_rel * S.tile_pixels;
           const int64_t tile = tp >> 6;
           const int within = (int)(tp & 63);
-          const int x = (int)(tile % pp.tiles_x) * 8 + (within & 7);
-          const int y = (int)(tile / pp.tiles_x) * 8 + (within >> 3);
-          if (x < W_img && y < H_img) {
-            pix = (uint32_t)(y * W_img + x);
-            sample = pp.sample_begin + (uint32_t)s_rel;
-            float ox = 0.5f, oy = 0.5f;
-            if (pp.flags & EAG_JITTER) {
-              const uint4 w = philox(make_uint4(pix, sample, JITTER_SEGMENT, cam.id), pp.k0, pp.k1);
-              ox = to_unit(w.x);
-              oy = to_unit(w.y);
-            }
-            O = v3(cam.eye[0], cam.eye[1], cam.eye[2]);
-            Wd = camera_dir(cam, x, y, ox, oy);
+          const int x = (int)(tile % S.tiles_x) * 8 + (within & 7);
+          const int y = (int)(tile / S.tiles_x) * 8 + (within >> 3);
+          if (x < S.cam.width && y < S.cam.height) {
+            slot = k;
+            pix = (uint32_t)(y * S.cam.width + x);
+            sample = S.sample_begin + (uint32_t)s_rel;
+            O = d3(S.cam.eye[0], S.cam.eye[1], S.cam.eye[2]);
+            Wd = pixel_dir(S.cam, pix, sample, S.flags, S.k0, S.k1);
             beta = v3(1.f, 1.f, 1.f);
             depth = 0;
             alive = true;
@@ -95,40 +94,43 @@ __global__ void __launch_bounds__(256) k_path_trace(TraceCtx tc, CamDev cam, PtP
       atomicAdd(&counters[0], (unsigned long long)__popcll(live));
     if (!alive) continue;
 
-    // ---- one segment
-    const SegOut s = trace_segment<Q_ALL>(tc, O, Wd);
+    // ---- one segment, through the attributes of this path's scene version
+    const PtSlot& S = L.s[slot];
+    TraceCtx tcl = tc;
+    tcl.attrs = S.attrs;
+    const SegOut s = trace_segment<Q_ALL>(tcl, O, Wd);
     n_rounds += s.rounds;
     n_tests += s.tests;
     n_hits += s.nhits;
-    const float A = 1.0f - s.T;
-    if (s.nhits == 0 || !(A > 0.0f)) {
+    n_visits += s.visits;
+    const double A = 1.0 - s.T;
+    if (s.nhits == 0 || !(A > 0.0)) {
       alive = false;
       continue;
     }
-    const bool emit = s.E > pp.tau_E;
-    if ((pp.flags & EAG_ADDITIVE_EMISSION) || emit) {
-      int64_t* acc = accum + (int64_t)pix * 3;
-      add_fixed(acc + 0, beta.x * s.R.x);
-      add_fixed(acc + 1, beta.y * s.R.y);
-      add_fixed(acc + 2, beta.z * s.R.z);
-      if (!(pp.flags & EAG_ADDITIVE_EMISSION)) {
+    const bool emit = (float)s.E > S.tau_E;
+    if ((S.flags & EAG_ADDITIVE_EMISSION) || emit) {
+      int64_t* acc = S.accum + (int64_t)pix * 3;
+      add_fixed(acc + 0, beta.x * (float)s.R.x);
+      add_fixed(acc + 1, beta.y * (float)s.R.y);
+      add_fixed(acc + 2, beta.z * (float)s.R.z);
+      if (!(S.flags & EAG_ADDITIVE_EMISSION)) {
         alive = false;
         continue;
       }
     }
-    if (depth >= pp.max_depth) {
+    if (depth >= S.max_depth) {
       alive = false;
       continue;
     }
-    beta = v3(beta.x * s.P.x, beta.y * s.P.y, beta.z * s.P.z);
-    const uint4 w = philox(make_uint4(pix, sample, (uint32_t)depth, cam.id), pp.k0, pp.k1);
-    const float il = 1.0f / sqrtf(dot(s.N, s.N));
-    const V3 Nt = il * s.N;
-    const float Dt = s.D / A;
-    O = v3(O.x + Dt * Wd.x, O.y + Dt * Wd.y, O.z + Dt * Wd.z);
+    beta = v3(beta.x * (float)s.P.x, beta.y * (float)s.P.y, beta.z * (float)s.P.z);
+    const uint4 w = philox(make_uint4(pix, sample, (uint32_t)depth, S.cam.id), S.k0, S.k1);
+    const D3 Nt = (1.0 / sqrt(dot(s.N, s.N))) * s.N;
+    const double Dt = s.D / A;
+    O = d3(O.x + Dt * Wd.x, O.y + Dt * Wd.y, O.z + Dt * Wd.z);
     Wd = cosine_dir(Nt, to_unit(w.x), to_unit(w.y));
     ++depth;
-    if (pp.rr_start > 0 && depth >= pp.rr_start) {
+    if (S.rr_start > 0 && depth >= S.rr_start) {
       const float q = fminf(0.95f, fmaxf(fmaxf(beta.x, beta.y), beta.z));
       if (!(to_unit(w.z) < q)) {
         alive = false;
@@ -143,6 +145,7 @@ __global__ void __launch_bounds__(256) k_path_trace(TraceCtx tc, CamDev cam, PtP
     atomicAdd(&counters[2], n_rounds);
     atomicAdd(&counters[3], n_tests);
     atomicAdd(&counters[4], n_hits);
+    atomicAdd(&counters[5], n_visits);
   }
 }
 
@@ -157,8 +160,8 @@ __global__ void k_resolve(const int64_t* accum, int64_t n, double scale, float* 
 
 }  // namespace
 
-void launch_path_trace(const TraceCtx& tc, const CamDev& cam, const PtParams& pp, int64_t* accum,
-                       unsigned long long* work_counter, unsigned long long* counters, hipStream_t st) {
+void launch_path_trace(const TraceCtx& tc, const PtLaunch& L, unsigned long long* work_counter,
+                       unsigned long long* counters, hipStream_t st) {
   int dev = 0, cus = 0, per_cu = 0;
   check_hip(hipGetDevice(&dev), "hipGetDevice");
   check_hip(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "CU count");
@@ -166,8 +169,7 @@ void launch_path_trace(const TraceCtx& tc, const CamDev& cam, const PtParams& pp
             "occupancy");
   if (per_cu < 1) per_cu = 1;
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, work_counter, 1);
-  hipLaunchKernelGGL(k_path_trace, dim3((unsigned)(cus * per_cu)), dim3(256), 0, st, tc, cam, pp, accum,
-                     work_counter, counters);
+  hipLaunchKernelGGL(k_path_trace, dim3((unsigned)(cus * per_cu)), dim3(256), 0, st, tc, L, work_counter, counters);
   check_hip(hipGetLastError(), "path_trace launch");
 }
 

@@ -11,6 +11,56 @@ struct CamBatch {
   CamDev c[MAX_CAMS_PER_LAUNCH];
 };
 
+constexpr uint32_t JITTER_SEGMENT = 0xffffffffu;
+
+// Camera ray through pixel `pix` (pixel centre, or a Philox jitter).
+__device__ __forceinline__ D3 pixel_dir(const CamDev& c, uint32_t pix, uint32_t sample, uint32_t flags, uint32_t k0,
+                                        uint32_t k1) {
+  const int x = (int)(pix % (uint32_t)c.width), y = (int)(pix / (uint32_t)c.width);
+  double ox = 0.5, oy = 0.5;
+  if (flags & EAG_JITTER) {
+    const uint4 w = philox(make_uint4(pix, sample, JITTER_SEGMENT, c.id), k0, k1);
+    ox = to_unit(w.x);
+    oy = to_unit(w.y);
+  }
+  return camera_dir(c, x, y, ox, oy);
+}
+
+// Per-pixel forward state of the single-bounce render (EAG_FWD_PIXEL_FLOATS
+// floats), all in double except E and the branch: Nt, Dt, |N|, A place the
+// bounce; R and P are the totals the adjoint subtracts running prefixes from.
+struct FwdState {
+  D3 Nt;
+  double Dt, Nlen, A;
+  D3 R, P;
+  float E;
+  float branch;   // 0 miss, 1 emitter, 2 reflect
+};
+
+__device__ __forceinline__ void store_state(float* p, const FwdState& s) {
+  double* d = reinterpret_cast<double*>(p);
+  d[0] = s.Nt.x; d[1] = s.Nt.y; d[2] = s.Nt.z;
+  d[3] = s.Dt; d[4] = s.Nlen; d[5] = s.A;
+  d[6] = s.R.x; d[7] = s.R.y; d[8] = s.R.z;
+  d[9] = s.P.x; d[10] = s.P.y; d[11] = s.P.z;
+  p[24] = s.E;
+  p[25] = s.branch;
+  p[26] = 0.0f;
+  p[27] = 0.0f;
+}
+
+__device__ __forceinline__ FwdState load_state(const float* p) {
+  const double* d = reinterpret_cast<const double*>(p);
+  FwdState s;
+  s.Nt = d3(d[0], d[1], d[2]);
+  s.Dt = d[3]; s.Nlen = d[4]; s.A = d[5];
+  s.R = d3(d[6], d[7], d[8]);
+  s.P = d3(d[9], d[10], d[11]);
+  s.E = p[24];
+  s.branch = p[25];
+  return s;
+}
+
 struct SbParams {
   int32_t spp;
   uint32_t flags;
@@ -19,25 +69,45 @@ struct SbParams {
 };
 
 void launch_single_bounce(const TraceCtx& tc, const CamBatch& cams, int64_t hw, int32_t n_cams,
-                          const SbParams& sp, float* state, float* r1, float* rgb, hipStream_t st);
+                          const SbParams& sp, float* state, double* r1, float* rgb, hipStream_t st);
 
-struct PtParams {
+// One request's share of a path-tracing launch. Work items of a request are
+// numbered sample-major over 8x8 pixel tiles: item w has sample
+// sample_begin + w / tile_pixels and tile slot w % tile_pixels. A launch
+// covers items [work_begin, work_begin + count) of each slot; slots are laid
+// end to end in the launch's own numbering (global_end = running total).
+struct PtSlot {
+  CamDev cam;
+  int64_t* accum;            // int64 fixed point [H][W][3]
+  const Attr* attrs;         // attribute records of the request's scene version
+  int64_t work_begin;
+  int64_t global_end;
+  int64_t tile_pixels;       // tiles_x * tiles_y * 64
+  uint32_t sample_begin;
+  int32_t tiles_x;           // 8x8 pixel tiles across
   int32_t max_depth;
   int32_t rr_start;
   uint32_t flags;
   uint32_t k0, k1;
   float tau_E;
-  uint32_t sample_begin;
-  uint32_t sample_count;
-  int32_t tiles_x;           // 8x8 pixel tiles across
-  int64_t tile_pixels;       // tiles_x * tiles_y * 64
 };
 
-void launch_path_trace(const TraceCtx& tc, const CamDev& cam, const PtParams& pp, int64_t* accum,
-                       unsigned long long* work_counter, unsigned long long* counters, hipStream_t st);
+constexpr int PT_MAX_SLOTS = 8;
+struct PtLaunch {
+  PtSlot s[PT_MAX_SLOTS];
+  int32_t n_slots;
+  int64_t n_work;            // = s[n_slots - 1].global_end
+};
+
+void launch_path_trace(const TraceCtx& tc, const PtLaunch& L, unsigned long long* work_counter,
+                       unsigned long long* counters, hipStream_t st);
+
 void launch_single_bounce_backward(const TraceCtx& tc, const eag_surfels& s, const CamBatch& cams, int64_t hw,
-                                   int32_t n_cams, const SbParams& sp, const float* state, const float* r1,
-                                   const float* dL, const eag_surfel_grads& g, float* scratch, hipStream_t st);
+                                   int32_t n_cams, const SbParams& sp, const float* state, const double* r1,
+                                   const float* dL, double* gacc, float* scratch, hipStream_t st);
+size_t grad_accum_doubles(int64_t n);
+void launch_grad_zero(double* gacc, int64_t n, hipStream_t st);
+void launch_grad_finalize(const double* gacc, int64_t n, const eag_surfel_grads& g, hipStream_t st);
 void launch_apply_edit(const eag_edit& e, const eag_surfel_attrs& a, hipStream_t st);
 void launch_accum_resolve(const int64_t* accum, int64_t n_values, double scale, float* rgb, hipStream_t st);
 

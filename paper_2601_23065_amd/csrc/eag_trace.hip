@@ -8,31 +8,36 @@ namespace eag {
 
 namespace {
 
-__global__ void __launch_bounds__(256) k_trace_rays(TraceCtx tc, int64_t n_rays, const float* o, const float* d,
+__global__ void __launch_bounds__(256) k_trace_rays(TraceCtx tc, int64_t n_rays, const double* o, const double* d,
                                                     float* out, int32_t* hit_idx, int32_t* hit_count,
-                                                    int32_t max_hits) {
+                                                    int32_t max_hits, int32_t* stats) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n_rays) return;
-  const V3 O = v3(o[i], o[n_rays + i], o[2 * n_rays + i]);
-  const V3 W = v3(d[i], d[n_rays + i], d[2 * n_rays + i]);
+  const D3 O = d3(o[i], o[n_rays + i], o[2 * n_rays + i]);
+  const D3 W = d3(d[i], d[n_rays + i], d[2 * n_rays + i]);
   int32_t* hl = hit_idx ? hit_idx + i * (int64_t)max_hits : nullptr;
-  const SegOut s = trace_segment<Q_ALL>(tc, O, W, hl, max_hits);
-  const float A = 1.0f - s.T;
+  const SegOut s = trace_segment<Q_ALL, true>(tc, O, W, hl, max_hits);
+  const double A = 1.0 - s.T;
   float v[12];
-  if (s.nhits > 0 && A > 0.0f) {
-    const float il = 1.0f / sqrtf(dot(s.N, s.N));
-    v[0] = s.N.x * il; v[1] = s.N.y * il; v[2] = s.N.z * il;
-    v[3] = s.D / A;
+  if (s.nhits > 0 && A > 0.0) {
+    const double il = 1.0 / sqrt(dot(s.N, s.N));
+    v[0] = (float)(s.N.x * il); v[1] = (float)(s.N.y * il); v[2] = (float)(s.N.z * il);
+    v[3] = (float)(s.D / A);
   } else {
     v[0] = v[1] = v[2] = v[3] = 0.0f;
   }
-  v[4] = s.R.x; v[5] = s.R.y; v[6] = s.R.z;
-  v[7] = s.E;
-  v[8] = s.P.x; v[9] = s.P.y; v[10] = s.P.z;
-  v[11] = s.nhits > 0 ? A : 0.0f;
+  v[4] = (float)s.R.x; v[5] = (float)s.R.y; v[6] = (float)s.R.z;
+  v[7] = (float)s.E;
+  v[8] = (float)s.P.x; v[9] = (float)s.P.y; v[10] = (float)s.P.z;
+  v[11] = s.nhits > 0 ? (float)A : 0.0f;
 #pragma unroll
   for (int k = 0; k < 12; ++k) out[k * n_rays + i] = v[k];
   if (hit_count) hit_count[i] = s.nhits;
+  if (stats) {
+    stats[i * 3 + 0] = s.rounds;
+    stats[i * 3 + 1] = s.tests;
+    stats[i * 3 + 2] = s.visits;
+  }
 }
 
 }  // namespace
@@ -47,18 +52,18 @@ TraceCtx make_ctx(const eag_bvh* b, const Attr* attrs, const eag_trace_params* p
   tc.max_bucket = ts.max_bucket;
   tc.inv_dq = ts.inv_dq;
   tc.t_min = p->t_min;
-  tc.k2 = p->k_sigma * p->k_sigma;
+  tc.k2 = (double)p->k_sigma * (double)p->k_sigma;
   tc.T_min = p->T_min;
   return tc;
 }
 
 void launch_trace_rays(const eag_bvh* b, const Attr* attrs, const eag_trace_params* p, const TraceSetup& ts,
-                       int64_t n_rays, const float* o, const float* d, float* out, int32_t* hit_idx,
-                       int32_t* hit_count, int32_t max_hits, hipStream_t st) {
+                       int64_t n_rays, const double* o, const double* d, float* out, int32_t* hit_idx,
+                       int32_t* hit_count, int32_t max_hits, int32_t* stats, hipStream_t st) {
   const TraceCtx tc = make_ctx(b, attrs, p, ts);
   const unsigned g = (unsigned)((n_rays + 255) / 256);
   hipLaunchKernelGGL(k_trace_rays, dim3(g), dim3(256), 0, st, tc, n_rays, o, d, out, hit_idx, hit_count,
-                     max_hits);
+                     max_hits, stats);
   check_hip(hipGetLastError(), "trace_rays launch");
 }
 

@@ -1,0 +1,135 @@
+"""Parity of the hand-written single-bounce adjoint with the oracle's
+gradient (1e-3) and with float64 central finite differences of the oracle's
+forward pass (1e-2), on pixels the oracle does not flag."""
+import numpy as np
+import pytest
+import torch
+
+import scenegen as sg
+from oracle.grad import PARAMS, signature, single_bounce_grad
+from oracle.render import single_bounce
+from oracle.tracer import Scene64
+from tests._util import gpu_scene, oracle_params, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu_grads(scene, cams, p, dL):
+    from paper_2601_23065_amd.api import BVH, render_single_bounce, single_bounce_backward
+    gs = gpu_scene(scene)
+    bvh = BVH(gs)
+    rgb, state = render_single_bounce(bvh, gs, cams, p, keep_state=True)
+    g = single_bounce_backward(bvh, gs, cams, p, torch.from_numpy(dL).cuda(), state)
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy().astype(np.float64) for k, v in g.items()}, rgb.cpu().numpy()
+
+
+def _unflagged_pixels(sc, cam, prm, count, seed):
+    rng = np.random.default_rng(seed)
+    cand = rng.choice(cam.width * cam.height, count * 3, replace=False)
+    fwd = single_bounce(sc, cam, prm, pixels=cand)
+    ok = cand[(fwd["flags"] == 0) & (fwd["branch"] > 0)]
+    return np.sort(ok[:count])
+
+
+def _compare(scene, cams, p, n_pix, seed, tol=1e-3):
+    prm = oracle_params(p)
+    sc = Scene64(scene)
+    H, W = cams[0].height, cams[0].width
+    rng = np.random.default_rng(seed)
+    dL = np.zeros((len(cams), H * W, 3), dtype=np.float32)
+    ref = {k: 0.0 for k in PARAMS}
+    for ci, cam in enumerate(cams):
+        prm_c = oracle_params(p)
+        prm_c.camera_id = p.camera_id + ci
+        pix = _unflagged_pixels(sc, cam, prm_c, n_pix, seed + ci)
+        c = rng.uniform(-1, 1, (pix.size, 3)).astype(np.float32)
+        dL[ci, pix] = c
+        g, _, _ = single_bounce_grad(scene, cam, prm_c, pix, dL_dI=c.astype(np.float64))
+        for k in PARAMS:
+            ref[k] = ref[k] + g[k]
+    got, _ = _gpu_grads(scene, cams, p, dL.reshape(len(cams), H, W, 3))
+    worst = {}
+    for k in PARAMS:
+        e = rel_err(got[k], ref[k])
+        worst[k] = float(e.max())
+    print("max rel err", {k: f"{v:.2e}" for k, v in worst.items()})
+    for k, v in worst.items():
+        assert v <= tol, (k, v)
+    return ref, got
+
+
+def test_adjoint_config1_cloud():
+    from paper_2601_23065_amd.api import Params
+    scene, cams, cfg = sg.config(1)
+    _compare(scene, cams, Params(spp=cfg["spp"]), 300, seed=1)
+
+
+def test_adjoint_room_bounce_chain():
+    from paper_2601_23065_amd.api import Params
+    scene = sg.room_scene(20000, (3.0, 2.5, 2.5), 3, seed=41, emissive_frac=0.02)
+    cams = sg.interior_cameras(scene, 2, 48, 40, seed=5)
+    _compare(scene, cams, Params(spp=4, seed=9), 120, seed=3)
+
+
+def test_adjoint_detached_bounce():
+    from paper_2601_23065_amd import DETACH_BOUNCE
+    from paper_2601_23065_amd.api import Params
+    scene = sg.room_scene(20000, (3.0, 2.5, 2.5), 3, seed=41, emissive_frac=0.02)
+    cams = sg.interior_cameras(scene, 1, 48, 40, seed=6)
+    _compare(scene, cams, Params(spp=4, flags=DETACH_BOUNCE), 120, seed=4)
+
+
+@pytest.mark.slow
+def test_adjoint_config2_masked():
+    """100k-surfel room, 8 cameras at 256x256, 8 spp; 48 unflagged pixels
+    per camera carry the loss."""
+    from paper_2601_23065_amd.api import Params
+    scene, cams, cfg = sg.config(2)
+    _compare(scene, cams, Params(spp=cfg["spp"]), 48, seed=7)
+
+
+def test_adjoint_against_finite_differences():
+    from paper_2601_23065_amd.api import Params
+    scene = sg.room_scene(8000, (3.0, 2.5, 2.5), 2, seed=43, emissive_frac=0.03)
+    cam = sg.Camera((0.5, 0.6, 1.2), (2.5, 1.9, 1.9), (0.0, 0.0, 1.0), 75.0, 32, 24)
+    p = Params(spp=3, seed=4)
+    prm = oracle_params(p)
+    sc = Scene64(scene)
+    pix = _unflagged_pixels(sc, cam, prm, 40, 11)
+    rng = np.random.default_rng(12)
+    c = rng.uniform(-1, 1, (pix.size, 3))
+    dL = np.zeros((1, cam.height * cam.width, 3), dtype=np.float32)
+    dL[0, pix] = c
+    got, _ = _gpu_grads(scene, [cam], p, dL.reshape(1, cam.height, cam.width, 3))
+    base = {k: np.asarray(v, dtype=np.float64).copy() for k, v in scene.arrays().items()}
+    fwd0 = single_bounce(Scene64(base), cam, prm, pixels=pix, keep_segments=True)
+    sig0 = signature(fwd0)
+    hit = sorted({int(h) for s in fwd0["cam"] for h in s.hits})
+    scale = max(np.abs(v).max() for v in got.values())
+    checked = tries = 0
+    while checked < 50 and tries < 400:
+        tries += 1
+        k = PARAMS[rng.integers(len(PARAMS))]
+        i = int(rng.choice(hit))
+        comp = int(rng.integers(base[k].shape[0])) if base[k].ndim == 2 else None
+        val = base[k][comp, i] if comp is not None else base[k][i]
+        h = 1e-6 * max(1.0, abs(val))
+        f = []
+        same = True
+        for sgn in (1, -1):
+            pert = {kk: vv.copy() for kk, vv in base.items()}
+            if comp is not None:
+                pert[k][comp, i] += sgn * h
+            else:
+                pert[k][i] += sgn * h
+            out = single_bounce(Scene64(pert), cam, prm, pixels=pix, keep_segments=True)
+            same &= signature(out) == sig0
+            f.append(float((out["L"] * c).sum()))
+        if not same:
+            continue
+        fd = (f[0] - f[1]) / (2 * h)
+        ad = got[k][comp, i] if comp is not None else got[k][i]
+        assert abs(ad - fd) <= 1e-2 * max(abs(fd), 1e-2 * scale), (k, comp, i, ad, fd)
+        checked += 1
+    assert checked == 50

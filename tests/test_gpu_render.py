@@ -47,12 +47,12 @@ def test_single_bounce_room_per_sample():
     bvh = BVH(gs)
     rgb, state = render_single_bounce(bvh, gs, [cam], p, keep_state=True)
     npix = cam.width * cam.height
-    r1 = state[npix * 16:].view(npix, p.spp, 3).cpu().numpy()
-    st = state[:npix * 16].view(npix, 16).cpu().numpy()
+    r1 = state[npix * 28:].view(torch.float64).view(npix, p.spp, 3).cpu().numpy()
+    st = state[:npix * 28].view(npix, 28).cpu().numpy()
     ref = o_single_bounce(Scene64(scene), cam, oracle_params(p))
     ok = ref["flags"] == 0
     assert ok.mean() > 0.5
-    np.testing.assert_array_equal(st[:, 13].astype(int)[ok], ref["branch"][ok])
+    np.testing.assert_array_equal(st[:, 25].astype(int)[ok], ref["branch"][ok])
     e1 = rel_err(r1, ref["R1"], np.broadcast_to(ok[:, None, None], r1.shape))
     eL = rel_err(rgb[0].cpu().numpy().reshape(-1, 3), ref["L"], np.broadcast_to(ok[:, None], (npix, 3)))
     print(f"unflagged={ok.mean():.3f} R1 err={e1.max():.2e} L err={eL.max():.2e}")

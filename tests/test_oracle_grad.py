@@ -22,11 +22,11 @@ def test_single_surfel_emitter_closed_form():
     s = dict(pos=f([[0.0], [0.0], [2.0]]), rot=f([[1.0], [0.0], [0.0], [0.0]]), scale=f([[0.5], [0.25]]),
              opacity=f([0.6]), albedo=f([[0.3], [0.3], [0.3]]), radiance=f([[2.0], [3.0], [4.0]]),
              emissive=f([1.0]))
-    cam = sg.Camera((0.1, 0.05, 0.0), (0.1, 0.05, 1.0), (0.0, 1.0, 0.0), 20.0, 1, 1)
+    cam = sg.Camera((0.125, 0.0625, 0.0), (0.125, 0.0625, 1.0), (0.0, 1.0, 0.0), 20.0, 1, 1)
     prm = Params(spp=2)
     g, L, fwd = single_bounce_grad(s, cam, prm, pixels=np.array([0]), dL_dI=np.ones((1, 3)))
     assert fwd["branch"][0] == 1
-    u, v = 0.1 / 0.5, 0.05 / 0.25
+    u, v = 0.125 / 0.5, 0.0625 / 0.25
     gg = np.exp(-0.5 * (u * u + v * v))
     sig = float(np.float32(0.6))
     np.testing.assert_allclose(L[0], sig * gg * np.array([2.0, 3.0, 4.0]), rtol=1e-12)
