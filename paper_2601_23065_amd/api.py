@@ -291,3 +291,91 @@ def apply_edit(scene: Scene, kind: int, idx, value, stream=None):
     e.value[:] = [float(v) for v in vals[:3]]
     a = scene.attrs_c()
     L.check(L.load().eag_apply_edit(C.byref(e), C.byref(a), _stream(stream)))
+
+
+class Server:
+    """Continuous-batching render server over a resident scene (eag_serve_*).
+
+    arena_bytes: device memory for the scene copy, BVH, attribute versions
+    and the request pool (per request: H*W*24 bytes of fixed-point
+    accumulator). The arena is one torch tensor owned by this object."""
+
+    def __init__(self, scene: Scene, arena_bytes: int, max_live_requests: int = 8,
+                 paths_per_launch: int = 1 << 22, stream=None):
+        lib = L.load()
+        need = lib.eag_serve_arena_bytes(scene.n, 3, 0)
+        self.arena = _bytes(max(int(arena_bytes), need), scene.device)
+        ap, ab = _aligned(self.arena)
+        cfg = L.ServerConfig()
+        cfg.arena, cfg.arena_bytes = ap, ab
+        cfg.max_live_requests = int(max_live_requests)
+        cfg.paths_per_launch = int(paths_per_launch)
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=scene.device)
+        cfg.stream = C.c_void_p(self.stream.cuda_stream)
+        sc = scene.c()
+        h = C.c_void_p()
+        L.check(lib.eag_serve_create(C.byref(sc), C.byref(cfg), C.byref(h)))
+        self.h = h
+        self.device = scene.device
+        self._keep = {}
+
+    def submit(self, cam, params: Params, out=None):
+        """Queue a path-tracing request; returns (ticket, output tensor)."""
+        if out is None:
+            out = torch.empty((cam.height, cam.width, 3), dtype=torch.float32, device=self.device)
+        r = L.Request()
+        r.cam = camera_struct(cam)
+        r.params = params.c()
+        r.out_rgb = _ptr(out)
+        t = C.c_uint64()
+        L.check(L.load().eag_serve_submit(self.h, C.byref(r), C.byref(t)))
+        self._keep[t.value] = out
+        return t.value, out
+
+    def edit(self, kind: int, idx, value):
+        """Queue an attribute edit (host index list); returns its ticket."""
+        import numpy as np
+        idx = np.ascontiguousarray(np.asarray(idx, dtype=np.int32))
+        e = L.Edit()
+        e.kind = int(kind)
+        e.idx = C.c_void_p(idx.ctypes.data)
+        e.count = idx.size
+        vals = list(value) + [0.0] * (3 - len(list(value)))
+        e.value[:] = [float(v) for v in vals[:3]]
+        t = C.c_uint64()
+        L.check(L.load().eag_serve_edit(self.h, C.byref(e), C.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int):
+        """Returns None while running, else a dict with status and times."""
+        res = L.Result()
+        st = L.load().eag_serve_poll(self.h, ticket, C.byref(res))
+        if st == L.EAG_NOT_READY:
+            return None
+        return dict(status=st, version=res.scene_version, t_submit=res.t_submit, t_admit=res.t_admit,
+                    t_done=res.t_done, paths=res.paths)
+
+    def wait(self, ticket: int, timeout: float = 120.0):
+        import time
+        t0 = time.time()
+        while True:
+            r = self.poll(ticket)
+            if r is not None:
+                return r
+            if time.time() - t0 > timeout:
+                raise TimeoutError(f"ticket {ticket} not done after {timeout} s")
+            time.sleep(0.0005)
+
+    def cancel(self, ticket: int):
+        L.check(L.load().eag_serve_cancel(self.h, ticket))
+
+    def close(self):
+        if getattr(self, "h", None):
+            h, self.h = self.h, None
+            L.check(L.load().eag_serve_destroy(h))
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -154,6 +154,10 @@ __device__ __forceinline__ uint64_t make_key(const TraceCtx& tc, double t, uint3
   }
   return ((uint64_t)bucket << (2 * tc.idx_bits)) | ((uint64_t)idx << tc.idx_bits) | (uint64_t)pos;
 }
+__device__ __forceinline__ uint64_t make_key_b(const TraceCtx& tc, uint32_t bucket, uint32_t idx, uint32_t pos) {
+  bucket = bucket >= tc.max_bucket ? tc.max_bucket : bucket;
+  return ((uint64_t)bucket << (2 * tc.idx_bits)) | ((uint64_t)idx << tc.idx_bits) | (uint64_t)pos;
+}
 __device__ __forceinline__ uint32_t key_pos(const TraceCtx& tc, uint64_t k) {
   return (uint32_t)(k & ((1ull << tc.idx_bits) - 1));
 }
@@ -233,7 +237,7 @@ __device__ __forceinline__ bool surfel_test(const Geo& g, D3 O, D3 W, double t_m
 }
 
 // The same test straight from a record, computing the frame piecewise so
-// that few double values are live at once (the traversal's inner loop).
+// that few double values are live at once.
 __device__ __forceinline__ bool record_test(const Record& r, D3 O, D3 W, double t_min, double k2, double& t) {
   if (!(r.p_sigma.w > 0.0f)) return false;
   double w = r.q.x, x = r.q.y, y = r.q.z, z = r.q.w;
@@ -251,6 +255,60 @@ __device__ __forceinline__ bool record_test(const Record& r, D3 O, D3 W, double 
   const double u = dot(yv, tu) / (double)r.s_idx.x;
   const double v = dot(yv, tv) / (double)r.s_idx.y;
   return u * u + v * v <= k2;
+}
+
+// Float32 filter for the surfel test. It evaluates the same formulas in
+// float with a bound on their distance from the double-precision values
+// (unit roundoff 2^-24 times the magnitudes involved, with a safety factor),
+// and decides only where the bound cannot change the outcome:
+//   REJECT  - the double test rejects (t <= t_min or outside the ellipse)
+//   ACCEPT  - the double test accepts, and t's bucket is known exactly
+//             (bucket_out), or at least bounded by [blo, bhi]
+//   EXACT   - undecided: run the double test
+enum { FILTER_REJECT = 0, FILTER_ACCEPT = 1, FILTER_EXACT = 2 };
+struct RayF {
+  V3 O, W;          // float copies of the ray
+  float Osum;       // |O.x| + |O.y| + |O.z|
+};
+
+__device__ __forceinline__ int record_filter(const Record& r, const RayF& rf, float t_min, float k2, float inv_dq,
+                                             uint32_t& blo, uint32_t& bhi) {
+  constexpr float U = 5.9604645e-08f;   // 2^-24
+  if (!(r.p_sigma.w > 0.0f)) return FILTER_REJECT;
+  float w = r.q.x, x = r.q.y, y = r.q.z, z = r.q.w;
+  const float iq = 1.0f / sqrtf(w * w + x * x + y * y + z * z);
+  w *= iq; x *= iq; y *= iq; z *= iq;
+  const V3 tu = v3(1.0f - 2.0f * (y * y + z * z), 2.0f * (x * y + w * z), 2.0f * (x * z - w * y));
+  const V3 tv = v3(2.0f * (x * y - w * z), 1.0f - 2.0f * (x * x + z * z), 2.0f * (y * z + w * x));
+  const V3 n = cross(tu, tv);
+  const float den = dot(rf.W, n);
+  const float aden = fabsf(den);
+  if (!(aden > 1e-3f)) return FILTER_EXACT;
+  const V3 d = v3(r.p_sigma.x - rf.O.x, r.p_sigma.y - rf.O.y, r.p_sigma.z - rf.O.z);
+  const float t = dot(d, n) / den;
+  const float mag = fabsf(r.p_sigma.x) + fabsf(r.p_sigma.y) + fabsf(r.p_sigma.z) + rf.Osum + fabsf(t);
+  const float et = 256.0f * U * mag / aden;
+  if (t + et <= t_min) return FILTER_REJECT;
+  if (t - et <= t_min) return FILTER_EXACT;
+  const V3 yv = v3(t * rf.W.x - d.x, t * rf.W.y - d.y, t * rf.W.z - d.z);
+  const float yl = fabsf(yv.x) + fabsf(yv.y) + fabsf(yv.z);
+  const float ey = 2.0f * et + 64.0f * U * (mag + yl);
+  const float su = r.s_idx.x, sv = r.s_idx.y;
+  const float u = dot(yv, tu) / su, v = dot(yv, tv) / sv;
+  const float eu = ey / su + 8.0f * U * fabsf(u), ev = ey / sv + 8.0f * U * fabsf(v);
+  const float q2 = u * u + v * v;
+  const float eq = 2.0f * (fabsf(u) * eu + fabsf(v) * ev) + eu * eu + ev * ev + 16.0f * U * q2;
+  if (q2 - eq > k2) return FILTER_REJECT;
+  if (q2 + eq > k2) return FILTER_EXACT;
+  if (inv_dq > 0.0f) {
+    // widened by half the bound so that rounding of t -+ et cannot cross a bucket edge
+    const float lo = floorf((t - 1.5f * et) * inv_dq), hi = floorf((t + 1.5f * et) * inv_dq);
+    if (!(lo >= 0.0f) || hi >= 4.0e9f) return FILTER_EXACT;
+    blo = (uint32_t)lo;
+    bhi = (uint32_t)hi;
+    return FILTER_ACCEPT;
+  }
+  return FILTER_EXACT;
 }
 
 // ---------------------------------------------------------------------------
@@ -294,6 +352,7 @@ struct NoHit {
 // deeper entries (rare) spill to a private array.
 constexpr int STACK_LDS = 24;
 constexpr int TRACE_BLOCK = 256;   // every tracing kernel runs 256-thread blocks
+constexpr int PEND = 8;            // postponed leaves per lane
 
 struct TravStack {
   int* lds;        // this lane's column: lds[i * TRACE_BLOCK]
@@ -334,8 +393,10 @@ template <int QMODE, bool DACC, class HitFn>
 __device__ SegOut trace_segment_cb(const TraceCtx& tc, D3 O, D3 W, HitFn& on_hit, int32_t* hit_out = nullptr,
                                    int max_hits = 0) {
   __shared__ int s_stack[STACK_LDS * TRACE_BLOCK];
+  __shared__ int s_pend[PEND * TRACE_BLOCK];
   TravStack st;
   st.lds = s_stack + threadIdx.x;
+  int* pend = s_pend + threadIdx.x;   // this lane's queue of postponed leaves
   SegOut o;
   o.N = d3(0.0, 0.0, 0.0);
   o.D = 0.0;
@@ -355,6 +416,11 @@ __device__ SegOut trace_segment_cb(const TraceCtx& tc, D3 O, D3 W, HitFn& on_hit
   bool have_last = false;
   float t_floor = 0.0f;         // boxes ending before this cannot hold a key > last
   bool done = false;
+  RayF rf;
+  rf.O = Of;
+  rf.W = v3(wx, wy, wz);
+  rf.Osum = fabsf(Of.x) + fabsf(Of.y) + fabsf(Of.z);
+  const float tmin_f = (float)tc.t_min, k2_f = (float)tc.k2, inv_dq_f = (float)tc.inv_dq;
   while (!done) {
     uint64_t kk[KBUF];
 #pragma unroll
@@ -362,61 +428,81 @@ __device__ SegOut trace_segment_cb(const TraceCtx& tc, D3 O, D3 W, HitFn& on_hit
     int cnt = 0;
     float t_cut = __builtin_inff();   // boxes entered after this cannot hold a key < kk[KBUF-1]
     const float tlo0 = fmaxf((float)tc.t_min, t_floor) * 0.99999f - 1e-6f;
+    // Two phases, so that the costly surfel test runs for many lanes at
+    // once: (1) visit internal nodes, postponing every leaf the ray reaches
+    // into a per-lane queue, until the queue is nearly full, the lane's
+    // traversal ends, or every lane of the wave has a leaf waiting; (2) test
+    // the queued leaves. Repeat until the stack and the queue are empty.
     st.sp = 0;
     int ref = tc.root;
+    int np = 0;
+    bool trav = ref >= 0;
+    if (!trav) pend[0] = ~ref, np = 1;   // the whole scene is one surfel
     while (true) {
-      if (ref >= 0) {
+      while (trav && np <= PEND - 2) {
         ++o.visits;
         const Node nd = tc.nodes[ref];
         const float e0 = slab(nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y, Of, iW, tlo0, t_cut);
         const float e1 = slab(nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w, Of, iW, tlo0, t_cut);
         const int c0 = nd.d.x, c1 = nd.d.y;
-        // leaf children are tested right away
-#pragma unroll
-        for (int side = 0; side < 2; ++side) {
-          const int c = side ? c1 : c0;
-          const float e = side ? e1 : e0;
-          if (c < 0 && e < __builtin_inff()) {
-            const uint32_t pos = (uint32_t)(~c);
-            const Record r = load_record(tc.recs, pos);
-            double t;
-            ++o.tests;
-            if (record_test(r, O, W, tc.t_min, tc.k2, t)) {
-              const uint64_t key = make_key(tc, t, rec_index(r), pos);
-              if ((!have_last || key > last) && key < kk[KBUF - 1]) {
-                kbuf_insert(kk, key);
-                if (++cnt >= KBUF) {
-                  cnt = KBUF;
-                  t_cut = key_thi(tc, kk[KBUF - 1]) * 1.000002f + 1e-6f;
-                }
-              }
-            }
-          }
-        }
         // a missed box reports +inf, which must not pass an infinite cut
-        const bool h0 = c0 >= 0 && e0 < __builtin_inff() && e0 <= t_cut;
-        const bool h1 = c1 >= 0 && e1 < __builtin_inff() && e1 <= t_cut;
+        const bool m0 = e0 < __builtin_inff() && e0 <= t_cut;
+        const bool m1 = e1 < __builtin_inff() && e1 <= t_cut;
+        if (c0 < 0 && m0) pend[(np++) * TRACE_BLOCK] = ~c0;
+        if (c1 < 0 && m1) pend[(np++) * TRACE_BLOCK] = ~c1;
+        const bool h0 = c0 >= 0 && m0;
+        const bool h1 = c1 >= 0 && m1;
         if (h0 && h1) {
           const bool first0 = e0 <= e1;
           st.push(first0 ? c1 : c0);
           ref = first0 ? c0 : c1;
-          continue;
+        } else if (h0) {
+          ref = c0;
+        } else if (h1) {
+          ref = c1;
+        } else if (st.sp > 0) {
+          ref = st.pop();
+        } else {
+          trav = false;
         }
-        if (h0) { ref = c0; continue; }
-        if (h1) { ref = c1; continue; }
-      } else {
-        // the whole scene is one surfel
-        const uint32_t pos = (uint32_t)(~ref);
+        if (__all(np > 0 || !trav)) break;
+      }
+      while (np > 0) {
+        const uint32_t pos = (uint32_t)pend[(--np) * TRACE_BLOCK];
         const Record r = load_record(tc.recs, pos);
-        double t;
         ++o.tests;
-        if (record_test(r, O, W, tc.t_min, tc.k2, t)) {
-          const uint64_t key = make_key(tc, t, rec_index(r), pos);
-          if (!have_last || key > last) { kk[0] = key; cnt = 1; }
+        uint32_t blo = 0, bhi = 0;
+        const int fr = record_filter(r, rf, tmin_f, k2_f, inv_dq_f, blo, bhi);
+        if (fr == FILTER_REJECT) continue;
+        uint64_t key;
+        if (fr == FILTER_ACCEPT) {
+          // whole-bucket bounds decide most keys without the exact distance
+          const uint64_t klo = make_key_b(tc, blo, 0u, 0u), khi = make_key_b(tc, bhi + 1u, 0u, 0u);
+          if (have_last && khi <= last) continue;
+          if (klo >= kk[KBUF - 1]) continue;
+          if (blo == bhi) {
+            key = make_key_b(tc, blo, rec_index(r), pos);
+          } else {
+            double t;
+            record_test(r, O, W, -1e300, 1e300, t);
+            key = make_key(tc, t, rec_index(r), pos);
+          }
+        } else {
+          double t;
+          if (!record_test(r, O, W, tc.t_min, tc.k2, t)) continue;
+          key = make_key(tc, t, rec_index(r), pos);
+        }
+        {
+          if ((!have_last || key > last) && key < kk[KBUF - 1]) {
+            kbuf_insert(kk, key);
+            if (++cnt >= KBUF) {
+              cnt = KBUF;
+              t_cut = key_thi(tc, kk[KBUF - 1]) * 1.000002f + 1e-6f;
+            }
+          }
         }
       }
-      if (st.sp == 0) break;
-      ref = st.pop();
+      if (!trav) break;
     }
     ++o.rounds;
 
