@@ -74,6 +74,18 @@ def cpu_baseline(scene, cam, params, budget_paths=96):
                       f"{wall:.1f} s wall on {cores} processes"}
 
 
+def copy_calibration(torch, mib):
+    """A plain device copy (read n bytes, write n bytes) through torch's
+    elementwise kernel, to scale the HBM byte counters of the other kernels."""
+    n = mib * (1 << 20) // 4
+    a = torch.rand(n, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        torch.neg(a, out=b)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_each_way": n * 4, "launches": 3}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -82,6 +94,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--surfels", type=int, default=1_000_000)
     ap.add_argument("--spp", type=int, default=None, help="override the workload's 64 spp (diagnostics only)")
+    ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
+                    help="only run an elementwise copy of MIB MiB three times (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
@@ -89,6 +103,10 @@ def main():
         sys.exit(2)
 
     import torch
+
+    if args.copy_calib:
+        copy_calibration(torch, args.copy_calib)
+        return
 
     import scenegen as sg
     from paper_2601_23065_amd.api import BVH, Params, Scene, path_trace, path_trace_workspace, resolve

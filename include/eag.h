@@ -124,7 +124,8 @@ void eag_default_params(eag_trace_params* p);
 
 /* ------------------------------------------------------------------------
  * Acceleration structure: a linear BVH over the surfels' k_sigma ellipse
- * bounds (63-bit Morton order, Karras hierarchy). The paper's implementation
+ * bounds (63-bit Morton order, Karras hierarchy), collapsed into a 4-wide
+ * tree for traversal. The paper's implementation
  * uses an OptiX acceleration structure (Sec. 5 "Implementation Details");
  * gfx950 has no ray-tracing units, so this one is built and traversed by
  * hand-written kernels.
@@ -144,8 +145,13 @@ typedef struct {
   const void* nodes;         /* device: (n-1) internal nodes, 64 B each:  */
                              /*   float lo0[3], hi0[3], lo1[3], hi1[3]; int32 child0, child1, pad[2] */
                              /*   child >= 0: internal node, child < 0: leaf at sorted position ~child */
-  const void* records;       /* device: n geometry records, 64 B each, in sorted (Morton) order */
+  const void* records;       /* device: n geometry records, 48 B each, in sorted (Morton) order */
   const int32_t* perm;       /* device [n]: sorted position -> surfel index */
+  const void* nodes4;        /* device: the 4-wide tree traversed by the tracer, 128 B per node: */
+                             /*   float box[4][6] (lo.xyz hi.xyz); int32 ref[4] (>= 0 node, < 0 leaf ~pos, */
+                             /*   0x7fffffff empty); int32 src[4] (binary-tree origin of each child) */
+  int32_t n_nodes4;          /* nodes in nodes4; node 0 is the root */
+  int32_t depth4;            /* levels of the 4-wide tree */
 } eag_bvh_info;
 
 size_t eag_bvh_bytes(int64_t n);

@@ -44,7 +44,8 @@ class TraceParams(C.Structure):
 
 class BvhInfo(C.Structure):
     _fields_ = [("n", C.c_int64), ("max_depth", C.c_int32), ("root", C.c_int32), ("lo", C.c_float * 3),
-                ("hi", C.c_float * 3), ("nodes", vp), ("records", vp), ("perm", vp)]
+                ("hi", C.c_float * 3), ("nodes", vp), ("records", vp), ("perm", vp), ("nodes4", vp),
+                ("n_nodes4", C.c_int32), ("depth4", C.c_int32)]
 
 
 class Edit(C.Structure):

@@ -85,7 +85,7 @@ TraceSetup trace_setup(const eag_bvh* b, const eag_trace_params* p, float t_max_
       fail(EAG_ERR_INVALID_ARGUMENT, "scene too deep for the order key at this depth_quantum and surfel count "
                                      "(raise depth_quantum)");
   }
-  if (b->max_depth > STACK_SIZE) fail(EAG_ERR_INTERNAL, "BVH deeper than the traversal stack");
+  if (3 * b->depth4 > STACK_SIZE) fail(EAG_ERR_INTERNAL, "BVH deeper than the traversal stack");
   return ts;
 }
 
@@ -236,6 +236,7 @@ eag_status eag_build_bvh(const eag_surfels* s, void* bvh_mem, size_t bvh_bytes, 
     b->mem_bytes = bvh_bytes;
     b->hdr = l.hdr;
     b->nodes = l.nodes;
+    b->nodes4 = l.nodes4;
     b->recs = l.recs;
     b->perm = l.perm;
     b->leaf_parent = l.leaf_parent;
@@ -246,7 +247,7 @@ eag_status eag_build_bvh(const eag_surfels* s, void* bvh_mem, size_t bvh_bytes, 
       delete b;
       throw;
     }
-    if (b->max_depth > STACK_SIZE) {
+    if (3 * b->depth4 > STACK_SIZE) {
       delete b;
       fail(EAG_ERR_INTERNAL, "BVH deeper than the traversal stack");
     }
@@ -275,6 +276,9 @@ eag_status eag_bvh_get_info(const eag_bvh* b, eag_bvh_info* out) {
     out->nodes = b->nodes;
     out->records = b->recs;
     out->perm = b->perm;
+    out->nodes4 = b->nodes4;
+    out->n_nodes4 = b->n_nodes4;
+    out->depth4 = b->depth4;
   });
 }
 

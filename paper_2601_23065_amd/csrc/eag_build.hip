@@ -15,6 +15,8 @@
 #include "eag_device.h"
 #include "eag_internal.h"
 
+#include <algorithm>
+
 namespace eag {
 
 namespace {
@@ -51,7 +53,11 @@ __global__ void k_init_header(BvhHeader* h) {
     h->blo[threadIdx.x] = 0xffffffffu;
     h->bhi[threadIdx.x] = 0u;
   }
-  if (threadIdx.x == 0) h->max_depth = 0;
+  if (threadIdx.x == 0) {
+    h->max_depth = 0;
+    h->n_nodes4 = 0;
+    h->depth4 = 0;
+  }
 }
 
 // Box of the k_sigma ellipse: half extent along axis a is
@@ -264,9 +270,155 @@ __global__ void k_attrs(eag_surfels s, const int32_t* perm, Attr* attrs) {
   a[1] = make_float4(s.radiance[i], s.radiance[n + i], s.radiance[2 * n + i], 0.0f);
 }
 
+// ---------------------------------------------------------------------------
+// Collapse of the binary tree into a 4-wide tree, level by level. A queue
+// entry (binary internal node b, 4-wide node m) expands b's two children;
+// while fewer than four children are held and one of them is an internal
+// binary node, the internal child with the largest box surface area is
+// replaced by its two children. Internal children left over become 4-wide
+// nodes of the next level.
+// ---------------------------------------------------------------------------
+struct Collapse {
+  int2* q[2];         // ping-pong queues of (binary node, 4-wide node)
+  int32_t* counts;    // counts[l] = entries of level l; counts[MAXL] = nodes allocated
+};
+constexpr int COLLAPSE_MAXL = 128;
+
+__device__ __forceinline__ void child_box(const Node& nd, int slot, float* lo, float* hi) {
+  const float* f = reinterpret_cast<const float*>(&nd);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = f[slot * 6 + a];
+    hi[a] = f[slot * 6 + 3 + a];
+  }
+}
+
+__device__ __forceinline__ float half_area(const float* lo, const float* hi) {
+  const float dx = hi[0] - lo[0], dy = hi[1] - lo[1], dz = hi[2] - lo[2];
+  return dx * dy + dy * dz + dz * dx;
+}
+
+__global__ void k_collapse_init(int32_t* counts, int2* q0) {
+  const int i = threadIdx.x;
+  for (int k = i; k <= COLLAPSE_MAXL; k += blockDim.x) counts[k] = 0;
+  if (i == 0) {
+    q0[0] = make_int2(0, 0);
+  }
+  __syncthreads();
+  if (i == 0) {
+    counts[0] = 1;
+    counts[COLLAPSE_MAXL] = 1;   // node 0 is the root
+  }
+}
+
+__global__ void k_collapse_level(const Node* bin, Node4* out, Collapse cq, int level) {
+  const int count = cq.counts[level];
+  const int2* qin = cq.q[level & 1];
+  int2* qout = cq.q[(level + 1) & 1];
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < count; e += gridDim.x * blockDim.x) {
+    const int2 job = qin[e];
+    int ref[4];
+    float lo[4][3], hi[4][3];
+    int cnt = 2;
+    ref[0] = bin[job.x].d.x;
+    ref[1] = bin[job.x].d.y;
+    child_box(bin[job.x], 0, lo[0], hi[0]);
+    child_box(bin[job.x], 1, lo[1], hi[1]);
+    while (cnt < 4) {
+      int best = -1;
+      float area = -1.0f;
+      for (int k = 0; k < cnt; ++k) {
+        if (ref[k] >= 0) {
+          const float a = half_area(lo[k], hi[k]);
+          if (a > area) { area = a; best = k; }
+        }
+      }
+      if (best < 0) break;
+      const Node& nb = bin[ref[best]];
+      ref[cnt] = nb.d.y;
+      child_box(nb, 1, lo[cnt], hi[cnt]);
+      ref[best] = nb.d.x;
+      child_box(nb, 0, lo[best], hi[best]);
+      ++cnt;
+    }
+    Node4& m = out[job.y];
+    float* bf = reinterpret_cast<float*>(m.b);
+    int dst[4], src[4];
+    for (int k = 0; k < 4; ++k) {
+      if (k < cnt) {
+        for (int a = 0; a < 3; ++a) {
+          bf[k * 6 + a] = lo[k][a];
+          bf[k * 6 + 3 + a] = hi[k][a];
+        }
+        src[k] = ref[k];
+        if (ref[k] >= 0) {
+          const int id = atomicAdd(&cq.counts[COLLAPSE_MAXL], 1);
+          const int slot = atomicAdd(&cq.counts[level + 1], 1);
+          qout[slot] = make_int2(ref[k], id);
+          dst[k] = id;
+        } else {
+          dst[k] = ref[k];
+        }
+      } else {
+        for (int a = 0; a < 6; ++a) bf[k * 6 + a] = 0.0f;
+        src[k] = NODE4_EMPTY;
+        dst[k] = NODE4_EMPTY;
+      }
+    }
+    m.ref = make_int4(dst[0], dst[1], dst[2], dst[3]);
+    m.src = make_int4(src[0], src[1], src[2], src[3]);
+  }
+}
+
+// Refit of 4-wide boxes from the binary tree (internal children) and the
+// surfel boxes (leaves).
+__global__ void k_node4_boxes(const Node* bin, Node4* out, int n4, const float* box, const int32_t* perm,
+                              int64_t n) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= n4) return;
+  Node4& nd = out[m];
+  const int s[4] = {nd.src.x, nd.src.y, nd.src.z, nd.src.w};
+  float* bf = reinterpret_cast<float*>(nd.b);
+  for (int k = 0; k < 4; ++k) {
+    if (s[k] == NODE4_EMPTY) continue;
+    float lo[3], hi[3];
+    if (s[k] >= 0) {
+      float l2[3], h2[3];
+      child_box(bin[s[k]], 0, lo, hi);
+      child_box(bin[s[k]], 1, l2, h2);
+      for (int a = 0; a < 3; ++a) {
+        lo[a] = fminf(lo[a], l2[a]);
+        hi[a] = fmaxf(hi[a], h2[a]);
+      }
+    } else {
+      const int64_t i = perm[~s[k]];
+      for (int a = 0; a < 3; ++a) {
+        lo[a] = box[a * n + i];
+        hi[a] = box[(3 + a) * n + i];
+      }
+    }
+    for (int a = 0; a < 3; ++a) {
+      bf[k * 6 + a] = lo[a];
+      bf[k * 6 + 3 + a] = hi[a];
+    }
+  }
+}
+
+__global__ void k_collapse_finish(const int32_t* counts, BvhHeader* h) {
+  if (threadIdx.x == 0) {
+    h->n_nodes4 = counts[COLLAPSE_MAXL];
+    int l = 0;
+    while (l < COLLAPSE_MAXL && counts[l] > 0) ++l;
+    h->depth4 = l;
+  }
+}
+
 inline unsigned blocks(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
 
 struct BuildWs {
+  int2* q0;
+  int2* q1;
+  int32_t* counts;
   float* box;
   uint64_t* codes_in;
   uint64_t* codes_out;
@@ -288,6 +440,9 @@ size_t sort_tmp_bytes(int64_t n) {
 BuildWs build_ws(void* base, int64_t n) {
   Carver c(base, ~size_t(0));
   BuildWs w;
+  w.q0 = c.take<int2>(n);
+  w.q1 = c.take<int2>(n);
+  w.counts = c.take<int32_t>(COLLAPSE_MAXL + 1);
   w.box = c.take<float>(6 * n);
   w.codes_in = c.take<uint64_t>(n);
   w.codes_out = c.take<uint64_t>(n);
@@ -308,6 +463,8 @@ void read_back(eag_bvh* b, hipStream_t st) {
     b->hi[a] = fdec(h.bhi[a]);
   }
   b->max_depth = h.max_depth;
+  b->n_nodes4 = h.n_nodes4;
+  b->depth4 = h.depth4;
 }
 
 }  // namespace
@@ -317,6 +474,7 @@ BvhLayout bvh_layout(void* base, int64_t n) {
   BvhLayout l;
   l.hdr = c.take<BvhHeader>(1);
   l.nodes = c.take<Node>(n > 1 ? n - 1 : 1);
+  l.nodes4 = c.take<Node4>(n > 1 ? n - 1 : 1);
   l.recs = c.take<Record>(n);
   l.perm = c.take<int32_t>(n);
   l.leaf_parent = c.take<int32_t>(n);
@@ -366,6 +524,17 @@ void build_bvh(const eag_surfels* s, eag_bvh* b, void* ws, size_t ws_bytes, hipS
   check_hip(hipGetLastError(), "build launch");
   b->root = n > 1 ? 0 : ~0;
   read_back(b, st);
+  if (n > 1) {
+    if (b->max_depth >= COLLAPSE_MAXL) fail(EAG_ERR_INTERNAL, "binary tree too deep to collapse");
+    Collapse cq{{w.q0, w.q1}, w.counts};
+    hipLaunchKernelGGL(k_collapse_init, dim3(1), dim3(256), 0, st, w.counts, w.q0);
+    const unsigned g = std::min<unsigned>(blocks(n), 1024u);
+    for (int level = 0; level < b->max_depth; ++level)
+      hipLaunchKernelGGL(k_collapse_level, dim3(g), dim3(256), 0, st, b->nodes, b->nodes4, cq, level);
+    hipLaunchKernelGGL(k_collapse_finish, dim3(1), dim3(64), 0, st, w.counts, b->hdr);
+    check_hip(hipGetLastError(), "collapse launch");
+    read_back(b, st);
+  }
 }
 
 void refit_bvh(const eag_surfels* s, eag_bvh* b, void* ws, size_t ws_bytes, hipStream_t st) {
@@ -381,11 +550,15 @@ void refit_bvh(const eag_surfels* s, eag_bvh* b, void* ws, size_t ws_bytes, hipS
     hipLaunchKernelGGL(k_zero_i32, dim3(blocks(n)), dim3(256), 0, st, w.visits, n);
     hipLaunchKernelGGL(k_bottom_up, dim3(blocks(n)), dim3(256), 0, st, n, w.box, b->perm, b->nodes,
                        b->leaf_parent, b->node_parent, w.visits);
+    hipLaunchKernelGGL(k_node4_boxes, dim3(blocks(b->n_nodes4)), dim3(256), 0, st, b->nodes, b->nodes4,
+                       b->n_nodes4, w.box, b->perm, n);
   }
   check_hip(hipGetLastError(), "refit launch");
-  const int32_t depth = b->max_depth;
+  const int32_t depth = b->max_depth, n4 = b->n_nodes4, d4 = b->depth4;
   read_back(b, st);
   b->max_depth = depth;
+  b->n_nodes4 = n4;
+  b->depth4 = d4;
 }
 
 void pack_attrs(const eag_surfels* s, const eag_bvh* b, Attr* attrs, hipStream_t st) {

@@ -27,6 +27,18 @@ struct __align__(16) Node {
   int4 d;     // child0 child1 - -
 };
 
+// 4-wide node, 128 B, collapsed from the binary tree: child k's box is
+// floats [6k, 6k+6) of b (lo.xyz, hi.xyz); ref.k >= 0 is a 4-wide node,
+// ref.k < 0 a leaf holding the surfel at sorted position ~ref.k, and
+// NODE4_EMPTY an unused slot. src.k is the binary-tree reference the child
+// came from (used to refit boxes).
+constexpr int NODE4_EMPTY = 0x7fffffff;
+struct __align__(16) Node4 {
+  float4 b[6];
+  int4 ref;
+  int4 src;
+};
+
 // Geometry record of one surfel in sorted order, 48 B (three float4 loads):
 //   p.x p.y p.z sigma | q.w q.x q.y q.z | s_u s_v index -
 // with q the caller's (unnormalised) quaternion and index the original surfel
@@ -132,7 +144,7 @@ __device__ __forceinline__ D3 cosine_dir(D3 n, double u0, double u1) {
 // record directly.
 // ---------------------------------------------------------------------------
 struct TraceCtx {
-  const Node* nodes;
+  const Node4* nodes;
   const Record* recs;
   const Attr* attrs;
   int32_t root;            // >= 0: internal node index; < 0: single leaf ~root
@@ -439,27 +451,45 @@ __device__ SegOut trace_segment_cb(const TraceCtx& tc, D3 O, D3 W, HitFn& on_hit
     bool trav = ref >= 0;
     if (!trav) pend[0] = ~ref, np = 1;   // the whole scene is one surfel
     while (true) {
-      while (trav && np <= PEND - 2) {
+      while (trav && np <= PEND - 4) {
         ++o.visits;
-        const Node nd = tc.nodes[ref];
-        const float e0 = slab(nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y, Of, iW, tlo0, t_cut);
-        const float e1 = slab(nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w, Of, iW, tlo0, t_cut);
-        const int c0 = nd.d.x, c1 = nd.d.y;
-        // a missed box reports +inf, which must not pass an infinite cut
-        const bool m0 = e0 < __builtin_inff() && e0 <= t_cut;
-        const bool m1 = e1 < __builtin_inff() && e1 <= t_cut;
-        if (c0 < 0 && m0) pend[(np++) * TRACE_BLOCK] = ~c0;
-        if (c1 < 0 && m1) pend[(np++) * TRACE_BLOCK] = ~c1;
-        const bool h0 = c0 >= 0 && m0;
-        const bool h1 = c1 >= 0 && m1;
-        if (h0 && h1) {
-          const bool first0 = e0 <= e1;
-          st.push(first0 ? c1 : c0);
-          ref = first0 ? c0 : c1;
-        } else if (h0) {
-          ref = c0;
-        } else if (h1) {
-          ref = c1;
+        const Node4* nd = tc.nodes + ref;
+        const int4 cr = nd->ref;
+        const float4* bb = nd->b;
+        const float4 b0 = bb[0], b1 = bb[1], b2 = bb[2], b3 = bb[3], b4 = bb[4], b5 = bb[5];
+        float e[4];
+        e[0] = slab(b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, Of, iW, tlo0, t_cut);
+        e[1] = slab(b1.z, b1.w, b2.x, b2.y, b2.z, b2.w, Of, iW, tlo0, t_cut);
+        e[2] = slab(b3.x, b3.y, b3.z, b3.w, b4.x, b4.y, Of, iW, tlo0, t_cut);
+        e[3] = slab(b4.z, b4.w, b5.x, b5.y, b5.z, b5.w, Of, iW, tlo0, t_cut);
+        const int c[4] = {cr.x, cr.y, cr.z, cr.w};
+        // children reached: leaves are queued, internal nodes kept with their entry
+        float ie[4];
+        int ic[4];
+        int ni = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          // a missed box reports +inf, which must not pass an infinite cut
+          const bool m = c[k] != NODE4_EMPTY && e[k] < __builtin_inff() && e[k] <= t_cut;
+          if (m && c[k] < 0) pend[(np++) * TRACE_BLOCK] = ~c[k];
+          ie[k] = (m && c[k] >= 0) ? e[k] : __builtin_inff();
+          ic[k] = c[k];
+          ni += (m && c[k] >= 0) ? 1 : 0;
+        }
+        if (ni > 0) {
+          // sort the four (entry, child) pairs by entry, misses (+inf) last
+#define EAG_CSWAP(i, j)                                        \
+          if (ie[j] < ie[i]) {                                 \
+            const float tf = ie[i]; ie[i] = ie[j]; ie[j] = tf; \
+            const int tc_ = ic[i]; ic[i] = ic[j]; ic[j] = tc_; \
+          }
+          EAG_CSWAP(0, 1) EAG_CSWAP(2, 3) EAG_CSWAP(0, 2) EAG_CSWAP(1, 3) EAG_CSWAP(1, 2)
+#undef EAG_CSWAP
+          // visit the nearest; push the others farthest first
+          if (ni > 3) st.push(ic[3]);
+          if (ni > 2) st.push(ic[2]);
+          if (ni > 1) st.push(ic[1]);
+          ref = ic[0];
         } else if (st.sp > 0) {
           ref = st.pop();
         } else {

@@ -13,6 +13,7 @@
 namespace eag {
 
 struct Node;
+struct Node4;
 struct Record;
 struct Attr;
 struct CamDev;
@@ -48,7 +49,9 @@ struct BvhHeader {
   uint32_t plo[3], phi[3];   // ordered-uint encoded centre bounds (Morton frame)
   uint32_t blo[3], bhi[3];   // ordered-uint encoded box bounds
   int32_t max_depth;
-  int32_t pad[3];
+  int32_t n_nodes4;     // 4-wide nodes written by the collapse
+  int32_t depth4;       // levels of the 4-wide tree
+  int32_t pad;
 };
 
 }  // namespace eag
@@ -63,6 +66,9 @@ struct eag_bvh {
   size_t mem_bytes;
   eag::BvhHeader* hdr;
   eag::Node* nodes;
+  eag::Node4* nodes4;
+  int32_t n_nodes4;
+  int32_t depth4;
   eag::Record* recs;
   int32_t* perm;
   int32_t* leaf_parent;
@@ -75,6 +81,7 @@ namespace eag {
 struct BvhLayout {
   BvhHeader* hdr;
   Node* nodes;
+  Node4* nodes4;
   Record* recs;
   int32_t* perm;
   int32_t* leaf_parent;

@@ -44,7 +44,7 @@ __global__ void __launch_bounds__(256) k_trace_rays(TraceCtx tc, int64_t n_rays,
 
 TraceCtx make_ctx(const eag_bvh* b, const Attr* attrs, const eag_trace_params* p, const TraceSetup& ts) {
   TraceCtx tc;
-  tc.nodes = b->nodes;
+  tc.nodes = b->nodes4;
   tc.recs = b->recs;
   tc.attrs = attrs;
   tc.root = b->root;

@@ -62,6 +62,49 @@ def test_bvh_invariants(which):
     assert np.all(lo <= scene.pos.min(axis=1)) and np.all(hi >= scene.pos.max(axis=1))
 
 
+@pytest.mark.parametrize("which", ["cloud", "room"])
+def test_bvh4_invariants(which):
+    """The 4-wide tree the tracer walks: every surfel in exactly one leaf slot,
+    every child box inside its parent's box and containing its surfel's centre,
+    and the reported depth."""
+    from paper_2601_23065_amd.api import BVH
+    scene = sg.cloud_scene(2000, seed=1) if which == "cloud" else sg.room_scene(30000, (4.0, 3.0, 2.5), 5, seed=8)
+    gs = gpu_scene(scene)
+    bvh = BVH(gs)
+    n = scene.n
+    info = bvh.info()
+    m = info.n_nodes4
+    assert 1 <= m <= n - 1
+    raw = _slice(bvh.mem, info.nodes4, m * 128).view(np.int32).reshape(m, 32)
+    boxes = raw[:, :24].view(np.float32).reshape(m, 4, 6)
+    refs = raw[:, 24:28]
+    perm = _slice(bvh.mem, info.perm, n * 4).view(np.int32)
+    seen = np.zeros(n, dtype=np.int64)
+    visited = np.zeros(m, dtype=np.int64)
+    depth = 0
+    stack = [(0, 1, None)]
+    while stack:
+        i, d, pbox = stack.pop()
+        visited[i] += 1
+        depth = max(depth, d)
+        for k in range(4):
+            r = int(refs[i, k])
+            if r == 0x7FFFFFFF:
+                continue
+            b = boxes[i, k]
+            assert np.all(b[:3] <= b[3:])
+            if pbox is not None:
+                assert np.all(b[:3] >= pbox[:3]) and np.all(b[3:] <= pbox[3:])
+            if r >= 0:
+                stack.append((r, d + 1, b))
+            else:
+                seen[~r] += 1
+                p = scene.pos[:, int(perm[~r])].astype(np.float64)
+                assert np.all(b[:3] < p) and np.all(p < b[3:])
+    assert np.all(seen == 1) and np.all(visited == 1)
+    assert info.depth4 == depth
+
+
 def test_single_surfel_scene():
     from paper_2601_23065_amd.api import BVH, Params, trace_rays
     s = sg.cloud_scene(1, seed=3)
