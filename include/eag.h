@@ -238,6 +238,10 @@ eag_status eag_single_bounce_backward(const eag_bvh* bvh, const eag_surfels* s, 
  * k-buffer rounds, candidate surfel tests, blended hits, BVH nodes visited}.
  * ------------------------------------------------------------------------ */
 #define EAG_ACCUM_SCALE 4294967296.0 /* 2^32 */
+/* Workspace of eag_path_trace: packed attributes (32 B per surfel), a work
+ * counter, and a hit list of 1 KiB per lane of the persistent grid, which
+ * depends on the current device (256 CUs x 512 lanes on MI355X: 128 MiB).
+ * Returns 0 and sets the last error if the device cannot be queried. */
 size_t eag_path_trace_workspace_bytes(int64_t n_surfels);
 eag_status eag_path_trace(const eag_bvh* bvh, const eag_surfels* s, const eag_camera* cam,
                           const eag_trace_params* p, uint32_t sample_begin, uint32_t sample_count,
@@ -299,7 +303,10 @@ typedef struct {
   double t_submit, t_admit, t_done;   /* seconds, host monotonic clock           */
   uint64_t paths;
 } eag_result;
-/* Bytes of arena needed for a scene of n surfels with `versions` attribute versions. */
+/* Bytes of arena needed for a scene of n surfels with `versions` attribute
+ * versions, on the current device (the arena holds the path tracer's hit
+ * list, whose size depends on the device; 0 and the last error if it cannot
+ * be queried). */
 size_t eag_serve_arena_bytes(int64_t n, int32_t versions, size_t request_bytes);
 /* Copies the scene into the arena and builds the BVH (synchronous). */
 eag_status eag_serve_create(const eag_surfels* s, const eag_server_config* cfg, eag_server** out);

@@ -155,10 +155,11 @@ struct RenderWs {
   float* adj;                 // per-sample dL/dX, dL/dNt of the adjoint
   double* gacc;               // double gradient accumulators of the adjoint
   unsigned long long* work;
+  uint64_t* hitlist;          // path tracing: HL_CAP keys per lane of the persistent grid
   size_t bytes;
 };
 
-RenderWs render_ws(void* base, int64_t n, int64_t n_pix, int64_t spp, bool own_state) {
+RenderWs render_ws(void* base, int64_t n, int64_t n_pix, int64_t spp, bool own_state, int64_t hl_lanes = 0) {
   Carver c(base, ~size_t(0));
   RenderWs w;
   w.attrs = c.take<Attr>(n);
@@ -167,6 +168,7 @@ RenderWs render_ws(void* base, int64_t n, int64_t n_pix, int64_t spp, bool own_s
   w.adj = own_state ? c.take<float>(n_pix * spp * 12) : nullptr;   // 6 doubles per sample
   w.gacc = own_state ? c.take<double>(grad_accum_doubles(n)) : nullptr;
   w.work = c.take<unsigned long long>(8);
+  w.hitlist = hl_lanes > 0 ? c.take<uint64_t>((size_t)hl_lanes * HL_CAP) : nullptr;
   w.bytes = c.bytes();
   return w;
 }
@@ -397,7 +399,15 @@ eag_status eag_single_bounce_backward(const eag_bvh* b, const eag_surfels* s, co
   });
 }
 
-size_t eag_path_trace_workspace_bytes(int64_t n) { return n < 1 ? 0 : render_ws(nullptr, n, 0, 0, false).bytes; }
+size_t eag_path_trace_workspace_bytes(int64_t n) {
+  if (n < 1) return 0;
+  try {
+    return render_ws(nullptr, n, 0, 0, false, pt_lanes()).bytes;
+  } catch (const Error& e) {
+    set_error(e.status, e.msg);
+    return 0;
+  }
+}
 
 eag_status eag_path_trace(const eag_bvh* b, const eag_surfels* s, const eag_camera* cam, const eag_trace_params* p,
                           uint32_t sample_begin, uint32_t sample_count, int64_t* accum, uint64_t* counters, void* ws,
@@ -407,7 +417,7 @@ eag_status eag_path_trace(const eag_bvh* b, const eag_surfels* s, const eag_came
     validate_params(p);
     if (!cam || !accum) fail(EAG_ERR_INVALID_ARGUMENT, "null argument");
     if ((uint64_t)sample_begin + sample_count > 0xffffffffull) fail(EAG_ERR_INVALID_ARGUMENT, "sample range overflow");
-    const RenderWs w = render_ws(ws, b->n, 0, 0, false);
+    const RenderWs w = render_ws(ws, b->n, 0, 0, false, pt_lanes());
     if (!ws || ws_bytes < w.bytes) fail(EAG_ERR_WORKSPACE_TOO_SMALL, "path-trace workspace too small");
     const CamDev cd = make_cam(*cam, p->camera_id);
     const TraceSetup ts = trace_setup(b, p, std::fmax(scene_t_max(b), camera_t_max(b, *cam)));
@@ -434,7 +444,7 @@ eag_status eag_path_trace(const eag_bvh* b, const eag_surfels* s, const eag_came
     S.tau_E = p->tau_E;
     L.n_slots = 1;
     L.n_work = S.global_end;
-    launch_path_trace(tc, L, w.work, reinterpret_cast<unsigned long long*>(counters), st);
+    launch_path_trace(tc, L, w.work, reinterpret_cast<unsigned long long*>(counters), w.hitlist, st);
   });
 }
 

@@ -154,7 +154,14 @@ struct TraceCtx {
   double t_min;
   double k2;               // k_sigma^2
   double T_min;
+  // Optional per-lane hit list (null: off). Entry j of this lane is
+  // hl[j * HL_STRIDE]; lanes of a wave interleave so that their accesses
+  // to the same entry share cache lines.
+  uint64_t* hl;
 };
+
+constexpr int HL_CAP = 128;        // entries per lane
+constexpr int HL_STRIDE = 64;      // lanes per wave
 
 __device__ __forceinline__ uint64_t make_key(const TraceCtx& tc, double t, uint32_t idx, uint32_t pos) {
   uint32_t bucket;
@@ -175,6 +182,15 @@ __device__ __forceinline__ uint32_t key_pos(const TraceCtx& tc, uint64_t k) {
 }
 __device__ __forceinline__ uint32_t key_idx(const TraceCtx& tc, uint64_t k) {
   return (uint32_t)((k >> tc.idx_bits) & ((1ull << tc.idx_bits) - 1));
+}
+__device__ __forceinline__ uint32_t key_bucket(const TraceCtx& tc, uint64_t k) {
+  return (uint32_t)(k >> (2 * tc.idx_bits));
+}
+// first key of the bucket after k's (saturating at the last bucket, which the
+// hit list then never claims to cover)
+__device__ __forceinline__ uint64_t next_bucket_key(const TraceCtx& tc, uint64_t k) {
+  const uint32_t b = key_bucket(tc, k);
+  return make_key_b(tc, b < tc.max_bucket ? b + 1u : tc.max_bucket, 0u, 0u);
 }
 // smallest t that can carry the given key's bucket (for culling)
 __device__ __forceinline__ float key_tlo(const TraceCtx& tc, uint64_t k) {
@@ -395,6 +411,16 @@ __device__ __forceinline__ void kbuf_insert(uint64_t (&kk)[KBUF], uint64_t key) 
 // Round r collects the KBUF smallest keys strictly greater than the last key
 // blended in round r-1, blends them in order, and stops the segment after the
 // first hit with T < T_min, or when a round returns fewer than KBUF hits.
+//
+// With a hit list (tc.hl), a traversal round also records every accepted key
+// whose depth bucket does not exceed that of the round's KBUF-th key. Such a
+// round has tested every surfel of those buckets (boxes are culled only
+// beyond them), so the list then holds every hit key in (last, lhi) with lhi
+// the first key of the next bucket. A later round takes its keys from the
+// list when it finds KBUF of them there, and otherwise traverses only for
+// keys >= lhi. On a surface where many coplanar surfels share one depth
+// bucket, this turns the repeated traversals of a long segment into scans
+// of a short list. If the list overflows it is dropped and rounds traverse.
 // on_hit(pos, t, alpha, w, T_before) is called for every blended hit, in
 // blending order. If hit_out is non-null, up to max_hits blended surfel
 // indices are written. Must be called from a TRACE_BLOCK-thread block.
@@ -426,8 +452,10 @@ __device__ SegOut trace_segment_cb(const TraceCtx& tc, D3 O, D3 W, HitFn& on_hit
                    1.0f / (fabsf(wz) > 1e-30f ? wz : copysignf(1e-30f, wz)));
   uint64_t last = 0;            // keys must exceed this once have_last
   bool have_last = false;
-  float t_floor = 0.0f;         // boxes ending before this cannot hold a key > last
   bool done = false;
+  uint64_t* const hl = tc.hl;
+  int nl = 0;                   // entries in the hit list
+  uint64_t lhi = 0;             // 0: list unusable; else it holds every hit key in (last, lhi)
   RayF rf;
   rf.O = Of;
   rf.W = v3(wx, wy, wz);
@@ -438,7 +466,40 @@ __device__ SegOut trace_segment_cb(const TraceCtx& tc, D3 O, D3 W, HitFn& on_hit
 #pragma unroll
     for (int j = 0; j < KBUF; ++j) kk[j] = ~0ull;
     int cnt = 0;
-    float t_cut = __builtin_inff();   // boxes entered after this cannot hold a key < kk[KBUF-1]
+    // keys taken this round must exceed `floor` (when have_floor)
+    uint64_t floor_key = last;
+    bool have_floor = have_last;
+    bool traverse = true;
+    if (lhi != 0) {
+      // keys in (last, lhi) from the list, compacted in place
+      int w = 0;
+      for (int j = 0; j < nl; ++j) {
+        const uint64_t k = hl[j * HL_STRIDE];
+        if (k > last && k < lhi) {
+          if (w != j) hl[w * HL_STRIDE] = k;
+          ++w;
+          if (k < kk[KBUF - 1]) {
+            kbuf_insert(kk, k);
+            ++cnt;
+          }
+        }
+      }
+      nl = w;
+      cnt = cnt > KBUF ? KBUF : cnt;
+      if (cnt == KBUF || lhi == ~0ull) {
+        traverse = false;
+      } else if (lhi - 1 > floor_key) {
+        floor_key = lhi - 1;
+        have_floor = true;
+      }
+    } else {
+      nl = 0;
+    }
+    bool over = false;            // the list overflowed this round
+    uint64_t cut_key = ~0ull;     // list entries must be below this (first key past kk[KBUF-1]'s bucket)
+    if (cnt == KBUF) cut_key = next_bucket_key(tc, kk[KBUF - 1]);
+    float t_cut = cnt == KBUF ? key_thi(tc, kk[KBUF - 1]) * 1.000002f + 1e-6f : __builtin_inff();
+    const float t_floor = have_floor ? key_tlo(tc, floor_key) : 0.0f;
     const float tlo0 = fmaxf((float)tc.t_min, t_floor) * 0.99999f - 1e-6f;
     // Two phases, so that the costly surfel test runs for many lanes at
     // once: (1) visit internal nodes, postponing every leaf the ray reaches
@@ -448,9 +509,9 @@ __device__ SegOut trace_segment_cb(const TraceCtx& tc, D3 O, D3 W, HitFn& on_hit
     st.sp = 0;
     int ref = tc.root;
     int np = 0;
-    bool trav = ref >= 0;
-    if (!trav) pend[0] = ~ref, np = 1;   // the whole scene is one surfel
-    while (true) {
+    bool trav = traverse && ref >= 0;
+    if (traverse && ref < 0) pend[0] = ~ref, np = 1;   // the whole scene is one surfel
+    while (traverse) {
       while (trav && np <= PEND - 4) {
         ++o.visits;
         const Node4* nd = tc.nodes + ref;
@@ -508,8 +569,8 @@ __device__ SegOut trace_segment_cb(const TraceCtx& tc, D3 O, D3 W, HitFn& on_hit
         if (fr == FILTER_ACCEPT) {
           // whole-bucket bounds decide most keys without the exact distance
           const uint64_t klo = make_key_b(tc, blo, 0u, 0u), khi = make_key_b(tc, bhi + 1u, 0u, 0u);
-          if (have_last && khi <= last) continue;
-          if (klo >= kk[KBUF - 1]) continue;
+          if (have_floor && khi <= floor_key) continue;
+          if (klo >= (hl ? cut_key : kk[KBUF - 1])) continue;
           if (blo == bhi) {
             key = make_key_b(tc, blo, rec_index(r), pos);
           } else {
@@ -522,18 +583,24 @@ __device__ SegOut trace_segment_cb(const TraceCtx& tc, D3 O, D3 W, HitFn& on_hit
           if (!record_test(r, O, W, tc.t_min, tc.k2, t)) continue;
           key = make_key(tc, t, rec_index(r), pos);
         }
-        {
-          if ((!have_last || key > last) && key < kk[KBUF - 1]) {
+        if (!have_floor || key > floor_key) {
+          if (hl && key < cut_key) {
+            if (nl < HL_CAP) hl[(nl++) * HL_STRIDE] = key;
+            else over = true;
+          }
+          if (key < kk[KBUF - 1]) {
             kbuf_insert(kk, key);
             if (++cnt >= KBUF) {
               cnt = KBUF;
               t_cut = key_thi(tc, kk[KBUF - 1]) * 1.000002f + 1e-6f;
+              cut_key = next_bucket_key(tc, kk[KBUF - 1]);
             }
           }
         }
       }
       if (!trav) break;
     }
+    if (hl && traverse) lhi = over ? 0ull : (cnt == KBUF ? cut_key : ~0ull);
     ++o.rounds;
 
     // blend this round's hits in key order (the buffer is shifted down one
@@ -581,7 +648,6 @@ __device__ SegOut trace_segment_cb(const TraceCtx& tc, D3 O, D3 W, HitFn& on_hit
     if (!done) {
       last = round_last;
       have_last = true;
-      t_floor = key_tlo(tc, last);
     }
   }
   o.R = d3(R0, R1, R2);

@@ -36,8 +36,11 @@ __device__ __forceinline__ void add_fixed(int64_t* acc, float v) {
 }
 
 __global__ void __launch_bounds__(256) k_path_trace(TraceCtx tc, PtLaunch L, unsigned long long* work_counter,
-                                                    unsigned long long* counters) {
+                                                    unsigned long long* counters, uint64_t* hitlist) {
   const int lane = (int)(threadIdx.x & 63);
+  uint64_t* const hl =
+      hitlist ? hitlist + ((int64_t)blockIdx.x * (TRACE_BLOCK / 64) + (threadIdx.x >> 6)) * (HL_CAP * HL_STRIDE) + lane
+              : nullptr;
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
   bool alive = false;
@@ -98,6 +101,7 @@ __global__ void __launch_bounds__(256) k_path_trace(TraceCtx tc, PtLaunch L, uns
     const PtSlot& S = L.s[slot];
     TraceCtx tcl = tc;
     tcl.attrs = S.attrs;
+    tcl.hl = hl;
     const SegOut s = trace_segment<Q_ALL>(tcl, O, Wd);
     n_rounds += s.rounds;
     n_tests += s.tests;
@@ -160,16 +164,23 @@ __global__ void k_resolve(const int64_t* accum, int64_t n, double scale, float* 
 
 }  // namespace
 
-void launch_path_trace(const TraceCtx& tc, const PtLaunch& L, unsigned long long* work_counter,
-                       unsigned long long* counters, hipStream_t st) {
+int64_t pt_lanes() {
   int dev = 0, cus = 0, per_cu = 0;
   check_hip(hipGetDevice(&dev), "hipGetDevice");
   check_hip(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "CU count");
-  check_hip(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k_path_trace), 256, 0),
+  check_hip(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k_path_trace),
+                                                        TRACE_BLOCK, 0),
             "occupancy");
   if (per_cu < 1) per_cu = 1;
+  return (int64_t)cus * per_cu * TRACE_BLOCK;
+}
+
+void launch_path_trace(const TraceCtx& tc, const PtLaunch& L, unsigned long long* work_counter,
+                       unsigned long long* counters, uint64_t* hitlist, hipStream_t st) {
+  // one resident block per TRACE_BLOCK lanes: the hit list is sized for exactly this grid
+  const unsigned blocks = (unsigned)(pt_lanes() / TRACE_BLOCK);
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, work_counter, 1);
-  hipLaunchKernelGGL(k_path_trace, dim3((unsigned)(cus * per_cu)), dim3(256), 0, st, tc, L, work_counter, counters);
+  hipLaunchKernelGGL(k_path_trace, dim3(blocks), dim3(TRACE_BLOCK), 0, st, tc, L, work_counter, counters, hitlist);
   check_hip(hipGetLastError(), "path_trace launch");
 }
 

@@ -99,8 +99,12 @@ struct PtLaunch {
   int64_t n_work;            // = s[n_slots - 1].global_end
 };
 
+// Lanes of the persistent path-tracing grid on the current device (the hit
+// list holds HL_CAP keys for each).
+int64_t pt_lanes();
+// hitlist: pt_lanes() * HL_CAP keys, or null to trace without the list.
 void launch_path_trace(const TraceCtx& tc, const PtLaunch& L, unsigned long long* work_counter,
-                       unsigned long long* counters, hipStream_t st);
+                       unsigned long long* counters, uint64_t* hitlist, hipStream_t st);
 
 void launch_single_bounce_backward(const TraceCtx& tc, const eag_surfels& s, const CamBatch& cams, int64_t hw,
                                    int32_t n_cams, const SbParams& sp, const float* state, const double* r1,

@@ -137,6 +137,7 @@ struct eag_server {
   uint32_t next_version_id = 1;
   eag_bvh* bvh = nullptr;
   unsigned long long* work = nullptr;
+  uint64_t* hitlist = nullptr;
   char* pool_base = nullptr;
   size_t pool_bytes = 0;
   Pool pool;
@@ -326,7 +327,7 @@ void eag_server::run() {
       ts.inv_dq = 1.0 / (double)p0.depth_quantum;
       const TraceCtx tc = make_ctx(bvh, nullptr, &p0, ts);
       lk.unlock();
-      launch_path_trace(tc, L, work, nullptr, st);
+      launch_path_trace(tc, L, work, nullptr, hitlist, st);
       check_hip(hipStreamSynchronize(st), "serve launch");
       lk.lock();
       for (int i = 0; i < nl; ++i) {
@@ -383,6 +384,12 @@ size_t eag_serve_arena_bytes(int64_t n, int32_t versions, size_t request_bytes) 
   b += (size_t)MAX_VERSIONS * (align_up(7 * n * sizeof(float)) + align_up(n * sizeof(Attr)));
   b += align_up(eag_bvh_bytes(n));
   b += align_up(64);
+  try {
+    b += align_up((size_t)pt_lanes() * HL_CAP * sizeof(uint64_t));
+  } catch (const Error& e) {
+    set_last_error(e.msg);
+    return 0;
+  }
   b += std::max(align_up(build_ws_bytes(n)), align_up(request_bytes));
   return b + 4096;
 }
@@ -415,6 +422,7 @@ eag_status eag_serve_create(const eag_surfels* s, const eag_server_config* cfg, 
     const size_t bvh_bytes = eag_bvh_bytes(n);
     void* bvh_mem = c.take<char>(bvh_bytes);
     srv->work = c.take<unsigned long long>(8);
+    srv->hitlist = c.take<uint64_t>((size_t)pt_lanes() * HL_CAP);
     c.used = align_up(c.used);
     if (c.used >= cfg->arena_bytes) fail(EAG_ERR_OUT_OF_BUDGET, "arena too small for the scene");
     srv->pool_base = static_cast<char*>(cfg->arena) + c.used;

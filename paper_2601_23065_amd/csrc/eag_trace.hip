@@ -54,6 +54,7 @@ TraceCtx make_ctx(const eag_bvh* b, const Attr* attrs, const eag_trace_params* p
   tc.t_min = p->t_min;
   tc.k2 = (double)p->k_sigma * (double)p->k_sigma;
   tc.T_min = p->T_min;
+  tc.hl = nullptr;
   return tc;
 }
 
