@@ -407,6 +407,7 @@ __device__ __forceinline__ void kbuf_insert(uint64_t (&kk)[KBUF], uint64_t key) 
   kk[0] = (p == 0) ? key : kk[0];
 }
 
+// ---------------------------------------------------------------------------
 // One ray segment: multi-round k-buffer traversal and front-to-back blending.
 // Round r collects the KBUF smallest keys strictly greater than the last key
 // blended in round r-1, blends them in order, and stops the segment after the
@@ -421,12 +422,293 @@ __device__ __forceinline__ void kbuf_insert(uint64_t (&kk)[KBUF], uint64_t key) 
 // keys >= lhi. On a surface where many coplanar surfels share one depth
 // bucket, this turns the repeated traversals of a long segment into scans
 // of a short list. If the list overflows it is dropped and rounds traverse.
-// on_hit(pos, t, alpha, w, T_before) is called for every blended hit, in
-// blending order. If hit_out is non-null, up to max_hits blended surfel
-// indices are written. Must be called from a TRACE_BLOCK-thread block.
-// QMODE: Q_ALL blends every quantity, Q_RADIANCE only r. DACC: accumulate
-// R, E, P in double (the single-bounce render, whose adjoint subtracts
-// running prefixes from these totals) or in float (path tracing).
+//
+// The steps are separate functions so that a kernel can interleave them
+// across lanes (the path tracer does); trace_segment_cb runs them in order.
+// ---------------------------------------------------------------------------
+
+// Segment state carried across rounds. DACC: accumulate R, E, P in double
+// (the single-bounce render, whose adjoint subtracts running prefixes from
+// these totals) or in float (path tracing).
+template <bool DACC>
+struct Seg {
+  using Acc = typename std::conditional<DACC, double, float>::type;
+  D3 O, W;            // the ray, double precision
+  RayF rf;            // float copies for the surfel filter
+  V3 iW;              // float reciprocal direction for the box tests
+  D3 N;
+  double D, T;
+  Acc R0, R1, R2, E, P0, P1, P2;
+  uint64_t last;      // keys must exceed this once have_last
+  bool have_last;
+  bool done;
+  int nl;             // entries in the hit list
+  uint64_t lhi;       // 0: list unusable; else it holds every hit key in (last, lhi)
+  int32_t nhits, rounds, tests, visits;
+};
+
+// State of one round: the k-buffer and the traversal. Internal nodes are
+// visited until a lane has PEND-4 leaves postponed, its traversal ends, or
+// every lane of the wave has a leaf waiting; then the postponed leaves are
+// tested, so that the costly surfel test runs for many lanes at once.
+struct Round {
+  uint64_t kk[KBUF];  // ascending; empty = ~0
+  int cnt;
+  uint64_t floor_key; // keys taken must exceed this (when have_floor)
+  bool have_floor;
+  uint64_t cut_key;   // hit list entries must be below this
+  float t_cut;        // boxes entered beyond this cannot hold a key < kk[KBUF-1]
+  float tlo0;         // boxes ending before this cannot hold a key > floor_key
+  bool over;          // the hit list overflowed this round
+  bool trav;          // internal nodes remain (ref, then the stack)
+  int ref;            // next internal node
+  int np;             // postponed leaves
+};
+
+template <bool DACC>
+__device__ __forceinline__ void seg_begin(Seg<DACC>& s, D3 O, D3 W) {
+  s.O = O;
+  s.W = W;
+  const float wx = (float)W.x, wy = (float)W.y, wz = (float)W.z;
+  s.rf.O = v3((float)O.x, (float)O.y, (float)O.z);
+  s.rf.W = v3(wx, wy, wz);
+  s.rf.Osum = fabsf(s.rf.O.x) + fabsf(s.rf.O.y) + fabsf(s.rf.O.z);
+  s.iW = v3(1.0f / (fabsf(wx) > 1e-30f ? wx : copysignf(1e-30f, wx)),
+            1.0f / (fabsf(wy) > 1e-30f ? wy : copysignf(1e-30f, wy)),
+            1.0f / (fabsf(wz) > 1e-30f ? wz : copysignf(1e-30f, wz)));
+  s.N = d3(0.0, 0.0, 0.0);
+  s.D = 0.0;
+  s.T = 1.0;
+  s.R0 = s.R1 = s.R2 = s.E = s.P0 = s.P1 = s.P2 = 0;
+  s.last = 0;
+  s.have_last = false;
+  s.done = false;
+  s.nl = 0;
+  s.lhi = 0;
+  s.nhits = s.rounds = s.tests = s.visits = 0;
+}
+
+// Start a round. Returns true when it must traverse (r.trav / r.np are set
+// up and the stack is empty), false when the hit list alone decides it.
+template <bool DACC>
+__device__ __forceinline__ bool round_begin(const TraceCtx& tc, Seg<DACC>& s, Round& r, TravStack& st, int* pend) {
+  ++s.rounds;
+#pragma unroll
+  for (int j = 0; j < KBUF; ++j) r.kk[j] = ~0ull;
+  r.cnt = 0;
+  r.floor_key = s.last;
+  r.have_floor = s.have_last;
+  r.over = false;
+  bool traverse = true;
+  if (s.lhi != 0) {
+    // keys in (last, lhi) from the list, compacted in place
+    uint64_t* const hl = tc.hl;
+    int w = 0;
+    for (int j = 0; j < s.nl; ++j) {
+      const uint64_t k = hl[j * HL_STRIDE];
+      if (k > s.last && k < s.lhi) {
+        if (w != j) hl[w * HL_STRIDE] = k;
+        ++w;
+        if (k < r.kk[KBUF - 1]) {
+          kbuf_insert(r.kk, k);
+          ++r.cnt;
+        }
+      }
+    }
+    s.nl = w;
+    r.cnt = r.cnt > KBUF ? KBUF : r.cnt;
+    if (r.cnt == KBUF || s.lhi == ~0ull) {
+      traverse = false;
+    } else if (s.lhi - 1 > r.floor_key) {
+      r.floor_key = s.lhi - 1;
+      r.have_floor = true;
+    }
+  } else {
+    s.nl = 0;
+  }
+  r.cut_key = r.cnt == KBUF ? next_bucket_key(tc, r.kk[KBUF - 1]) : ~0ull;
+  r.t_cut = r.cnt == KBUF ? key_thi(tc, r.kk[KBUF - 1]) * 1.000002f + 1e-6f : __builtin_inff();
+  const float t_floor = r.have_floor ? key_tlo(tc, r.floor_key) : 0.0f;
+  r.tlo0 = fmaxf((float)tc.t_min, t_floor) * 0.99999f - 1e-6f;
+  st.sp = 0;
+  r.ref = tc.root;
+  r.np = 0;
+  r.trav = traverse && tc.root >= 0;
+  if (traverse && tc.root < 0) {   // the whole scene is one surfel
+    pend[0] = ~tc.root;
+    r.np = 1;
+  }
+  return traverse;
+}
+
+// Visit internal node r.ref: leaves the ray reaches are postponed, internal
+// children are visited nearest first (the others pushed farthest first).
+template <bool DACC>
+__device__ __forceinline__ void node_visit(const TraceCtx& tc, Seg<DACC>& s, Round& r, TravStack& st, int* pend) {
+  ++s.visits;
+  const Node4* nd = tc.nodes + r.ref;
+  const int4 cr = nd->ref;
+  const float4* bb = nd->b;
+  const float4 b0 = bb[0], b1 = bb[1], b2 = bb[2], b3 = bb[3], b4 = bb[4], b5 = bb[5];
+  const V3 Of = s.rf.O;
+  float e[4];
+  e[0] = slab(b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, Of, s.iW, r.tlo0, r.t_cut);
+  e[1] = slab(b1.z, b1.w, b2.x, b2.y, b2.z, b2.w, Of, s.iW, r.tlo0, r.t_cut);
+  e[2] = slab(b3.x, b3.y, b3.z, b3.w, b4.x, b4.y, Of, s.iW, r.tlo0, r.t_cut);
+  e[3] = slab(b4.z, b4.w, b5.x, b5.y, b5.z, b5.w, Of, s.iW, r.tlo0, r.t_cut);
+  const int c[4] = {cr.x, cr.y, cr.z, cr.w};
+  float ie[4];
+  int ic[4];
+  int ni = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    // a missed box reports +inf, which must not pass an infinite cut
+    const bool m = c[k] != NODE4_EMPTY && e[k] < __builtin_inff() && e[k] <= r.t_cut;
+    if (m && c[k] < 0) pend[(r.np++) * TRACE_BLOCK] = ~c[k];
+    ie[k] = (m && c[k] >= 0) ? e[k] : __builtin_inff();
+    ic[k] = c[k];
+    ni += (m && c[k] >= 0) ? 1 : 0;
+  }
+  if (ni > 0) {
+    // sort the four (entry, child) pairs by entry, misses (+inf) last
+#define EAG_CSWAP(i, j)                                  \
+    if (ie[j] < ie[i]) {                                 \
+      const float tf = ie[i]; ie[i] = ie[j]; ie[j] = tf; \
+      const int tc_ = ic[i]; ic[i] = ic[j]; ic[j] = tc_; \
+    }
+    EAG_CSWAP(0, 1) EAG_CSWAP(2, 3) EAG_CSWAP(0, 2) EAG_CSWAP(1, 3) EAG_CSWAP(1, 2)
+#undef EAG_CSWAP
+    if (ni > 3) st.push(ic[3]);
+    if (ni > 2) st.push(ic[2]);
+    if (ni > 1) st.push(ic[1]);
+    r.ref = ic[0];
+  } else if (st.sp > 0) {
+    r.ref = st.pop();
+  } else {
+    r.trav = false;
+  }
+}
+
+// Test the most recently postponed leaf and take its key if it qualifies.
+template <bool DACC>
+__device__ __forceinline__ void leaf_test(const TraceCtx& tc, Seg<DACC>& s, Round& r, int* pend) {
+  const uint32_t pos = (uint32_t)pend[(--r.np) * TRACE_BLOCK];
+  const Record rec = load_record(tc.recs, pos);
+  ++s.tests;
+  uint32_t blo = 0, bhi = 0;
+  const int fr = record_filter(rec, s.rf, (float)tc.t_min, (float)tc.k2, (float)tc.inv_dq, blo, bhi);
+  if (fr == FILTER_REJECT) return;
+  uint64_t key;
+  if (fr == FILTER_ACCEPT) {
+    // whole-bucket bounds decide most keys without the exact distance
+    const uint64_t klo = make_key_b(tc, blo, 0u, 0u), khi = make_key_b(tc, bhi + 1u, 0u, 0u);
+    if (r.have_floor && khi <= r.floor_key) return;
+    if (klo >= (tc.hl ? r.cut_key : r.kk[KBUF - 1])) return;
+    if (blo == bhi) {
+      key = make_key_b(tc, blo, rec_index(rec), pos);
+    } else {
+      double t;
+      record_test(rec, s.O, s.W, -1e300, 1e300, t);
+      key = make_key(tc, t, rec_index(rec), pos);
+    }
+  } else {
+    double t;
+    if (!record_test(rec, s.O, s.W, tc.t_min, tc.k2, t)) return;
+    key = make_key(tc, t, rec_index(rec), pos);
+  }
+  if (r.have_floor && key <= r.floor_key) return;
+  if (tc.hl && key < r.cut_key) {
+    if (s.nl < HL_CAP) tc.hl[(s.nl++) * HL_STRIDE] = key;
+    else r.over = true;
+  }
+  if (key < r.kk[KBUF - 1]) {
+    kbuf_insert(r.kk, key);
+    if (++r.cnt >= KBUF) {
+      r.cnt = KBUF;
+      r.t_cut = key_thi(tc, r.kk[KBUF - 1]) * 1.000002f + 1e-6f;
+      r.cut_key = next_bucket_key(tc, r.kk[KBUF - 1]);
+    }
+  }
+}
+
+// After a traversal round: what the hit list now covers.
+template <bool DACC>
+__device__ __forceinline__ void round_end_traversal(const TraceCtx& tc, Seg<DACC>& s, const Round& r) {
+  if (tc.hl) s.lhi = r.over ? 0ull : (r.cnt == KBUF ? r.cut_key : ~0ull);
+}
+
+// Traverse one round to completion for this lane.
+template <bool DACC>
+__device__ __forceinline__ void traverse_round(const TraceCtx& tc, Seg<DACC>& s, Round& r, TravStack& st,
+                                               int* pend) {
+  while (true) {
+    while (r.trav && r.np <= PEND - 4) {
+      node_visit(tc, s, r, st, pend);
+      if (__all(r.np > 0 || !r.trav)) break;
+    }
+    while (r.np > 0) leaf_test(tc, s, r, pend);
+    if (!r.trav) break;
+  }
+  round_end_traversal(tc, s, r);
+}
+
+// Blend the round's hits in key order (the buffer is shifted down one entry
+// per hit, which keeps its indexing static); t and alpha are recomputed from
+// the record with the same double-precision test. Sets s.done after the
+// first hit with T < T_min or when the round returned fewer than KBUF hits.
+// on_hit(pos, t, alpha, w, T_before) is called for every blended hit; if
+// hit_out is non-null, up to max_hits blended surfel indices are written.
+template <int QMODE, bool DACC, class HitFn>
+__device__ __forceinline__ void blend_round(const TraceCtx& tc, Seg<DACC>& s, Round& r, HitFn& on_hit,
+                                           int32_t* hit_out, int max_hits) {
+  using Acc = typename Seg<DACC>::Acc;
+  const uint64_t round_last = r.kk[KBUF - 1];
+  for (int j = 0; j < r.cnt && !s.done; ++j) {
+    const uint64_t key = r.kk[0];
+#pragma unroll
+    for (int m = 0; m < KBUF - 1; ++m) r.kk[m] = r.kk[m + 1];
+    const uint32_t pos = key_pos(tc, key);
+    const Geo ge = surfel_geo(load_record(tc.recs, pos));
+    double t = 0.0, q2 = 0.0;
+    surfel_test(ge, s.O, s.W, -1e300, 1e300, t, q2);
+    const double a = ge.sigma * exp(-0.5 * q2);
+    const double w = s.T * a;
+    const Acc wf = (Acc)w;
+    if (QMODE == Q_ALL) {
+      const double sw = dot(s.W, ge.n) > 0.0 ? -w : w;  // n' faces the origin
+      s.N.x += sw * ge.n.x;
+      s.N.y += sw * ge.n.y;
+      s.N.z += sw * ge.n.z;
+      s.D += w * t;
+      const Attr at = tc.attrs[pos];
+      s.P0 += wf * at.rho_e.x;
+      s.P1 += wf * at.rho_e.y;
+      s.P2 += wf * at.rho_e.z;
+      s.E += wf * at.rho_e.w;
+      s.R0 += wf * at.r.x;
+      s.R1 += wf * at.r.y;
+      s.R2 += wf * at.r.z;
+    } else {
+      const float4 rr = tc.attrs[pos].r;
+      s.R0 += wf * rr.x;
+      s.R1 += wf * rr.y;
+      s.R2 += wf * rr.z;
+    }
+    if (hit_out && s.nhits < max_hits) hit_out[s.nhits] = (int32_t)key_idx(tc, key);
+    on_hit(pos, t, a, w, s.T);
+    ++s.nhits;
+    s.T *= (1.0 - a);
+    if (s.T < tc.T_min) s.done = true;
+  }
+  if (r.cnt < KBUF) s.done = true;
+  if (!s.done) {
+    s.last = round_last;
+    s.have_last = true;
+  }
+}
+
+// A whole segment for this lane. Must be called from a TRACE_BLOCK-thread
+// block (the traversal stack and the postponed leaves live in LDS).
 template <int QMODE, bool DACC, class HitFn>
 __device__ SegOut trace_segment_cb(const TraceCtx& tc, D3 O, D3 W, HitFn& on_hit, int32_t* hit_out = nullptr,
                                    int max_hits = 0) {
@@ -434,225 +716,26 @@ __device__ SegOut trace_segment_cb(const TraceCtx& tc, D3 O, D3 W, HitFn& on_hit
   __shared__ int s_pend[PEND * TRACE_BLOCK];
   TravStack st;
   st.lds = s_stack + threadIdx.x;
+  st.sp = 0;
   int* pend = s_pend + threadIdx.x;   // this lane's queue of postponed leaves
-  SegOut o;
-  o.N = d3(0.0, 0.0, 0.0);
-  o.D = 0.0;
-  o.T = 1.0;
-  o.nhits = 0;
-  o.rounds = 0;
-  o.tests = 0;
-  o.visits = 0;
-  using Acc = typename std::conditional<DACC, double, float>::type;
-  Acc R0 = 0, R1 = 0, R2 = 0, E = 0, P0 = 0, P1 = 0, P2 = 0;
-  const V3 Of = v3((float)O.x, (float)O.y, (float)O.z);
-  const float wx = (float)W.x, wy = (float)W.y, wz = (float)W.z;
-  const V3 iW = v3(1.0f / (fabsf(wx) > 1e-30f ? wx : copysignf(1e-30f, wx)),
-                   1.0f / (fabsf(wy) > 1e-30f ? wy : copysignf(1e-30f, wy)),
-                   1.0f / (fabsf(wz) > 1e-30f ? wz : copysignf(1e-30f, wz)));
-  uint64_t last = 0;            // keys must exceed this once have_last
-  bool have_last = false;
-  bool done = false;
-  uint64_t* const hl = tc.hl;
-  int nl = 0;                   // entries in the hit list
-  uint64_t lhi = 0;             // 0: list unusable; else it holds every hit key in (last, lhi)
-  RayF rf;
-  rf.O = Of;
-  rf.W = v3(wx, wy, wz);
-  rf.Osum = fabsf(Of.x) + fabsf(Of.y) + fabsf(Of.z);
-  const float tmin_f = (float)tc.t_min, k2_f = (float)tc.k2, inv_dq_f = (float)tc.inv_dq;
-  while (!done) {
-    uint64_t kk[KBUF];
-#pragma unroll
-    for (int j = 0; j < KBUF; ++j) kk[j] = ~0ull;
-    int cnt = 0;
-    // keys taken this round must exceed `floor` (when have_floor)
-    uint64_t floor_key = last;
-    bool have_floor = have_last;
-    bool traverse = true;
-    if (lhi != 0) {
-      // keys in (last, lhi) from the list, compacted in place
-      int w = 0;
-      for (int j = 0; j < nl; ++j) {
-        const uint64_t k = hl[j * HL_STRIDE];
-        if (k > last && k < lhi) {
-          if (w != j) hl[w * HL_STRIDE] = k;
-          ++w;
-          if (k < kk[KBUF - 1]) {
-            kbuf_insert(kk, k);
-            ++cnt;
-          }
-        }
-      }
-      nl = w;
-      cnt = cnt > KBUF ? KBUF : cnt;
-      if (cnt == KBUF || lhi == ~0ull) {
-        traverse = false;
-      } else if (lhi - 1 > floor_key) {
-        floor_key = lhi - 1;
-        have_floor = true;
-      }
-    } else {
-      nl = 0;
-    }
-    bool over = false;            // the list overflowed this round
-    uint64_t cut_key = ~0ull;     // list entries must be below this (first key past kk[KBUF-1]'s bucket)
-    if (cnt == KBUF) cut_key = next_bucket_key(tc, kk[KBUF - 1]);
-    float t_cut = cnt == KBUF ? key_thi(tc, kk[KBUF - 1]) * 1.000002f + 1e-6f : __builtin_inff();
-    const float t_floor = have_floor ? key_tlo(tc, floor_key) : 0.0f;
-    const float tlo0 = fmaxf((float)tc.t_min, t_floor) * 0.99999f - 1e-6f;
-    // Two phases, so that the costly surfel test runs for many lanes at
-    // once: (1) visit internal nodes, postponing every leaf the ray reaches
-    // into a per-lane queue, until the queue is nearly full, the lane's
-    // traversal ends, or every lane of the wave has a leaf waiting; (2) test
-    // the queued leaves. Repeat until the stack and the queue are empty.
-    st.sp = 0;
-    int ref = tc.root;
-    int np = 0;
-    bool trav = traverse && ref >= 0;
-    if (traverse && ref < 0) pend[0] = ~ref, np = 1;   // the whole scene is one surfel
-    while (traverse) {
-      while (trav && np <= PEND - 4) {
-        ++o.visits;
-        const Node4* nd = tc.nodes + ref;
-        const int4 cr = nd->ref;
-        const float4* bb = nd->b;
-        const float4 b0 = bb[0], b1 = bb[1], b2 = bb[2], b3 = bb[3], b4 = bb[4], b5 = bb[5];
-        float e[4];
-        e[0] = slab(b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, Of, iW, tlo0, t_cut);
-        e[1] = slab(b1.z, b1.w, b2.x, b2.y, b2.z, b2.w, Of, iW, tlo0, t_cut);
-        e[2] = slab(b3.x, b3.y, b3.z, b3.w, b4.x, b4.y, Of, iW, tlo0, t_cut);
-        e[3] = slab(b4.z, b4.w, b5.x, b5.y, b5.z, b5.w, Of, iW, tlo0, t_cut);
-        const int c[4] = {cr.x, cr.y, cr.z, cr.w};
-        // children reached: leaves are queued, internal nodes kept with their entry
-        float ie[4];
-        int ic[4];
-        int ni = 0;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          // a missed box reports +inf, which must not pass an infinite cut
-          const bool m = c[k] != NODE4_EMPTY && e[k] < __builtin_inff() && e[k] <= t_cut;
-          if (m && c[k] < 0) pend[(np++) * TRACE_BLOCK] = ~c[k];
-          ie[k] = (m && c[k] >= 0) ? e[k] : __builtin_inff();
-          ic[k] = c[k];
-          ni += (m && c[k] >= 0) ? 1 : 0;
-        }
-        if (ni > 0) {
-          // sort the four (entry, child) pairs by entry, misses (+inf) last
-#define EAG_CSWAP(i, j)                                        \
-          if (ie[j] < ie[i]) {                                 \
-            const float tf = ie[i]; ie[i] = ie[j]; ie[j] = tf; \
-            const int tc_ = ic[i]; ic[i] = ic[j]; ic[j] = tc_; \
-          }
-          EAG_CSWAP(0, 1) EAG_CSWAP(2, 3) EAG_CSWAP(0, 2) EAG_CSWAP(1, 3) EAG_CSWAP(1, 2)
-#undef EAG_CSWAP
-          // visit the nearest; push the others farthest first
-          if (ni > 3) st.push(ic[3]);
-          if (ni > 2) st.push(ic[2]);
-          if (ni > 1) st.push(ic[1]);
-          ref = ic[0];
-        } else if (st.sp > 0) {
-          ref = st.pop();
-        } else {
-          trav = false;
-        }
-        if (__all(np > 0 || !trav)) break;
-      }
-      while (np > 0) {
-        const uint32_t pos = (uint32_t)pend[(--np) * TRACE_BLOCK];
-        const Record r = load_record(tc.recs, pos);
-        ++o.tests;
-        uint32_t blo = 0, bhi = 0;
-        const int fr = record_filter(r, rf, tmin_f, k2_f, inv_dq_f, blo, bhi);
-        if (fr == FILTER_REJECT) continue;
-        uint64_t key;
-        if (fr == FILTER_ACCEPT) {
-          // whole-bucket bounds decide most keys without the exact distance
-          const uint64_t klo = make_key_b(tc, blo, 0u, 0u), khi = make_key_b(tc, bhi + 1u, 0u, 0u);
-          if (have_floor && khi <= floor_key) continue;
-          if (klo >= (hl ? cut_key : kk[KBUF - 1])) continue;
-          if (blo == bhi) {
-            key = make_key_b(tc, blo, rec_index(r), pos);
-          } else {
-            double t;
-            record_test(r, O, W, -1e300, 1e300, t);
-            key = make_key(tc, t, rec_index(r), pos);
-          }
-        } else {
-          double t;
-          if (!record_test(r, O, W, tc.t_min, tc.k2, t)) continue;
-          key = make_key(tc, t, rec_index(r), pos);
-        }
-        if (!have_floor || key > floor_key) {
-          if (hl && key < cut_key) {
-            if (nl < HL_CAP) hl[(nl++) * HL_STRIDE] = key;
-            else over = true;
-          }
-          if (key < kk[KBUF - 1]) {
-            kbuf_insert(kk, key);
-            if (++cnt >= KBUF) {
-              cnt = KBUF;
-              t_cut = key_thi(tc, kk[KBUF - 1]) * 1.000002f + 1e-6f;
-              cut_key = next_bucket_key(tc, kk[KBUF - 1]);
-            }
-          }
-        }
-      }
-      if (!trav) break;
-    }
-    if (hl && traverse) lhi = over ? 0ull : (cnt == KBUF ? cut_key : ~0ull);
-    ++o.rounds;
-
-    // blend this round's hits in key order (the buffer is shifted down one
-    // entry per hit, which keeps its indexing static); t and alpha are
-    // recomputed from the record with the same double-precision test
-    const uint64_t round_last = kk[KBUF - 1];
-    for (int j = 0; j < cnt && !done; ++j) {
-      const uint64_t key = kk[0];
-#pragma unroll
-      for (int m = 0; m < KBUF - 1; ++m) kk[m] = kk[m + 1];
-      const uint32_t pos = key_pos(tc, key);
-      const Geo ge = surfel_geo(load_record(tc.recs, pos));
-      double t = 0.0, q2 = 0.0;
-      surfel_test(ge, O, W, -1e300, 1e300, t, q2);
-      const double a = ge.sigma * exp(-0.5 * q2);
-      const double w = o.T * a;
-      const Acc wf = (Acc)w;
-      if (QMODE == Q_ALL) {
-        const double sw = dot(W, ge.n) > 0.0 ? -w : w;  // n' faces the origin
-        o.N.x += sw * ge.n.x;
-        o.N.y += sw * ge.n.y;
-        o.N.z += sw * ge.n.z;
-        o.D += w * t;
-        const Attr at = tc.attrs[pos];
-        P0 += wf * at.rho_e.x;
-        P1 += wf * at.rho_e.y;
-        P2 += wf * at.rho_e.z;
-        E += wf * at.rho_e.w;
-        R0 += wf * at.r.x;
-        R1 += wf * at.r.y;
-        R2 += wf * at.r.z;
-      } else {
-        const float4 rr = tc.attrs[pos].r;
-        R0 += wf * rr.x;
-        R1 += wf * rr.y;
-        R2 += wf * rr.z;
-      }
-      if (hit_out && o.nhits < max_hits) hit_out[o.nhits] = (int32_t)key_idx(tc, key);
-      on_hit(pos, t, a, w, o.T);
-      ++o.nhits;
-      o.T *= (1.0 - a);
-      if (o.T < tc.T_min) done = true;
-    }
-    if (cnt < KBUF) done = true;
-    if (!done) {
-      last = round_last;
-      have_last = true;
-    }
+  Seg<DACC> s;
+  seg_begin(s, O, W);
+  while (!s.done) {
+    Round r;
+    if (round_begin(tc, s, r, st, pend)) traverse_round(tc, s, r, st, pend);
+    blend_round<QMODE>(tc, s, r, on_hit, hit_out, max_hits);
   }
-  o.R = d3(R0, R1, R2);
-  o.E = E;
-  o.P = d3(P0, P1, P2);
+  SegOut o;
+  o.N = s.N;
+  o.D = s.D;
+  o.R = d3(s.R0, s.R1, s.R2);
+  o.E = s.E;
+  o.P = d3(s.P0, s.P1, s.P2);
+  o.T = s.T;
+  o.nhits = s.nhits;
+  o.rounds = s.rounds;
+  o.tests = s.tests;
+  o.visits = s.visits;
   return o;
 }
 
