@@ -419,7 +419,10 @@ __device__ __forceinline__ void kbuf_insert(uint64_t (&kk)[KBUF], uint64_t key) 
 // beyond them), so the list then holds every hit key in (last, lhi) with lhi
 // the first key of the next bucket. A later round takes its keys from the
 // list when it finds KBUF of them there, and otherwise traverses only for
-// keys >= lhi. On a surface where many coplanar surfels share one depth
+// keys >= lhi; when the list holds some but fewer than KBUF such keys, they
+// are blended first as a round of their own, and the traversal beyond lhi
+// happens only if the segment is still open. On a surface where many
+// coplanar surfels share one depth
 // bucket, this turns the repeated traversals of a long segment into scans
 // of a short list. If the list overflows it is dropped and rounds traverse.
 //
@@ -460,6 +463,8 @@ struct Round {
   float t_cut;        // boxes entered beyond this cannot hold a key < kk[KBUF-1]
   float tlo0;         // boxes ending before this cannot hold a key > floor_key
   bool over;          // the hit list overflowed this round
+  bool partial;       // list keys below lhi only: blend them, then traverse beyond lhi if still open
+  uint64_t plast;     // largest key of a partial round
   bool trav;          // internal nodes remain (ref, then the stack)
   int ref;            // next internal node
   int np;             // postponed leaves
@@ -499,16 +504,19 @@ __device__ __forceinline__ bool round_begin(const TraceCtx& tc, Seg<DACC>& s, Ro
   r.floor_key = s.last;
   r.have_floor = s.have_last;
   r.over = false;
+  r.partial = false;
   bool traverse = true;
   if (s.lhi != 0) {
     // keys in (last, lhi) from the list, compacted in place
     uint64_t* const hl = tc.hl;
     int w = 0;
+    r.plast = 0;
     for (int j = 0; j < s.nl; ++j) {
       const uint64_t k = hl[j * HL_STRIDE];
       if (k > s.last && k < s.lhi) {
         if (w != j) hl[w * HL_STRIDE] = k;
         ++w;
+        r.plast = k > r.plast ? k : r.plast;
         if (k < r.kk[KBUF - 1]) {
           kbuf_insert(r.kk, k);
           ++r.cnt;
@@ -519,6 +527,11 @@ __device__ __forceinline__ bool round_begin(const TraceCtx& tc, Seg<DACC>& s, Ro
     r.cnt = r.cnt > KBUF ? KBUF : r.cnt;
     if (r.cnt == KBUF || s.lhi == ~0ull) {
       traverse = false;
+    } else if (r.cnt > 0) {
+      // Every key >= lhi follows these, so they can be blended first; the
+      // segment often ends among them, and then nothing beyond lhi is needed.
+      traverse = false;
+      r.partial = true;
     } else if (s.lhi - 1 > r.floor_key) {
       r.floor_key = s.lhi - 1;
       r.have_floor = true;
@@ -662,7 +675,7 @@ template <int QMODE, bool DACC, class HitFn>
 __device__ __forceinline__ void blend_round(const TraceCtx& tc, Seg<DACC>& s, Round& r, HitFn& on_hit,
                                            int32_t* hit_out, int max_hits) {
   using Acc = typename Seg<DACC>::Acc;
-  const uint64_t round_last = r.kk[KBUF - 1];
+  const uint64_t round_last = r.partial ? r.plast : r.kk[KBUF - 1];
   for (int j = 0; j < r.cnt && !s.done; ++j) {
     const uint64_t key = r.kk[0];
 #pragma unroll
@@ -700,7 +713,7 @@ __device__ __forceinline__ void blend_round(const TraceCtx& tc, Seg<DACC>& s, Ro
     s.T *= (1.0 - a);
     if (s.T < tc.T_min) s.done = true;
   }
-  if (r.cnt < KBUF) s.done = true;
+  if (r.cnt < KBUF && !r.partial) s.done = true;
   if (!s.done) {
     s.last = round_last;
     s.have_last = true;
