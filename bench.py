@@ -16,9 +16,25 @@ segment, over the kernel's duration from HIP events on its stream.
 The CPU baseline times the FP64 brute-force oracle on a fixed sample of the
 same workload's paths on the host cores.
 
+Two further workloads print their own JSON line (not the default run):
+  --workload rooms5m   5M surfels in three 8x6x3 m rooms joined by doorways,
+                       one 1920x1080 camera, 256 spp as 16 progressive passes
+                       of 16, max depth 8, RR from 3; then an edit (radiance
+                       zeroed on a random half of the emitters, albedo redrawn
+                       on a random 10% of the surfels in 8 groups), a refit,
+                       and the same 256 spp again.
+  --workload serve     continuous-batching server against one-at-a-time FIFO
+                       on the same Poisson arrivals over a resident 3M-surfel
+                       room (request mix scaled down: 128x128 or 256x256,
+                       4 or 16 spp, 5% edits), at 0.5, 0.8 and 0.95 of the
+                       FIFO service rate; latency percentiles per load.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+                       [--workload room1m|rooms5m|serve]
 """
 import argparse
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -30,6 +46,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, HERE)
 
 PEAK_HBM_GBS = 8000.0
+PROFILE = os.path.join(HERE, "profiles", "k_path_trace_room1m_1024x768_64spp.md")
 ALGO_BYTES_PER_HIT = 68
 ALGO_BYTES_PER_SEGMENT = 96
 
@@ -85,6 +102,237 @@ def copy_calibration(torch, mib):
     torch.cuda.synchronize()
     print(json.dumps({"copy_calibration_bytes_each_way": n * 4, "launches": 3}))
 
+def kernel_source_hash():
+    """sha256 over the library's kernel sources and public header (relative
+    names and contents, in sorted order)."""
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(HERE, "paper_2601_23065_amd", "csrc", "*")) +
+                   glob.glob(os.path.join(HERE, "include", "*.h")))
+    for f in files:
+        h.update(os.path.relpath(f, HERE).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the path-tracing kernel on the default
+    workload, from the committed counter profile (FETCH_SIZE and WRITE_SIZE,
+    each scaled by a copy kernel's reading); None when the kernel sources
+    have changed since the counters were taken."""
+    try:
+        with open(PROFILE) as fh:
+            kv = dict(line.split(": ", 1) for line in fh.read().splitlines() if ": " in line)
+    except OSError:
+        return None
+    if kv.get("source_sha256") != kernel_source_hash() or "traffic_bytes_per_launch" not in kv:
+        return None
+    return float(kv["traffic_bytes_per_launch"])
+
+
+def _roofline(blended, segments, pt_ms):
+    algo_bytes = blended * ALGO_BYTES_PER_HIT + segments * ALGO_BYTES_PER_SEGMENT
+    achieved = algo_bytes / (pt_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 2), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 5), "traffic": None}
+
+
+def bench_rooms5m(torch, args):
+    """Progressive rendering of the three-room scene, an edit, a refit, and
+    the same render again (one JSON line)."""
+    import scenegen as sg
+    from paper_2601_23065_amd import EDIT_SET_ALBEDO, EDIT_SET_RADIANCE
+    from paper_2601_23065_amd.api import BVH, Params, Scene, apply_edit, path_trace, path_trace_workspace, resolve
+
+    scene, cams, cfg = sg.config(4, n_override=args.surfels)
+    cam = cams[0]
+    spp, pass_spp = args.spp or cfg["spp"], cfg["pass_spp"]
+    params = Params(spp=spp, max_depth=cfg["max_depth"], rr_start=cfg["rr_start"], seed=0, camera_id=0)
+    _log(f"scene ready: {scene.n} surfels, {cam.width}x{cam.height}, {spp} spp in passes of {pass_spp}")
+    gs = Scene(scene.arrays())
+    ws = path_trace_workspace(gs)
+    counters = torch.zeros(6, dtype=torch.int64, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def ev():
+        e = torch.cuda.Event(enable_timing=True)
+        e.record(stream)
+        return e
+
+    eb0 = ev()
+    bvh = BVH(gs)
+    eb1 = ev()
+
+    def render(tag):
+        acc, evs = None, []
+        for s0 in range(0, spp, pass_spp):
+            a = ev()
+            acc = path_trace(bvh, gs, cam, params, s0, min(pass_spp, spp - s0), accum=acc, counters=counters, ws=ws)
+            evs.append((a, ev()))
+        img = resolve(acc, spp)
+        torch.cuda.synchronize()
+        passes = [a.elapsed_time(b) for a, b in evs]
+        _log(f"{tag}: {len(passes)} passes, {sum(passes):.0f} ms")
+        return img, passes
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    img0, passes0 = render("before the edit")
+    rng = np.random.default_rng(4)
+    emit = np.nonzero(scene.emissive > 0)[0]
+    off = np.sort(rng.choice(emit, emit.size // 2, replace=False)).astype(np.int32)
+    groups = np.array_split(np.sort(rng.choice(scene.n, scene.n // 10, replace=False)).astype(np.int32), 8)
+    colors = [tuple(map(float, rng.uniform(0.05, 0.9, 3))) for _ in groups]
+    off_d = torch.from_numpy(off).cuda()
+    groups_d = [torch.from_numpy(g).cuda() for g in groups]
+    ee0 = ev()
+    apply_edit(gs, EDIT_SET_RADIANCE, off_d, (0.0, 0.0, 0.0))
+    for g, c in zip(groups_d, colors):
+        apply_edit(gs, EDIT_SET_ALBEDO, g, c)
+    ee1 = ev()
+    bvh.refit(gs)
+    ee2 = ev()
+    img1, passes1 = render("after the edit")
+    wall = time.perf_counter() - t0
+    c = counters.cpu().numpy().astype(np.float64)
+    segments, paths, rounds, tests, blended, visits = c
+    pt_ms = sum(passes0) + sum(passes1)
+    rec = {
+        "metric": "Mrays/s multi-bounce PT over 2D Gaussians",
+        "value": round(segments / wall / 1e6, 3),
+        "unit": "Mrays/s",
+        "n_gpus": 1,
+        "steps": 2,
+        "warmup": 0,
+        "ms_per_step": round(wall / 2 * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"progressive path tracing, {scene.n} surfels in three 8x6x3 m rooms joined by "
+                               f"doorways, {cam.width}x{cam.height}, {spp} spp in passes of {pass_spp}, max depth "
+                               f"{params.max_depth}, RR from {params.rr_start}; step = one full render; between the "
+                               f"two steps: radiance edit on half the emitters, albedo edit on 10% of the surfels, "
+                               f"refit",
+                   "surfels": scene.n, "width": cam.width, "height": cam.height, "spp": spp,
+                   "max_depth": params.max_depth},
+        "roofline": _roofline(blended, segments, pt_ms),
+        "detail": {"segments": segments, "paths": paths, "kbuf_rounds_per_segment": round(rounds / segments, 3),
+                   "candidate_tests_per_segment": round(tests / segments, 2),
+                   "nodes_visited_per_segment": round(visits / segments, 2),
+                   "blended_hits_per_segment": round(blended / segments, 3),
+                   "bvh_build_ms": round(eb0.elapsed_time(eb1), 3),
+                   "pass_ms_before": [round(x, 1) for x in passes0], "pass_ms_after": [round(x, 1) for x in passes1],
+                   "edit_ms": round(ee0.elapsed_time(ee1), 3), "refit_ms": round(ee1.elapsed_time(ee2), 3),
+                   "emitters_zeroed": int(off.size), "surfels_recoloured": int(sum(g.size for g in groups)),
+                   "image_mean_before": float(img0.mean()), "image_mean_after": float(img1.mean())},
+    }
+    print(json.dumps(rec))
+
+
+def bench_serve(torch, args):
+    """Continuous batching against FIFO on the same arrivals (one JSON line)."""
+    import scenegen as sg
+    from paper_2601_23065_amd import EDIT_SCALE_RADIANCE, EDIT_SET_ALBEDO
+    from paper_2601_23065_amd.api import BVH, Params, Scene, Server, apply_edit, path_trace, resolve
+
+    scene, _, cfg = sg.config(5, n_override=args.surfels)
+    n_req = args.requests
+    mix = dict(resolutions=((128, 128), (256, 256)), spps=(4, 16))
+    kinds = {"scale_radiance": EDIT_SCALE_RADIANCE, "set_albedo": EDIT_SET_ALBEDO}
+    _log(f"scene ready: {scene.n} surfels, {n_req} requests per run")
+
+    def params_of(i, r):
+        return Params(spp=r["spp"], max_depth=cfg["max_depth"], rr_start=cfg["rr_start"], seed=0, camera_id=i)
+
+    def fifo(reqs, realtime):
+        """One request at a time through the plain path tracer, in arrival
+        order; returns (latencies or service times in s, renders)."""
+        gs = Scene(scene.arrays())
+        bvh = BVH(gs)
+        torch.cuda.synchronize()
+        out = []
+        t_start = time.perf_counter()
+        for i, r in enumerate(reqs):
+            if realtime:
+                delay = t_start + r["t"] - time.perf_counter()
+                if delay > 0:
+                    time.sleep(delay)
+            t_req = time.perf_counter()
+            if r["kind"] == "edit":
+                apply_edit(gs, kinds[r["op"]], torch.from_numpy(r["idx"]).cuda(), r["value"])
+                continue
+            acc = path_trace(bvh, gs, r["camera"], params_of(i, r))
+            resolve(acc, r["spp"])
+            torch.cuda.synchronize()
+            done = time.perf_counter()
+            out.append(done - (t_start + r["t"]) if realtime else done - t_req)
+        return np.array(out)
+
+    def batched(reqs):
+        gs = Scene(scene.arrays())
+        need = L_arena(scene.n)
+        srv = Server(gs, arena_bytes=need, max_live_requests=8, paths_per_launch=1 << 20)
+        tickets = []
+        t_start = time.perf_counter()
+        for i, r in enumerate(reqs):
+            delay = t_start + r["t"] - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            if r["kind"] == "edit":
+                srv.edit(kinds[r["op"]], r["idx"], r["value"])
+            else:
+                tickets.append(srv.submit(r["camera"], params_of(i, r))[0])
+        lat = []
+        for t in tickets:
+            res = srv.wait(t, timeout=600.0)
+            assert res["status"] == 0, res
+            lat.append(res["t_done"] - res["t_submit"])
+        srv.close()
+        return np.array(lat)
+
+    def L_arena(n):
+        from paper_2601_23065_amd import _lib
+        return int(_lib.load().eag_serve_arena_bytes(n, 3, 8 * 256 * 256 * 24)) + (64 << 20)
+
+    cal = sg.arrivals(scene, n_req, 1.0, **mix)
+    fifo(cal[:4], False)   # warm-up: code objects, allocator
+    service = fifo(cal, False)
+    mu = service.size / service.sum()
+    _log(f"FIFO service rate {mu:.2f} requests/s (mean {service.mean() * 1e3:.1f} ms)")
+    loads = {}
+    for rho in (0.5, 0.8, 0.95):
+        reqs = sg.arrivals(scene, n_req, rho * mu, **mix)
+        lf = fifo(reqs, True)
+        lb = batched(reqs)
+        loads[str(rho)] = {k: {"p50_ms": round(float(np.percentile(v, 50)) * 1e3, 2),
+                               "p99_ms": round(float(np.percentile(v, 99)) * 1e3, 2),
+                               "mean_ms": round(float(v.mean()) * 1e3, 2)} for k, v in (("batched", lb), ("fifo", lf))}
+        _log(f"load {rho}: {loads[str(rho)]}")
+    rec = {
+        "metric": "p99 request latency at 0.8 load, continuous batching",
+        "value": loads["0.8"]["batched"]["p99_ms"],
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": n_req,
+        "warmup": 4,
+        "ms_per_step": round(1e3 / mu, 3),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"render server over a resident {scene.n}-surfel 8x6x3 m room, Poisson arrivals of "
+                               f"{n_req} requests (128x128 or 256x256, 4 or 16 spp, depth 5, 5% attribute edits) "
+                               f"at 0.5/0.8/0.95 of the FIFO service rate",
+                   "surfels": scene.n, "requests": n_req},
+        "detail": {"fifo_service_rate_per_s": round(mu, 3), "fifo_mean_service_ms": round(service.mean() * 1e3, 3),
+                   "loads": loads},
+    }
+    print(json.dumps(rec))
+
+
 
 def main():
     ap = argparse.ArgumentParser()
@@ -92,8 +340,10 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--surfels", type=int, default=1_000_000)
+    ap.add_argument("--surfels", type=int, default=None, help="override the workload's surfel count")
+    ap.add_argument("--requests", type=int, default=100, help="requests per run of the serve workload")
     ap.add_argument("--spp", type=int, default=None, help="override the workload's 64 spp (diagnostics only)")
+    ap.add_argument("--workload", default="room1m", choices=["room1m", "rooms5m", "serve"])
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run an elementwise copy of MIB MiB three times (HBM counter calibration)")
     args = ap.parse_args()
@@ -107,11 +357,17 @@ def main():
     if args.copy_calib:
         copy_calibration(torch, args.copy_calib)
         return
+    if args.workload == "rooms5m":
+        bench_rooms5m(torch, args)
+        return
+    if args.workload == "serve":
+        bench_serve(torch, args)
+        return
 
     import scenegen as sg
     from paper_2601_23065_amd.api import BVH, Params, Scene, path_trace, path_trace_workspace, resolve
 
-    scene, cams, cfg = sg.config(3, n_override=args.surfels if args.surfels != 1_000_000 else None)
+    scene, cams, cfg = sg.config(3, n_override=args.surfels)
     cam = cams[0]
     params = Params(spp=args.spp or cfg["spp"], max_depth=cfg["max_depth"], rr_start=cfg["rr_start"], seed=0,
                     camera_id=0)
@@ -122,13 +378,15 @@ def main():
     stream = torch.cuda.current_stream()
 
     def step():
+        evb = torch.cuda.Event(enable_timing=True)
+        evb.record(stream)
         bvh = BVH(gs)
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         ev0.record(stream)
         acc = path_trace(bvh, gs, cam, params, 0, params.spp, counters=counters, ws=ws)
         ev1.record(stream)
         img = resolve(acc, params.spp)
-        return img, (ev0, ev1)
+        return img, (ev0, ev1, evb)
 
     for i in range(args.warmup):
         step()
@@ -149,7 +407,8 @@ def main():
     wall = time.perf_counter() - t0
     c = counters.cpu().numpy().astype(np.float64)
     segments, paths, rounds, tests, blended, visits = (c[i] / args.steps for i in range(6))
-    pt_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    pt_ms = float(np.mean([a.elapsed_time(b) for a, b, _ in evs]))
+    build_ms = float(np.mean([c.elapsed_time(a) for a, b, c in evs]))
     ms_per_step = wall / args.steps * 1e3
     value = segments / (ms_per_step * 1e-3) / 1e6
     algo_bytes = blended * ALGO_BYTES_PER_HIT + segments * ALGO_BYTES_PER_SEGMENT
@@ -173,12 +432,13 @@ def main():
                    "surfels": scene.n, "width": cam.width, "height": cam.height, "spp": params.spp,
                    "max_depth": params.max_depth},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": round(achieved / PEAK_HBM_GBS, 5), "traffic": None},
+                     "frac": round(achieved / PEAK_HBM_GBS, 5),
+                     "traffic": measured_traffic() if args.spp is None and args.surfels is None else None},
         "detail": {"segments_per_step": segments, "paths_per_step": paths, "kbuf_rounds_per_segment":
                    round(rounds / max(segments, 1), 3), "candidate_tests_per_segment": round(tests / max(segments, 1), 2),
                    "nodes_visited_per_segment": round(visits / max(segments, 1), 2),
                    "blended_hits_per_segment": round(blended / max(segments, 1), 3),
-                   "pt_kernel_ms": round(pt_ms, 3), "paths_per_s": round(paths / (ms_per_step * 1e-3), 1),
+                   "pt_kernel_ms": round(pt_ms, 3), "bvh_build_ms": round(build_ms, 3), "paths_per_s": round(paths / (ms_per_step * 1e-3), 1),
                    "image_mean": float(img.mean())},
     }
     if not args.no_cpu:

@@ -288,7 +288,7 @@ typedef struct eag_server eag_server;
 typedef struct {
   void* arena;                  /* device memory owned by the caller            */
   size_t arena_bytes;
-  int32_t max_live_requests;    /* slots, 1..64                                 */
+  int32_t max_live_requests;    /* slots, 1..8                                  */
   int64_t paths_per_launch;     /* work quantum of one launch (all live requests) */
   void* stream;                 /* stream the server launches on                */
 } eag_server_config;

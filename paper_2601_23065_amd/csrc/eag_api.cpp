@@ -123,16 +123,16 @@ CamDev make_cam(const eag_camera& c, uint32_t id) {
   return d;
 }
 
-// Longest distance a ray of this camera can travel inside the scene box.
+// Largest distance from the camera to a point of the scene box (its
+// farthest corner): no camera-ray hit lies farther.
 float camera_t_max(const eag_bvh* b, const eag_camera& c) {
-  double d2 = 0, diag2 = 0;
+  double d2 = 0;
   for (int a = 0; a < 3; ++a) {
     const double lo = b->lo[a], hi = b->hi[a], e = c.eye[a];
     const double far = std::fmax(std::fabs(e - lo), std::fabs(e - hi));
     d2 += far * far;
-    diag2 += (hi - lo) * (hi - lo);
   }
-  return (float)(std::sqrt(d2) + std::sqrt(diag2));
+  return (float)std::sqrt(d2);
 }
 
 float scene_t_max(const eag_bvh* b) {

@@ -380,7 +380,7 @@ struct NoHit {
 // deeper entries (rare) spill to a private array.
 constexpr int STACK_LDS = 24;
 constexpr int TRACE_BLOCK = 256;   // every tracing kernel runs 256-thread blocks
-constexpr int PEND = 8;            // postponed leaves per lane
+constexpr int PEND = 32;           // postponed leaves per lane
 
 struct TravStack {
   int* lds;        // this lane's column: lds[i * TRACE_BLOCK]

@@ -10,8 +10,10 @@
 //     free and their fixed-point accumulator fits the arena's request pool
 //     (first fit);
 //   * each iteration launches the multi-request path-tracing kernel over a
-//     quantum of work split evenly across the live requests, so requests
-//     that arrive while others run join the next launch and share the GPU;
+//     budget of paths taken by the live requests oldest first, so the order
+//     is FIFO's while requests that arrive meanwhile fill the rest of the
+//     GPU from the next launch on (requests whose ray-segment parameters
+//     differ from the oldest one's wait for a launch of their own);
 //   * a request whose work is complete is resolved into its output image and
 //     retired; latency = completion - submit.
 // Results do not depend on batching: each path's random numbers come from
@@ -290,17 +292,29 @@ void eag_server::run() {
         cv.wait_for(lk, std::chrono::milliseconds(2));
         continue;
       }
-      // ---- one launch over every live request
+      // ---- one launch: live requests in arrival order take work until the
+      // launch's path budget is spent (the oldest first, so the order is
+      // FIFO's, and younger requests fill what the older ones leave). One
+      // launch traces with one set of ray-segment parameters, so it takes
+      // only requests whose T_min, t_min, k_sigma and depth_quantum equal
+      // the oldest live request's.
       PtLaunch L;
       std::memset(&L, 0, sizeof(L));
-      const int nl = (int)live.size();
-      const int64_t quota = std::max<int64_t>(cfg.paths_per_launch / nl, 4096);
+      const eag_trace_params& p0 = live[0]->r.params;
+      int64_t budget = std::max<int64_t>(cfg.paths_per_launch, 1);
       int64_t total = 0;
-      std::vector<int64_t> take(nl);
-      for (int i = 0; i < nl; ++i) {
+      std::vector<std::pair<Req*, int64_t>> take;
+      for (size_t i = 0; i < live.size() && budget > 0; ++i) {
         Req& r = *live[i];
-        take[i] = std::min(quota, r.total - r.done);
-        PtSlot& S = L.s[i];
+        const eag_trace_params& q = r.r.params;
+        if (q.T_min != p0.T_min || q.t_min != p0.t_min || q.k_sigma != p0.k_sigma ||
+            q.depth_quantum != p0.depth_quantum)
+          continue;
+        const int64_t t = std::min(budget, r.total - r.done);
+        if (t <= 0) continue;
+        budget -= t;
+        PtSlot& S = L.s[take.size()];
+        take.emplace_back(&r, t);
         S.cam = make_cam(r.r.cam, r.r.params.camera_id);
         S.accum = r.accum;
         S.attrs = ver[r.version].attrs;
@@ -308,18 +322,17 @@ void eag_server::run() {
         S.tile_pixels = r.tile_pixels;
         S.tiles_x = (int32_t)r.tiles_x;
         S.sample_begin = 0;
-        S.max_depth = r.r.params.max_depth;
-        S.rr_start = r.r.params.rr_start;
-        S.flags = r.r.params.flags;
-        S.k0 = (uint32_t)(r.r.params.seed & 0xffffffffu);
-        S.k1 = (uint32_t)(r.r.params.seed >> 32);
-        S.tau_E = r.r.params.tau_E;
-        total += take[i];
+        S.max_depth = q.max_depth;
+        S.rr_start = q.rr_start;
+        S.flags = q.flags;
+        S.k0 = (uint32_t)(q.seed & 0xffffffffu);
+        S.k1 = (uint32_t)(q.seed >> 32);
+        S.tau_E = q.tau_E;
+        total += t;
         S.global_end = total;
       }
-      L.n_slots = nl;
+      L.n_slots = (int32_t)take.size();
       L.n_work = total;
-      const eag_trace_params& p0 = live[0]->r.params;
       TraceSetup ts;
       ts.idx_bits = bvh->idx_bits;
       const int bucket_bits = 64 - 2 * ts.idx_bits;
@@ -327,13 +340,12 @@ void eag_server::run() {
       ts.inv_dq = 1.0 / (double)p0.depth_quantum;
       const TraceCtx tc = make_ctx(bvh, nullptr, &p0, ts);
       lk.unlock();
-      launch_path_trace(tc, L, work, nullptr, hitlist, st);
-      check_hip(hipStreamSynchronize(st), "serve launch");
-      lk.lock();
-      for (int i = 0; i < nl; ++i) {
-        Req& r = *live[i];
-        r.done += take[i];
+      if (total > 0) {
+        launch_path_trace(tc, L, work, nullptr, hitlist, st);
+        check_hip(hipStreamSynchronize(st), "serve launch");
       }
+      lk.lock();
+      for (auto& [r, t] : take) r->done += t;
       // ---- retire finished requests
       for (auto it = live.begin(); it != live.end();) {
         Req& r = **it;

@@ -49,6 +49,28 @@ def test_mixed_equals_alone():
         assert torch.equal(out, ref), (cam.width, cam.height)
 
 
+def test_requests_with_different_segment_parameters():
+    """Requests whose T_min, t_min or k_sigma differ are never traced in one
+    launch with another request's values: each equals its render alone."""
+    import dataclasses
+    from paper_2601_23065_amd.api import BVH, Server
+    scene = _scene()
+    gs = gpu_scene(scene)
+    bvh = BVH(gs)
+    reqs = _requests(scene)
+    reqs = [(cam, dataclasses.replace(p, **kw)) for (cam, p), kw in
+            zip(reqs, ({}, {"T_min": 1e-2}, {"t_min": 1e-2}, {"k_sigma": 2.0}))]
+    srv = Server(gs, arena_bytes=64 << 20, max_live_requests=4, paths_per_launch=20000)
+    tickets = [srv.submit(cam, p) for cam, p in reqs]
+    res = [srv.wait(t) for t, _ in tickets]
+    srv.close()
+    for (cam, p), (t, out), r in zip(reqs, tickets, res):
+        assert r["status"] == 0
+        ref = _alone(gs, bvh, cam, p)
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref), p
+
+
 def test_edits_are_ordered_with_submits():
     from paper_2601_23065_amd import EDIT_SCALE_RADIANCE
     from paper_2601_23065_amd.api import BVH, Server, apply_edit
