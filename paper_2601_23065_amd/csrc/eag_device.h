@@ -155,13 +155,14 @@ struct TraceCtx {
   double k2;               // k_sigma^2
   double T_min;
   // Optional per-lane hit list (null: off). Entry j of this lane is
-  // hl[j * HL_STRIDE]; lanes of a wave interleave so that their accesses
-  // to the same entry share cache lines.
+  // hl[j * HL_STRIDE]. A lane's entries are contiguous: appends happen at
+  // different times in different lanes, and a lane filling its own cache
+  // lines writes each line back once.
   uint64_t* hl;
 };
 
 constexpr int HL_CAP = 128;        // entries per lane
-constexpr int HL_STRIDE = 64;      // lanes per wave
+constexpr int HL_STRIDE = 1;
 
 __device__ __forceinline__ uint64_t make_key(const TraceCtx& tc, double t, uint32_t idx, uint32_t pos) {
   uint32_t bucket;
@@ -414,10 +415,11 @@ __device__ __forceinline__ void kbuf_insert(uint64_t (&kk)[KBUF], uint64_t key) 
 // first hit with T < T_min, or when a round returns fewer than KBUF hits.
 //
 // With a hit list (tc.hl), a traversal round also records every accepted key
-// whose depth bucket does not exceed that of the round's KBUF-th key. Such a
-// round has tested every surfel of those buckets (boxes are culled only
-// beyond them), so the list then holds every hit key in (last, lhi) with lhi
-// the first key of the next bucket. A later round takes its keys from the
+// that the k-buffer rejects or evicts and whose depth bucket does not exceed
+// that of the round's KBUF-th key. Such a round has tested every surfel of
+// those buckets (boxes are culled only beyond them), so after blending the
+// round the list holds every hit key in (last, lhi) with lhi the first key
+// of the next bucket. A later round takes its keys from the
 // list when it finds KBUF of them there, and otherwise traverses only for
 // keys >= lhi; when the list holds some but fewer than KBUF such keys, they
 // are blended first as a round of their own, and the traversal beyond lhi
@@ -507,14 +509,14 @@ __device__ __forceinline__ bool round_begin(const TraceCtx& tc, Seg<DACC>& s, Ro
   r.partial = false;
   bool traverse = true;
   if (s.lhi != 0) {
-    // keys in (last, lhi) from the list, compacted in place
+    // keys in (last, lhi) from the list (entries at or below last were
+    // blended by earlier rounds and are skipped, not removed)
     uint64_t* const hl = tc.hl;
     int w = 0;
     r.plast = 0;
     for (int j = 0; j < s.nl; ++j) {
       const uint64_t k = hl[j * HL_STRIDE];
       if (k > s.last && k < s.lhi) {
-        if (w != j) hl[w * HL_STRIDE] = k;
         ++w;
         r.plast = k > r.plast ? k : r.plast;
         if (k < r.kk[KBUF - 1]) {
@@ -523,7 +525,7 @@ __device__ __forceinline__ bool round_begin(const TraceCtx& tc, Seg<DACC>& s, Ro
         }
       }
     }
-    s.nl = w;
+    if (w == 0) s.nl = 0;
     r.cnt = r.cnt > KBUF ? KBUF : r.cnt;
     if (r.cnt == KBUF || s.lhi == ~0ull) {
       traverse = false;
@@ -630,17 +632,21 @@ __device__ __forceinline__ void leaf_test(const TraceCtx& tc, Seg<DACC>& s, Roun
     key = make_key(tc, t, rec_index(rec), pos);
   }
   if (r.have_floor && key <= r.floor_key) return;
-  if (tc.hl && key < r.cut_key) {
-    if (s.nl < HL_CAP) tc.hl[(s.nl++) * HL_STRIDE] = key;
-    else r.over = true;
-  }
+  // The list needs only keys beyond the round's final KBUF-th key: a key
+  // goes there when the k-buffer rejects it or later evicts it.
+  uint64_t spill = key;
   if (key < r.kk[KBUF - 1]) {
+    spill = r.kk[KBUF - 1];   // ~0 while the buffer is not full
     kbuf_insert(r.kk, key);
     if (++r.cnt >= KBUF) {
       r.cnt = KBUF;
       r.t_cut = key_thi(tc, r.kk[KBUF - 1]) * 1.000002f + 1e-6f;
       r.cut_key = next_bucket_key(tc, r.kk[KBUF - 1]);
     }
+  }
+  if (tc.hl && spill < r.cut_key) {
+    if (s.nl < HL_CAP) tc.hl[(s.nl++) * HL_STRIDE] = spill;
+    else r.over = true;
   }
 }
 

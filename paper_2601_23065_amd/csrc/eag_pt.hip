@@ -59,9 +59,7 @@ __global__ void __launch_bounds__(TRACE_BLOCK) k_path_trace(TraceCtx tc, PtLaunc
   const int lane = (int)(threadIdx.x & 63);
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   TraceCtx tcl = tc;
-  tcl.hl = hitlist ? hitlist + ((int64_t)blockIdx.x * (TRACE_BLOCK / 64) + (threadIdx.x >> 6)) * (HL_CAP * HL_STRIDE) +
-                         lane
-                   : nullptr;
+  tcl.hl = hitlist ? hitlist + ((int64_t)blockIdx.x * TRACE_BLOCK + threadIdx.x) * HL_CAP : nullptr;
 
   int stage = ST_IDLE;
   int slot = 0;
