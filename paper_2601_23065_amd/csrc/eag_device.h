@@ -383,9 +383,12 @@ constexpr int STACK_LDS = 24;
 constexpr int TRACE_BLOCK = 256;   // every tracing kernel runs 256-thread blocks
 constexpr int PEND = 32;           // postponed leaves per lane
 
+// The overflow array is the caller's (a private array of the kernel): kept
+// out of this struct so that the struct itself stays in registers.
+constexpr int STACK_OVF = STACK_SIZE - STACK_LDS;
 struct TravStack {
   int* lds;        // this lane's column: lds[i * TRACE_BLOCK]
-  int ovf[STACK_SIZE - STACK_LDS];
+  int* ovf;        // this lane's overflow entries, STACK_OVF of them
   int sp;
   __device__ __forceinline__ void push(int v) {
     if (sp < STACK_LDS) lds[sp * TRACE_BLOCK] = v;
@@ -394,7 +397,10 @@ struct TravStack {
   }
   __device__ __forceinline__ int pop() {
     --sp;
-    return sp < STACK_LDS ? lds[sp * TRACE_BLOCK] : ovf[sp - STACK_LDS];
+    if (sp < STACK_LDS) return lds[sp * TRACE_BLOCK];
+    // volatile keeps the (rare) private read a load of its own, so that the
+    // common LDS read is not merged with it into a generic-address load
+    return static_cast<volatile int*>(ovf)[sp - STACK_LDS];
   }
 };
 
@@ -604,11 +610,11 @@ __device__ __forceinline__ void node_visit(const TraceCtx& tc, Seg<DACC>& s, Rou
   }
 }
 
-// Test the most recently postponed leaf and take its key if it qualifies.
+// Test one postponed leaf (its record already loaded) and take its key if it
+// qualifies.
 template <bool DACC>
-__device__ __forceinline__ void leaf_test(const TraceCtx& tc, Seg<DACC>& s, Round& r, int* pend) {
-  const uint32_t pos = (uint32_t)pend[(--r.np) * TRACE_BLOCK];
-  const Record rec = load_record(tc.recs, pos);
+__device__ __forceinline__ void leaf_eval(const TraceCtx& tc, Seg<DACC>& s, Round& r, const Record& rec,
+                                          uint32_t pos) {
   ++s.tests;
   uint32_t blo = 0, bhi = 0;
   const int fr = record_filter(rec, s.rf, (float)tc.t_min, (float)tc.k2, (float)tc.inv_dq, blo, bhi);
@@ -650,6 +656,29 @@ __device__ __forceinline__ void leaf_test(const TraceCtx& tc, Seg<DACC>& s, Roun
   }
 }
 
+// Test every postponed leaf, most recent first. The next leaf's record is
+// loaded before the current one is tested, so that its latency overlaps the
+// test's arithmetic.
+template <bool DACC>
+__device__ __forceinline__ void leaf_phase(const TraceCtx& tc, Seg<DACC>& s, Round& r, int* pend) {
+  if (r.np <= 0) return;
+  uint32_t pos = (uint32_t)pend[(--r.np) * TRACE_BLOCK];
+  Record rec = load_record(tc.recs, pos);
+  while (true) {
+    const bool more = r.np > 0;
+    uint32_t npos = 0;
+    Record nrec;
+    if (more) {
+      npos = (uint32_t)pend[(--r.np) * TRACE_BLOCK];
+      nrec = load_record(tc.recs, npos);
+    }
+    leaf_eval(tc, s, r, rec, pos);
+    if (!more) break;
+    pos = npos;
+    rec = nrec;
+  }
+}
+
 // After a traversal round: what the hit list now covers.
 template <bool DACC>
 __device__ __forceinline__ void round_end_traversal(const TraceCtx& tc, Seg<DACC>& s, const Round& r) {
@@ -665,7 +694,7 @@ __device__ __forceinline__ void traverse_round(const TraceCtx& tc, Seg<DACC>& s,
       node_visit(tc, s, r, st, pend);
       if (__all(r.np > 0 || !r.trav)) break;
     }
-    while (r.np > 0) leaf_test(tc, s, r, pend);
+    leaf_phase(tc, s, r, pend);
     if (!r.trav) break;
   }
   round_end_traversal(tc, s, r);
@@ -733,8 +762,10 @@ __device__ SegOut trace_segment_cb(const TraceCtx& tc, D3 O, D3 W, HitFn& on_hit
                                    int max_hits = 0) {
   __shared__ int s_stack[STACK_LDS * TRACE_BLOCK];
   __shared__ int s_pend[PEND * TRACE_BLOCK];
+  int s_ovf[STACK_OVF];
   TravStack st;
   st.lds = s_stack + threadIdx.x;
+  st.ovf = s_ovf;
   st.sp = 0;
   int* pend = s_pend + threadIdx.x;   // this lane's queue of postponed leaves
   Seg<DACC> s;

@@ -52,8 +52,10 @@ __global__ void __launch_bounds__(TRACE_BLOCK) k_path_trace(TraceCtx tc, PtLaunc
                                                             unsigned long long* counters, uint64_t* hitlist) {
   __shared__ int s_stack[STACK_LDS * TRACE_BLOCK];
   __shared__ int s_pend[PEND * TRACE_BLOCK];
+  int s_ovf[STACK_OVF];
   TravStack st;
   st.lds = s_stack + threadIdx.x;
+  st.ovf = s_ovf;
   st.sp = 0;
   int* const pend = s_pend + threadIdx.x;
   const int lane = (int)(threadIdx.x & 63);
@@ -131,7 +133,7 @@ __global__ void __launch_bounds__(TRACE_BLOCK) k_path_trace(TraceCtx tc, PtLaunc
           node_visit(tcl, s, r, st, pend);
           if (__all(r.np > 0 || !r.trav)) break;
         }
-        while (r.np > 0) leaf_test(tcl, s, r, pend);
+        leaf_phase(tcl, s, r, pend);
         if (!r.trav) {
           round_end_traversal(tcl, s, r);
           stage = ST_BLEND;
