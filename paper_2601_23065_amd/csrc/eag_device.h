@@ -711,12 +711,28 @@ __device__ __forceinline__ void blend_round(const TraceCtx& tc, Seg<DACC>& s, Ro
                                            int32_t* hit_out, int max_hits) {
   using Acc = typename Seg<DACC>::Acc;
   const uint64_t round_last = r.partial ? r.plast : r.kk[KBUF - 1];
+  // the next hit's record and attributes are loaded while the current one
+  // is blended
+  Record rec;
+  Attr at;
+  if (r.cnt > 0) {
+    const uint32_t p0 = key_pos(tc, r.kk[0]);
+    rec = load_record(tc.recs, p0);
+    at = tc.attrs[p0];
+  }
   for (int j = 0; j < r.cnt && !s.done; ++j) {
     const uint64_t key = r.kk[0];
 #pragma unroll
     for (int m = 0; m < KBUF - 1; ++m) r.kk[m] = r.kk[m + 1];
     const uint32_t pos = key_pos(tc, key);
-    const Geo ge = surfel_geo(load_record(tc.recs, pos));
+    Record nrec;
+    Attr nat;
+    if (j + 1 < r.cnt) {
+      const uint32_t np = key_pos(tc, r.kk[0]);
+      nrec = load_record(tc.recs, np);
+      nat = tc.attrs[np];
+    }
+    const Geo ge = surfel_geo(rec);
     double t = 0.0, q2 = 0.0;
     surfel_test(ge, s.O, s.W, -1e300, 1e300, t, q2);
     const double a = ge.sigma * exp(-0.5 * q2);
@@ -728,25 +744,21 @@ __device__ __forceinline__ void blend_round(const TraceCtx& tc, Seg<DACC>& s, Ro
       s.N.y += sw * ge.n.y;
       s.N.z += sw * ge.n.z;
       s.D += w * t;
-      const Attr at = tc.attrs[pos];
       s.P0 += wf * at.rho_e.x;
       s.P1 += wf * at.rho_e.y;
       s.P2 += wf * at.rho_e.z;
       s.E += wf * at.rho_e.w;
-      s.R0 += wf * at.r.x;
-      s.R1 += wf * at.r.y;
-      s.R2 += wf * at.r.z;
-    } else {
-      const float4 rr = tc.attrs[pos].r;
-      s.R0 += wf * rr.x;
-      s.R1 += wf * rr.y;
-      s.R2 += wf * rr.z;
     }
+    s.R0 += wf * at.r.x;
+    s.R1 += wf * at.r.y;
+    s.R2 += wf * at.r.z;
     if (hit_out && s.nhits < max_hits) hit_out[s.nhits] = (int32_t)key_idx(tc, key);
     on_hit(pos, t, a, w, s.T);
     ++s.nhits;
     s.T *= (1.0 - a);
     if (s.T < tc.T_min) s.done = true;
+    rec = nrec;
+    at = nat;
   }
   if (r.cnt < KBUF && !r.partial) s.done = true;
   if (!s.done) {
