@@ -161,8 +161,9 @@ struct TraceCtx {
   uint64_t* hl;
 };
 
-constexpr int HL_CAP = 128;        // entries per lane
+constexpr int HL_CAP = 128;        // entries per lane (a multiple of 8: the list is scanned 8 at a time)
 constexpr int HL_STRIDE = 1;
+static_assert(HL_CAP % 8 == 0 && HL_STRIDE == 1, "hit-list scan reads 8 contiguous entries");
 
 __device__ __forceinline__ uint64_t make_key(const TraceCtx& tc, double t, uint32_t idx, uint32_t pos) {
   uint32_t bucket;
@@ -284,6 +285,18 @@ __device__ __forceinline__ bool record_test(const Record& r, D3 O, D3 W, double 
   const double u = dot(yv, tu) / (double)r.s_idx.x;
   const double v = dot(yv, tv) / (double)r.s_idx.y;
   return u * u + v * v <= k2;
+}
+
+// Distance along the ray to the surfel's plane, in double precision, for a
+// surfel the filter has already accepted. The third column of the rotation
+// of the unnormalised quaternion is |q|^2 n, and the factor cancels in
+// t = ((p - O).n) / (W.n), so neither the normalisation nor the tangent
+// axes are needed.
+__device__ __forceinline__ double record_t(const Record& r, D3 O, D3 W) {
+  const double w = r.q.x, x = r.q.y, y = r.q.z, z = r.q.w;
+  const D3 m = d3(2.0 * (x * z + w * y), 2.0 * (y * z - w * x), w * w - x * x - y * y + z * z);
+  const D3 d = d3((double)r.p_sigma.x - O.x, (double)r.p_sigma.y - O.y, (double)r.p_sigma.z - O.z);
+  return dot(d, m) / dot(W, m);
 }
 
 // Float32 filter for the surfel test. It evaluates the same formulas in
@@ -517,17 +530,29 @@ __device__ __forceinline__ bool round_begin(const TraceCtx& tc, Seg<DACC>& s, Ro
   if (s.lhi != 0) {
     // keys in (last, lhi) from the list (entries at or below last were
     // blended by earlier rounds and are skipped, not removed)
-    uint64_t* const hl = tc.hl;
+    // (loaded 8 at a time: entries up to HL_CAP are this lane's, those past
+    // nl are ignored)
+    const uint64_t* const hl = tc.hl;
     int w = 0;
     r.plast = 0;
-    for (int j = 0; j < s.nl; ++j) {
-      const uint64_t k = hl[j * HL_STRIDE];
-      if (k > s.last && k < s.lhi) {
-        ++w;
-        r.plast = k > r.plast ? k : r.plast;
-        if (k < r.kk[KBUF - 1]) {
-          kbuf_insert(r.kk, k);
-          ++r.cnt;
+    for (int j = 0; j < s.nl; j += 8) {
+      uint64_t e[8];
+#pragma unroll
+      for (int u = 0; u < 8; u += 2) {
+        const ulonglong2 v = *reinterpret_cast<const ulonglong2*>(hl + j + u);
+        e[u] = v.x;
+        e[u + 1] = v.y;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const uint64_t k = e[u];
+        if (j + u < s.nl && k > s.last && k < s.lhi) {
+          ++w;
+          r.plast = k > r.plast ? k : r.plast;
+          if (k < r.kk[KBUF - 1]) {
+            kbuf_insert(r.kk, k);
+            ++r.cnt;
+          }
         }
       }
     }
@@ -625,13 +650,8 @@ __device__ __forceinline__ void leaf_eval(const TraceCtx& tc, Seg<DACC>& s, Roun
     const uint64_t klo = make_key_b(tc, blo, 0u, 0u), khi = make_key_b(tc, bhi + 1u, 0u, 0u);
     if (r.have_floor && khi <= r.floor_key) return;
     if (klo >= (tc.hl ? r.cut_key : r.kk[KBUF - 1])) return;
-    if (blo == bhi) {
-      key = make_key_b(tc, blo, rec_index(rec), pos);
-    } else {
-      double t;
-      record_test(rec, s.O, s.W, -1e300, 1e300, t);
-      key = make_key(tc, t, rec_index(rec), pos);
-    }
+    key = blo == bhi ? make_key_b(tc, blo, rec_index(rec), pos)
+                     : make_key(tc, record_t(rec, s.O, s.W), rec_index(rec), pos);
   } else {
     double t;
     if (!record_test(rec, s.O, s.W, tc.t_min, tc.k2, t)) return;
