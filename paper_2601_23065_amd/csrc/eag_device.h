@@ -417,14 +417,19 @@ struct TravStack {
   }
 };
 
-// Accept a candidate key into the sorted k-buffer (ascending; empty = ~0).
-__device__ __forceinline__ void kbuf_insert(uint64_t (&kk)[KBUF], uint64_t key) {
-  int p = 0;
+// Accept a candidate key into the sorted k-buffer (ascending; empty = ~0):
+// one compare-exchange per entry carries the larger key down the buffer.
+// Returns the key that falls off the end (the old last entry, or the
+// candidate itself when it is not below it).
+__device__ __forceinline__ uint64_t kbuf_insert(uint64_t (&kk)[KBUF], uint64_t key) {
 #pragma unroll
-  for (int j = 0; j < KBUF; ++j) p += (kk[j] < key) ? 1 : 0;
-#pragma unroll
-  for (int j = KBUF - 1; j > 0; --j) kk[j] = (j > p) ? kk[j - 1] : (j == p ? key : kk[j]);
-  kk[0] = (p == 0) ? key : kk[0];
+  for (int j = 0; j < KBUF; ++j) {
+    const bool lt = key < kk[j];
+    const uint64_t lo = lt ? key : kk[j];
+    key = lt ? kk[j] : key;
+    kk[j] = lo;
+  }
+  return key;
 }
 
 // ---------------------------------------------------------------------------
@@ -635,35 +640,43 @@ __device__ __forceinline__ void node_visit(const TraceCtx& tc, Seg<DACC>& s, Rou
   }
 }
 
-// Test one postponed leaf (its record already loaded) and take its key if it
-// qualifies.
-template <bool DACC>
-__device__ __forceinline__ void leaf_eval(const TraceCtx& tc, Seg<DACC>& s, Round& r, const Record& rec,
-                                          uint32_t pos) {
-  ++s.tests;
+// The order key of a postponed leaf (its record already loaded) for the ray
+// (O, W; rf its float copies) in a round whose keys must exceed floor_key
+// (when have_floor); ~0 when the surfel is missed or its key cannot enter
+// the round. cutlim: keys whose whole bucket range lies at or above it are
+// dropped early (the k-buffer's last key, or the hit list's cut; any larger
+// value is also correct).
+__device__ __forceinline__ uint64_t leaf_key(const TraceCtx& tc, const Record& rec, uint32_t pos, D3 O, D3 W,
+                                             const RayF& rf, bool have_floor, uint64_t floor_key,
+                                             uint64_t cutlim) {
   uint32_t blo = 0, bhi = 0;
-  const int fr = record_filter(rec, s.rf, (float)tc.t_min, (float)tc.k2, (float)tc.inv_dq, blo, bhi);
-  if (fr == FILTER_REJECT) return;
+  const int fr = record_filter(rec, rf, (float)tc.t_min, (float)tc.k2, (float)tc.inv_dq, blo, bhi);
+  if (fr == FILTER_REJECT) return ~0ull;
   uint64_t key;
   if (fr == FILTER_ACCEPT) {
     // whole-bucket bounds decide most keys without the exact distance
     const uint64_t klo = make_key_b(tc, blo, 0u, 0u), khi = make_key_b(tc, bhi + 1u, 0u, 0u);
-    if (r.have_floor && khi <= r.floor_key) return;
-    if (klo >= (tc.hl ? r.cut_key : r.kk[KBUF - 1])) return;
+    if (have_floor && khi <= floor_key) return ~0ull;
+    if (klo >= cutlim) return ~0ull;
     key = blo == bhi ? make_key_b(tc, blo, rec_index(rec), pos)
-                     : make_key(tc, record_t(rec, s.O, s.W), rec_index(rec), pos);
+                     : make_key(tc, record_t(rec, O, W), rec_index(rec), pos);
   } else {
     double t;
-    if (!record_test(rec, s.O, s.W, tc.t_min, tc.k2, t)) return;
+    if (!record_test(rec, O, W, tc.t_min, tc.k2, t)) return ~0ull;
     key = make_key(tc, t, rec_index(rec), pos);
   }
-  if (r.have_floor && key <= r.floor_key) return;
-  // The list needs only keys beyond the round's final KBUF-th key: a key
-  // goes there when the k-buffer rejects it or later evicts it.
+  if (have_floor && key <= floor_key) return ~0ull;
+  return key;
+}
+
+// Take a qualifying key into the round. The list needs only keys beyond the
+// round's final KBUF-th key: a key goes there when the k-buffer rejects it
+// or later evicts it.
+template <bool DACC>
+__device__ __forceinline__ void take_key(const TraceCtx& tc, Seg<DACC>& s, Round& r, uint64_t key) {
   uint64_t spill = key;
   if (key < r.kk[KBUF - 1]) {
-    spill = r.kk[KBUF - 1];   // ~0 while the buffer is not full
-    kbuf_insert(r.kk, key);
+    spill = kbuf_insert(r.kk, key);   // ~0 while the buffer is not full
     if (++r.cnt >= KBUF) {
       r.cnt = KBUF;
       r.t_cut = key_thi(tc, r.kk[KBUF - 1]) * 1.000002f + 1e-6f;
@@ -674,6 +687,20 @@ __device__ __forceinline__ void leaf_eval(const TraceCtx& tc, Seg<DACC>& s, Roun
     if (s.nl < HL_CAP) tc.hl[(s.nl++) * HL_STRIDE] = spill;
     else r.over = true;
   }
+}
+
+template <bool DACC>
+__device__ __forceinline__ uint64_t round_cutlim(const TraceCtx& tc, const Round& r) {
+  return tc.hl ? r.cut_key : r.kk[KBUF - 1];
+}
+
+// Test one postponed leaf of this lane's own ray and take its key.
+template <bool DACC>
+__device__ __forceinline__ void leaf_eval(const TraceCtx& tc, Seg<DACC>& s, Round& r, const Record& rec,
+                                          uint32_t pos) {
+  ++s.tests;
+  const uint64_t key = leaf_key(tc, rec, pos, s.O, s.W, s.rf, r.have_floor, r.floor_key, round_cutlim<DACC>(tc, r));
+  if (key != ~0ull) take_key(tc, s, r, key);
 }
 
 // Test every postponed leaf, most recent first. The next leaf's record is
