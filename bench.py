@@ -66,7 +66,7 @@ def _oracle_worker(args):
 _ORACLE = {}
 
 
-def cpu_baseline(scene, cam, params, budget_paths=96):
+def cpu_baseline(scene, cam, params, budget_paths=1024):
     """Oracle segments/s on a fixed sample of the workload's paths, across
     the host cores with a fork pool."""
     import multiprocessing as mp
