@@ -23,6 +23,10 @@ Two further workloads print their own JSON line (not the default run):
                        zeroed on a random half of the emitters, albedo redrawn
                        on a random 10% of the surfels in 8 groups), a refit,
                        and the same 256 spp again.
+  --workload sb100k    single-bounce reconstruction step: 100k surfels in a
+                       6x4x3 m room with 12 boxes, 8 cameras at 256x256,
+                       8 spp, forward render + adjoint of an L2 loss against
+                       the render of a perturbed copy of the scene.
   --workload serve     continuous-batching server against one-at-a-time FIFO
                        on the same Poisson arrivals over a resident 3M-surfel
                        room (request mix scaled down: 128x128 or 256x256,
@@ -30,7 +34,7 @@ Two further workloads print their own JSON line (not the default run):
                        FIFO service rate; latency percentiles per load.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
-                       [--workload room1m|rooms5m|serve]
+                       [--workload room1m|rooms5m|sb100k|serve]
 """
 import argparse
 import glob
@@ -230,6 +234,77 @@ def bench_rooms5m(torch, args):
     }
     print(json.dumps(rec))
 
+def bench_sb100k(torch, args):
+    """Single-bounce reconstruction step on the 100k-surfel room (one JSON
+    line): forward render of 8 cameras, then the adjoint of an L2 loss
+    against the render of a perturbed copy of the scene."""
+    import scenegen as sg
+    from paper_2601_23065_amd.api import BVH, Params, Scene, SingleBounceRender, render_single_bounce
+
+    scene, cams, cfg = sg.config(2, n_override=args.surfels)
+    p = Params(spp=args.spp or cfg["spp"], seed=0)
+    tgt = sg.perturb(scene)
+    gt = Scene(tgt.arrays())
+    target = render_single_bounce(BVH(gt), gt, cams, p)
+    gs = Scene(scene.arrays())
+    bvh = BVH(gs)
+    leaves = {k: getattr(gs, k).clone().requires_grad_(k != "emissive")
+              for k in ("pos", "rot", "scale", "opacity", "albedo", "radiance", "emissive")}
+    # rays of one forward: a camera segment per pixel, spp secondary segments per reflecting pixel
+    _, state = render_single_bounce(bvh, gs, cams, p, keep_state=True)
+    npix = len(cams) * cams[0].width * cams[0].height
+    reflect = int((state[:npix * 28].view(npix, 28)[:, 25] == 2.0).sum())
+    rays = npix + reflect * p.spp
+    _log(f"scene ready: {scene.n} surfels, {len(cams)} cameras {cams[0].width}x{cams[0].height}, {p.spp} spp, "
+         f"{rays} segments per forward")
+    stream = torch.cuda.current_stream()
+
+    def step():
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        for v in leaves.values():
+            v.grad = None
+        e[0].record(stream)
+        rgb = SingleBounceRender.apply(*leaves.values(), bvh, gs, cams, p)
+        e[1].record(stream)
+        loss = ((rgb - target) ** 2).sum()
+        loss.backward()
+        e[2].record(stream)
+        return e
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    evs = [step() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    fwd = float(np.mean([a.elapsed_time(b) for a, b, _ in evs]))
+    bwd = float(np.mean([b.elapsed_time(c) for _, b, c in evs]))
+    gnorm = {k: float(v.grad.norm()) for k, v in leaves.items() if v.grad is not None}
+    rec = {
+        "metric": "Mrays/s single-bounce forward (segments traced per second)",
+        "value": round(rays / (fwd * 1e-3) / 1e6, 3),
+        "unit": "Mrays/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"single-bounce reconstruction step, {scene.n} surfels in a 6x4x3 m room with 12 "
+                               f"boxes, {len(cams)} cameras {cams[0].width}x{cams[0].height}, {p.spp} spp; step = "
+                               f"forward render + adjoint of an L2 loss against a perturbed scene's render",
+                   "surfels": scene.n, "cameras": len(cams), "width": cams[0].width, "height": cams[0].height,
+                   "spp": p.spp},
+        "detail": {"forward_ms": round(fwd, 3), "backward_ms": round(bwd, 3), "segments_per_forward": rays,
+                   "backward_Mrays_per_s": round(rays / (bwd * 1e-3) / 1e6, 3), "grad_norms": gnorm},
+    }
+    print(json.dumps(rec))
+
+
 
 def bench_serve(torch, args):
     """Continuous batching against FIFO on the same arrivals (one JSON line)."""
@@ -343,7 +418,7 @@ def main():
     ap.add_argument("--surfels", type=int, default=None, help="override the workload's surfel count")
     ap.add_argument("--requests", type=int, default=100, help="requests per run of the serve workload")
     ap.add_argument("--spp", type=int, default=None, help="override the workload's 64 spp (diagnostics only)")
-    ap.add_argument("--workload", default="room1m", choices=["room1m", "rooms5m", "serve"])
+    ap.add_argument("--workload", default="room1m", choices=["room1m", "rooms5m", "serve", "sb100k"])
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run an elementwise copy of MIB MiB three times (HBM counter calibration)")
     args = ap.parse_args()
@@ -362,6 +437,9 @@ def main():
         return
     if args.workload == "serve":
         bench_serve(torch, args)
+        return
+    if args.workload == "sb100k":
+        bench_sb100k(torch, args)
         return
 
     import scenegen as sg
