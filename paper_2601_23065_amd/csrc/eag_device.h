@@ -703,16 +703,19 @@ __device__ __forceinline__ void leaf_eval(const TraceCtx& tc, Seg<DACC>& s, Roun
   if (key != ~0ull) take_key(tc, s, r, key);
 }
 
-// Test every postponed leaf, most recent first. The next leaf's record is
-// loaded before the current one is tested, so that its latency overlaps the
-// test's arithmetic.
+// Test postponed leaves, most recent first. The next leaf's record is loaded
+// before the current one is tested, so that its latency overlaps the test's
+// arithmetic. A lane whose traversal continues stops once fewer than
+// LEAF_MIN_LANES lanes of the wave still hold leaves, and keeps the rest for
+// its next leaf phase; a lane whose traversal has ended tests all of them.
+constexpr int LEAF_MIN_LANES = 16;
 template <bool DACC>
 __device__ __forceinline__ void leaf_phase(const TraceCtx& tc, Seg<DACC>& s, Round& r, int* pend) {
   if (r.np <= 0) return;
   uint32_t pos = (uint32_t)pend[(--r.np) * TRACE_BLOCK];
   Record rec = load_record(tc.recs, pos);
   while (true) {
-    const bool more = r.np > 0;
+    const bool more = r.np > 0 && !(r.trav && __popcll(__ballot(r.np > 0)) < LEAF_MIN_LANES);
     uint32_t npos = 0;
     Record nrec;
     if (more) {
