@@ -301,8 +301,10 @@ __device__ __forceinline__ double record_t(const Record& r, D3 O, D3 W) {
 
 // Float32 filter for the surfel test. It evaluates the same formulas in
 // float with a bound on their distance from the double-precision values
-// (unit roundoff 2^-24 times the magnitudes involved, with a safety factor),
-// and decides only where the bound cannot change the outcome:
+// (unit roundoff 2^-24 times the magnitudes involved, with a safety factor
+// several times what the operations need, which also covers the 1-ulp
+// hardware reciprocal and reciprocal square root used here), and decides
+// only where the bound cannot change the outcome:
 //   REJECT  - the double test rejects (t <= t_min or outside the ellipse)
 //   ACCEPT  - the double test accepts, and t's bucket is known exactly
 //             (bucket_out), or at least bounded by [blo, bhi]
@@ -318,7 +320,7 @@ __device__ __forceinline__ int record_filter(const Record& r, const RayF& rf, fl
   constexpr float U = 5.9604645e-08f;   // 2^-24
   if (!(r.p_sigma.w > 0.0f)) return FILTER_REJECT;
   float w = r.q.x, x = r.q.y, y = r.q.z, z = r.q.w;
-  const float iq = 1.0f / sqrtf(w * w + x * x + y * y + z * z);
+  const float iq = __builtin_amdgcn_rsqf(w * w + x * x + y * y + z * z);
   w *= iq; x *= iq; y *= iq; z *= iq;
   const V3 tu = v3(1.0f - 2.0f * (y * y + z * z), 2.0f * (x * y + w * z), 2.0f * (x * z - w * y));
   const V3 tv = v3(2.0f * (x * y - w * z), 1.0f - 2.0f * (x * x + z * z), 2.0f * (y * z + w * x));
@@ -327,21 +329,25 @@ __device__ __forceinline__ int record_filter(const Record& r, const RayF& rf, fl
   const float aden = fabsf(den);
   if (!(aden > 1e-3f)) return FILTER_EXACT;
   const V3 d = v3(r.p_sigma.x - rf.O.x, r.p_sigma.y - rf.O.y, r.p_sigma.z - rf.O.z);
-  const float t = dot(d, n) / den;
+  const float iden = __builtin_amdgcn_rcpf(den);
+  const float t = dot(d, n) * iden;
   const float mag = fabsf(r.p_sigma.x) + fabsf(r.p_sigma.y) + fabsf(r.p_sigma.z) + rf.Osum + fabsf(t);
-  const float et = 256.0f * U * mag / aden;
+  const float et = 256.0f * U * mag * fabsf(iden);
+  // (comparisons are arranged so that a NaN, from degenerate scales or
+  // quaternions, always falls through to the exact test)
   if (t + et <= t_min) return FILTER_REJECT;
-  if (t - et <= t_min) return FILTER_EXACT;
+  if (!(t - et > t_min)) return FILTER_EXACT;
   const V3 yv = v3(t * rf.W.x - d.x, t * rf.W.y - d.y, t * rf.W.z - d.z);
   const float yl = fabsf(yv.x) + fabsf(yv.y) + fabsf(yv.z);
   const float ey = 2.0f * et + 64.0f * U * (mag + yl);
   const float su = r.s_idx.x, sv = r.s_idx.y;
-  const float u = dot(yv, tu) / su, v = dot(yv, tv) / sv;
-  const float eu = ey / su + 8.0f * U * fabsf(u), ev = ey / sv + 8.0f * U * fabsf(v);
+  const float isu = __builtin_amdgcn_rcpf(su), isv = __builtin_amdgcn_rcpf(sv);
+  const float u = dot(yv, tu) * isu, v = dot(yv, tv) * isv;
+  const float eu = ey * isu + 8.0f * U * fabsf(u), ev = ey * isv + 8.0f * U * fabsf(v);
   const float q2 = u * u + v * v;
   const float eq = 2.0f * (fabsf(u) * eu + fabsf(v) * ev) + eu * eu + ev * ev + 16.0f * U * q2;
   if (q2 - eq > k2) return FILTER_REJECT;
-  if (q2 + eq > k2) return FILTER_EXACT;
+  if (!(q2 + eq <= k2)) return FILTER_EXACT;
   if (inv_dq > 0.0f) {
     // widened by half the bound so that rounding of t -+ et cannot cross a bucket edge
     const float lo = floorf((t - 1.5f * et) * inv_dq), hi = floorf((t + 1.5f * et) * inv_dq);

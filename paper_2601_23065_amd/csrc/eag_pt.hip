@@ -36,7 +36,7 @@ namespace eag {
 
 namespace {
 
-constexpr int PT_BLEND_BATCH = 32;   // lanes waiting to blend that end a traversal stretch
+constexpr int PT_BLEND_BATCH = 20;   // lanes waiting to blend that end a traversal stretch
 
 enum { ST_IDLE = 0, ST_ROUND = 1, ST_TRAV = 2, ST_BLEND = 3 };
 
