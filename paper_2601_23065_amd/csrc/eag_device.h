@@ -621,7 +621,10 @@ __device__ __forceinline__ void node_visit(const TraceCtx& tc, Seg<DACC>& s, Rou
   for (int k = 0; k < 4; ++k) {
     // a missed box reports +inf, which must not pass an infinite cut
     const bool m = c[k] != NODE4_EMPTY && e[k] < __builtin_inff() && e[k] <= r.t_cut;
-    if (m && c[k] < 0) pend[(r.np++) * TRACE_BLOCK] = ~c[k];
+    // leaves are queued without a branch: the slot past the queue is always
+    // written (nodes are visited only while np <= PEND - 4, so it exists)
+    pend[r.np * TRACE_BLOCK] = ~c[k];
+    r.np += (m && c[k] < 0) ? 1 : 0;
     ie[k] = (m && c[k] >= 0) ? e[k] : __builtin_inff();
     ic[k] = c[k];
     ni += (m && c[k] >= 0) ? 1 : 0;
@@ -635,9 +638,20 @@ __device__ __forceinline__ void node_visit(const TraceCtx& tc, Seg<DACC>& s, Rou
     }
     EAG_CSWAP(0, 1) EAG_CSWAP(2, 3) EAG_CSWAP(0, 2) EAG_CSWAP(1, 3) EAG_CSWAP(1, 2)
 #undef EAG_CSWAP
-    if (ni > 3) st.push(ic[3]);
-    if (ni > 2) st.push(ic[2]);
-    if (ni > 1) st.push(ic[1]);
+    // push the others farthest first: bottom to top ic[ni-1] .. ic[1]
+    if (st.sp + 3 <= STACK_LDS) {
+      // branch-free: three slots written, the stack grows by ni - 1
+      const int v0 = ni > 3 ? ic[3] : (ni > 2 ? ic[2] : ic[1]);
+      const int v1 = ni > 3 ? ic[2] : ic[1];
+      st.lds[(st.sp + 0) * TRACE_BLOCK] = v0;
+      st.lds[(st.sp + 1) * TRACE_BLOCK] = v1;
+      st.lds[(st.sp + 2) * TRACE_BLOCK] = ic[1];
+      st.sp += ni - 1;
+    } else {
+      if (ni > 3) st.push(ic[3]);
+      if (ni > 2) st.push(ic[2]);
+      if (ni > 1) st.push(ic[1]);
+    }
     r.ref = ic[0];
   } else if (st.sp > 0) {
     r.ref = st.pop();
