@@ -318,7 +318,10 @@ struct RayF {
 __device__ __forceinline__ int record_filter(const Record& r, const RayF& rf, float t_min, float k2, float inv_dq,
                                              uint32_t& blo, uint32_t& bhi) {
   constexpr float U = 5.9604645e-08f;   // 2^-24
-  if (!(r.p_sigma.w > 0.0f)) return FILTER_REJECT;
+  // Everything is evaluated and the decisions are combined at the end, with
+  // no branches: the wave would run both sides of each anyway. Comparisons
+  // are arranged so that a NaN (degenerate scales or quaternion) always
+  // lands in EXACT or REJECT through the paths the exact test agrees with.
   float w = r.q.x, x = r.q.y, y = r.q.z, z = r.q.w;
   const float iq = __builtin_amdgcn_rsqf(w * w + x * x + y * y + z * z);
   w *= iq; x *= iq; y *= iq; z *= iq;
@@ -327,16 +330,11 @@ __device__ __forceinline__ int record_filter(const Record& r, const RayF& rf, fl
   const V3 n = cross(tu, tv);
   const float den = dot(rf.W, n);
   const float aden = fabsf(den);
-  if (!(aden > 1e-3f)) return FILTER_EXACT;
   const V3 d = v3(r.p_sigma.x - rf.O.x, r.p_sigma.y - rf.O.y, r.p_sigma.z - rf.O.z);
   const float iden = __builtin_amdgcn_rcpf(den);
   const float t = dot(d, n) * iden;
   const float mag = fabsf(r.p_sigma.x) + fabsf(r.p_sigma.y) + fabsf(r.p_sigma.z) + rf.Osum + fabsf(t);
   const float et = 256.0f * U * mag * fabsf(iden);
-  // (comparisons are arranged so that a NaN, from degenerate scales or
-  // quaternions, always falls through to the exact test)
-  if (t + et <= t_min) return FILTER_REJECT;
-  if (!(t - et > t_min)) return FILTER_EXACT;
   const V3 yv = v3(t * rf.W.x - d.x, t * rf.W.y - d.y, t * rf.W.z - d.z);
   const float yl = fabsf(yv.x) + fabsf(yv.y) + fabsf(yv.z);
   const float ey = 2.0f * et + 64.0f * U * (mag + yl);
@@ -346,17 +344,15 @@ __device__ __forceinline__ int record_filter(const Record& r, const RayF& rf, fl
   const float eu = ey * isu + 8.0f * U * fabsf(u), ev = ey * isv + 8.0f * U * fabsf(v);
   const float q2 = u * u + v * v;
   const float eq = 2.0f * (fabsf(u) * eu + fabsf(v) * ev) + eu * eu + ev * ev + 16.0f * U * q2;
-  if (q2 - eq > k2) return FILTER_REJECT;
-  if (!(q2 + eq <= k2)) return FILTER_EXACT;
-  if (inv_dq > 0.0f) {
-    // widened by half the bound so that rounding of t -+ et cannot cross a bucket edge
-    const float lo = floorf((t - 1.5f * et) * inv_dq), hi = floorf((t + 1.5f * et) * inv_dq);
-    if (!(lo >= 0.0f) || hi >= 4.0e9f) return FILTER_EXACT;
-    blo = (uint32_t)lo;
-    bhi = (uint32_t)hi;
-    return FILTER_ACCEPT;
-  }
-  return FILTER_EXACT;
+  // widened by half the bound so that rounding of t -+ et cannot cross a bucket edge
+  const float lo = floorf((t - 1.5f * et) * inv_dq), hi = floorf((t + 1.5f * et) * inv_dq);
+  const bool geom = aden > 1e-3f;   // false for a NaN too
+  const bool reject = !(r.p_sigma.w > 0.0f) || (geom && (t + et <= t_min || q2 - eq > k2));
+  const bool exact = !geom || !(t - et > t_min) || !(q2 + eq <= k2) || !(inv_dq > 0.0f) || !(lo >= 0.0f) ||
+                     !(hi < 4.0e9f);
+  blo = exact ? 0u : (uint32_t)lo;
+  bhi = exact ? 0u : (uint32_t)hi;
+  return reject ? FILTER_REJECT : (exact ? FILTER_EXACT : FILTER_ACCEPT);
 }
 
 // ---------------------------------------------------------------------------
@@ -556,15 +552,13 @@ __device__ __forceinline__ bool round_begin(const TraceCtx& tc, Seg<DACC>& s, Ro
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        const uint64_t k = e[u];
-        if (j + u < s.nl && k > s.last && k < s.lhi) {
-          ++w;
-          r.plast = k > r.plast ? k : r.plast;
-          if (k < r.kk[KBUF - 1]) {
-            kbuf_insert(r.kk, k);
-            ++r.cnt;
-          }
-        }
+        // branch-free: a key outside (last, lhi) enters the chain as ~0
+        const bool in = j + u < s.nl && e[u] > s.last && e[u] < s.lhi;
+        const uint64_t k = in ? e[u] : ~0ull;
+        w += in ? 1 : 0;
+        r.plast = in && k > r.plast ? k : r.plast;
+        r.cnt += k < r.kk[KBUF - 1] ? 1 : 0;
+        kbuf_insert(r.kk, k);
       }
     }
     if (w == 0) s.nl = 0;
@@ -694,14 +688,15 @@ __device__ __forceinline__ uint64_t leaf_key(const TraceCtx& tc, const Record& r
 // or later evicts it.
 template <bool DACC>
 __device__ __forceinline__ void take_key(const TraceCtx& tc, Seg<DACC>& s, Round& r, uint64_t key) {
-  uint64_t spill = key;
-  if (key < r.kk[KBUF - 1]) {
-    spill = kbuf_insert(r.kk, key);   // ~0 while the buffer is not full
-    if (++r.cnt >= KBUF) {
-      r.cnt = KBUF;
-      r.t_cut = key_thi(tc, r.kk[KBUF - 1]) * 1.000002f + 1e-6f;
-      r.cut_key = next_bucket_key(tc, r.kk[KBUF - 1]);
-    }
+  // The insert runs without a branch: a key not below the last entry passes
+  // through the chain unchanged and comes back as the spill.
+  const bool ins = key < r.kk[KBUF - 1];
+  const uint64_t spill = kbuf_insert(r.kk, key);   // ~0 while the buffer is not full
+  r.cnt += ins ? 1 : 0;
+  if (ins && r.cnt >= KBUF) {
+    r.cnt = KBUF;
+    r.t_cut = key_thi(tc, r.kk[KBUF - 1]) * 1.000002f + 1e-6f;
+    r.cut_key = next_bucket_key(tc, r.kk[KBUF - 1]);
   }
   if (tc.hl && spill < r.cut_key) {
     if (s.nl < HL_CAP) tc.hl[(s.nl++) * HL_STRIDE] = spill;
