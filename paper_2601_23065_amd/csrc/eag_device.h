@@ -665,22 +665,34 @@ __device__ __forceinline__ uint64_t leaf_key(const TraceCtx& tc, const Record& r
                                              uint64_t cutlim) {
   uint32_t blo = 0, bhi = 0;
   const int fr = record_filter(rec, rf, (float)tc.t_min, (float)tc.k2, (float)tc.inv_dq, blo, bhi);
-  if (fr == FILTER_REJECT) return ~0ull;
-  uint64_t key;
-  if (fr == FILTER_ACCEPT) {
-    // whole-bucket bounds decide most keys without the exact distance
-    const uint64_t klo = make_key_b(tc, blo, 0u, 0u), khi = make_key_b(tc, bhi + 1u, 0u, 0u);
-    if (have_floor && khi <= floor_key) return ~0ull;
-    if (klo >= cutlim) return ~0ull;
-    key = blo == bhi ? make_key_b(tc, blo, rec_index(rec), pos)
-                     : make_key(tc, record_t(rec, O, W), rec_index(rec), pos);
-  } else {
-    double t;
-    if (!record_test(rec, O, W, tc.t_min, tc.k2, t)) return ~0ull;
-    key = make_key(tc, t, rec_index(rec), pos);
-  }
-  if (have_floor && key <= floor_key) return ~0ull;
-  return key;
+  // whole-bucket bounds drop most keys that cannot enter the round
+  const uint64_t klo = make_key_b(tc, blo, 0u, 0u), khi = make_key_b(tc, bhi + 1u, 0u, 0u);
+  const bool early_out = fr == FILTER_ACCEPT && ((have_floor && khi <= floor_key) || klo >= cutlim);
+  // Double precision for every candidate, without branches (a wave nearly
+  // always holds some candidate that needs it). The columns of the rotation
+  // of the unnormalised quaternion are |q|^2 (t_u, t_v, n): the distance
+  // t = ((p - O).n) / (W.n) needs no normalisation, and the ellipse test
+  // becomes u'^2 / s_u^2 + v'^2 / s_v^2 <= k^2 |q|^4 with u' = y.(|q|^2 t_u).
+  // Its rounding differs from the normalised evaluation by a few ulp, well
+  // inside the margins within which rim and t_min decisions are flagged.
+  const double w = rec.q.x, x = rec.q.y, y = rec.q.z, z = rec.q.w;
+  const double q2n = w * w + x * x + y * y + z * z;
+  const D3 cu = d3(w * w + x * x - y * y - z * z, 2.0 * (x * y + w * z), 2.0 * (x * z - w * y));
+  const D3 cv = d3(2.0 * (x * y - w * z), w * w - x * x + y * y - z * z, 2.0 * (y * z + w * x));
+  const D3 cn = d3(2.0 * (x * z + w * y), 2.0 * (y * z - w * x), w * w - x * x - y * y + z * z);
+  const D3 d = d3((double)rec.p_sigma.x - O.x, (double)rec.p_sigma.y - O.y, (double)rec.p_sigma.z - O.z);
+  const double den = dot(W, cn);
+  const double t = dot(d, cn) / den;
+  const D3 yv = d3(t * W.x - d.x, t * W.y - d.y, t * W.z - d.z);
+  const double su2 = (double)rec.s_idx.x * rec.s_idx.x, sv2 = (double)rec.s_idx.y * rec.s_idx.y;
+  const double up = dot(yv, cu), vp = dot(yv, cv);
+  // (multiplied through by s_u^2 s_v^2, all positive: no division)
+  const bool exact_ok = fabs(den) > 1e-12 * q2n && rec.p_sigma.w > 0.0f && t > tc.t_min &&
+                        up * up * sv2 + vp * vp * su2 <= tc.k2 * q2n * q2n * su2 * sv2;
+  const bool hit = (fr == FILTER_ACCEPT && !early_out) || (fr == FILTER_EXACT && exact_ok);
+  const uint64_t key = fr == FILTER_ACCEPT && blo == bhi ? make_key_b(tc, blo, rec_index(rec), pos)
+                                                         : make_key(tc, t, rec_index(rec), pos);
+  return hit && !(have_floor && key <= floor_key) ? key : ~0ull;
 }
 
 // Take a qualifying key into the round. The list needs only keys beyond the
