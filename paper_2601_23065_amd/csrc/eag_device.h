@@ -809,17 +809,26 @@ __device__ __forceinline__ void blend_round(const TraceCtx& tc, Seg<DACC>& s, Ro
       nrec = load_record(tc.recs, np);
       nat = tc.attrs[np];
     }
-    const Geo ge = surfel_geo(rec);
-    double t = 0.0, q2 = 0.0;
-    surfel_test(ge, s.O, s.W, -1e300, 1e300, t, q2);
-    const double a = ge.sigma * exp(-0.5 * q2);
+    // t, u, v and the unit normal from the columns of the unnormalised
+    // quaternion's rotation, |q|^2 (t_u, t_v, n): no square root
+    const double qw = rec.q.x, qx = rec.q.y, qy = rec.q.z, qz = rec.q.w;
+    const double iq2 = 1.0 / (qw * qw + qx * qx + qy * qy + qz * qz);
+    const D3 cu = d3(qw * qw + qx * qx - qy * qy - qz * qz, 2.0 * (qx * qy + qw * qz), 2.0 * (qx * qz - qw * qy));
+    const D3 cv = d3(2.0 * (qx * qy - qw * qz), qw * qw - qx * qx + qy * qy - qz * qz, 2.0 * (qy * qz + qw * qx));
+    const D3 cn = d3(2.0 * (qx * qz + qw * qy), 2.0 * (qy * qz - qw * qx), qw * qw - qx * qx - qy * qy + qz * qz);
+    const D3 dp = d3((double)rec.p_sigma.x - s.O.x, (double)rec.p_sigma.y - s.O.y, (double)rec.p_sigma.z - s.O.z);
+    const double dn = dot(s.W, cn);
+    const double t = dot(dp, cn) / dn;
+    const D3 yv = d3(t * s.W.x - dp.x, t * s.W.y - dp.y, t * s.W.z - dp.z);
+    const double u = dot(yv, cu) * iq2 / (double)rec.s_idx.x, v = dot(yv, cv) * iq2 / (double)rec.s_idx.y;
+    const double a = (double)rec.p_sigma.w * exp(-0.5 * (u * u + v * v));
     const double w = s.T * a;
     const Acc wf = (Acc)w;
     if (QMODE == Q_ALL) {
-      const double sw = dot(s.W, ge.n) > 0.0 ? -w : w;  // n' faces the origin
-      s.N.x += sw * ge.n.x;
-      s.N.y += sw * ge.n.y;
-      s.N.z += sw * ge.n.z;
+      const double sw = (dn > 0.0 ? -w : w) * iq2;  // n' faces the origin
+      s.N.x += sw * cn.x;
+      s.N.y += sw * cn.y;
+      s.N.z += sw * cn.z;
       s.D += w * t;
       s.P0 += wf * at.rho_e.x;
       s.P1 += wf * at.rho_e.y;
