@@ -208,10 +208,11 @@ __device__ __forceinline__ float key_thi(const TraceCtx& tc, uint64_t k) {
 }
 
 // ---------------------------------------------------------------------------
-// Ray-surfel test on the tangent plane (Eq. 1), in double precision: the
-// local coordinates come from a difference of nearly equal distances, and
-// float32 there would cost ~1e-5 in u at room scale, which the bounce point
-// and direction then amplify.
+// Ray-surfel geometry on the tangent plane (Eq. 1). Decisions and blended
+// quantities are evaluated in double precision: the local coordinates come
+// from a difference of nearly equal distances, and float32 there would cost
+// ~1e-5 in u at room scale, which the bounce point and direction then
+// amplify. A float32 filter with an error bound screens candidates first.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ Record load_record(const Record* recs, uint32_t pos) {
   const float4* p = reinterpret_cast<const float4*>(recs + pos);
@@ -224,9 +225,10 @@ __device__ __forceinline__ Record load_record(const Record* recs, uint32_t pos) 
 
 __device__ __forceinline__ uint32_t rec_index(const Record& r) { return __float_as_uint(r.s_idx.z); }
 
-// A surfel's geometry in double precision (Sec. 3.1): centre p, tangent axes
-// t_u, t_v = the first two columns of the rotation of q / |q|, normal
-// n = t_u x t_v, scales.
+// A surfel's geometry in double precision (Sec. 3.1), as the adjoint's chain
+// rule needs it: centre p, tangent axes t_u, t_v = the first two columns of
+// the rotation of q / |q|, normal n = t_u x t_v, scales, and the normalised
+// quaternion.
 struct Geo {
   D3 p, tu, tv, n;
   double su, sv, sigma;
@@ -247,56 +249,6 @@ __device__ __forceinline__ Geo surfel_geo(const Record& r) {
   g.su = r.s_idx.x;
   g.sv = r.s_idx.y;
   return g;
-}
-
-// Returns true and (t, q2 = u^2 + v^2) when the ray meets the surfel's
-// k_sigma ellipse beyond t_min: den = W.n, t = ((p - O).n) / den,
-// y = O + t W - p, u = y.t_u / s_u, v = y.t_v / s_v.
-__device__ __forceinline__ bool surfel_test(const Geo& g, D3 O, D3 W, double t_min, double k2, double& t,
-                                            double& q2) {
-  const D3 d = g.p - O;
-  const double den = dot(W, g.n);
-  if (!(fabs(den) > 1e-12) || !(g.sigma > 0.0)) return false;
-  t = dot(d, g.n) / den;
-  if (!(t > t_min)) return false;
-  const D3 y = d3(t * W.x - d.x, t * W.y - d.y, t * W.z - d.z);
-  const double u = dot(y, g.tu) / g.su;
-  const double v = dot(y, g.tv) / g.sv;
-  q2 = u * u + v * v;
-  return q2 <= k2;
-}
-
-// The same test straight from a record, computing the frame piecewise so
-// that few double values are live at once.
-__device__ __forceinline__ bool record_test(const Record& r, D3 O, D3 W, double t_min, double k2, double& t) {
-  if (!(r.p_sigma.w > 0.0f)) return false;
-  double w = r.q.x, x = r.q.y, y = r.q.z, z = r.q.w;
-  const double iq = 1.0 / sqrt(w * w + x * x + y * y + z * z);
-  w *= iq; x *= iq; y *= iq; z *= iq;
-  const D3 tu = d3(1.0 - 2.0 * (y * y + z * z), 2.0 * (x * y + w * z), 2.0 * (x * z - w * y));
-  const D3 tv = d3(2.0 * (x * y - w * z), 1.0 - 2.0 * (x * x + z * z), 2.0 * (y * z + w * x));
-  const D3 n = cross(tu, tv);
-  const double den = dot(W, n);
-  if (!(fabs(den) > 1e-12)) return false;
-  const D3 d = d3((double)r.p_sigma.x - O.x, (double)r.p_sigma.y - O.y, (double)r.p_sigma.z - O.z);
-  t = dot(d, n) / den;
-  if (!(t > t_min)) return false;
-  const D3 yv = d3(t * W.x - d.x, t * W.y - d.y, t * W.z - d.z);
-  const double u = dot(yv, tu) / (double)r.s_idx.x;
-  const double v = dot(yv, tv) / (double)r.s_idx.y;
-  return u * u + v * v <= k2;
-}
-
-// Distance along the ray to the surfel's plane, in double precision, for a
-// surfel the filter has already accepted. The third column of the rotation
-// of the unnormalised quaternion is |q|^2 n, and the factor cancels in
-// t = ((p - O).n) / (W.n), so neither the normalisation nor the tangent
-// axes are needed.
-__device__ __forceinline__ double record_t(const Record& r, D3 O, D3 W) {
-  const double w = r.q.x, x = r.q.y, y = r.q.z, z = r.q.w;
-  const D3 m = d3(2.0 * (x * z + w * y), 2.0 * (y * z - w * x), w * w - x * x - y * y + z * z);
-  const D3 d = d3((double)r.p_sigma.x - O.x, (double)r.p_sigma.y - O.y, (double)r.p_sigma.z - O.z);
-  return dot(d, m) / dot(W, m);
 }
 
 // Float32 filter for the surfel test. It evaluates the same formulas in
