@@ -319,7 +319,12 @@ int64_t eag_fwd_state_floats(const eag_camera* cams, int32_t n_cams, const eag_t
 size_t eag_render_workspace_bytes(int64_t n, const eag_camera* cams, int32_t n_cams, const eag_trace_params* p) {
   if (n < 1 || !cams || n_cams < 1 || !p || p->spp < 1) return 0;
   const int64_t np = (int64_t)cams[0].width * cams[0].height * n_cams;
-  return render_ws(nullptr, n, np, p->spp, true).bytes;
+  try {
+    return render_ws(nullptr, n, np, p->spp, true, runner_lanes()).bytes;
+  } catch (const Error& e) {
+    set_error(e.status, e.msg);
+    return 0;
+  }
 }
 
 eag_status eag_render_single_bounce(const eag_bvh* b, const eag_surfels* s, const eag_camera* cams, int32_t n_cams,
@@ -332,7 +337,7 @@ eag_status eag_render_single_bounce(const eag_bvh* b, const eag_surfels* s, cons
     if (!rgb) fail(EAG_ERR_INVALID_ARGUMENT, "rgb is null");
     const int64_t hw = (int64_t)cams[0].width * cams[0].height;
     const int64_t np = hw * n_cams;
-    const RenderWs w = render_ws(ws, b->n, np, p->spp, true);
+    const RenderWs w = render_ws(ws, b->n, np, p->spp, true, runner_lanes());
     if (!ws || ws_bytes < w.bytes) fail(EAG_ERR_WORKSPACE_TOO_SMALL, "render workspace too small");
     float t_max = scene_t_max(b);
     for (int i = 0; i < n_cams; ++i) t_max = std::fmax(t_max, camera_t_max(b, cams[i]));
@@ -354,7 +359,7 @@ eag_status eag_render_single_bounce(const eag_bvh* b, const eag_surfels* s, cons
       std::memset(&cb, 0, sizeof(cb));
       for (int i = 0; i < nc; ++i) cb.c[i] = make_cam(cams[c0 + i], p->camera_id + (uint32_t)(c0 + i));
       launch_single_bounce(tc, cb, hw, nc, sp, state + c0 * hw * EAG_FWD_PIXEL_FLOATS, r1 + c0 * hw * p->spp * 3,
-                           rgb + c0 * hw * 3, st);
+                           rgb + c0 * hw * 3, w.work, w.hitlist, st);
     }
   });
 }
@@ -371,7 +376,7 @@ eag_status eag_single_bounce_backward(const eag_bvh* b, const eag_surfels* s, co
       fail(EAG_ERR_INVALID_ARGUMENT, "a gradient pointer is null");
     const int64_t hw = (int64_t)cams[0].width * cams[0].height;
     const int64_t np = hw * n_cams;
-    const RenderWs w = render_ws(ws, b->n, np, p->spp, true);
+    const RenderWs w = render_ws(ws, b->n, np, p->spp, true, runner_lanes());
     if (!ws || ws_bytes < w.bytes) fail(EAG_ERR_WORKSPACE_TOO_SMALL, "render workspace too small");
     float t_max = scene_t_max(b);
     for (int i = 0; i < n_cams; ++i) t_max = std::fmax(t_max, camera_t_max(b, cams[i]));
@@ -402,7 +407,7 @@ eag_status eag_single_bounce_backward(const eag_bvh* b, const eag_surfels* s, co
 size_t eag_path_trace_workspace_bytes(int64_t n) {
   if (n < 1) return 0;
   try {
-    return render_ws(nullptr, n, 0, 0, false, pt_lanes()).bytes;
+    return render_ws(nullptr, n, 0, 0, false, runner_lanes()).bytes;
   } catch (const Error& e) {
     set_error(e.status, e.msg);
     return 0;
@@ -417,7 +422,7 @@ eag_status eag_path_trace(const eag_bvh* b, const eag_surfels* s, const eag_came
     validate_params(p);
     if (!cam || !accum) fail(EAG_ERR_INVALID_ARGUMENT, "null argument");
     if ((uint64_t)sample_begin + sample_count > 0xffffffffull) fail(EAG_ERR_INVALID_ARGUMENT, "sample range overflow");
-    const RenderWs w = render_ws(ws, b->n, 0, 0, false, pt_lanes());
+    const RenderWs w = render_ws(ws, b->n, 0, 0, false, runner_lanes());
     if (!ws || ws_bytes < w.bytes) fail(EAG_ERR_WORKSPACE_TOO_SMALL, "path-trace workspace too small");
     const CamDev cd = make_cam(*cam, p->camera_id);
     const TraceSetup ts = trace_setup(b, p, std::fmax(scene_t_max(b), camera_t_max(b, *cam)));

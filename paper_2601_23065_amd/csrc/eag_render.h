@@ -68,8 +68,10 @@ struct SbParams {
   float tau_E;
 };
 
+// work: a device counter; hitlist: runner_lanes() * HL_CAP keys.
 void launch_single_bounce(const TraceCtx& tc, const CamBatch& cams, int64_t hw, int32_t n_cams,
-                          const SbParams& sp, float* state, double* r1, float* rgb, hipStream_t st);
+                          const SbParams& sp, float* state, double* r1, float* rgb, unsigned long long* work,
+                          uint64_t* hitlist, hipStream_t st);
 
 // One request's share of a path-tracing launch. Work items of a request are
 // numbered sample-major over 8x8 pixel tiles: item w has sample
@@ -99,9 +101,10 @@ struct PtLaunch {
   int64_t n_work;            // = s[n_slots - 1].global_end
 };
 
-// Lanes of the persistent path-tracing grid on the current device (the hit
-// list holds HL_CAP keys for each).
-int64_t pt_lanes();
+// Lanes of the persistent runner grid on the current device (the hit list
+// holds HL_CAP keys for each), and a launch that zeroes n counters.
+int64_t runner_lanes();
+void launch_zero_u64(unsigned long long* p, int n, hipStream_t st);
 // hitlist: pt_lanes() * HL_CAP keys, or null to trace without the list.
 void launch_path_trace(const TraceCtx& tc, const PtLaunch& L, unsigned long long* work_counter,
                        unsigned long long* counters, uint64_t* hitlist, hipStream_t st);

@@ -2,14 +2,16 @@
 //
 // k_sb_camera     one thread per pixel: camera segment, branch (miss / emit /
 //                 reflect), forward state.
-// k_sb_secondary  one thread per (pixel, sample): cosine-sampled direction
-//                 about Nt from X = O + Dt w, secondary segment blending r
-//                 only (the radiance cache), R1 per sample.
+// k_sb_secondary  one work item per (pixel, sample) on the persistent
+//                 segment runner: cosine-sampled direction about Nt from
+//                 X = O + Dt w, secondary segment blending r only (the
+//                 radiance cache), R1 per sample.
 // k_sb_resolve    one thread per pixel: L = P * mean_s R1 (fixed summation
 //                 order, so the image does not depend on scheduling).
 #include "eag_device.h"
 #include "eag_internal.h"
 #include "eag_render.h"
+#include "eag_runner.h"
 
 namespace eag {
 
@@ -54,27 +56,60 @@ __global__ void __launch_bounds__(256) k_sb_camera(TraceCtx tc, const CamBatch c
   rgb[g * 3 + 2] = L.z;
 }
 
-__global__ void __launch_bounds__(256) k_sb_secondary(TraceCtx tc, const CamBatch cams, int64_t hw, int32_t n_cams,
-                                                      SbParams sp, const float* state, double* r1) {
-  const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const int64_t S = sp.spp;
-  if (t >= hw * n_cams * S) return;
-  const int64_t g = t / S;
-  const uint32_t s = (uint32_t)(t % S);
-  const FwdState st = load_state(state + g * EAG_FWD_PIXEL_FLOATS);
-  D3 R = d3(0.0, 0.0, 0.0);
-  if (st.branch == 2.0f) {
-    const CamDev& c = cams.c[g / hw];
+// One (pixel, sample) secondary segment per work item; a pixel whose camera
+// segment did not take the reflect branch gets R1 = 0 without tracing.
+struct SecondarySource {
+  const CamBatch* cams;
+  int64_t hw;
+  int32_t S;
+  SbParams sp;
+  const float* state;
+  double* r1;
+  int64_t item;
+
+  __device__ __forceinline__ bool start(int64_t wid, TraceCtx&, D3& O, D3& W) {
+    item = wid;
+    const int64_t g = wid / S;
+    const uint32_t s = (uint32_t)(wid - g * S);
+    const float* ps = state + g * EAG_FWD_PIXEL_FLOATS;
+    if (ps[25] != 2.0f) {
+      r1[wid * 3 + 0] = 0.0;
+      r1[wid * 3 + 1] = 0.0;
+      r1[wid * 3 + 2] = 0.0;
+      return false;
+    }
+    const double* d = reinterpret_cast<const double*>(ps);
+    const D3 Nt = d3(d[0], d[1], d[2]);
+    const double Dt = d[3];
+    const CamDev& c = cams->c[g / hw];
     const uint32_t pix = (uint32_t)(g % hw);
-    const D3 W = pixel_dir(c, pix, 0, sp.flags, sp.k0, sp.k1);
-    const D3 X = d3(c.eye[0] + st.Dt * W.x, c.eye[1] + st.Dt * W.y, c.eye[2] + st.Dt * W.z);
+    const D3 Wc = pixel_dir(c, pix, 0, sp.flags, sp.k0, sp.k1);
+    O = d3(c.eye[0] + Dt * Wc.x, c.eye[1] + Dt * Wc.y, c.eye[2] + Dt * Wc.z);
     const uint4 w = philox(make_uint4(pix, s, 0u, c.id), sp.k0, sp.k1);
-    const D3 Wd = cosine_dir(st.Nt, to_unit(w.x), to_unit(w.y));
-    R = trace_segment<Q_RADIANCE, true>(tc, X, Wd).R;
+    W = cosine_dir(Nt, to_unit(w.x), to_unit(w.y));
+    return true;
   }
-  r1[t * 3 + 0] = R.x;
-  r1[t * 3 + 1] = R.y;
-  r1[t * 3 + 2] = R.z;
+
+  __device__ __forceinline__ bool finish(const Seg<true>& sg, D3&, D3&) {
+    r1[item * 3 + 0] = sg.R0;
+    r1[item * 3 + 1] = sg.R1;
+    r1[item * 3 + 2] = sg.R2;
+    return false;
+  }
+};
+
+__global__ void __launch_bounds__(TRACE_BLOCK) k_sb_secondary(
+    TraceCtx tc, const CamBatch cams, int64_t hw, int32_t n_cams, SbParams sp, const float* state, double* r1,
+    unsigned long long* work, uint64_t* hitlist) {
+  SecondarySource src;
+  src.cams = &cams;
+  src.hw = hw;
+  src.S = sp.spp;
+  src.sp = sp;
+  src.state = state;
+  src.r1 = r1;
+  src.item = 0;
+  run_segments<Q_RADIANCE, true>(tc, src, work, hw * n_cams * sp.spp, hitlist, nullptr);
 }
 
 __global__ void k_sb_resolve(int64_t n_pix, SbParams sp, const float* state, const double* r1, float* rgb) {
@@ -98,13 +133,14 @@ __global__ void k_sb_resolve(int64_t n_pix, SbParams sp, const float* state, con
 }  // namespace
 
 void launch_single_bounce(const TraceCtx& tc, const CamBatch& cams, int64_t hw, int32_t n_cams,
-                          const SbParams& sp, float* state, double* r1, float* rgb, hipStream_t st) {
+                          const SbParams& sp, float* state, double* r1, float* rgb, unsigned long long* work,
+                          uint64_t* hitlist, hipStream_t st) {
   const int64_t np = hw * n_cams;
   hipLaunchKernelGGL(k_sb_camera, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, st, tc, cams, hw, n_cams, sp,
                      state, rgb);
-  const int64_t ns = np * sp.spp;
-  hipLaunchKernelGGL(k_sb_secondary, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, st, tc, cams, hw, n_cams,
-                     sp, (const float*)state, r1);
+  launch_zero_u64(work, 1, st);
+  hipLaunchKernelGGL(k_sb_secondary, dim3((unsigned)(runner_lanes() / TRACE_BLOCK)), dim3(TRACE_BLOCK), 0, st, tc,
+                     cams, hw, n_cams, sp, (const float*)state, r1, work, hitlist);
   hipLaunchKernelGGL(k_sb_resolve, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, st, np, sp,
                      (const float*)state, (const double*)r1, rgb);
   check_hip(hipGetLastError(), "single-bounce launch");

@@ -397,7 +397,7 @@ size_t eag_serve_arena_bytes(int64_t n, int32_t versions, size_t request_bytes) 
   b += align_up(eag_bvh_bytes(n));
   b += align_up(64);
   try {
-    b += align_up((size_t)pt_lanes() * HL_CAP * sizeof(uint64_t));
+    b += align_up((size_t)runner_lanes() * HL_CAP * sizeof(uint64_t));
   } catch (const Error& e) {
     set_last_error(e.msg);
     return 0;
@@ -434,7 +434,7 @@ eag_status eag_serve_create(const eag_surfels* s, const eag_server_config* cfg, 
     const size_t bvh_bytes = eag_bvh_bytes(n);
     void* bvh_mem = c.take<char>(bvh_bytes);
     srv->work = c.take<unsigned long long>(8);
-    srv->hitlist = c.take<uint64_t>((size_t)pt_lanes() * HL_CAP);
+    srv->hitlist = c.take<uint64_t>((size_t)runner_lanes() * HL_CAP);
     c.used = align_up(c.used);
     if (c.used >= cfg->arena_bytes) fail(EAG_ERR_OUT_OF_BUDGET, "arena too small for the scene");
     srv->pool_base = static_cast<char*>(cfg->arena) + c.used;
