@@ -398,7 +398,8 @@ eag_status eag_single_bounce_backward(const eag_bvh* b, const eag_surfels* s, co
       std::memset(&cb, 0, sizeof(cb));
       for (int i = 0; i < nc; ++i) cb.c[i] = make_cam(cams[c0 + i], p->camera_id + (uint32_t)(c0 + i));
       launch_single_bounce_backward(tc, *s, cb, hw, nc, sp, fwd_state + c0 * hw * EAG_FWD_PIXEL_FLOATS,
-                                    r1 + c0 * hw * p->spp * 3, dL_drgb + c0 * hw * 3, w.gacc, w.adj, st);
+                                    r1 + c0 * hw * p->spp * 3, dL_drgb + c0 * hw * 3, w.gacc, w.adj, w.work,
+                                    w.hitlist, st);
     }
     launch_grad_finalize(w.gacc, b->n, *grads, st);
   });

@@ -9,7 +9,8 @@
 // where the suffix V - V_{<=j} comes from the forward's stored total minus
 // the running prefix; A = 1 - T_m adds T_m / (1 - alpha_j).
 //
-// k_sb_bwd_secondary  one thread per (pixel, sample) of reflecting pixels:
+// k_sb_bwd_secondary  one work item per (pixel, sample) of reflecting pixels,
+//   on the persistent segment runner:
 //   upstream dR1 = P * dL / spp; per hit: radiance gradient, alpha -> opacity,
 //   tangent-plane coordinates -> centre, quaternion, scales, and the ray's
 //   origin X and direction w'. Writes dL/dX and dL/dNt (through the
@@ -23,6 +24,7 @@
 #include "eag_device.h"
 #include "eag_internal.h"
 #include "eag_render.h"
+#include "eag_runner.h"
 
 namespace eag {
 
@@ -98,40 +100,119 @@ __device__ void chain_hit(const Geo& ge, const GradPtrs& gp, uint32_t idx, D3 O,
   atomicAdd(gp.opacity + idx, g_sigma);
 }
 
-// Secondary segment: only R1 = sum w r is used.
-struct SecondaryAdj {
-  const TraceCtx* tc;
-  const float* rot;
+// Secondary segments on the persistent segment runner (eag_runner.h): one
+// work item per (pixel, sample); only R1 = sum w r is used. Items of pixels
+// that did not take the reflect branch write zero adjoints without tracing.
+struct SecondaryAdjSource {
+  const Record* recs;
+  const Attr* attrs;
+  const CamBatch* cams;
+  int64_t hw;
+  int32_t S;
+  SbParams sp;
+  const float* state;
+  const double* r1;
+  const float* dL;
   GradPtrs gp;
-  D3 O, W;
+  double* adj;
+  bool ray_grad;
+  // per item
+  int64_t item;
   D3 gR1;
   double G;          // gR1 . R1 (the forward total)
   double prefix;
-  bool ray_grad;
   D3 gO, gW;
-  __device__ void operator()(uint32_t pos, double t, double alpha, double w, double Tb) {
-    const Record r = load_record(tc->recs, pos);
+
+  // the item's pixel state, camera and bounce samples
+  __device__ __forceinline__ void frame(int64_t g, uint32_t s, D3& X, D3& Nt, double& u0, double& u1) const {
+    const double* d = reinterpret_cast<const double*>(state + g * EAG_FWD_PIXEL_FLOATS);
+    Nt = d3(d[0], d[1], d[2]);
+    const double Dt = d[3];
+    const CamDev& c = cams->c[g / hw];
+    const uint32_t pix = (uint32_t)(g % hw);
+    const D3 Wc = pixel_dir(c, pix, 0, sp.flags, sp.k0, sp.k1);
+    X = d3(c.eye[0] + Dt * Wc.x, c.eye[1] + Dt * Wc.y, c.eye[2] + Dt * Wc.z);
+    const uint4 w4 = philox(make_uint4(pix, s, 0u, c.id), sp.k0, sp.k1);
+    u0 = to_unit(w4.x);
+    u1 = to_unit(w4.y);
+  }
+
+  __device__ __forceinline__ bool start(int64_t wid, TraceCtx&, D3& O, D3& W) {
+    item = wid;
+    const int64_t g = wid / S;
+    const uint32_t s = (uint32_t)(wid - g * S);
+    if (state[g * EAG_FWD_PIXEL_FLOATS + 25] != 2.0f) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) adj[wid * 6 + k] = 0.0;
+      return false;
+    }
+    D3 Nt;
+    double u0, u1;
+    frame(g, s, O, Nt, u0, u1);
+    W = cosine_dir(Nt, u0, u1);
+    const double* d = reinterpret_cast<const double*>(state + g * EAG_FWD_PIXEL_FLOATS);
+    const double inv = 1.0 / (double)S;
+    gR1 = d3(d[9] * dL[g * 3 + 0] * inv, d[10] * dL[g * 3 + 1] * inv, d[11] * dL[g * 3 + 2] * inv);
+    const double* R1 = r1 + wid * 3;
+    G = gR1.x * R1[0] + gR1.y * R1[1] + gR1.z * R1[2];
+    prefix = 0.0;
+    gO = d3(0.0, 0.0, 0.0);
+    gW = d3(0.0, 0.0, 0.0);
+    return true;
+  }
+
+  __device__ __forceinline__ void operator()(uint32_t pos, double t, double alpha, double w, double Tb, D3 O, D3 W) {
+    const Record r = load_record(recs, pos);
     const uint32_t idx = rec_index(r);
     const Geo ge = surfel_geo(r);
-    const float4 rr = tc->attrs[pos].r;
+    const float4 rr = attrs[pos].r;
     const double c = gR1.x * rr.x + gR1.y * rr.y + gR1.z * rr.z;
     prefix += w * c;
     const double g_alpha = Tb * c - (G - prefix) / (1.0 - alpha);
     atomic_add3(gp.radiance, gp.n, idx, w * gR1);
     chain_hit(ge, gp, idx, O, W, t, g_alpha, 0.0, d3(0.0, 0.0, 0.0), ray_grad, gO, gW);
   }
+
+  __device__ __forceinline__ bool finish(const Seg<true>&, D3&, D3&) {
+    double out[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (ray_grad) {
+      const int64_t g = item / S;
+      const uint32_t s = (uint32_t)(item - g * S);
+      D3 X, Nt;
+      double u0, u1;
+      frame(g, s, X, Nt, u0, u1);
+      // w' = c1 b1 + c2 b2 + c3 Nt, b1 = m / |m|, m = h - (h.Nt) Nt, b2 = Nt x b1
+      const D3 h = d3(HX, HY, HZ);
+      const double hn = dot(h, Nt);
+      const D3 m = h - hn * Nt;
+      const double ml = sqrt(dot(m, m));
+      const D3 b1 = (1.0 / ml) * m;
+      const double rr = sqrt(u0);
+      double sn, cs;
+      sincos(TWO_PI * u1, &sn, &cs);
+      const double c1 = rr * cs, c2 = rr * sn, c3 = sqrt(1.0 - u0);
+      const D3 gb2 = c2 * gW;
+      const D3 gb1 = c1 * gW + cross(gb2, Nt);
+      D3 gNt = c3 * gW + cross(b1, gb2);
+      const D3 gm = (1.0 / ml) * (gb1 - dot(b1, gb1) * b1);
+      gNt = gNt - hn * gm - dot(gm, Nt) * h;
+      out[0] = gO.x; out[1] = gO.y; out[2] = gO.z;
+      out[3] = gNt.x; out[4] = gNt.y; out[5] = gNt.z;
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) adj[item * 6 + k] = out[k];
+    return false;
+  }
 };
 
 // Camera segment: N, D, R (emitter pixels), P (reflecting pixels), A.
 struct CameraAdj {
   const TraceCtx* tc;
-  const float* rot;
   GradPtrs gp;
-  D3 O, W;
   D3 gN, gR, gP;
   double gD, gA, Tm, G, prefix;
   bool has_R, has_P;
-  __device__ void operator()(uint32_t pos, double t, double alpha, double w, double Tb) {
+  __device__ void operator()(uint32_t pos, double t, double alpha, double w, double Tb, D3 O, D3 W) {
     const Record r = load_record(tc->recs, pos);
     const uint32_t idx = rec_index(r);
     const Geo ge = surfel_geo(r);
@@ -149,70 +230,33 @@ struct CameraAdj {
   }
 };
 
-__global__ void __launch_bounds__(256) k_sb_bwd_secondary(TraceCtx tc, const CamBatch cams, int64_t hw,
-                                                          int32_t n_cams, SbParams sp, const float* state,
-                                                          const double* r1, const float* dL, const float* rot,
-                                                          GradPtrs gp, double* adj) {
-  const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const int64_t S = sp.spp;
-  if (tid >= hw * n_cams * S) return;
-  const int64_t g = tid / S;
-  const uint32_t s = (uint32_t)(tid % S);
-  const FwdState st = load_state(state + g * EAG_FWD_PIXEL_FLOATS);
-  double out[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  if (st.branch == 2.0f) {
-    const CamDev& c = cams.c[g / hw];
-    const uint32_t pix = (uint32_t)(g % hw);
-    const D3 Wc = pixel_dir(c, pix, 0, sp.flags, sp.k0, sp.k1);
-    const D3 X = d3(c.eye[0] + st.Dt * Wc.x, c.eye[1] + st.Dt * Wc.y, c.eye[2] + st.Dt * Wc.z);
-    const D3 Nt = st.Nt;
-    const uint4 w4 = philox(make_uint4(pix, s, 0u, c.id), sp.k0, sp.k1);
-    const double u0 = to_unit(w4.x), u1 = to_unit(w4.y);
-    const D3 Wd = cosine_dir(Nt, u0, u1);
-    const double inv = 1.0 / (double)S;
-    SecondaryAdj a;
-    a.tc = &tc;
-    a.rot = rot;
-    a.gp = gp;
-    a.O = X;
-    a.W = Wd;
-    a.gR1 = d3(st.P.x * dL[g * 3 + 0] * inv, st.P.y * dL[g * 3 + 1] * inv, st.P.z * dL[g * 3 + 2] * inv);
-    const double* R1 = r1 + (g * S + s) * 3;
-    a.G = a.gR1.x * R1[0] + a.gR1.y * R1[1] + a.gR1.z * R1[2];
-    a.prefix = 0.0;
-    a.ray_grad = !(sp.flags & EAG_DETACH_BOUNCE);
-    a.gO = d3(0.0, 0.0, 0.0);
-    a.gW = d3(0.0, 0.0, 0.0);
-    trace_segment_cb<Q_RADIANCE, true>(tc, X, Wd, a);
-    if (a.ray_grad) {
-      // w' = c1 b1 + c2 b2 + c3 Nt, b1 = m / |m|, m = h - (h.Nt) Nt, b2 = Nt x b1
-      const D3 h = d3(HX, HY, HZ);
-      const double hn = dot(h, Nt);
-      const D3 m = h - hn * Nt;
-      const double ml = sqrt(dot(m, m));
-      const D3 b1 = (1.0 / ml) * m;
-      const double rr = sqrt(u0);
-      double sn, cs;
-      sincos(TWO_PI * u1, &sn, &cs);
-      const double c1 = rr * cs, c2 = rr * sn, c3 = sqrt(1.0 - u0);
-      const D3 gw = a.gW;
-      const D3 gb2 = c2 * gw;
-      const D3 gb1 = c1 * gw + cross(gb2, Nt);
-      D3 gNt = c3 * gw + cross(b1, gb2);
-      const D3 gm = (1.0 / ml) * (gb1 - dot(b1, gb1) * b1);
-      gNt = gNt - hn * gm - dot(gm, Nt) * h;
-      out[0] = a.gO.x; out[1] = a.gO.y; out[2] = a.gO.z;
-      out[3] = gNt.x; out[4] = gNt.y; out[5] = gNt.z;
-    }
-  }
-#pragma unroll
-  for (int k = 0; k < 6; ++k) adj[tid * 6 + k] = out[k];
+__global__ void __launch_bounds__(TRACE_BLOCK) k_sb_bwd_secondary(TraceCtx tc, const CamBatch cams, int64_t hw,
+                                                                  int32_t n_cams, SbParams sp, const float* state,
+                                                                  const double* r1, const float* dL, GradPtrs gp,
+                                                                  double* adj, unsigned long long* work,
+                                                                  uint64_t* hitlist) {
+  SecondaryAdjSource src;
+  src.recs = tc.recs;
+  src.attrs = tc.attrs;
+  src.cams = &cams;
+  src.hw = hw;
+  src.S = sp.spp;
+  src.sp = sp;
+  src.state = state;
+  src.r1 = r1;
+  src.dL = dL;
+  src.gp = gp;
+  src.adj = adj;
+  src.ray_grad = !(sp.flags & EAG_DETACH_BOUNCE);
+  src.item = 0;
+  src.gR1 = src.gO = src.gW = d3(0.0, 0.0, 0.0);
+  src.G = src.prefix = 0.0;
+  run_segments<Q_RADIANCE, true>(tc, src, work, hw * n_cams * sp.spp, hitlist, nullptr);
 }
 
 __global__ void __launch_bounds__(256) k_sb_bwd_camera(TraceCtx tc, const CamBatch cams, int64_t hw, int32_t n_cams,
                                                        SbParams sp, const float* state, const double* r1,
-                                                       const double* adj, const float* dL, const float* rot,
-                                                       GradPtrs gp) {
+                                                       const double* adj, const float* dL, GradPtrs gp) {
   const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (g >= hw * n_cams) return;
   const FwdState st = load_state(state + g * EAG_FWD_PIXEL_FLOATS);
@@ -221,12 +265,10 @@ __global__ void __launch_bounds__(256) k_sb_bwd_camera(TraceCtx tc, const CamBat
   const uint32_t pix = (uint32_t)(g % hw);
   const D3 W = pixel_dir(c, pix, 0, sp.flags, sp.k0, sp.k1);
   const D3 dl = d3(dL[g * 3 + 0], dL[g * 3 + 1], dL[g * 3 + 2]);
+  const D3 O = d3(c.eye[0], c.eye[1], c.eye[2]);
   CameraAdj a;
   a.tc = &tc;
-  a.rot = rot;
   a.gp = gp;
-  a.O = d3(c.eye[0], c.eye[1], c.eye[2]);
-  a.W = W;
   a.gN = d3(0.0, 0.0, 0.0);
   a.gR = d3(0.0, 0.0, 0.0);
   a.gP = d3(0.0, 0.0, 0.0);
@@ -262,7 +304,7 @@ __global__ void __launch_bounds__(256) k_sb_bwd_camera(TraceCtx tc, const CamBat
     a.G = dot(a.gN, st.Nlen * st.Nt) + a.gD * (st.Dt * st.A) + dot(a.gP, P);
   }
   a.prefix = 0.0;
-  trace_segment_cb<Q_ALL, true>(tc, a.O, W, a);
+  trace_segment_cb<Q_ALL, true>(tc, O, W, a);
 }
 
 __global__ void k_zero_f64(double* p, int64_t n) {
@@ -290,15 +332,16 @@ size_t grad_accum_doubles(int64_t n) { return (size_t)n * GRAD_ROWS; }
 
 void launch_single_bounce_backward(const TraceCtx& tc, const eag_surfels& s, const CamBatch& cams, int64_t hw,
                                    int32_t n_cams, const SbParams& sp, const float* state, const double* r1,
-                                   const float* dL, double* gacc, float* scratch, hipStream_t st) {
+                                   const float* dL, double* gacc, float* scratch, unsigned long long* work,
+                                   uint64_t* hitlist, hipStream_t st) {
   const int64_t n = s.n;
   GradPtrs gp{gacc, gacc + 3 * n, gacc + 7 * n, gacc + 9 * n, gacc + 10 * n, gacc + 13 * n, n};
   const int64_t np = hw * n_cams;
-  const int64_t ns = np * sp.spp;
-  hipLaunchKernelGGL(k_sb_bwd_secondary, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, st, tc, cams, hw, n_cams,
-                     sp, state, r1, dL, s.rot, gp, reinterpret_cast<double*>(scratch));
+  launch_zero_u64(work, 1, st);
+  hipLaunchKernelGGL(k_sb_bwd_secondary, dim3((unsigned)(runner_lanes() / TRACE_BLOCK)), dim3(TRACE_BLOCK), 0, st, tc,
+                     cams, hw, n_cams, sp, state, r1, dL, gp, reinterpret_cast<double*>(scratch), work, hitlist);
   hipLaunchKernelGGL(k_sb_bwd_camera, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, st, tc, cams, hw, n_cams, sp,
-                     state, r1, reinterpret_cast<const double*>(scratch), dL, s.rot, gp);
+                     state, r1, reinterpret_cast<const double*>(scratch), dL, gp);
   check_hip(hipGetLastError(), "single-bounce backward launch");
 }
 

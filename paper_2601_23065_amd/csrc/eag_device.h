@@ -340,7 +340,7 @@ __device__ __forceinline__ float slab(float lx, float ly, float lz, float hx, fl
 
 // No per-hit callback (forward passes).
 struct NoHit {
-  __device__ __forceinline__ void operator()(uint32_t, double, double, double, double) const {}
+  __device__ __forceinline__ void operator()(uint32_t, double, double, double, double, D3, D3) const {}
 };
 
 // Traversal stack: the top STACK_LDS entries of every lane live in LDS,
@@ -733,7 +733,7 @@ __device__ __forceinline__ void traverse_round(const TraceCtx& tc, Seg<DACC>& s,
 // per hit, which keeps its indexing static); t and alpha are recomputed from
 // the record with the same double-precision test. Sets s.done after the
 // first hit with T < T_min or when the round returned fewer than KBUF hits.
-// on_hit(pos, t, alpha, w, T_before) is called for every blended hit; if
+// on_hit(pos, t, alpha, w, T_before, O, W) is called for every blended hit; if
 // hit_out is non-null, up to max_hits blended surfel indices are written.
 template <int QMODE, bool DACC, class HitFn>
 __device__ __forceinline__ void blend_round(const TraceCtx& tc, Seg<DACC>& s, Round& r, HitFn& on_hit,
@@ -791,7 +791,7 @@ __device__ __forceinline__ void blend_round(const TraceCtx& tc, Seg<DACC>& s, Ro
     s.R1 += wf * at.r.y;
     s.R2 += wf * at.r.z;
     if (hit_out && s.nhits < max_hits) hit_out[s.nhits] = (int32_t)key_idx(tc, key);
-    on_hit(pos, t, a, w, s.T);
+    on_hit(pos, t, a, w, s.T, s.O, s.W);
     ++s.nhits;
     s.T *= (1.0 - a);
     if (s.T < tc.T_min) s.done = true;

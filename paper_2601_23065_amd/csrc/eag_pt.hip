@@ -63,6 +63,8 @@ struct PathSource {
     return true;
   }
 
+  __device__ __forceinline__ void operator()(uint32_t, double, double, double, double, D3, D3) const {}
+
   __device__ __forceinline__ bool finish(const Seg<false>& s, D3& O, D3& W) {
     const PtSlot& S = L->s[slot];
     const double A = 1.0 - s.T;

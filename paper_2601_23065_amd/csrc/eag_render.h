@@ -111,7 +111,8 @@ void launch_path_trace(const TraceCtx& tc, const PtLaunch& L, unsigned long long
 
 void launch_single_bounce_backward(const TraceCtx& tc, const eag_surfels& s, const CamBatch& cams, int64_t hw,
                                    int32_t n_cams, const SbParams& sp, const float* state, const double* r1,
-                                   const float* dL, double* gacc, float* scratch, hipStream_t st);
+                                   const float* dL, double* gacc, float* scratch, unsigned long long* work,
+                                   uint64_t* hitlist, hipStream_t st);
 size_t grad_accum_doubles(int64_t n);
 void launch_grad_zero(double* gacc, int64_t n, hipStream_t st);
 void launch_grad_finalize(const double* gacc, int64_t n, const eag_surfel_grads& g, hipStream_t st);

@@ -90,6 +90,8 @@ struct SecondarySource {
     return true;
   }
 
+  __device__ __forceinline__ void operator()(uint32_t, double, double, double, double, D3, D3) const {}
+
   __device__ __forceinline__ bool finish(const Seg<true>& sg, D3&, D3&) {
     r1[item * 3 + 0] = sg.R0;
     r1[item * 3 + 1] = sg.R1;

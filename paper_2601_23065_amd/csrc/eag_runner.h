@@ -23,7 +23,10 @@
 //       segment's ray in (O, W) (and tcl.attrs set), false when the item
 //       needs no tracing (the source then writes its own result);
 //   bool finish(const Seg<DACC>& s, D3& O, D3& W)
-//       the lane's segment has ended; true with the next segment's ray.
+//       the lane's segment has ended; true with the next segment's ray;
+//   void operator()(uint32_t pos, double t, double alpha, double w,
+//                   double T_before, D3 O, D3 W)
+//       called for every blended hit, in blending order (may be empty).
 #pragma once
 
 #include "eag_device.h"
@@ -130,8 +133,7 @@ __device__ __forceinline__ void run_segments(const TraceCtx& tc, Src& src, unsig
 
     // ---- blend, and finish ended segments
     if (stage != ST_BLEND) continue;
-    NoHit nh;
-    blend_round<QMODE>(tcl, s, r, nh, nullptr, 0);
+    blend_round<QMODE>(tcl, s, r, src, nullptr, 0);
     if (!s.done) {
       stage = ST_ROUND;
       continue;
