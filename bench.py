@@ -29,9 +29,11 @@ Two further workloads print their own JSON line (not the default run):
                        the render of a perturbed copy of the scene.
   --workload serve     continuous-batching server against one-at-a-time FIFO
                        on the same Poisson arrivals over a resident 3M-surfel
-                       room (request mix scaled down: 128x128 or 256x256,
-                       4 or 16 spp, 5% edits), at 0.5, 0.8 and 0.95 of the
-                       FIFO service rate; latency percentiles per load.
+                       room (request mix scaled down by default: 128x128 or
+                       256x256, 4 or 16 spp, 5% edits; --mix full takes the
+                       configuration's 256^2..1920x1080 and 16..256 spp), at
+                       0.5, 0.8 and 0.95 of the FIFO service rate; latency
+                       percentiles per load.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
                        [--workload room1m|rooms5m|sb100k|serve]
@@ -314,7 +316,10 @@ def bench_serve(torch, args):
 
     scene, _, cfg = sg.config(5, n_override=args.surfels)
     n_req = args.requests
-    mix = dict(resolutions=((128, 128), (256, 256)), spps=(4, 16))
+    if args.mix == "full":
+        mix = dict(resolutions=((256, 256), (512, 512), (1024, 768), (1920, 1080)), spps=(16, 64, 256))
+    else:
+        mix = dict(resolutions=((128, 128), (256, 256)), spps=(4, 16))
     kinds = {"scale_radiance": EDIT_SCALE_RADIANCE, "set_albedo": EDIT_SET_ALBEDO}
     _log(f"scene ready: {scene.n} surfels, {n_req} requests per run")
 
@@ -343,12 +348,15 @@ def bench_serve(torch, args):
             torch.cuda.synchronize()
             done = time.perf_counter()
             out.append(done - (t_start + r["t"]) if realtime else done - t_req)
+            if i % 10 == 9:
+                _log(f"fifo: {i + 1} of {len(reqs)} requests")
         return np.array(out)
 
     def batched(reqs):
         gs = Scene(scene.arrays())
         need = L_arena(scene.n)
-        srv = Server(gs, arena_bytes=need, max_live_requests=8, paths_per_launch=1 << 20)
+        srv = Server(gs, arena_bytes=need, max_live_requests=8,
+                     paths_per_launch=(1 << 22) if args.mix == "full" else (1 << 20))
         tickets = []
         t_start = time.perf_counter()
         for i, r in enumerate(reqs):
@@ -359,17 +367,21 @@ def bench_serve(torch, args):
                 srv.edit(kinds[r["op"]], r["idx"], r["value"])
             else:
                 tickets.append(srv.submit(r["camera"], params_of(i, r))[0])
+        _log("batched: all requests submitted")
         lat = []
-        for t in tickets:
+        for k, t in enumerate(tickets):
             res = srv.wait(t, timeout=600.0)
             assert res["status"] == 0, res
             lat.append(res["t_done"] - res["t_submit"])
+            if k % 10 == 9:
+                _log(f"batched: {k + 1} of {len(tickets)} requests done")
         srv.close()
         return np.array(lat)
 
     def L_arena(n):
         from paper_2601_23065_amd import _lib
-        return int(_lib.load().eag_serve_arena_bytes(n, 3, 8 * 256 * 256 * 24)) + (64 << 20)
+        w, h = max(mix["resolutions"], key=lambda r: r[0] * r[1])
+        return int(_lib.load().eag_serve_arena_bytes(n, 3, 8 * w * h * 24)) + (64 << 20)
 
     cal = sg.arrivals(scene, n_req, 1.0, **mix)
     fifo(cal[:4], False)   # warm-up: code objects, allocator
@@ -399,8 +411,8 @@ def bench_serve(torch, args):
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"render server over a resident {scene.n}-surfel 8x6x3 m room, Poisson arrivals of "
-                               f"{n_req} requests (128x128 or 256x256, 4 or 16 spp, depth 5, 5% attribute edits) "
-                               f"at 0.5/0.8/0.95 of the FIFO service rate",
+                               f"{n_req} requests (resolutions {mix['resolutions']}, spp {mix['spps']}, depth 5, "
+                               f"5% attribute edits) at 0.5/0.8/0.95 of the FIFO service rate",
                    "surfels": scene.n, "requests": n_req},
         "detail": {"fifo_service_rate_per_s": round(mu, 3), "fifo_mean_service_ms": round(service.mean() * 1e3, 3),
                    "loads": loads},
@@ -417,6 +429,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--surfels", type=int, default=None, help="override the workload's surfel count")
     ap.add_argument("--requests", type=int, default=100, help="requests per run of the serve workload")
+    ap.add_argument("--mix", default="small", choices=["small", "full"],
+                    help="serve workload request mix: small (128^2 or 256^2, 4 or 16 spp) or full "
+                         "(256^2 .. 1920x1080, 16 .. 256 spp)")
     ap.add_argument("--spp", type=int, default=None, help="override the workload's 64 spp (diagnostics only)")
     ap.add_argument("--workload", default="room1m", choices=["room1m", "rooms5m", "serve", "sb100k"])
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
