@@ -367,6 +367,8 @@ def bench_serve(torch, args):
                 srv.edit(kinds[r["op"]], r["idx"], r["value"])
             else:
                 tickets.append(srv.submit(r["camera"], params_of(i, r))[0])
+            if i % 10 == 9:
+                _log(f"batched: {i + 1} of {len(reqs)} requests submitted")
         _log("batched: all requests submitted")
         lat = []
         for k, t in enumerate(tickets):
