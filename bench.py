@@ -108,16 +108,25 @@ def copy_calibration(torch, mib):
     torch.cuda.synchronize()
     print(json.dumps({"copy_calibration_bytes_each_way": n * 4, "launches": 3}))
 
+def _code_tokens(text):
+    """Source text without C/C++ comments and with whitespace collapsed, so
+    that only code changes alter the hash."""
+    import re
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def kernel_source_hash():
-    """sha256 over the library's kernel sources and public header (relative
-    names and contents, in sorted order)."""
+    """sha256 over the code of the library's kernel sources and public header
+    (relative names and comment-free contents, in sorted order)."""
     h = hashlib.sha256()
     files = sorted(glob.glob(os.path.join(HERE, "paper_2601_23065_amd", "csrc", "*")) +
                    glob.glob(os.path.join(HERE, "include", "*.h")))
     for f in files:
         h.update(os.path.relpath(f, HERE).encode())
-        with open(f, "rb") as fh:
-            h.update(fh.read())
+        with open(f, encoding="utf-8") as fh:
+            h.update(_code_tokens(fh.read()).encode())
     return h.hexdigest()
 
 

@@ -203,6 +203,12 @@ eag_status eag_trace_rays(const eag_bvh* bvh, const eag_surfels* s, const eag_tr
  * Total floats: n_cams*H*W*(EAG_FWD_PIXEL_FLOATS + 6*spp). */
 #define EAG_FWD_PIXEL_FLOATS 28
 int64_t eag_fwd_state_floats(const eag_camera* cams, int32_t n_cams, const eag_trace_params* p);
+/* Workspace of eag_render_single_bounce and eag_single_bounce_backward
+ * (the same size for both): packed attributes, forward state, per-sample
+ * adjoints, double gradient accumulators, a work counter and the hit list
+ * of the persistent secondary passes (1 KiB per lane of the persistent grid,
+ * which depends on the current device: 128 MiB on MI355X). Returns 0 and
+ * sets the last error if the device cannot be queried. */
 size_t eag_render_workspace_bytes(int64_t n_surfels, const eag_camera* cams, int32_t n_cams,
                                   const eag_trace_params* p);
 /* cams: host [n_cams], all the same width and height.
