@@ -237,10 +237,15 @@ void eag_server::retire(const std::shared_ptr<Req>& r, int status) {
 }
 
 void eag_server::run() {
-  hipSetDevice(device);
   std::unique_lock<std::mutex> lk(mu);
+  bool on_device = false;
   while (true) {
     try {
+      // (inside the try, so that a failure reaches every request below)
+      if (!on_device) {
+        check_hip(hipSetDevice(device), "hipSetDevice");
+        on_device = true;
+      }
       // ---- ordered inbox: submits capture the current version, edits make one
       while (!inbox.empty()) {
         Op& op = inbox.front();
