@@ -381,6 +381,7 @@ void eag_server::run() {
         inbox.pop_front();
       }
       if (stop) break;
+      if (!on_device) cv.wait_for(lk, std::chrono::milliseconds(10));   // retried for the next requests
     }
   }
 }
