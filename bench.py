@@ -39,7 +39,6 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
                        [--workload room1m|rooms5m|sb100k|serve]
 """
 import argparse
-import glob
 import hashlib
 import json
 import os
@@ -117,12 +116,17 @@ def _code_tokens(text):
     return " ".join(text.split())
 
 
+# what the path-tracing kernel is compiled from
+KERNEL_SOURCES = ["paper_2601_23065_amd/csrc/eag_pt.hip", "paper_2601_23065_amd/csrc/eag_runner.h",
+                  "paper_2601_23065_amd/csrc/eag_device.h", "paper_2601_23065_amd/csrc/eag_render.h",
+                  "paper_2601_23065_amd/csrc/eag_internal.h", "include/eag.h", "paper_2601_23065_amd/build.py"]
+
+
 def kernel_source_hash():
-    """sha256 over the code of the library's kernel sources and public header
-    (relative names and comment-free contents, in sorted order)."""
+    """sha256 over the code the path-tracing kernel is compiled from
+    (relative names and comment-free contents, in a fixed order)."""
     h = hashlib.sha256()
-    files = sorted(glob.glob(os.path.join(HERE, "paper_2601_23065_amd", "csrc", "*")) +
-                   glob.glob(os.path.join(HERE, "include", "*.h")))
+    files = [os.path.join(HERE, f) for f in KERNEL_SOURCES]
     for f in files:
         h.update(os.path.relpath(f, HERE).encode())
         with open(f, encoding="utf-8") as fh:
