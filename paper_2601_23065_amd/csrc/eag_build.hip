@@ -132,10 +132,12 @@ __global__ void k_morton(eag_surfels s, const BvhHeader* h, uint64_t* codes, uin
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
   uint32_t q[3];
+  float ext = 0.0f;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) ext = fmaxf(ext, fdec(h->phi[a]) - fdec(h->plo[a]));
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const float lo = fdec(h->plo[a]), hi = fdec(h->phi[a]);
-    const float ext = hi - lo;
+    const float lo = fdec(h->plo[a]);
     float x = ext > 0.0f ? (s.pos[a * n + i] - lo) / ext : 0.0f;
     x = fminf(fmaxf(x, 0.0f), 1.0f);
     q[a] = min((uint32_t)(x * 2097152.0f), 2097151u);
