@@ -116,8 +116,9 @@ def _code_tokens(text):
     return " ".join(text.split())
 
 
-# what the path-tracing kernel is compiled from
-KERNEL_SOURCES = ["paper_2601_23065_amd/csrc/eag_pt.hip", "paper_2601_23065_amd/csrc/eag_runner.h",
+# what the path-tracing kernel is compiled from, and the BVH build it traverses
+KERNEL_SOURCES = ["paper_2601_23065_amd/csrc/eag_pt.hip", "paper_2601_23065_amd/csrc/eag_build.hip",
+                  "paper_2601_23065_amd/csrc/eag_runner.h",
                   "paper_2601_23065_amd/csrc/eag_device.h", "paper_2601_23065_amd/csrc/eag_render.h",
                   "paper_2601_23065_amd/csrc/eag_internal.h", "include/eag.h", "paper_2601_23065_amd/build.py"]
 
