@@ -15,7 +15,7 @@
 //   tangent-plane coordinates -> centre, quaternion, scales, and the ray's
 //   origin X and direction w'. Writes dL/dX and dL/dNt (through the
 //   hemisphere frame) per sample.
-// k_sb_bwd_camera     one thread per pixel: gathers its samples' dX, dNt in
+// k_sb_bwd_camera     one work item per pixel, on the runner: gathers its samples' dX, dNt in
 //   order, maps them to dN, dD, dA through Nt = N/|N| and Dt = D/A, adds dP =
 //   dL * mean R1 (or dR = dL for emitter pixels) and reverses the camera
 //   segment.
@@ -205,31 +205,6 @@ struct SecondaryAdjSource {
   }
 };
 
-// Camera segment: N, D, R (emitter pixels), P (reflecting pixels), A.
-struct CameraAdj {
-  const TraceCtx* tc;
-  GradPtrs gp;
-  D3 gN, gR, gP;
-  double gD, gA, Tm, G, prefix;
-  bool has_R, has_P;
-  __device__ void operator()(uint32_t pos, double t, double alpha, double w, double Tb, D3 O, D3 W) {
-    const Record r = load_record(tc->recs, pos);
-    const uint32_t idx = rec_index(r);
-    const Geo ge = surfel_geo(r);
-    const Attr at = tc->attrs[pos];
-    const D3 nn = ge.n;
-    const double sgn = dot(W, nn) > 0.0 ? -1.0 : 1.0;   // n' = sgn n faces the origin
-    const D3 rho = d3(at.rho_e.x, at.rho_e.y, at.rho_e.z), rad = d3(at.r.x, at.r.y, at.r.z);
-    const double c = sgn * dot(gN, nn) + gD * t + dot(gR, rad) + dot(gP, rho);
-    prefix += w * c;
-    const double g_alpha = Tb * c - (G - prefix - gA * Tm) / (1.0 - alpha);
-    if (has_R) atomic_add3(gp.radiance, gp.n, idx, w * gR);
-    if (has_P) atomic_add3(gp.albedo, gp.n, idx, w * gP);
-    D3 dummyO = d3(0.0, 0.0, 0.0), dummyW = d3(0.0, 0.0, 0.0);
-    chain_hit(ge, gp, idx, O, W, t, g_alpha, w * gD, (sgn * w) * gN, false, dummyO, dummyW);
-  }
-};
-
 __global__ void __launch_bounds__(TRACE_BLOCK) k_sb_bwd_secondary(TraceCtx tc, const CamBatch cams, int64_t hw,
                                                                   int32_t n_cams, SbParams sp, const float* state,
                                                                   const double* r1, const float* dL, GradPtrs gp,
@@ -254,57 +229,108 @@ __global__ void __launch_bounds__(TRACE_BLOCK) k_sb_bwd_secondary(TraceCtx tc, c
   run_segments<Q_RADIANCE, true>(tc, src, work, hw * n_cams * sp.spp, hitlist, nullptr);
 }
 
-__global__ void __launch_bounds__(256) k_sb_bwd_camera(TraceCtx tc, const CamBatch cams, int64_t hw, int32_t n_cams,
-                                                       SbParams sp, const float* state, const double* r1,
-                                                       const double* adj, const float* dL, GradPtrs gp) {
-  const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (g >= hw * n_cams) return;
-  const FwdState st = load_state(state + g * EAG_FWD_PIXEL_FLOATS);
-  if (st.branch == 0.0f) return;
-  const CamDev& c = cams.c[g / hw];
-  const uint32_t pix = (uint32_t)(g % hw);
-  const D3 W = pixel_dir(c, pix, 0, sp.flags, sp.k0, sp.k1);
-  const D3 dl = d3(dL[g * 3 + 0], dL[g * 3 + 1], dL[g * 3 + 2]);
-  const D3 O = d3(c.eye[0], c.eye[1], c.eye[2]);
-  CameraAdj a;
-  a.tc = &tc;
-  a.gp = gp;
-  a.gN = d3(0.0, 0.0, 0.0);
-  a.gR = d3(0.0, 0.0, 0.0);
-  a.gP = d3(0.0, 0.0, 0.0);
-  a.gD = 0.0;
-  a.gA = 0.0;
-  a.Tm = 1.0 - st.A;
-  a.has_R = st.branch == 1.0f;
-  a.has_P = st.branch == 2.0f;
-  const D3 R = st.R, P = st.P;
-  if (a.has_R) {
-    a.gR = dl;
-    a.G = dot(dl, R);
-  } else {
-    const int S = sp.spp;
-    double m0 = 0.0, m1 = 0.0, m2 = 0.0;
-    D3 gX = d3(0.0, 0.0, 0.0), gNt = d3(0.0, 0.0, 0.0);
-    for (int s = 0; s < S; ++s) {
-      const double* q = r1 + (g * S + s) * 3;
-      m0 += q[0];
-      m1 += q[1];
-      m2 += q[2];
-      const double* ad = adj + (g * S + s) * 6;
-      gX = gX + d3(ad[0], ad[1], ad[2]);
-      gNt = gNt + d3(ad[3], ad[4], ad[5]);
+// Camera segments on the persistent segment runner: one work item per pixel;
+// N, D, R (emitter pixels), P (reflecting pixels) and A are reversed. The
+// pixel's samples' dX, dNt are gathered in order and mapped to dN, dD, dA
+// through Nt = N/|N| and Dt = D/A; dP = dL * mean R1 (or dR = dL for emitter
+// pixels). Missed pixels have nothing to reverse.
+struct CameraAdjSource {
+  const Record* recs;
+  const Attr* attrs;
+  const CamBatch* cams;
+  int64_t hw;
+  SbParams sp;
+  const float* state;
+  const double* r1;
+  const double* adj;
+  const float* dL;
+  GradPtrs gp;
+  // per item
+  D3 gN, gR, gP;
+  double gD, gA, Tm, G, prefix;
+  bool has_R, has_P;
+
+  __device__ __forceinline__ bool start(int64_t g, TraceCtx&, D3& O, D3& W) {
+    const FwdState st = load_state(state + g * EAG_FWD_PIXEL_FLOATS);
+    if (st.branch == 0.0f) return false;
+    const CamDev& c = cams->c[g / hw];
+    W = pixel_dir(c, (uint32_t)(g % hw), 0, sp.flags, sp.k0, sp.k1);
+    O = d3(c.eye[0], c.eye[1], c.eye[2]);
+    const D3 dl = d3(dL[g * 3 + 0], dL[g * 3 + 1], dL[g * 3 + 2]);
+    gN = gR = gP = d3(0.0, 0.0, 0.0);
+    gD = gA = 0.0;
+    Tm = 1.0 - st.A;
+    has_R = st.branch == 1.0f;
+    has_P = st.branch == 2.0f;
+    if (has_R) {
+      gR = dl;
+      G = dot(dl, st.R);
+    } else {
+      const int S = sp.spp;
+      double m0 = 0.0, m1 = 0.0, m2 = 0.0;
+      D3 gX = d3(0.0, 0.0, 0.0), gNt = d3(0.0, 0.0, 0.0);
+      for (int s = 0; s < S; ++s) {
+        const double* q = r1 + (g * S + s) * 3;
+        m0 += q[0];
+        m1 += q[1];
+        m2 += q[2];
+        const double* ad = adj + (g * S + s) * 6;
+        gX = gX + d3(ad[0], ad[1], ad[2]);
+        gNt = gNt + d3(ad[3], ad[4], ad[5]);
+      }
+      const double inv = 1.0 / (double)S;
+      gP = d3(dl.x * (m0 * inv), dl.y * (m1 * inv), dl.z * (m2 * inv));
+      // X = O + Dt W; Nt = N / |N|; Dt = D / A
+      const double gDt = dot(gX, W);
+      gN = (1.0 / st.Nlen) * (gNt - dot(st.Nt, gNt) * st.Nt);
+      gD = gDt / st.A;
+      gA = -gDt * st.Dt / st.A;
+      G = dot(gN, st.Nlen * st.Nt) + gD * (st.Dt * st.A) + dot(gP, st.P);
     }
-    const double inv = 1.0 / (double)S;
-    a.gP = d3(dl.x * (m0 * inv), dl.y * (m1 * inv), dl.z * (m2 * inv));
-    // X = O + Dt W; Nt = N / |N|; Dt = D / A
-    const double gDt = dot(gX, W);
-    a.gN = (1.0 / st.Nlen) * (gNt - dot(st.Nt, gNt) * st.Nt);
-    a.gD = gDt / st.A;
-    a.gA = -gDt * st.Dt / st.A;
-    a.G = dot(a.gN, st.Nlen * st.Nt) + a.gD * (st.Dt * st.A) + dot(a.gP, P);
+    prefix = 0.0;
+    return true;
   }
-  a.prefix = 0.0;
-  trace_segment_cb<Q_ALL, true>(tc, O, W, a);
+
+  __device__ __forceinline__ void operator()(uint32_t pos, double t, double alpha, double w, double Tb, D3 O, D3 W) {
+    const Record r = load_record(recs, pos);
+    const uint32_t idx = rec_index(r);
+    const Geo ge = surfel_geo(r);
+    const Attr at = attrs[pos];
+    const D3 nn = ge.n;
+    const double sgn = dot(W, nn) > 0.0 ? -1.0 : 1.0;   // n' = sgn n faces the origin
+    const D3 rho = d3(at.rho_e.x, at.rho_e.y, at.rho_e.z), rad = d3(at.r.x, at.r.y, at.r.z);
+    const double c = sgn * dot(gN, nn) + gD * t + dot(gR, rad) + dot(gP, rho);
+    prefix += w * c;
+    const double g_alpha = Tb * c - (G - prefix - gA * Tm) / (1.0 - alpha);
+    if (has_R) atomic_add3(gp.radiance, gp.n, idx, w * gR);
+    if (has_P) atomic_add3(gp.albedo, gp.n, idx, w * gP);
+    D3 dummyO = d3(0.0, 0.0, 0.0), dummyW = d3(0.0, 0.0, 0.0);
+    chain_hit(ge, gp, idx, O, W, t, g_alpha, w * gD, (sgn * w) * gN, false, dummyO, dummyW);
+  }
+
+  __device__ __forceinline__ bool finish(const Seg<true>&, D3&, D3&) { return false; }
+};
+
+__global__ void __launch_bounds__(TRACE_BLOCK) k_sb_bwd_camera(TraceCtx tc, const CamBatch cams, int64_t hw,
+                                                               int32_t n_cams, SbParams sp, const float* state,
+                                                               const double* r1, const double* adj, const float* dL,
+                                                               GradPtrs gp, unsigned long long* work,
+                                                               uint64_t* hitlist) {
+  CameraAdjSource src;
+  src.recs = tc.recs;
+  src.attrs = tc.attrs;
+  src.cams = &cams;
+  src.hw = hw;
+  src.sp = sp;
+  src.state = state;
+  src.r1 = r1;
+  src.adj = adj;
+  src.dL = dL;
+  src.gp = gp;
+  src.gN = src.gR = src.gP = d3(0.0, 0.0, 0.0);
+  src.gD = src.gA = src.Tm = src.G = src.prefix = 0.0;
+  src.has_R = src.has_P = false;
+  run_segments<Q_ALL, true>(tc, src, work, hw * n_cams, hitlist, nullptr);
 }
 
 __global__ void k_zero_f64(double* p, int64_t n) {
@@ -336,12 +362,12 @@ void launch_single_bounce_backward(const TraceCtx& tc, const eag_surfels& s, con
                                    uint64_t* hitlist, hipStream_t st) {
   const int64_t n = s.n;
   GradPtrs gp{gacc, gacc + 3 * n, gacc + 7 * n, gacc + 9 * n, gacc + 10 * n, gacc + 13 * n, n};
-  const int64_t np = hw * n_cams;
   launch_zero_u64(work, 1, st);
   hipLaunchKernelGGL(k_sb_bwd_secondary, dim3((unsigned)(runner_lanes() / TRACE_BLOCK)), dim3(TRACE_BLOCK), 0, st, tc,
                      cams, hw, n_cams, sp, state, r1, dL, gp, reinterpret_cast<double*>(scratch), work, hitlist);
-  hipLaunchKernelGGL(k_sb_bwd_camera, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, st, tc, cams, hw, n_cams, sp,
-                     state, r1, reinterpret_cast<const double*>(scratch), dL, gp);
+  launch_zero_u64(work, 1, st);
+  hipLaunchKernelGGL(k_sb_bwd_camera, dim3((unsigned)(runner_lanes() / TRACE_BLOCK)), dim3(TRACE_BLOCK), 0, st, tc,
+                     cams, hw, n_cams, sp, state, r1, reinterpret_cast<const double*>(scratch), dL, gp, work, hitlist);
   check_hip(hipGetLastError(), "single-bounce backward launch");
 }
 
