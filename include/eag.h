@@ -222,8 +222,9 @@ eag_status eag_render_single_bounce(const eag_bvh* bvh, const eag_surfels* s, co
  * emitter branch); includes the chain through X (via Dt) and w' (via Nt and
  * the hemisphere frame) unless EAG_DETACH_BOUNCE. Hit lists are recomputed,
  * not stored. dL_drgb: device [n_cams][H][W][3]; fwd_state from the forward
- * call with the same arguments. Gradients are accumulated into `grads` with
- * float atomics. */
+ * call with the same arguments. Per-hit contributions are summed with double
+ * atomics into the workspace's accumulator, which is then added once to
+ * `grads` (grads += sum; the caller zeroes them for a fresh gradient). */
 eag_status eag_single_bounce_backward(const eag_bvh* bvh, const eag_surfels* s, const eag_camera* cams,
                                       int32_t n_cams, const eag_trace_params* p, const float* dL_drgb,
                                       const float* fwd_state, const eag_surfel_grads* grads,
