@@ -386,6 +386,42 @@ __device__ __forceinline__ uint64_t kbuf_insert(uint64_t (&kk)[KBUF], uint64_t k
   return key;
 }
 
+// Compare-exchange: afterwards a <= b.
+__device__ __forceinline__ void cswap_key(uint64_t& a, uint64_t& b) {
+  const bool lt = b < a;
+  const uint64_t lo = lt ? b : a;
+  b = lt ? a : b;
+  a = lo;
+}
+
+// Sort eight keys ascending: the 19-comparator, depth-6 sorting network for
+// eight inputs (checked on all 256 zero-one inputs).
+__device__ __forceinline__ void sort8_keys(uint64_t (&e)[8]) {
+  cswap_key(e[0], e[2]); cswap_key(e[1], e[3]); cswap_key(e[4], e[6]); cswap_key(e[5], e[7]);
+  cswap_key(e[0], e[4]); cswap_key(e[1], e[5]); cswap_key(e[2], e[6]); cswap_key(e[3], e[7]);
+  cswap_key(e[0], e[1]); cswap_key(e[2], e[3]); cswap_key(e[4], e[5]); cswap_key(e[6], e[7]);
+  cswap_key(e[2], e[4]); cswap_key(e[3], e[5]);
+  cswap_key(e[1], e[4]); cswap_key(e[3], e[6]);
+  cswap_key(e[1], e[2]); cswap_key(e[3], e[4]); cswap_key(e[5], e[6]);
+}
+
+// Merge eight ascending keys into the k-buffer, keeping its KBUF smallest.
+// Against the buffer's upper half, taken in reverse, the elementwise minimum
+// leaves the sixteen smallest of both as a bitonic sequence, which four
+// compare-exchange stages sort: 8 minima and 32 compare-exchanges in place
+// of the 128 steps of eight single inserts.
+static_assert(KBUF == 16, "the merge network is built for a 16-entry k-buffer");
+__device__ __forceinline__ void kbuf_merge8(uint64_t (&kk)[KBUF], const uint64_t (&e)[8]) {
+#pragma unroll
+  for (int i = 0; i < 8; ++i) kk[8 + i] = e[7 - i] < kk[8 + i] ? e[7 - i] : kk[8 + i];
+#pragma unroll
+  for (int st = 8; st >= 1; st >>= 1) {
+#pragma unroll
+    for (int i = 0; i < KBUF; ++i)
+      if ((i & st) == 0) cswap_key(kk[i], kk[i + st]);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // One ray segment: multi-round k-buffer traversal and front-to-back blending.
 // Round r collects the KBUF smallest keys strictly greater than the last key
@@ -493,7 +529,6 @@ __device__ __forceinline__ bool round_begin(const TraceCtx& tc, Seg<DACC>& s, Ro
     // nl are ignored)
     const uint64_t* const hl = tc.hl;
     int w = 0;
-    r.plast = 0;
     for (int j = 0; j < s.nl; j += 8) {
       uint64_t e[8];
 #pragma unroll
@@ -504,17 +539,20 @@ __device__ __forceinline__ bool round_begin(const TraceCtx& tc, Seg<DACC>& s, Ro
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        // branch-free: a key outside (last, lhi) enters the chain as ~0
+        // branch-free: a key outside (last, lhi) enters the merge as ~0
         const bool in = j + u < s.nl && e[u] > s.last && e[u] < s.lhi;
-        const uint64_t k = in ? e[u] : ~0ull;
+        e[u] = in ? e[u] : ~0ull;
         w += in ? 1 : 0;
-        r.plast = in && k > r.plast ? k : r.plast;
-        r.cnt += k < r.kk[KBUF - 1] ? 1 : 0;
-        kbuf_insert(r.kk, k);
       }
+      sort8_keys(e);
+      kbuf_merge8(r.kk, e);
     }
     if (w == 0) s.nl = 0;
-    r.cnt = r.cnt > KBUF ? KBUF : r.cnt;
+    // every key in range is below the buffer's last entry until it is full
+    r.cnt = w > KBUF ? KBUF : w;
+    r.plast = 0;
+#pragma unroll
+    for (int j = 0; j < KBUF; ++j) r.plast = j < r.cnt ? r.kk[j] : r.plast;
     if (r.cnt == KBUF || s.lhi == ~0ull) {
       traverse = false;
     } else if (r.cnt > 0) {
