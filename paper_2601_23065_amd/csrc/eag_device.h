@@ -151,6 +151,7 @@ struct TraceCtx {
   int32_t idx_bits;        // bits of an index (both index fields)
   uint32_t max_bucket;     // largest representable bucket
   double inv_dq;           // 1 / dq, or 0 for exact-t keys
+  double dq;               // the depth quantum (a power of two, so b * dq == b / inv_dq exactly), or 0
   double t_min;
   double k2;               // k_sigma^2
   double T_min;
@@ -197,13 +198,13 @@ __device__ __forceinline__ uint64_t next_bucket_key(const TraceCtx& tc, uint64_t
 // smallest t that can carry the given key's bucket (for culling)
 __device__ __forceinline__ float key_tlo(const TraceCtx& tc, uint64_t k) {
   const uint32_t b = (uint32_t)(k >> (2 * tc.idx_bits));
-  if (tc.inv_dq > 0.0) return (float)((double)b / tc.inv_dq);
+  if (tc.inv_dq > 0.0) return (float)((double)b * tc.dq);
   return __uint_as_float(b);
 }
 // largest t whose bucket does not exceed the key's bucket
 __device__ __forceinline__ float key_thi(const TraceCtx& tc, uint64_t k) {
   const uint32_t b = (uint32_t)(k >> (2 * tc.idx_bits));
-  if (tc.inv_dq > 0.0) return (float)((double)(b + 1u) / tc.inv_dq);
+  if (tc.inv_dq > 0.0) return (float)((double)(b + 1u) * tc.dq);
   return __uint_as_float(b);
 }
 

@@ -51,6 +51,7 @@ TraceCtx make_ctx(const eag_bvh* b, const Attr* attrs, const eag_trace_params* p
   tc.idx_bits = ts.idx_bits;
   tc.max_bucket = ts.max_bucket;
   tc.inv_dq = ts.inv_dq;
+  tc.dq = ts.inv_dq > 0.0 ? 1.0 / ts.inv_dq : 0.0;
   tc.t_min = p->t_min;
   tc.k2 = (double)p->k_sigma * (double)p->k_sigma;
   tc.T_min = p->T_min;
