@@ -203,14 +203,21 @@ eag_status eag_trace_rays(const eag_bvh* bvh, const eag_surfels* s, const eag_tr
  * Total floats: n_cams*H*W*(EAG_FWD_PIXEL_FLOATS + 6*spp). */
 #define EAG_FWD_PIXEL_FLOATS 28
 int64_t eag_fwd_state_floats(const eag_camera* cams, int32_t n_cams, const eag_trace_params* p);
-/* Workspace of eag_render_single_bounce and eag_single_bounce_backward
- * (the same size for both): packed attributes, forward state, per-sample
- * adjoints, double gradient accumulators, a work counter and the hit list
- * of the persistent secondary passes (1 KiB per lane of the persistent grid,
- * which depends on the current device: 128 MiB on MI355X). Returns 0 and
- * sets the last error if the device cannot be queried. */
+/* Workspace of eag_render_single_bounce: packed attributes, forward state,
+ * per-sample adjoints, double gradient accumulators, a work counter and the
+ * hit list of the persistent secondary passes (1 KiB per lane of the
+ * persistent grid, which depends on the current device: 128 MiB on MI355X).
+ * Returns 0 and sets the last error if the device cannot be queried. */
 size_t eag_render_workspace_bytes(int64_t n_surfels, const eag_camera* cams, int32_t n_cams,
                                   const eag_trace_params* p);
+/* Workspace of eag_single_bounce_backward: the render workspace plus the
+ * per-hit gradient records of the secondary adjoint: 128 B for up to 12 hits
+ * per (pixel, sample) of one batch of up to 8 cameras, at most 2^26 records
+ * (8 GiB), and per-surfel counters. Hits beyond the records are added with
+ * atomics instead, so the result does not depend on the size; the speed
+ * does. Returns 0 and sets the last error if the device cannot be queried. */
+size_t eag_backward_workspace_bytes(int64_t n_surfels, const eag_camera* cams, int32_t n_cams,
+                                    const eag_trace_params* p);
 /* cams: host [n_cams], all the same width and height.
  * rgb: device [n_cams][H][W][3].
  * fwd_state: nullable device buffer of eag_fwd_state_floats() floats. */
@@ -222,9 +229,11 @@ eag_status eag_render_single_bounce(const eag_bvh* bvh, const eag_surfels* s, co
  * emitter branch); includes the chain through X (via Dt) and w' (via Nt and
  * the hemisphere frame) unless EAG_DETACH_BOUNCE. Hit lists are recomputed,
  * not stored. dL_drgb: device [n_cams][H][W][3]; fwd_state from the forward
- * call with the same arguments. Per-hit contributions are summed with double
- * atomics into the workspace's accumulator, which is then added once to
- * `grads` (grads += sum; the caller zeroes them for a fresh gradient). */
+ * call with the same arguments; ws of eag_backward_workspace_bytes() bytes.
+ * Per-hit contributions are summed in double precision in the workspace (the
+ * secondary pass through per-hit records grouped by surfel, the camera pass
+ * with atomics), and the sums are added once to `grads` (grads += sum; the
+ * caller zeroes them for a fresh gradient). */
 eag_status eag_single_bounce_backward(const eag_bvh* bvh, const eag_surfels* s, const eag_camera* cams,
                                       int32_t n_cams, const eag_trace_params* p, const float* dL_drgb,
                                       const float* fwd_state, const eag_surfel_grads* grads,

@@ -86,6 +86,7 @@ SIGNATURES = {
                                  C.c_size_t, vp]),
     "eag_fwd_state_floats": (C.c_int64, [P(Camera), C.c_int32, P(TraceParams)]),
     "eag_render_workspace_bytes": (C.c_size_t, [C.c_int64, P(Camera), C.c_int32, P(TraceParams)]),
+    "eag_backward_workspace_bytes": (C.c_size_t, [C.c_int64, P(Camera), C.c_int32, P(TraceParams)]),
     "eag_render_single_bounce": (C.c_int, [vp, P(Surfels), P(Camera), C.c_int32, P(TraceParams), vp, vp, vp,
                                            C.c_size_t, vp]),
     "eag_single_bounce_backward": (C.c_int, [vp, P(Surfels), P(Camera), C.c_int32, P(TraceParams), vp, vp,

@@ -216,7 +216,7 @@ def single_bounce_backward(bvh: BVH, scene: Scene, cams, params: Params, dL_drgb
     g = L.SurfelGrads()
     for k in ("pos", "rot", "scale", "opacity", "albedo", "radiance"):
         setattr(g, k, _ptr(grads[k]))
-    ws = _bytes(lib.eag_render_workspace_bytes(scene.n, ca, len(cams), C.byref(p)), dev)
+    ws = _bytes(lib.eag_backward_workspace_bytes(scene.n, ca, len(cams), C.byref(p)), dev)
     wp, wb = _aligned(ws)
     sc = scene.c(overrides)
     L.check(lib.eag_single_bounce_backward(bvh.h, C.byref(sc), ca, len(cams), C.byref(p),

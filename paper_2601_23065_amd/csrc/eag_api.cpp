@@ -2,6 +2,7 @@
 // conversion. Every entry point catches everything and returns a status.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -154,12 +155,16 @@ struct RenderWs {
   double* r1;
   float* adj;                 // per-sample dL/dX, dL/dNt of the adjoint
   double* gacc;               // double gradient accumulators of the adjoint
+  GradRecs grecs;             // per-hit gradient records of the secondary adjoint
   unsigned long long* work;
   uint64_t* hitlist;          // path tracing: HL_CAP keys per lane of the persistent grid
   size_t bytes;
 };
 
-RenderWs render_ws(void* base, int64_t n, int64_t n_pix, int64_t spp, bool own_state, int64_t hl_lanes = 0) {
+// records: the backward's per-hit gradient records, for camera batches of
+// n_pix_batch pixels (the forward needs none).
+RenderWs render_ws(void* base, int64_t n, int64_t n_pix, int64_t spp, bool own_state, int64_t hl_lanes = 0,
+                   int64_t n_pix_batch = 0, bool records = false) {
   Carver c(base, ~size_t(0));
   RenderWs w;
   w.attrs = c.take<Attr>(n);
@@ -167,6 +172,23 @@ RenderWs render_ws(void* base, int64_t n, int64_t n_pix, int64_t spp, bool own_s
   w.r1 = own_state ? c.take<double>(n_pix * spp * 3) : nullptr;
   w.adj = own_state ? c.take<float>(n_pix * spp * 12) : nullptr;   // 6 doubles per sample
   w.gacc = own_state ? c.take<double>(grad_accum_doubles(n)) : nullptr;
+  std::memset(&w.grecs, 0, sizeof(w.grecs));
+  if (own_state && records) {
+    // sized for the largest camera batch of one launch
+    GradRecs& g = w.grecs;
+    const int64_t waves = std::max<int64_t>(1, hl_lanes / 64);
+    g.per_wave = std::max<int64_t>(1, grad_rec_capacity(std::min<int64_t>(n_pix, n_pix_batch) * spp) / waves);
+    g.cap = g.per_wave * waves;
+    g.wused = c.take<uint32_t>(waves);
+    g.rec = c.take<double>((size_t)g.cap * 16);
+    g.idx = c.take<uint32_t>(g.cap);
+    g.order = c.take<uint32_t>(g.cap);
+    g.cnt = c.take<uint32_t>(n);
+    g.cursor = c.take<uint32_t>(n);
+    g.off = c.take<uint32_t>(n);
+    g.scan_bytes = grad_rec_scan_bytes(n);
+    g.scan_tmp = c.take<char>(g.scan_bytes);
+  }
   w.work = c.take<unsigned long long>(8);
   w.hitlist = hl_lanes > 0 ? c.take<uint64_t>((size_t)hl_lanes * HL_CAP) : nullptr;
   w.bytes = c.bytes();
@@ -327,6 +349,17 @@ size_t eag_render_workspace_bytes(int64_t n, const eag_camera* cams, int32_t n_c
   }
 }
 
+size_t eag_backward_workspace_bytes(int64_t n, const eag_camera* cams, int32_t n_cams, const eag_trace_params* p) {
+  if (n < 1 || !cams || n_cams < 1 || !p || p->spp < 1) return 0;
+  const int64_t hw = (int64_t)cams[0].width * cams[0].height;
+  try {
+    return render_ws(nullptr, n, hw * n_cams, p->spp, true, runner_lanes(), hw * MAX_CAMS_PER_LAUNCH, true).bytes;
+  } catch (const Error& e) {
+    set_error(e.status, e.msg);
+    return 0;
+  }
+}
+
 eag_status eag_render_single_bounce(const eag_bvh* b, const eag_surfels* s, const eag_camera* cams, int32_t n_cams,
                                     const eag_trace_params* p, float* rgb, float* fwd_state, void* ws,
                                     size_t ws_bytes, void* stream) {
@@ -376,8 +409,8 @@ eag_status eag_single_bounce_backward(const eag_bvh* b, const eag_surfels* s, co
       fail(EAG_ERR_INVALID_ARGUMENT, "a gradient pointer is null");
     const int64_t hw = (int64_t)cams[0].width * cams[0].height;
     const int64_t np = hw * n_cams;
-    const RenderWs w = render_ws(ws, b->n, np, p->spp, true, runner_lanes());
-    if (!ws || ws_bytes < w.bytes) fail(EAG_ERR_WORKSPACE_TOO_SMALL, "render workspace too small");
+    const RenderWs w = render_ws(ws, b->n, np, p->spp, true, runner_lanes(), hw * MAX_CAMS_PER_LAUNCH, true);
+    if (!ws || ws_bytes < w.bytes) fail(EAG_ERR_WORKSPACE_TOO_SMALL, "backward workspace too small");
     float t_max = scene_t_max(b);
     for (int i = 0; i < n_cams; ++i) t_max = std::fmax(t_max, camera_t_max(b, cams[i]));
     const TraceSetup ts = trace_setup(b, p, t_max);
@@ -398,8 +431,8 @@ eag_status eag_single_bounce_backward(const eag_bvh* b, const eag_surfels* s, co
       std::memset(&cb, 0, sizeof(cb));
       for (int i = 0; i < nc; ++i) cb.c[i] = make_cam(cams[c0 + i], p->camera_id + (uint32_t)(c0 + i));
       launch_single_bounce_backward(tc, *s, cb, hw, nc, sp, fwd_state + c0 * hw * EAG_FWD_PIXEL_FLOATS,
-                                    r1 + c0 * hw * p->spp * 3, dL_drgb + c0 * hw * 3, w.gacc, w.adj, w.work,
-                                    w.hitlist, st);
+                                    r1 + c0 * hw * p->spp * 3, dL_drgb + c0 * hw * 3, w.gacc, w.adj, w.grecs,
+                                    w.work, w.hitlist, st);
     }
     launch_grad_finalize(w.gacc, b->n, *grads, st);
   });

@@ -26,6 +26,8 @@
 #include "eag_render.h"
 #include "eag_runner.h"
 
+#include <rocprim/device/device_scan.hpp>
+
 namespace eag {
 
 namespace {
@@ -53,11 +55,11 @@ __device__ __forceinline__ void atomic_add3(double* base, int64_t n, int64_t i, 
 
 // Chain of one hit's opacity-term gradient g_alpha, distance gradient g_t and
 // normal gradient g_n into the surfel's centre, quaternion, scales and opacity
-// (atomics), and into the ray origin and direction (accumulated in gO, gW).
-// Double precision, like the forward geometry.
-__device__ void chain_hit(const Geo& ge, const GradPtrs& gp, uint32_t idx, D3 O, D3 W, double t, double g_alpha,
-                          double g_t, D3 g_n, bool ray_grad, D3& gO, D3& gW) {
-  const int64_t n = gp.n;
+// (out, in accumulator-row order: pos 0-2, rot 3-6, scale 7-8, opacity 9), and
+// into the ray origin and direction (accumulated in gO, gW). Double
+// precision, like the forward geometry.
+__device__ __forceinline__ void chain_values(const Geo& ge, D3 O, D3 W, double t, double g_alpha, double g_t, D3 g_n,
+                                             bool ray_grad, D3& gO, D3& gW, double (&out)[10]) {
   const D3 d = ge.p - O;
   const double den = dot(W, ge.n);
   const D3 y = d3(t * W.x - d.x, t * W.y - d.y, t * W.z - d.z);
@@ -90,14 +92,72 @@ __device__ void chain_hit(const Geo& ge, const GradPtrs& gp, uint32_t idx, D3 O,
   const double gqz = 2.0 * (-2.0 * gtu.x * qz + gtu.y * qw + gtu.z * qx - gtv.x * qw - 2.0 * gtv.y * qz + gtv.z * qy);
   // q_hat = q / |q|
   const double proj = qw * gqw + qx * gqx + qy * gqy + qz * gqz;
-  atomicAdd(gp.rot + idx, (gqw - qw * proj) * ge.iq);
-  atomicAdd(gp.rot + n + idx, (gqx - qx * proj) * ge.iq);
-  atomicAdd(gp.rot + 2 * n + idx, (gqy - qy * proj) * ge.iq);
-  atomicAdd(gp.rot + 3 * n + idx, (gqz - qz * proj) * ge.iq);
-  atomic_add3(gp.pos, n, idx, gd);
-  atomicAdd(gp.scale + idx, gsu);
-  atomicAdd(gp.scale + n + idx, gsv);
-  atomicAdd(gp.opacity + idx, g_sigma);
+  out[0] = gd.x;
+  out[1] = gd.y;
+  out[2] = gd.z;
+  out[3] = (gqw - qw * proj) * ge.iq;
+  out[4] = (gqx - qx * proj) * ge.iq;
+  out[5] = (gqy - qy * proj) * ge.iq;
+  out[6] = (gqz - qz * proj) * ge.iq;
+  out[7] = gsu;
+  out[8] = gsv;
+  out[9] = g_sigma;
+}
+
+// The same, added to the accumulators with atomics.
+__device__ void chain_hit(const Geo& ge, const GradPtrs& gp, uint32_t idx, D3 O, D3 W, double t, double g_alpha,
+                          double g_t, D3 g_n, bool ray_grad, D3& gO, D3& gW) {
+  double v[10];
+  chain_values(ge, O, W, t, g_alpha, g_t, g_n, ray_grad, gO, gW, v);
+  const int64_t n = gp.n;
+  atomic_add3(gp.pos, n, idx, d3(v[0], v[1], v[2]));
+#pragma unroll
+  for (int k = 0; k < 4; ++k) atomicAdd(gp.rot + k * n + idx, v[3 + k]);
+  atomicAdd(gp.scale + idx, v[7]);
+  atomicAdd(gp.scale + n + idx, v[8]);
+  atomicAdd(gp.opacity + idx, v[9]);
+}
+
+// Per-hit gradient records of the secondary adjoint. The secondary pass is
+// limited by the rate of its atomics (13 per hit). Instead, each hit writes
+// one record of the 16 accumulator rows (128 B, albedo rows zero) to the next
+// slot of its wave's range, whose cursor lives in LDS, and counts itself in a
+// per-surfel counter with an atomic whose result it does not wait for. After
+// the pass, an exclusive scan of the counters and a placement pass group the
+// slots by surfel, and one wave per surfel sums its records. Hits beyond a
+// wave's range fall back to atomics, so any capacity is correct.
+__device__ __forceinline__ void emit_record(const GradRecs& gr, const GradPtrs& gp, unsigned* wcur, uint32_t idx,
+                                            const double (&v)[GRAD_ROWS]) {
+  // Each wave owns per_wave slots; its cursor lives in LDS (wcur), and the
+  // lanes calling this together take consecutive slots: no global atomic.
+  const uint64_t act = __ballot(1);
+  const int lane = (int)(threadIdx.x & 63);
+  const int leader = __ffsll((unsigned long long)act) - 1;
+  unsigned base = 0;
+  if (lane == leader) {
+    base = *wcur;
+    *wcur = base + (unsigned)__popcll(act);
+  }
+  base = __shfl(base, leader);
+  const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  const int64_t j = (int64_t)base + __popcll(act & below);
+  if (j < gr.per_wave) {
+    const int64_t slot = ((int64_t)blockIdx.x * (TRACE_BLOCK / 64) + (threadIdx.x >> 6)) * gr.per_wave + j;
+    double2* dst = reinterpret_cast<double2*>(gr.rec + slot * GRAD_ROWS);
+#pragma unroll
+    for (int k = 0; k < GRAD_ROWS / 2; ++k) dst[k] = make_double2(v[2 * k], v[2 * k + 1]);
+    gr.idx[slot] = idx;
+    atomicAdd(gr.cnt + idx, 1u);   // no return value: the lane does not wait for it
+  } else {
+    const int64_t n = gp.n;
+    atomic_add3(gp.pos, n, idx, d3(v[0], v[1], v[2]));
+#pragma unroll
+    for (int k = 0; k < 4; ++k) atomicAdd(gp.rot + k * n + idx, v[3 + k]);
+    atomicAdd(gp.scale + idx, v[7]);
+    atomicAdd(gp.scale + n + idx, v[8]);
+    atomicAdd(gp.opacity + idx, v[9]);
+    atomic_add3(gp.radiance, n, idx, d3(v[13], v[14], v[15]));
+  }
 }
 
 // Secondary segments on the persistent segment runner (eag_runner.h): one
@@ -114,6 +174,8 @@ struct SecondaryAdjSource {
   const double* r1;
   const float* dL;
   GradPtrs gp;
+  GradRecs gr;
+  unsigned* wcur;     // this wave's record cursor (LDS)
   double* adj;
   bool ray_grad;
   // per item
@@ -169,8 +231,16 @@ struct SecondaryAdjSource {
     const double c = gR1.x * rr.x + gR1.y * rr.y + gR1.z * rr.z;
     prefix += w * c;
     const double g_alpha = Tb * c - (G - prefix) / (1.0 - alpha);
-    atomic_add3(gp.radiance, gp.n, idx, w * gR1);
-    chain_hit(ge, gp, idx, O, W, t, g_alpha, 0.0, d3(0.0, 0.0, 0.0), ray_grad, gO, gW);
+    double v[GRAD_ROWS];
+    double cv[10];
+    chain_values(ge, O, W, t, g_alpha, 0.0, d3(0.0, 0.0, 0.0), ray_grad, gO, gW, cv);
+#pragma unroll
+    for (int k = 0; k < 10; ++k) v[k] = cv[k];
+    v[10] = v[11] = v[12] = 0.0;   // albedo: the secondary pass has none
+    v[13] = w * gR1.x;
+    v[14] = w * gR1.y;
+    v[15] = w * gR1.z;
+    emit_record(gr, gp, wcur, idx, v);
   }
 
   __device__ __forceinline__ bool finish(const Seg<true>&, D3&, D3&) {
@@ -205,10 +275,10 @@ struct SecondaryAdjSource {
   }
 };
 
-__global__ void __launch_bounds__(TRACE_BLOCK) k_sb_bwd_secondary(TraceCtx tc, const CamBatch cams, int64_t hw,
+__global__ void __launch_bounds__(TRACE_BLOCK) __attribute__((amdgpu_waves_per_eu(2))) k_sb_bwd_secondary(TraceCtx tc, const CamBatch cams, int64_t hw,
                                                                   int32_t n_cams, SbParams sp, const float* state,
                                                                   const double* r1, const float* dL, GradPtrs gp,
-                                                                  double* adj, unsigned long long* work,
+                                                                  GradRecs gr, double* adj, unsigned long long* work,
                                                                   uint64_t* hitlist) {
   SecondaryAdjSource src;
   src.recs = tc.recs;
@@ -220,13 +290,23 @@ __global__ void __launch_bounds__(TRACE_BLOCK) k_sb_bwd_secondary(TraceCtx tc, c
   src.state = state;
   src.r1 = r1;
   src.dL = dL;
+  __shared__ unsigned s_wcur[TRACE_BLOCK / 64];
+  const int wv = (int)(threadIdx.x >> 6);
+  if ((threadIdx.x & 63) == 0) s_wcur[wv] = 0u;
   src.gp = gp;
+  src.gr = gr;
+  src.wcur = s_wcur + wv;
   src.adj = adj;
   src.ray_grad = !(sp.flags & EAG_DETACH_BOUNCE);
   src.item = 0;
   src.gR1 = src.gO = src.gW = d3(0.0, 0.0, 0.0);
   src.G = src.prefix = 0.0;
   run_segments<Q_RADIANCE, true>(tc, src, work, hw * n_cams * sp.spp, hitlist, nullptr);
+  // (the runner's loop ends for the whole wave at once)
+  if ((threadIdx.x & 63) == 0 && gr.cap > 0) {
+    const unsigned used = s_wcur[wv];
+    gr.wused[blockIdx.x * (TRACE_BLOCK / 64) + wv] = used < (unsigned)gr.per_wave ? used : (unsigned)gr.per_wave;
+  }
 }
 
 // Camera segments on the persistent segment runner: one work item per pixel;
@@ -333,6 +413,56 @@ __global__ void __launch_bounds__(TRACE_BLOCK) k_sb_bwd_camera(TraceCtx tc, cons
   run_segments<Q_ALL, true>(tc, src, work, hw * n_cams, hitlist, nullptr);
 }
 
+__global__ void k_zero_u32(uint32_t* p, int64_t n) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+// A used slot s (below its wave's count) goes to the next free position of
+// its surfel's range [off[i], off[i] + cnt[i]) of order (cursor: zeroed
+// per-surfel counts).
+__global__ void k_rec_place(GradRecs gr) {
+  const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (s >= gr.cap) return;
+  const int64_t w = s / gr.per_wave;
+  if (s - w * gr.per_wave >= (int64_t)gr.wused[w]) return;
+  const uint32_t i = gr.idx[s];
+  gr.order[gr.off[i] + atomicAdd(gr.cursor + i, 1u)] = (uint32_t)s;
+}
+
+// One wave per surfel: its records, summed lane-strided and then across the
+// wave in a fixed order, are added to the accumulator rows (the albedo rows,
+// zero in every record, are skipped).
+__global__ void __launch_bounds__(256) k_rec_reduce(GradRecs gr, double* gacc, int64_t n) {
+  const int64_t i = blockIdx.x * 4 + (int64_t)(threadIdx.x >> 6);
+  const int lane = (int)(threadIdx.x & 63);
+  if (i >= n) return;
+  const uint32_t c = gr.cnt[i], o = gr.off[i];
+  if (c == 0) return;
+  double acc[GRAD_ROWS];
+#pragma unroll
+  for (int k = 0; k < GRAD_ROWS; ++k) acc[k] = 0.0;
+  for (uint32_t j = (uint32_t)lane; j < c; j += 64) {
+    const double2* r = reinterpret_cast<const double2*>(gr.rec + (size_t)gr.order[o + j] * GRAD_ROWS);
+#pragma unroll
+    for (int k = 0; k < GRAD_ROWS / 2; ++k) {
+      const double2 v = r[k];
+      acc[2 * k] += v.x;
+      acc[2 * k + 1] += v.y;
+    }
+  }
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+#pragma unroll
+    for (int k = 0; k < GRAD_ROWS; ++k) acc[k] += __shfl_xor(acc[k], m);
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < GRAD_ROWS; ++k)
+      if (k < 10 || k > 12) gacc[k * n + i] += acc[k];
+  }
+}
+
 __global__ void k_zero_f64(double* p, int64_t n) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0.0;
@@ -356,15 +486,38 @@ __global__ void k_grad_finalize(const double* acc, int64_t n, eag_surfel_grads g
 
 size_t grad_accum_doubles(int64_t n) { return (size_t)n * GRAD_ROWS; }
 
+int64_t grad_rec_capacity(int64_t n_items) {
+  const int64_t c = n_items * GRAD_RECS_PER_ITEM;
+  return c < GRAD_RECS_MAX ? c : GRAD_RECS_MAX;
+}
+
+size_t grad_rec_scan_bytes(int64_t n) {
+  size_t b = 0;
+  check_hip(rocprim::exclusive_scan(nullptr, b, (const uint32_t*)nullptr, (uint32_t*)nullptr, 0u, (size_t)n,
+                                    rocprim::plus<uint32_t>(), (hipStream_t)0),
+            "exclusive_scan size query");
+  return b;
+}
+
 void launch_single_bounce_backward(const TraceCtx& tc, const eag_surfels& s, const CamBatch& cams, int64_t hw,
                                    int32_t n_cams, const SbParams& sp, const float* state, const double* r1,
-                                   const float* dL, double* gacc, float* scratch, unsigned long long* work,
-                                   uint64_t* hitlist, hipStream_t st) {
+                                   const float* dL, double* gacc, float* scratch, const GradRecs& grecs,
+                                   unsigned long long* work, uint64_t* hitlist, hipStream_t st) {
   const int64_t n = s.n;
   GradPtrs gp{gacc, gacc + 3 * n, gacc + 7 * n, gacc + 9 * n, gacc + 10 * n, gacc + 13 * n, n};
+  const GradRecs& gr = grecs;
   launch_zero_u64(work, 1, st);
+  hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, gr.cnt, n);
+  hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, gr.cursor, n);
   hipLaunchKernelGGL(k_sb_bwd_secondary, dim3((unsigned)(runner_lanes() / TRACE_BLOCK)), dim3(TRACE_BLOCK), 0, st, tc,
-                     cams, hw, n_cams, sp, state, r1, dL, gp, reinterpret_cast<double*>(scratch), work, hitlist);
+                     cams, hw, n_cams, sp, state, r1, dL, gp, gr, reinterpret_cast<double*>(scratch), work, hitlist);
+  if (gr.cap > 0) {
+    size_t tb = gr.scan_bytes;
+    check_hip(rocprim::exclusive_scan(gr.scan_tmp, tb, gr.cnt, gr.off, 0u, (size_t)n, rocprim::plus<uint32_t>(), st),
+              "record count scan");
+    hipLaunchKernelGGL(k_rec_place, dim3((unsigned)((gr.cap + 255) / 256)), dim3(256), 0, st, gr);
+    hipLaunchKernelGGL(k_rec_reduce, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, gr, gacc, n);
+  }
   launch_zero_u64(work, 1, st);
   hipLaunchKernelGGL(k_sb_bwd_camera, dim3((unsigned)(runner_lanes() / TRACE_BLOCK)), dim3(TRACE_BLOCK), 0, st, tc,
                      cams, hw, n_cams, sp, state, r1, reinterpret_cast<const double*>(scratch), dL, gp, work, hitlist);

@@ -109,10 +109,30 @@ void launch_zero_u64(unsigned long long* p, int n, hipStream_t st);
 void launch_path_trace(const TraceCtx& tc, const PtLaunch& L, unsigned long long* work_counter,
                        unsigned long long* counters, uint64_t* hitlist, hipStream_t st);
 
+// Per-hit gradient records of the secondary adjoint (see eag_backward.hip):
+// workspace buffers for cap records of a camera batch.
+constexpr int64_t GRAD_RECS_PER_ITEM = 12;          // records per (pixel, sample) item
+constexpr int64_t GRAD_RECS_MAX = int64_t(1) << 26;   // at most 8 GiB of records
+struct GradRecs {
+  double* rec;                  // [cap][16] accumulator rows of each hit
+  uint32_t* idx;                // [cap] surfel index of each record
+  uint32_t* cnt;                // [n] records per surfel
+  uint32_t* cursor;             // [n] placement cursor per surfel
+  uint32_t* off;                // [n] exclusive scan of cnt
+  uint32_t* order;              // [cap] slots grouped by surfel
+  uint32_t* wused;              // [waves] slots used by each wave of the persistent grid
+  int64_t per_wave;             // slots per wave
+  int64_t cap;                  // waves * per_wave
+  void* scan_tmp;
+  size_t scan_bytes;
+};
+int64_t grad_rec_capacity(int64_t n_items);
+size_t grad_rec_scan_bytes(int64_t n);
+
 void launch_single_bounce_backward(const TraceCtx& tc, const eag_surfels& s, const CamBatch& cams, int64_t hw,
                                    int32_t n_cams, const SbParams& sp, const float* state, const double* r1,
-                                   const float* dL, double* gacc, float* scratch, unsigned long long* work,
-                                   uint64_t* hitlist, hipStream_t st);
+                                   const float* dL, double* gacc, float* scratch, const GradRecs& grecs,
+                                   unsigned long long* work, uint64_t* hitlist, hipStream_t st);
 size_t grad_accum_doubles(int64_t n);
 void launch_grad_zero(double* gacc, int64_t n, hipStream_t st);
 void launch_grad_finalize(const double* gacc, int64_t n, const eag_surfel_grads& g, hipStream_t st);
