@@ -19,8 +19,9 @@
 //   order, maps them to dN, dD, dA through Nt = N/|N| and Dt = D/A, adds dP =
 //   dL * mean R1 (or dR = dL for emitter pixels) and reverses the camera
 //   segment.
-// Gradients are scattered with double atomics into a workspace accumulator
-// and added to the caller's float arrays at the end.
+// Gradients are summed in double precision in a workspace accumulator (the
+// secondary pass through per-hit records grouped by surfel, the camera pass
+// with atomics) and added to the caller's float arrays at the end.
 #include "eag_device.h"
 #include "eag_internal.h"
 #include "eag_render.h"
