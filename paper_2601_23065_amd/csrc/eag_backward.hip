@@ -19,9 +19,9 @@
 //   order, maps them to dN, dD, dA through Nt = N/|N| and Dt = D/A, adds dP =
 //   dL * mean R1 (or dR = dL for emitter pixels) and reverses the camera
 //   segment.
-// Gradients are summed in double precision in a workspace accumulator (the
-// secondary pass through per-hit records grouped by surfel, the camera pass
-// with atomics) and added to the caller's float arrays at the end.
+// Gradients are summed in double precision in a workspace accumulator,
+// through per-hit records grouped by surfel, and added to the caller's float
+// arrays at the end.
 #include "eag_device.h"
 #include "eag_internal.h"
 #include "eag_render.h"
@@ -105,28 +105,14 @@ __device__ __forceinline__ void chain_values(const Geo& ge, D3 O, D3 W, double t
   out[9] = g_sigma;
 }
 
-// The same, added to the accumulators with atomics.
-__device__ void chain_hit(const Geo& ge, const GradPtrs& gp, uint32_t idx, D3 O, D3 W, double t, double g_alpha,
-                          double g_t, D3 g_n, bool ray_grad, D3& gO, D3& gW) {
-  double v[10];
-  chain_values(ge, O, W, t, g_alpha, g_t, g_n, ray_grad, gO, gW, v);
-  const int64_t n = gp.n;
-  atomic_add3(gp.pos, n, idx, d3(v[0], v[1], v[2]));
-#pragma unroll
-  for (int k = 0; k < 4; ++k) atomicAdd(gp.rot + k * n + idx, v[3 + k]);
-  atomicAdd(gp.scale + idx, v[7]);
-  atomicAdd(gp.scale + n + idx, v[8]);
-  atomicAdd(gp.opacity + idx, v[9]);
-}
-
-// Per-hit gradient records of the secondary adjoint. The secondary pass is
-// limited by the rate of its atomics (13 per hit). Instead, each hit writes
-// one record of the 16 accumulator rows (128 B, albedo rows zero) to the next
-// slot of its wave's range, whose cursor lives in LDS, and counts itself in a
-// per-surfel counter with an atomic whose result it does not wait for. After
-// the pass, an exclusive scan of the counters and a placement pass group the
-// slots by surfel, and one wave per surfel sums its records. Hits beyond a
-// wave's range fall back to atomics, so any capacity is correct.
+// Per-hit gradient records of both adjoint passes. Added with atomics, a
+// pass is limited by their rate (13 to 16 per hit). Instead, each hit writes
+// one record of the 16 accumulator rows (128 B) to the next slot of its
+// wave's range, whose cursor lives in LDS, and counts itself in a per-surfel
+// counter with an atomic whose result it does not wait for. After the pass,
+// an exclusive scan of the counters and a placement pass group the slots by
+// surfel, and one wave per surfel sums its records. Hits beyond a wave's
+// range fall back to atomics, so any capacity is correct.
 __device__ __forceinline__ void emit_record(const GradRecs& gr, const GradPtrs& gp, unsigned* wcur, uint32_t idx,
                                             const double (&v)[GRAD_ROWS]) {
   // Each wave owns per_wave slots; its cursor lives in LDS (wcur), and the
@@ -157,6 +143,7 @@ __device__ __forceinline__ void emit_record(const GradRecs& gr, const GradPtrs& 
     atomicAdd(gp.scale + idx, v[7]);
     atomicAdd(gp.scale + n + idx, v[8]);
     atomicAdd(gp.opacity + idx, v[9]);
+    atomic_add3(gp.albedo, n, idx, d3(v[10], v[11], v[12]));
     atomic_add3(gp.radiance, n, idx, d3(v[13], v[14], v[15]));
   }
 }
@@ -326,6 +313,8 @@ struct CameraAdjSource {
   const double* adj;
   const float* dL;
   GradPtrs gp;
+  GradRecs gr;
+  unsigned* wcur;     // this wave's record cursor (LDS)
   // per item
   D3 gN, gR, gP;
   double gD, gA, Tm, G, prefix;
@@ -383,19 +372,28 @@ struct CameraAdjSource {
     const double c = sgn * dot(gN, nn) + gD * t + dot(gR, rad) + dot(gP, rho);
     prefix += w * c;
     const double g_alpha = Tb * c - (G - prefix - gA * Tm) / (1.0 - alpha);
-    if (has_R) atomic_add3(gp.radiance, gp.n, idx, w * gR);
-    if (has_P) atomic_add3(gp.albedo, gp.n, idx, w * gP);
     D3 dummyO = d3(0.0, 0.0, 0.0), dummyW = d3(0.0, 0.0, 0.0);
-    chain_hit(ge, gp, idx, O, W, t, g_alpha, w * gD, (sgn * w) * gN, false, dummyO, dummyW);
+    double v[GRAD_ROWS];
+    double cv[10];
+    chain_values(ge, O, W, t, g_alpha, w * gD, (sgn * w) * gN, false, dummyO, dummyW, cv);
+#pragma unroll
+    for (int k = 0; k < 10; ++k) v[k] = cv[k];
+    v[10] = has_P ? w * gP.x : 0.0;
+    v[11] = has_P ? w * gP.y : 0.0;
+    v[12] = has_P ? w * gP.z : 0.0;
+    v[13] = has_R ? w * gR.x : 0.0;
+    v[14] = has_R ? w * gR.y : 0.0;
+    v[15] = has_R ? w * gR.z : 0.0;
+    emit_record(gr, gp, wcur, idx, v);
   }
 
   __device__ __forceinline__ bool finish(const Seg<true>&, D3&, D3&) { return false; }
 };
 
-__global__ void __launch_bounds__(TRACE_BLOCK) k_sb_bwd_camera(TraceCtx tc, const CamBatch cams, int64_t hw,
+__global__ void __launch_bounds__(TRACE_BLOCK) __attribute__((amdgpu_waves_per_eu(2))) k_sb_bwd_camera(TraceCtx tc, const CamBatch cams, int64_t hw,
                                                                int32_t n_cams, SbParams sp, const float* state,
                                                                const double* r1, const double* adj, const float* dL,
-                                                               GradPtrs gp, unsigned long long* work,
+                                                               GradPtrs gp, GradRecs gr, unsigned long long* work,
                                                                uint64_t* hitlist) {
   CameraAdjSource src;
   src.recs = tc.recs;
@@ -408,10 +406,19 @@ __global__ void __launch_bounds__(TRACE_BLOCK) k_sb_bwd_camera(TraceCtx tc, cons
   src.adj = adj;
   src.dL = dL;
   src.gp = gp;
+  __shared__ unsigned s_wcur[TRACE_BLOCK / 64];
+  const int wv = (int)(threadIdx.x >> 6);
+  if ((threadIdx.x & 63) == 0) s_wcur[wv] = 0u;
+  src.gr = gr;
+  src.wcur = s_wcur + wv;
   src.gN = src.gR = src.gP = d3(0.0, 0.0, 0.0);
   src.gD = src.gA = src.Tm = src.G = src.prefix = 0.0;
   src.has_R = src.has_P = false;
   run_segments<Q_ALL, true>(tc, src, work, hw * n_cams, hitlist, nullptr);
+  if ((threadIdx.x & 63) == 0 && gr.cap > 0) {
+    const unsigned used = s_wcur[wv];
+    gr.wused[blockIdx.x * (TRACE_BLOCK / 64) + wv] = used < (unsigned)gr.per_wave ? used : (unsigned)gr.per_wave;
+  }
 }
 
 __global__ void k_zero_u32(uint32_t* p, int64_t n) {
@@ -432,8 +439,7 @@ __global__ void k_rec_place(GradRecs gr) {
 }
 
 // One wave per surfel: its records, summed lane-strided and then across the
-// wave in a fixed order, are added to the accumulator rows (the albedo rows,
-// zero in every record, are skipped).
+// wave in a fixed order, are added to the accumulator rows.
 __global__ void __launch_bounds__(256) k_rec_reduce(GradRecs gr, double* gacc, int64_t n) {
   const int64_t i = blockIdx.x * 4 + (int64_t)(threadIdx.x >> 6);
   const int lane = (int)(threadIdx.x & 63);
@@ -459,8 +465,7 @@ __global__ void __launch_bounds__(256) k_rec_reduce(GradRecs gr, double* gacc, i
   }
   if (lane == 0) {
 #pragma unroll
-    for (int k = 0; k < GRAD_ROWS; ++k)
-      if (k < 10 || k > 12) gacc[k * n + i] += acc[k];
+    for (int k = 0; k < GRAD_ROWS; ++k) gacc[k * n + i] += acc[k];
   }
 }
 
@@ -500,6 +505,22 @@ size_t grad_rec_scan_bytes(int64_t n) {
   return b;
 }
 
+void zero_record_counts(const GradRecs& gr, int64_t n, hipStream_t st) {
+  if (gr.cap <= 0) return;
+  hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, gr.cnt, n);
+  hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, gr.cursor, n);
+}
+
+// Group the records of the pass just run by surfel and add their sums.
+void reduce_records(const GradRecs& gr, double* gacc, int64_t n, hipStream_t st) {
+  if (gr.cap <= 0) return;
+  size_t tb = gr.scan_bytes;
+  check_hip(rocprim::exclusive_scan(gr.scan_tmp, tb, gr.cnt, gr.off, 0u, (size_t)n, rocprim::plus<uint32_t>(), st),
+            "record count scan");
+  hipLaunchKernelGGL(k_rec_place, dim3((unsigned)((gr.cap + 255) / 256)), dim3(256), 0, st, gr);
+  hipLaunchKernelGGL(k_rec_reduce, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, gr, gacc, n);
+}
+
 void launch_single_bounce_backward(const TraceCtx& tc, const eag_surfels& s, const CamBatch& cams, int64_t hw,
                                    int32_t n_cams, const SbParams& sp, const float* state, const double* r1,
                                    const float* dL, double* gacc, float* scratch, const GradRecs& grecs,
@@ -507,21 +528,17 @@ void launch_single_bounce_backward(const TraceCtx& tc, const eag_surfels& s, con
   const int64_t n = s.n;
   GradPtrs gp{gacc, gacc + 3 * n, gacc + 7 * n, gacc + 9 * n, gacc + 10 * n, gacc + 13 * n, n};
   const GradRecs& gr = grecs;
+  const unsigned grid = (unsigned)(runner_lanes() / TRACE_BLOCK);
   launch_zero_u64(work, 1, st);
-  hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, gr.cnt, n);
-  hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, gr.cursor, n);
-  hipLaunchKernelGGL(k_sb_bwd_secondary, dim3((unsigned)(runner_lanes() / TRACE_BLOCK)), dim3(TRACE_BLOCK), 0, st, tc,
-                     cams, hw, n_cams, sp, state, r1, dL, gp, gr, reinterpret_cast<double*>(scratch), work, hitlist);
-  if (gr.cap > 0) {
-    size_t tb = gr.scan_bytes;
-    check_hip(rocprim::exclusive_scan(gr.scan_tmp, tb, gr.cnt, gr.off, 0u, (size_t)n, rocprim::plus<uint32_t>(), st),
-              "record count scan");
-    hipLaunchKernelGGL(k_rec_place, dim3((unsigned)((gr.cap + 255) / 256)), dim3(256), 0, st, gr);
-    hipLaunchKernelGGL(k_rec_reduce, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, gr, gacc, n);
-  }
+  zero_record_counts(gr, n, st);
+  hipLaunchKernelGGL(k_sb_bwd_secondary, dim3(grid), dim3(TRACE_BLOCK), 0, st, tc, cams, hw, n_cams, sp, state, r1,
+                     dL, gp, gr, reinterpret_cast<double*>(scratch), work, hitlist);
+  reduce_records(gr, gacc, n, st);
   launch_zero_u64(work, 1, st);
-  hipLaunchKernelGGL(k_sb_bwd_camera, dim3((unsigned)(runner_lanes() / TRACE_BLOCK)), dim3(TRACE_BLOCK), 0, st, tc,
-                     cams, hw, n_cams, sp, state, r1, reinterpret_cast<const double*>(scratch), dL, gp, work, hitlist);
+  zero_record_counts(gr, n, st);
+  hipLaunchKernelGGL(k_sb_bwd_camera, dim3(grid), dim3(TRACE_BLOCK), 0, st, tc, cams, hw, n_cams, sp, state, r1,
+                     reinterpret_cast<const double*>(scratch), dL, gp, gr, work, hitlist);
+  reduce_records(gr, gacc, n, st);
   check_hip(hipGetLastError(), "single-bounce backward launch");
 }
 
