@@ -211,8 +211,8 @@ int64_t eag_fwd_state_floats(const eag_camera* cams, int32_t n_cams, const eag_t
 size_t eag_render_workspace_bytes(int64_t n_surfels, const eag_camera* cams, int32_t n_cams,
                                   const eag_trace_params* p);
 /* Workspace of eag_single_bounce_backward: the render workspace plus the
- * per-hit gradient records of the adjoint passes: 128 B for up to 12 hits
- * per (pixel, sample) of one batch of up to 8 cameras, at most 2^26 records
+ * per-hit gradient records of the adjoint passes: 64 B for up to 20 hits
+ * per (pixel, sample) of one batch of up to 8 cameras, at most 2^27 records
  * (8 GiB), and per-surfel counters. Hits beyond the records are added with
  * atomics instead, so the result does not depend on the size; the speed
  * does. Returns 0 and sets the last error if the device cannot be queried. */
@@ -230,8 +230,9 @@ eag_status eag_render_single_bounce(const eag_bvh* bvh, const eag_surfels* s, co
  * the hemisphere frame) unless EAG_DETACH_BOUNCE. Hit lists are recomputed,
  * not stored. dL_drgb: device [n_cams][H][W][3]; fwd_state from the forward
  * call with the same arguments; ws of eag_backward_workspace_bytes() bytes.
- * Per-hit contributions are summed in double precision in the workspace,
- * through per-hit records grouped by surfel, and the sums are added once to
+ * Per-hit contributions, rounded to float, are summed in double precision in
+ * the workspace, through per-hit records grouped by surfel (a sum's error is
+ * about 2^-24 of the sum of its terms' magnitudes at most), and added once to
  * `grads` (grads += sum; the caller zeroes them for a fresh gradient). */
 eag_status eag_single_bounce_backward(const eag_bvh* bvh, const eag_surfels* s, const eag_camera* cams,
                                       int32_t n_cams, const eag_trace_params* p, const float* dL_drgb,

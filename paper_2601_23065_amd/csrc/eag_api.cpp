@@ -176,13 +176,14 @@ RenderWs render_ws(void* base, int64_t n, int64_t n_pix, int64_t spp, bool own_s
   if (own_state && records) {
     // sized for the largest camera batch of one launch
     GradRecs& g = w.grecs;
-    const int64_t waves = std::max<int64_t>(1, hl_lanes / 64);
-    g.per_wave = std::max<int64_t>(1, grad_rec_capacity(std::min<int64_t>(n_pix, n_pix_batch) * spp) / waves);
-    g.cap = g.per_wave * waves;
-    g.wused = c.take<uint32_t>(waves);
-    g.rec = c.take<double>((size_t)g.cap * 16);
-    g.idx = c.take<uint32_t>(g.cap);
-    g.order = c.take<uint32_t>(g.cap);
+    // (at least one chunk per wave of the persistent grid)
+    const int64_t want = grad_rec_capacity(std::min<int64_t>(n_pix, n_pix_batch) * spp);
+    g.n_chunks = std::max<int64_t>(std::max<int64_t>(1, hl_lanes / 64), (want + REC_CHUNK - 1) / REC_CHUNK);
+    const int64_t cap = g.n_chunks * REC_CHUNK;
+    g.chunk_used = c.take<uint32_t>(g.n_chunks);
+    g.rec = c.take<float>((size_t)cap * 16);
+    g.idx = c.take<uint32_t>(cap);
+    g.order = c.take<uint32_t>(cap);
     g.cnt = c.take<uint32_t>(n);
     g.cursor = c.take<uint32_t>(n);
     g.off = c.take<uint32_t>(n);

@@ -20,8 +20,8 @@
 //   dL * mean R1 (or dR = dL for emitter pixels) and reverses the camera
 //   segment.
 // Gradients are summed in double precision in a workspace accumulator,
-// through per-hit records grouped by surfel, and added to the caller's float
-// arrays at the end.
+// through per-hit records (float terms) grouped by surfel, and added to the
+// caller's float arrays at the end.
 #include "eag_device.h"
 #include "eag_internal.h"
 #include "eag_render.h"
@@ -107,32 +107,49 @@ __device__ __forceinline__ void chain_values(const Geo& ge, D3 O, D3 W, double t
 
 // Per-hit gradient records of both adjoint passes. Added with atomics, a
 // pass is limited by their rate (13 to 16 per hit). Instead, each hit writes
-// one record of the 16 accumulator rows (128 B) to the next slot of its
-// wave's range, whose cursor lives in LDS, and counts itself in a per-surfel
-// counter with an atomic whose result it does not wait for. After the pass,
-// an exclusive scan of the counters and a placement pass group the slots by
-// surfel, and one wave per surfel sums its records. Hits beyond a wave's
-// range fall back to atomics, so any capacity is correct.
+// one record of the 16 accumulator rows (64 B: each term rounded to float,
+// their sums taken in double, so a surfel's sum carries an error of about
+// 2^-24 of the sum of its terms' magnitudes at most) to the next slot of its
+// wave's current chunk of REC_CHUNK slots, and counts itself in a per-surfel
+// counter with an atomic whose result it does not wait for. A wave claims a
+// chunk from a global counter when the lanes of a call do not fit in its
+// current one (one atomic per many hits) and records how much of the chunk it
+// used; its cursor lives in LDS. After the pass, an exclusive scan of the
+// counters and a placement pass group the slots by surfel, and one wave per
+// surfel sums its records. Hits that find the chunks exhausted fall back to
+// atomics, so any capacity is correct.
+constexpr unsigned REC_NO_CHUNK = 0xffffffffu;   // none claimed yet
+constexpr unsigned REC_SPENT = 0xfffffffeu;      // the chunks are exhausted: atomics from here on
 __device__ __forceinline__ void emit_record(const GradRecs& gr, const GradPtrs& gp, unsigned* wcur, uint32_t idx,
                                             const double (&v)[GRAD_ROWS]) {
-  // Each wave owns per_wave slots; its cursor lives in LDS (wcur), and the
-  // lanes calling this together take consecutive slots: no global atomic.
+  // wcur[0]: slots used in the wave's chunk, wcur[1]: the chunk (or none)
   const uint64_t act = __ballot(1);
   const int lane = (int)(threadIdx.x & 63);
   const int leader = __ffsll((unsigned long long)act) - 1;
-  unsigned base = 0;
+  const unsigned k = (unsigned)__popcll(act);
+  unsigned base = 0, chunk = REC_NO_CHUNK;
   if (lane == leader) {
-    base = *wcur;
-    *wcur = base + (unsigned)__popcll(act);
+    unsigned cur = wcur[0], ch = wcur[1];
+    if (ch == REC_NO_CHUNK || (ch != REC_SPENT && cur + k > (unsigned)REC_CHUNK)) {
+      if (ch < (unsigned)gr.n_chunks) gr.chunk_used[ch] = cur;
+      const unsigned long long c = atomicAdd(gr.chunk_next, 1ull);
+      ch = c < (unsigned long long)gr.n_chunks ? (unsigned)c : REC_SPENT;
+      cur = 0;
+    }
+    base = cur;
+    chunk = ch;
+    wcur[0] = cur + k;
+    wcur[1] = ch;
   }
   base = __shfl(base, leader);
+  chunk = __shfl(chunk, leader);
   const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-  const int64_t j = (int64_t)base + __popcll(act & below);
-  if (j < gr.per_wave) {
-    const int64_t slot = ((int64_t)blockIdx.x * (TRACE_BLOCK / 64) + (threadIdx.x >> 6)) * gr.per_wave + j;
-    double2* dst = reinterpret_cast<double2*>(gr.rec + slot * GRAD_ROWS);
+  if (chunk < (unsigned)gr.n_chunks) {
+    const int64_t slot = (int64_t)chunk * REC_CHUNK + base + __popcll(act & below);
+    float4* dst = reinterpret_cast<float4*>(gr.rec + slot * GRAD_ROWS);
 #pragma unroll
-    for (int k = 0; k < GRAD_ROWS / 2; ++k) dst[k] = make_double2(v[2 * k], v[2 * k + 1]);
+    for (int q = 0; q < GRAD_ROWS / 4; ++q)
+      dst[q] = make_float4((float)v[4 * q], (float)v[4 * q + 1], (float)v[4 * q + 2], (float)v[4 * q + 3]);
     gr.idx[slot] = idx;
     atomicAdd(gr.cnt + idx, 1u);   // no return value: the lane does not wait for it
   } else {
@@ -163,7 +180,7 @@ struct SecondaryAdjSource {
   const float* dL;
   GradPtrs gp;
   GradRecs gr;
-  unsigned* wcur;     // this wave's record cursor (LDS)
+  unsigned* wcur;     // this wave's record cursor and chunk (LDS)
   double* adj;
   bool ray_grad;
   // per item
@@ -278,12 +295,15 @@ __global__ void __launch_bounds__(TRACE_BLOCK) __attribute__((amdgpu_waves_per_e
   src.state = state;
   src.r1 = r1;
   src.dL = dL;
-  __shared__ unsigned s_wcur[TRACE_BLOCK / 64];
+  __shared__ unsigned s_wcur[2 * (TRACE_BLOCK / 64)];
   const int wv = (int)(threadIdx.x >> 6);
-  if ((threadIdx.x & 63) == 0) s_wcur[wv] = 0u;
+  if ((threadIdx.x & 63) == 0) {
+    s_wcur[2 * wv] = 0u;
+    s_wcur[2 * wv + 1] = REC_NO_CHUNK;
+  }
   src.gp = gp;
   src.gr = gr;
-  src.wcur = s_wcur + wv;
+  src.wcur = s_wcur + 2 * wv;
   src.adj = adj;
   src.ray_grad = !(sp.flags & EAG_DETACH_BOUNCE);
   src.item = 0;
@@ -291,10 +311,8 @@ __global__ void __launch_bounds__(TRACE_BLOCK) __attribute__((amdgpu_waves_per_e
   src.G = src.prefix = 0.0;
   run_segments<Q_RADIANCE, true>(tc, src, work, hw * n_cams * sp.spp, hitlist, nullptr);
   // (the runner's loop ends for the whole wave at once)
-  if ((threadIdx.x & 63) == 0 && gr.cap > 0) {
-    const unsigned used = s_wcur[wv];
-    gr.wused[blockIdx.x * (TRACE_BLOCK / 64) + wv] = used < (unsigned)gr.per_wave ? used : (unsigned)gr.per_wave;
-  }
+  if ((threadIdx.x & 63) == 0 && s_wcur[2 * wv + 1] < (unsigned)gr.n_chunks)
+    gr.chunk_used[s_wcur[2 * wv + 1]] = s_wcur[2 * wv];
 }
 
 // Camera segments on the persistent segment runner: one work item per pixel;
@@ -314,7 +332,7 @@ struct CameraAdjSource {
   const float* dL;
   GradPtrs gp;
   GradRecs gr;
-  unsigned* wcur;     // this wave's record cursor (LDS)
+  unsigned* wcur;     // this wave's record cursor and chunk (LDS)
   // per item
   D3 gN, gR, gP;
   double gD, gA, Tm, G, prefix;
@@ -406,19 +424,20 @@ __global__ void __launch_bounds__(TRACE_BLOCK) __attribute__((amdgpu_waves_per_e
   src.adj = adj;
   src.dL = dL;
   src.gp = gp;
-  __shared__ unsigned s_wcur[TRACE_BLOCK / 64];
+  __shared__ unsigned s_wcur[2 * (TRACE_BLOCK / 64)];
   const int wv = (int)(threadIdx.x >> 6);
-  if ((threadIdx.x & 63) == 0) s_wcur[wv] = 0u;
+  if ((threadIdx.x & 63) == 0) {
+    s_wcur[2 * wv] = 0u;
+    s_wcur[2 * wv + 1] = REC_NO_CHUNK;
+  }
   src.gr = gr;
-  src.wcur = s_wcur + wv;
+  src.wcur = s_wcur + 2 * wv;
   src.gN = src.gR = src.gP = d3(0.0, 0.0, 0.0);
   src.gD = src.gA = src.Tm = src.G = src.prefix = 0.0;
   src.has_R = src.has_P = false;
   run_segments<Q_ALL, true>(tc, src, work, hw * n_cams, hitlist, nullptr);
-  if ((threadIdx.x & 63) == 0 && gr.cap > 0) {
-    const unsigned used = s_wcur[wv];
-    gr.wused[blockIdx.x * (TRACE_BLOCK / 64) + wv] = used < (unsigned)gr.per_wave ? used : (unsigned)gr.per_wave;
-  }
+  if ((threadIdx.x & 63) == 0 && s_wcur[2 * wv + 1] < (unsigned)gr.n_chunks)
+    gr.chunk_used[s_wcur[2 * wv + 1]] = s_wcur[2 * wv];
 }
 
 __global__ void k_zero_u32(uint32_t* p, int64_t n) {
@@ -426,14 +445,14 @@ __global__ void k_zero_u32(uint32_t* p, int64_t n) {
   if (i < n) p[i] = 0u;
 }
 
-// A used slot s (below its wave's count) goes to the next free position of
+// A used slot s (below its chunk's count) goes to the next free position of
 // its surfel's range [off[i], off[i] + cnt[i]) of order (cursor: zeroed
 // per-surfel counts).
 __global__ void k_rec_place(GradRecs gr) {
   const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (s >= gr.cap) return;
-  const int64_t w = s / gr.per_wave;
-  if (s - w * gr.per_wave >= (int64_t)gr.wused[w]) return;
+  if (s >= gr.n_chunks * REC_CHUNK) return;
+  const int64_t ch = s / REC_CHUNK;
+  if (s - ch * REC_CHUNK >= (int64_t)gr.chunk_used[ch]) return;
   const uint32_t i = gr.idx[s];
   gr.order[gr.off[i] + atomicAdd(gr.cursor + i, 1u)] = (uint32_t)s;
 }
@@ -450,12 +469,14 @@ __global__ void __launch_bounds__(256) k_rec_reduce(GradRecs gr, double* gacc, i
 #pragma unroll
   for (int k = 0; k < GRAD_ROWS; ++k) acc[k] = 0.0;
   for (uint32_t j = (uint32_t)lane; j < c; j += 64) {
-    const double2* r = reinterpret_cast<const double2*>(gr.rec + (size_t)gr.order[o + j] * GRAD_ROWS);
+    const float4* r = reinterpret_cast<const float4*>(gr.rec + (size_t)gr.order[o + j] * GRAD_ROWS);
 #pragma unroll
-    for (int k = 0; k < GRAD_ROWS / 2; ++k) {
-      const double2 v = r[k];
-      acc[2 * k] += v.x;
-      acc[2 * k + 1] += v.y;
+    for (int k = 0; k < GRAD_ROWS / 4; ++k) {
+      const float4 v = r[k];
+      acc[4 * k] += v.x;
+      acc[4 * k + 1] += v.y;
+      acc[4 * k + 2] += v.z;
+      acc[4 * k + 3] += v.w;
     }
   }
 #pragma unroll
@@ -506,18 +527,21 @@ size_t grad_rec_scan_bytes(int64_t n) {
 }
 
 void zero_record_counts(const GradRecs& gr, int64_t n, hipStream_t st) {
-  if (gr.cap <= 0) return;
+  if (gr.n_chunks <= 0) return;
   hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, gr.cnt, n);
   hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, gr.cursor, n);
+  hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)((gr.n_chunks + 255) / 256)), dim3(256), 0, st, gr.chunk_used,
+                     gr.n_chunks);
+  launch_zero_u64(gr.chunk_next, 1, st);
 }
 
 // Group the records of the pass just run by surfel and add their sums.
 void reduce_records(const GradRecs& gr, double* gacc, int64_t n, hipStream_t st) {
-  if (gr.cap <= 0) return;
+  if (gr.n_chunks <= 0) return;
   size_t tb = gr.scan_bytes;
   check_hip(rocprim::exclusive_scan(gr.scan_tmp, tb, gr.cnt, gr.off, 0u, (size_t)n, rocprim::plus<uint32_t>(), st),
             "record count scan");
-  hipLaunchKernelGGL(k_rec_place, dim3((unsigned)((gr.cap + 255) / 256)), dim3(256), 0, st, gr);
+  hipLaunchKernelGGL(k_rec_place, dim3((unsigned)((gr.n_chunks * REC_CHUNK + 255) / 256)), dim3(256), 0, st, gr);
   hipLaunchKernelGGL(k_rec_reduce, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, gr, gacc, n);
 }
 
@@ -527,7 +551,8 @@ void launch_single_bounce_backward(const TraceCtx& tc, const eag_surfels& s, con
                                    unsigned long long* work, uint64_t* hitlist, hipStream_t st) {
   const int64_t n = s.n;
   GradPtrs gp{gacc, gacc + 3 * n, gacc + 7 * n, gacc + 9 * n, gacc + 10 * n, gacc + 13 * n, n};
-  const GradRecs& gr = grecs;
+  GradRecs gr = grecs;
+  gr.chunk_next = work + 1;
   const unsigned grid = (unsigned)(runner_lanes() / TRACE_BLOCK);
   launch_zero_u64(work, 1, st);
   zero_record_counts(gr, n, st);

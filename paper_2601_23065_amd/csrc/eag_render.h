@@ -110,19 +110,20 @@ void launch_path_trace(const TraceCtx& tc, const PtLaunch& L, unsigned long long
                        unsigned long long* counters, uint64_t* hitlist, hipStream_t st);
 
 // Per-hit gradient records of the secondary adjoint (see eag_backward.hip):
-// workspace buffers for cap records of a camera batch.
-constexpr int64_t GRAD_RECS_PER_ITEM = 12;          // records per (pixel, sample) item
-constexpr int64_t GRAD_RECS_MAX = int64_t(1) << 26;   // at most 8 GiB of records
+// workspace buffers for the records of a camera batch.
+constexpr int64_t GRAD_RECS_PER_ITEM = 20;          // records per (pixel, sample) item
+constexpr int64_t GRAD_RECS_MAX = int64_t(1) << 27;   // at most 8 GiB of records
+constexpr int64_t REC_CHUNK = 1024;                   // slots a wave claims at a time
 struct GradRecs {
-  double* rec;                  // [cap][16] accumulator rows of each hit
-  uint32_t* idx;                // [cap] surfel index of each record
+  float* rec;                   // [n_chunks * REC_CHUNK][16] accumulator rows of each hit
+  uint32_t* idx;                // surfel index of each record
   uint32_t* cnt;                // [n] records per surfel
   uint32_t* cursor;             // [n] placement cursor per surfel
   uint32_t* off;                // [n] exclusive scan of cnt
-  uint32_t* order;              // [cap] slots grouped by surfel
-  uint32_t* wused;              // [waves] slots used by each wave of the persistent grid
-  int64_t per_wave;             // slots per wave
-  int64_t cap;                  // waves * per_wave
+  uint32_t* order;              // slots grouped by surfel
+  uint32_t* chunk_used;         // [n_chunks] slots used in each chunk of REC_CHUNK slots
+  unsigned long long* chunk_next;   // chunks claimed (set by the launch)
+  int64_t n_chunks;             // records: n_chunks * REC_CHUNK
   void* scan_tmp;
   size_t scan_bytes;
 };
