@@ -9,7 +9,7 @@ import scenegen as sg
 from oracle.grad import PARAMS, signature, single_bounce_grad
 from oracle.render import single_bounce
 from oracle.tracer import Scene64
-from tests._util import gpu_scene, oracle_params, rel_err
+from tests._util import coplanar_stack, gpu_scene, oracle_params, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -87,6 +87,19 @@ def test_adjoint_config2_masked():
     from paper_2601_23065_amd.api import Params
     scene, cams, cfg = sg.config(2)
     _compare(scene, cams, Params(spp=cfg["spp"]), 48, seed=7)
+
+
+def test_adjoint_deep_stack_beyond_the_record_slots():
+    """A 300-layer coplanar stack filling a 90x90 image: the camera pass
+    blends 300 hits per pixel, 2.43 M in all, more than the 2^21 record slots
+    its workspace holds on a 256-CU device (one 1024-slot chunk per wave of
+    the persistent grid), so the last hits take the atomic path; every pixel
+    is an emitter pixel (E > tau_E), whose gradient flows through the camera
+    segment alone."""
+    from paper_2601_23065_amd.api import Params
+    scene = coplanar_stack(300, 5)
+    cam = sg.Camera((0.0, 0.0, -2.0), (0.0, 0.0, 0.0), (0.0, 1.0, 0.0), 5.0, 90, 90)
+    _compare(scene, [cam], Params(spp=2, seed=5), 40, seed=8)
 
 
 def test_adjoint_against_finite_differences():

@@ -10,7 +10,7 @@ import scenegen as sg
 from oracle.render import path_trace as o_path_trace
 from oracle.render import single_bounce as o_single_bounce
 from oracle.tracer import Scene64
-from tests._util import gpu_scene, oracle_params, rel_err
+from tests._util import coplanar_stack, gpu_scene, oracle_params, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -124,16 +124,7 @@ def test_path_trace_deep_coplanar_stack(layers):
     stack, and random radiance makes the pixel depend on the blending order
     (the surfel index within the bucket)."""
     from paper_2601_23065_amd.api import BVH, Params
-    rng = np.random.default_rng(61 + layers)
-    n = layers
-    pos = np.zeros((3, n))
-    pos[:2] = rng.uniform(-0.02, 0.02, (2, n))
-    rot = np.zeros((4, n))
-    rot[0] = 1.0
-    f32 = lambda a: np.ascontiguousarray(a, dtype=np.float32)   # noqa: E731
-    scene = sg.Scene(f32(pos), f32(rot), f32(np.full((2, n), 0.2)), f32(np.full(n, 0.02)),
-                     f32(rng.uniform(0.1, 0.8, (3, n))), f32(rng.uniform(1.0, 10.0, (3, n))), f32(np.ones(n)),
-                     bounds=(np.full(3, -1.0), np.full(3, 1.0)))
+    scene = coplanar_stack(layers, 61 + layers)
     cam = sg.Camera((0.0, 0.0, -2.0), (0.0, 0.0, 0.0), (0.0, 1.0, 0.0), 5.0, 8, 8)
     p = Params(spp=2, max_depth=0, rr_start=0, seed=3)
     gs = gpu_scene(scene)
