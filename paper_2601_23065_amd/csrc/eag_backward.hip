@@ -445,16 +445,20 @@ __global__ void k_zero_u32(uint32_t* p, int64_t n) {
   if (i < n) p[i] = 0u;
 }
 
-// A used slot s (below its chunk's count) goes to the next free position of
-// its surfel's range [off[i], off[i] + cnt[i]) of order (cursor: zeroed
-// per-surfel counts).
-__global__ void k_rec_place(GradRecs gr) {
-  const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (s >= gr.n_chunks * REC_CHUNK) return;
-  const int64_t ch = s / REC_CHUNK;
-  if (s - ch * REC_CHUNK >= (int64_t)gr.chunk_used[ch]) return;
-  const uint32_t i = gr.idx[s];
-  gr.order[gr.off[i] + atomicAdd(gr.cursor + i, 1u)] = (uint32_t)s;
+// Every used slot of the claimed chunks goes to the next free position of its
+// surfel's range [off[i], off[i] + cnt[i]) of order (cursor: zeroed per-surfel
+// counts). Blocks stride over the claimed chunks only.
+__global__ void __launch_bounds__(256) k_rec_place(GradRecs gr) {
+  const unsigned long long claimed = *gr.chunk_next;
+  const int64_t nc = claimed < (unsigned long long)gr.n_chunks ? (int64_t)claimed : gr.n_chunks;
+  for (int64_t ch = blockIdx.x; ch < nc; ch += gridDim.x) {
+    const uint32_t used = gr.chunk_used[ch];
+    for (uint32_t j = threadIdx.x; j < used; j += blockDim.x) {
+      const int64_t s = ch * REC_CHUNK + j;
+      const uint32_t i = gr.idx[s];
+      gr.order[gr.off[i] + atomicAdd(gr.cursor + i, 1u)] = (uint32_t)s;
+    }
+  }
 }
 
 // One wave per surfel: its records, summed lane-strided and then across the
@@ -541,7 +545,7 @@ void reduce_records(const GradRecs& gr, double* gacc, int64_t n, hipStream_t st)
   size_t tb = gr.scan_bytes;
   check_hip(rocprim::exclusive_scan(gr.scan_tmp, tb, gr.cnt, gr.off, 0u, (size_t)n, rocprim::plus<uint32_t>(), st),
             "record count scan");
-  hipLaunchKernelGGL(k_rec_place, dim3((unsigned)((gr.n_chunks * REC_CHUNK + 255) / 256)), dim3(256), 0, st, gr);
+  hipLaunchKernelGGL(k_rec_place, dim3(4096), dim3(256), 0, st, gr);
   hipLaunchKernelGGL(k_rec_reduce, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, gr, gacc, n);
 }
 
