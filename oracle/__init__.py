@@ -21,6 +21,8 @@ Modules:
   render   - 0-bounce, single-bounce (Eq. 5-7) and path-traced (Eq. 9) images
   grad     - the single-bounce map re-expressed in torch.float64 (CPU) with
              every discrete decision fixed, differentiated by autograd
+  bake     - light baking: the PQ-encoded L1 loss between 0-bounce and
+             path-traced images, its radiance gradient, and the Adam step
 
 Parity status of each function is stated in its module docstring.
 """
