@@ -12,6 +12,8 @@
  *     and its gradient (Stage 1 objective)     Sec. 3.3, Eq. 8
  *   - multi-bounce path tracing                Sec. 3.4, Eq. 9
  *   - scene edits (relighting, recolouring)    Sec. 1 and Sec. 5 results
+ *   - light baking into r (0-bounce render,
+ *     its radiance gradient, PQ-L1 loss, Adam)  Sec. 3.4 "Light Baking", Eq. 10
  *
  * Conventions for every call:
  *   - Plain C. No exceptions cross the boundary; every entry point returns
@@ -289,6 +291,59 @@ typedef struct {
   float* emissive;              /* device [n]    */
 } eag_surfel_attrs;
 eag_status eag_apply_edit(const eag_edit* e, const eag_surfel_attrs* a, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Light baking (Sec. 3.4 "Light Baking", Eq. 10): the per-surfel radiance r
+ * is refitted so that the 0-bounce image (R composited along each camera
+ * ray, Sec. 3.2) matches path-traced renders of the (edited) scene:
+ * min_r L1(PQ(L0), PQ(Lpt)). Geometry and opacity are fixed, so the
+ * blending weights of every camera ray do not depend on r and L0 is linear
+ * in it. PQ is SMPTE ST 2084 on Y = max(L, 0) / 10000 (radiance read as
+ * cd/m^2), its derivative taken at max(Y, 2^-24). One camera ray per pixel:
+ * sample 0, the pixel centre unless EAG_JITTER.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  float lr;                     /* step size                                     */
+  float beta1, beta2;           /* moment decay rates (0.9, 0.999)               */
+  float eps;                    /* added to sqrt(v_hat) (1e-15)                  */
+} eag_adam;
+/* Workspace of the calls below for n_cams cameras of one size: packed
+ * attributes, the persistent grid's hit list (device dependent: 128 MiB on
+ * MI355X), double radiance-gradient accumulators, and the image and image
+ * gradient of eag_bake_step. 0 and the last error if the device cannot be
+ * queried. */
+size_t eag_bake_workspace_bytes(int64_t n_surfels, const eag_camera* cams, int32_t n_cams);
+/* 0-bounce image. rgb: device [n_cams][H][W][3] (written). Only the
+ * geometry, opacity and radiance of s are read. */
+eag_status eag_render_zero_bounce(const eag_bvh* bvh, const eag_surfels* s, const eag_camera* cams,
+                                  int32_t n_cams, const eag_trace_params* p, float* rgb,
+                                  void* ws, size_t ws_bytes, void* stream);
+/* Radiance gradient of sum(dL_drgb * L0): every blended hit i of a pixel
+ * adds w_i * dL to its surfel's row (w_i = T_{i-1} alpha_i), summed in
+ * double precision, then grad_radiance += sum. dL_drgb: device
+ * [n_cams][H][W][3]; grad_radiance: device [3][n] (caller zeroes it for a
+ * fresh gradient). Pixels whose dL is zero are not traced. */
+eag_status eag_zero_bounce_backward(const eag_bvh* bvh, const eag_surfels* s, const eag_camera* cams,
+                                    int32_t n_cams, const eag_trace_params* p, const float* dL_drgb,
+                                    float* grad_radiance, void* ws, size_t ws_bytes, void* stream);
+/* loss = mean over the n_values values of |PQ(rgb) - PQ(target)| (device
+ * double, written), dL_drgb = its derivative in rgb (device, n_values,
+ * written; 0 where the two are equal). */
+eag_status eag_bake_loss(const float* rgb, const float* target, int64_t n_values, float* dL_drgb,
+                         double* loss, void* stream);
+/* One Adam update with bias correction (step counts from 1) of the n
+ * values of param, then param clamped at 0: m, v are the caller's first
+ * and second moment arrays (device, n each, zero before the first step). */
+eag_status eag_adam_step(float* param, const float* grad, float* m, float* v, int64_t n, const eag_adam* a,
+                         int32_t step, void* stream);
+/* One baking iteration over n_cams views: 0-bounce render, loss against
+ * targets (device [n_cams][H][W][3], e.g. resolved path-traced images),
+ * radiance gradient and the Adam update of radiance, which must be
+ * s->radiance (device [3][n], updated in place; m, v as for eag_adam_step).
+ * loss: device double, written with the loss before the update. */
+eag_status eag_bake_step(const eag_bvh* bvh, const eag_surfels* s, const eag_camera* cams, int32_t n_cams,
+                         const eag_trace_params* p, const float* targets, float* radiance, float* m, float* v,
+                         const eag_adam* a, int32_t step, double* loss, void* ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
  * Serving: a resident scene answering path-tracing requests with continuous

@@ -52,6 +52,10 @@ class Edit(C.Structure):
     _fields_ = [("kind", C.c_int32), ("idx", vp), ("count", C.c_int64), ("value", C.c_float * 3)]
 
 
+class Adam(C.Structure):
+    _fields_ = [("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float)]
+
+
 class SurfelAttrs(C.Structure):
     _fields_ = [("n", C.c_int64), ("albedo", vp), ("radiance", vp), ("emissive", vp)]
 
@@ -96,6 +100,15 @@ SIGNATURES = {
                                  C.c_size_t, vp]),
     "eag_accum_resolve": (C.c_int, [vp, C.c_int64, C.c_int32, vp, vp]),
     "eag_apply_edit": (C.c_int, [P(Edit), P(SurfelAttrs), vp]),
+    "eag_bake_workspace_bytes": (C.c_size_t, [C.c_int64, P(Camera), C.c_int32]),
+    "eag_render_zero_bounce": (C.c_int, [vp, P(Surfels), P(Camera), C.c_int32, P(TraceParams), vp, vp, C.c_size_t,
+                                         vp]),
+    "eag_zero_bounce_backward": (C.c_int, [vp, P(Surfels), P(Camera), C.c_int32, P(TraceParams), vp, vp, vp,
+                                           C.c_size_t, vp]),
+    "eag_bake_loss": (C.c_int, [vp, vp, C.c_int64, vp, vp, vp]),
+    "eag_adam_step": (C.c_int, [vp, vp, vp, vp, C.c_int64, P(Adam), C.c_int32, vp]),
+    "eag_bake_step": (C.c_int, [vp, P(Surfels), P(Camera), C.c_int32, P(TraceParams), vp, vp, vp, vp, P(Adam),
+                                C.c_int32, vp, vp, C.c_size_t, vp]),
     "eag_serve_arena_bytes": (C.c_size_t, [C.c_int64, C.c_int32, C.c_size_t]),
     "eag_serve_create": (C.c_int, [P(Surfels), P(ServerConfig), P(vp)]),
     "eag_serve_submit": (C.c_int, [vp, P(Request), P(C.c_uint64)]),

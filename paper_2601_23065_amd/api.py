@@ -293,6 +293,94 @@ def apply_edit(scene: Scene, kind: int, idx, value, stream=None):
     L.check(L.load().eag_apply_edit(C.byref(e), C.byref(a), _stream(stream)))
 
 
+def bake_workspace(scene: Scene, cams):
+    return _bytes(L.load().eag_bake_workspace_bytes(scene.n, _cams(cams), len(cams)), scene.device)
+
+
+def render_zero_bounce(bvh: BVH, scene: Scene, cams, params: Params, ws=None, stream=None):
+    """0-bounce images [n_cams, H, W, 3]: R composited along each camera ray."""
+    lib = L.load()
+    ca = _cams(cams)
+    rgb = torch.empty((len(cams), cams[0].height, cams[0].width, 3), dtype=torch.float32, device=scene.device)
+    ws = bake_workspace(scene, cams) if ws is None else ws
+    wp, wb = _aligned(ws)
+    sc = scene.c()
+    L.check(lib.eag_render_zero_bounce(bvh.h, C.byref(sc), ca, len(cams), C.byref(params.c()), _ptr(rgb), wp, wb,
+                                       _stream(stream)))
+    return rgb
+
+
+def zero_bounce_backward(bvh: BVH, scene: Scene, cams, params: Params, dL_drgb, grad_radiance=None, ws=None,
+                         stream=None):
+    """grad_radiance [3, n] += d<dL_drgb, 0-bounce image>/d radiance."""
+    lib = L.load()
+    ca = _cams(cams)
+    if grad_radiance is None:
+        grad_radiance = torch.zeros_like(scene.t["radiance"])
+    ws = bake_workspace(scene, cams) if ws is None else ws
+    wp, wb = _aligned(ws)
+    sc = scene.c()
+    L.check(lib.eag_zero_bounce_backward(bvh.h, C.byref(sc), ca, len(cams), C.byref(params.c()),
+                                         _ptr(dL_drgb.contiguous()), _ptr(grad_radiance), wp, wb, _stream(stream)))
+    return grad_radiance
+
+
+def bake_loss(rgb, target, stream=None):
+    """(loss as a device float64 scalar, dloss/drgb) of mean |PQ(rgb) - PQ(target)|."""
+    rgb, target = rgb.contiguous(), target.contiguous()
+    dL = torch.empty_like(rgb)
+    loss = torch.empty((), dtype=torch.float64, device=rgb.device)
+    L.check(L.load().eag_bake_loss(_ptr(rgb), _ptr(target), rgb.numel(), _ptr(dL), _ptr(loss), _stream(stream)))
+    return loss, dL
+
+
+@dataclass
+class Adam:
+    """Mirror of eag_adam."""
+    lr: float = 0.01
+    beta1: float = 0.9
+    beta2: float = 0.999
+    eps: float = 1e-15
+
+    def c(self):
+        a = L.Adam()
+        a.lr, a.beta1, a.beta2, a.eps = self.lr, self.beta1, self.beta2, self.eps
+        return a
+
+
+def adam_step(param, grad, m, v, adam: Adam, step: int, stream=None):
+    """In-place projected Adam update of param (m, v: moment tensors)."""
+    L.check(L.load().eag_adam_step(_ptr(param), _ptr(grad), _ptr(m), _ptr(v), param.numel(), C.byref(adam.c()),
+                                   int(step), _stream(stream)))
+
+
+class Baker:
+    """Light baking (Eq. 10) of the scene's radiance into its 0-bounce image
+    against target images [n_cams, H, W, 3]; step() runs one iteration
+    (render, loss, radiance gradient, Adam update of scene.radiance in place)
+    and returns the loss before the update as a device float64 scalar."""
+
+    def __init__(self, bvh: BVH, scene: Scene, cams, params: Params, targets, adam: Adam | None = None):
+        self.bvh, self.scene, self.cams, self.params = bvh, scene, list(cams), params
+        self.targets = targets.contiguous()
+        self.adam = adam or Adam()
+        self.m = torch.zeros_like(scene.t["radiance"])
+        self.v = torch.zeros_like(scene.t["radiance"])
+        self.ws = bake_workspace(scene, self.cams)
+        self.loss = torch.zeros((), dtype=torch.float64, device=scene.device)
+        self.steps = 0
+
+    def step(self, stream=None):
+        lib = L.load()
+        self.steps += 1
+        wp, wb = _aligned(self.ws)
+        sc = self.scene.c()
+        L.check(lib.eag_bake_step(self.bvh.h, C.byref(sc), _cams(self.cams), len(self.cams), C.byref(self.params.c()),
+                                  _ptr(self.targets), _ptr(self.scene.t["radiance"]), _ptr(self.m), _ptr(self.v),
+                                  C.byref(self.adam.c()), self.steps, _ptr(self.loss), wp, wb, _stream(stream)))
+        return self.loss
+
+
 class Server:
     """Continuous-batching render server over a resident scene (eag_serve_*).
 

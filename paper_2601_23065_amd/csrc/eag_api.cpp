@@ -209,6 +209,77 @@ void check_bvh(const eag_bvh* b, const eag_surfels* s) {
   if (s->n != b->n) fail(EAG_ERR_INVALID_ARGUMENT, "surfel count differs from the BVH's");
 }
 
+// Light-baking workspace: packed attributes, work counter, hit list, double
+// radiance-gradient accumulators [3][n], and the image, image gradient and
+// loss of eag_bake_step.
+struct BakeWs {
+  Attr* attrs;
+  unsigned long long* work;
+  uint64_t* hitlist;
+  double* gacc;
+  float* rgb;
+  float* dL;
+  double* loss;
+  size_t bytes;
+};
+
+BakeWs bake_ws(void* base, int64_t n, int64_t n_values, int64_t hl_lanes) {
+  Carver c(base, ~size_t(0));
+  BakeWs w;
+  w.attrs = c.take<Attr>(n);
+  w.work = c.take<unsigned long long>(8);
+  w.hitlist = c.take<uint64_t>((size_t)hl_lanes * HL_CAP);
+  w.gacc = c.take<double>((size_t)n * 3);
+  w.rgb = c.take<float>(n_values);
+  w.dL = c.take<float>(n_values);
+  w.loss = c.take<double>(1);
+  w.bytes = c.bytes();
+  return w;
+}
+
+// Trace setup, attributes and camera batches shared by the light-baking calls.
+struct BakeCall {
+  TraceCtx tc;
+  SbParams sp;
+  int64_t hw;
+};
+
+BakeCall bake_setup(const eag_bvh* b, const eag_surfels* s, const eag_camera* cams, int32_t n_cams,
+                    const eag_trace_params* p, const BakeWs& w, hipStream_t st) {
+  float t_max = scene_t_max(b);
+  for (int i = 0; i < n_cams; ++i) t_max = std::fmax(t_max, camera_t_max(b, cams[i]));
+  const TraceSetup ts = trace_setup(b, p, t_max);
+  pack_attrs(s, b, w.attrs, st);
+  BakeCall k;
+  k.tc = make_ctx(b, w.attrs, p, ts);
+  k.tc.hl = w.hitlist;
+  k.sp.spp = 1;
+  k.sp.flags = p->flags;
+  k.sp.k0 = (uint32_t)(p->seed & 0xffffffffu);
+  k.sp.k1 = (uint32_t)(p->seed >> 32);
+  k.sp.tau_E = p->tau_E;
+  k.hw = (int64_t)cams[0].width * cams[0].height;
+  return k;
+}
+
+template <class F>
+void for_camera_batches(const eag_camera* cams, int32_t n_cams, const eag_trace_params* p, F&& f) {
+  for (int c0 = 0; c0 < n_cams; c0 += MAX_CAMS_PER_LAUNCH) {
+    const int nc = std::min(MAX_CAMS_PER_LAUNCH, n_cams - c0);
+    CamBatch cb;
+    std::memset(&cb, 0, sizeof(cb));
+    for (int i = 0; i < nc; ++i) cb.c[i] = make_cam(cams[c0 + i], p->camera_id + (uint32_t)(c0 + i));
+    f(c0, nc, cb);
+  }
+}
+
+void check_adam(const eag_adam* a) {
+  if (!a) fail(EAG_ERR_INVALID_ARGUMENT, "adam parameters are null");
+  if (!(a->lr >= 0.0f) || !(a->beta1 >= 0.0f && a->beta1 < 1.0f) || !(a->beta2 >= 0.0f && a->beta2 < 1.0f) ||
+      !(a->eps >= 0.0f))
+    fail(EAG_ERR_INVALID_ARGUMENT, "adam parameters out of range (lr >= 0, 0 <= beta < 1, eps >= 0)");
+}
+
 }  // namespace
 
 extern "C" {
@@ -485,6 +556,102 @@ eag_status eag_path_trace(const eag_bvh* b, const eag_surfels* s, const eag_came
     L.n_slots = 1;
     L.n_work = S.global_end;
     launch_path_trace(tc, L, w.work, reinterpret_cast<unsigned long long*>(counters), w.hitlist, st);
+  });
+}
+
+size_t eag_bake_workspace_bytes(int64_t n, const eag_camera* cams, int32_t n_cams) {
+  if (n < 1 || !cams || n_cams < 1) return 0;
+  try {
+    return bake_ws(nullptr, n, (int64_t)cams[0].width * cams[0].height * n_cams * 3, runner_lanes()).bytes;
+  } catch (const Error& e) {
+    set_error(e.status, e.msg);
+    return 0;
+  }
+}
+
+eag_status eag_render_zero_bounce(const eag_bvh* b, const eag_surfels* s, const eag_camera* cams, int32_t n_cams,
+                                  const eag_trace_params* p, float* rgb, void* ws, size_t ws_bytes, void* stream) {
+  return guarded([&] {
+    check_bvh(b, s);
+    validate_params(p);
+    check_cams(cams, n_cams);
+    if (!rgb) fail(EAG_ERR_INVALID_ARGUMENT, "rgb is null");
+    const int64_t hw = (int64_t)cams[0].width * cams[0].height;
+    const BakeWs w = bake_ws(ws, b->n, hw * n_cams * 3, runner_lanes());
+    if (!ws || ws_bytes < w.bytes) fail(EAG_ERR_WORKSPACE_TOO_SMALL, "bake workspace too small");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const BakeCall k = bake_setup(b, s, cams, n_cams, p, w, st);
+    for_camera_batches(cams, n_cams, p, [&](int c0, int nc, const CamBatch& cb) {
+      launch_zero_bounce(k.tc, cb, hw, nc, k.sp, rgb + c0 * hw * 3, w.work, w.hitlist, st);
+    });
+  });
+}
+
+eag_status eag_zero_bounce_backward(const eag_bvh* b, const eag_surfels* s, const eag_camera* cams, int32_t n_cams,
+                                    const eag_trace_params* p, const float* dL_drgb, float* grad_radiance, void* ws,
+                                    size_t ws_bytes, void* stream) {
+  return guarded([&] {
+    check_bvh(b, s);
+    validate_params(p);
+    check_cams(cams, n_cams);
+    if (!dL_drgb || !grad_radiance) fail(EAG_ERR_INVALID_ARGUMENT, "null argument");
+    const int64_t hw = (int64_t)cams[0].width * cams[0].height;
+    const BakeWs w = bake_ws(ws, b->n, hw * n_cams * 3, runner_lanes());
+    if (!ws || ws_bytes < w.bytes) fail(EAG_ERR_WORKSPACE_TOO_SMALL, "bake workspace too small");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const BakeCall k = bake_setup(b, s, cams, n_cams, p, w, st);
+    launch_zero_f64(w.gacc, b->n * 3, st);
+    for_camera_batches(cams, n_cams, p, [&](int c0, int nc, const CamBatch& cb) {
+      launch_zero_bounce_adj_r(k.tc, cb, hw, nc, k.sp, dL_drgb + c0 * hw * 3, w.gacc, b->n, w.work, w.hitlist, st);
+    });
+    launch_add_grad(w.gacc, b->n * 3, grad_radiance, st);
+  });
+}
+
+eag_status eag_bake_loss(const float* rgb, const float* target, int64_t n_values, float* dL_drgb, double* loss,
+                         void* stream) {
+  return guarded([&] {
+    if (!rgb || !target || !dL_drgb || !loss || n_values < 0) fail(EAG_ERR_INVALID_ARGUMENT, "bad loss arguments");
+    launch_bake_loss(rgb, target, n_values, dL_drgb, loss, static_cast<hipStream_t>(stream));
+  });
+}
+
+eag_status eag_adam_step(float* param, const float* grad, float* m, float* v, int64_t n, const eag_adam* a,
+                         int32_t step, void* stream) {
+  return guarded([&] {
+    if (!param || !grad || !m || !v || n < 0) fail(EAG_ERR_INVALID_ARGUMENT, "bad adam arguments");
+    check_adam(a);
+    if (step < 1) fail(EAG_ERR_INVALID_ARGUMENT, "adam step counts from 1");
+    launch_adam(param, grad, m, v, n, *a, step, static_cast<hipStream_t>(stream));
+  });
+}
+
+eag_status eag_bake_step(const eag_bvh* b, const eag_surfels* s, const eag_camera* cams, int32_t n_cams,
+                         const eag_trace_params* p, const float* targets, float* radiance, float* m, float* v,
+                         const eag_adam* a, int32_t step, double* loss, void* ws, size_t ws_bytes, void* stream) {
+  return guarded([&] {
+    check_bvh(b, s);
+    validate_params(p);
+    check_cams(cams, n_cams);
+    check_adam(a);
+    if (!targets || !radiance || !m || !v || !loss) fail(EAG_ERR_INVALID_ARGUMENT, "null argument");
+    if (radiance != s->radiance) fail(EAG_ERR_INVALID_ARGUMENT, "radiance must be the scene's radiance array");
+    if (step < 1) fail(EAG_ERR_INVALID_ARGUMENT, "adam step counts from 1");
+    const int64_t hw = (int64_t)cams[0].width * cams[0].height;
+    const int64_t nv = hw * n_cams * 3;
+    const BakeWs w = bake_ws(ws, b->n, nv, runner_lanes());
+    if (!ws || ws_bytes < w.bytes) fail(EAG_ERR_WORKSPACE_TOO_SMALL, "bake workspace too small");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const BakeCall k = bake_setup(b, s, cams, n_cams, p, w, st);
+    for_camera_batches(cams, n_cams, p, [&](int c0, int nc, const CamBatch& cb) {
+      launch_zero_bounce(k.tc, cb, hw, nc, k.sp, w.rgb + c0 * hw * 3, w.work, w.hitlist, st);
+    });
+    launch_bake_loss(w.rgb, targets, nv, w.dL, loss, st);
+    launch_zero_f64(w.gacc, b->n * 3, st);
+    for_camera_batches(cams, n_cams, p, [&](int c0, int nc, const CamBatch& cb) {
+      launch_zero_bounce_adj_r(k.tc, cb, hw, nc, k.sp, w.dL + c0 * hw * 3, w.gacc, b->n, w.work, w.hitlist, st);
+    });
+    launch_adam(radiance, w.gacc, m, v, b->n * 3, *a, step, st);
   });
 }
 

@@ -134,6 +134,20 @@ void launch_single_bounce_backward(const TraceCtx& tc, const eag_surfels& s, con
                                    int32_t n_cams, const SbParams& sp, const float* state, const double* r1,
                                    const float* dL, double* gacc, float* scratch, const GradRecs& grecs,
                                    unsigned long long* work, uint64_t* hitlist, hipStream_t st);
+// Light baking (eag_bake.hip).
+void launch_zero_bounce(const TraceCtx& tc, const CamBatch& cams, int64_t hw, int32_t n_cams, const SbParams& sp,
+                        float* rgb, unsigned long long* work, uint64_t* hitlist, hipStream_t st);
+void launch_zero_bounce_adj_r(const TraceCtx& tc, const CamBatch& cams, int64_t hw, int32_t n_cams,
+                              const SbParams& sp, const float* dL, double* gacc, int64_t n, unsigned long long* work,
+                              uint64_t* hitlist, hipStream_t st);
+void launch_zero_f64(double* p, int64_t count, hipStream_t st);
+void launch_add_grad(const double* acc, int64_t count, float* g, hipStream_t st);
+void launch_bake_loss(const float* rgb, const float* target, int64_t m, float* dL, double* loss, hipStream_t st);
+void launch_adam(float* r, const double* g, float* m, float* v, int64_t count, const eag_adam& a, int32_t step,
+                 hipStream_t st);
+void launch_adam(float* r, const float* g, float* m, float* v, int64_t count, const eag_adam& a, int32_t step,
+                 hipStream_t st);
+
 size_t grad_accum_doubles(int64_t n);
 void launch_grad_zero(double* gacc, int64_t n, hipStream_t st);
 void launch_grad_finalize(const double* gacc, int64_t n, const eag_surfel_grads& g, hipStream_t st);
