@@ -16,7 +16,7 @@ segment, over the kernel's duration from HIP events on its stream.
 The CPU baseline times the FP64 brute-force oracle on a fixed sample of the
 same workload's paths on the host cores.
 
-Two further workloads print their own JSON line (not the default run):
+Further workloads print their own JSON line (not the default run):
   --workload rooms5m   5M surfels in three 8x6x3 m rooms joined by doorways,
                        one 1920x1080 camera, 256 spp as 16 progressive passes
                        of 16, max depth 8, RR from 3; then an edit (radiance
@@ -27,6 +27,11 @@ Two further workloads print their own JSON line (not the default run):
                        6x4x3 m room with 12 boxes, 8 cameras at 256x256,
                        8 spp, forward render + adjoint of an L2 loss against
                        the render of a perturbed copy of the scene.
+  --workload bake      light baking: the 1M-surfel room with half its
+                       emitters off, path-traced targets of 8 interior views
+                       at 512x384 (64 spp, depth 5), one bake iteration
+                       (0-bounce render, PQ-L1 loss, radiance gradient, Adam)
+                       per step.
   --workload serve     continuous-batching server against one-at-a-time FIFO
                        on the same Poisson arrivals over a resident 3M-surfel
                        room (request mix scaled down by default: 128x128 or
@@ -36,7 +41,7 @@ Two further workloads print their own JSON line (not the default run):
                        percentiles per load.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
-                       [--workload room1m|rooms5m|sb100k|serve]
+                       [--workload room1m|rooms5m|sb100k|bake|serve]
 """
 import argparse
 import hashlib
@@ -322,6 +327,76 @@ def bench_sb100k(torch, args):
 
 
 
+def bench_bake(torch, args):
+    """Light baking (one JSON line): the 1M-surfel room with half of its
+    emitters switched off, path-traced targets (64 spp, depth 5, RR from 3)
+    for 8 interior views at 512x384, then bake iterations of the radiance
+    into the 0-bounce image starting from the unedited radiance; a step is
+    one iteration (render, PQ-L1 loss, radiance gradient, Adam update)."""
+    import scenegen as sg
+    from paper_2601_23065_amd import EDIT_SET_RADIANCE
+    from paper_2601_23065_amd.api import Adam, Baker, BVH, Params, Scene, apply_edit, path_trace, resolve
+
+    scene, _, cfg = sg.config(3, n_override=args.surfels)
+    cams = sg.interior_cameras(scene, 8, 512, 384, seed=21)
+    gs = Scene(scene.arrays())
+    bvh = BVH(gs)
+    emit = np.nonzero(scene.emissive > 0)[0]
+    off = np.sort(np.random.default_rng(5).choice(emit, emit.size // 2, replace=False)).astype(np.int32)
+    r0 = gs.t["radiance"].clone()
+    apply_edit(gs, EDIT_SET_RADIANCE, torch.from_numpy(off).cuda(), (0.0, 0.0, 0.0))
+    pt = Params(spp=args.spp or cfg["spp"], max_depth=cfg["max_depth"], rr_start=cfg["rr_start"], seed=1)
+    tg = []
+    for ci, cam in enumerate(cams):
+        pt.camera_id = ci
+        tg.append(resolve(path_trace(bvh, gs, cam, pt), pt.spp))
+    targets = torch.stack(tg)
+    gs.t["radiance"].copy_(r0)
+    baker = Baker(bvh, gs, cams, Params(spp=1), targets, Adam(lr=0.05))
+    npix = len(cams) * cams[0].width * cams[0].height
+    _log(f"targets ready: {scene.n} surfels, {len(cams)} views {cams[0].width}x{cams[0].height}, {pt.spp} spp")
+    stream = torch.cuda.current_stream()
+    losses = []
+    for _ in range(args.warmup):
+        losses.append(float(baker.step()))
+    torch.cuda.synchronize()
+    evs = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        loss = baker.step()
+        b.record(stream)
+        evs.append((a, b, loss.clone()))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = float(np.mean([a.elapsed_time(b) for a, b, _ in evs]))
+    losses += [float(l) for _, _, l in evs]
+    rec = {
+        "metric": "light-baking iterations per second",
+        "value": round(1e3 / ms, 3),
+        "unit": "iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"light baking, {scene.n} surfels in an 8x6x3 m room with 40 boxes, half the emitters "
+                               f"off, path-traced targets ({pt.spp} spp, depth {pt.max_depth}) of {len(cams)} views "
+                               f"{cams[0].width}x{cams[0].height}; step = 0-bounce render + PQ-L1 loss + radiance "
+                               f"gradient + Adam update",
+                   "surfels": scene.n, "views": len(cams), "width": cams[0].width, "height": cams[0].height},
+        "detail": {"iteration_ms": round(ms, 3), "camera_rays_per_iteration": 2 * npix,
+                   "Mrays_per_s": round(2 * npix / (ms * 1e-3) / 1e6, 3),
+                   "loss_first": losses[0], "loss_last": losses[-1]},
+    }
+    print(json.dumps(rec))
+
+
 def bench_serve(torch, args):
     """Continuous batching against FIFO on the same arrivals (one JSON line)."""
     import scenegen as sg
@@ -449,7 +524,7 @@ def main():
                     help="serve workload request mix: small (128^2 or 256^2, 4 or 16 spp) or full "
                          "(256^2 .. 1920x1080, 16 .. 256 spp)")
     ap.add_argument("--spp", type=int, default=None, help="override the workload's 64 spp (diagnostics only)")
-    ap.add_argument("--workload", default="room1m", choices=["room1m", "rooms5m", "serve", "sb100k"])
+    ap.add_argument("--workload", default="room1m", choices=["room1m", "rooms5m", "serve", "sb100k", "bake"])
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run an elementwise copy of MIB MiB three times (HBM counter calibration)")
     args = ap.parse_args()
@@ -471,6 +546,9 @@ def main():
         return
     if args.workload == "sb100k":
         bench_sb100k(torch, args)
+        return
+    if args.workload == "bake":
+        bench_bake(torch, args)
         return
 
     import scenegen as sg
