@@ -32,12 +32,15 @@ Functions:
                                             emissive), image gradients
   image_objective(images, targets, ...)     the loss as a function of the
                                             images alone, and its gradient
+  images_vjp(scene, cam, prm, d_images)     parameter gradients of a linear
+                                            function of the images
 
 Pinned by tests/test_oracle_stage0.py: closed forms for one surfel seen
 head-on (Nt = n facing the camera, Dt = t, R = alpha r, E = alpha e); the
 distance normal of a tilted plane equals the plane's normal; central
 differences of the float64 forward on random parameters with an unchanged
-discrete signature; central differences of the image objective.
+discrete signature; central differences of the image objective; the
+chain rule stage0_objective = images_vjp(image gradients).
 """
 import numpy as np
 import torch
@@ -131,6 +134,49 @@ def _rays(cam, prm):
     return torch.from_numpy(O), torch.from_numpy(W)
 
 
+def _images_t(th, segs, images, O, Wd):
+    fr = _frames(th["rot"])
+    idx, mask = _pad([s.hits for s in segs])
+    den0 = (Wd[:, None, :] * fr[2].detach()[idx]).sum(-1)
+    sign = torch.where(mask, -torch.sign(den0), torch.zeros_like(den0))
+    N, D, R, E, _, A = _segment(th, fr, O, Wd, idx, mask, sign)
+    h = torch.as_tensor(np.asarray(images["hit"]))
+    one = torch.ones_like(A)
+    Nl = torch.linalg.norm(torch.where(h[:, None], N, torch.ones_like(N)), dim=1)   # (no 0/0 at misses)
+    Nt = torch.where(h[:, None], N / Nl[:, None], torch.zeros_like(N))
+    Dt = torch.where(h, D / torch.where(h, A, one), torch.zeros_like(D))
+    R = torch.where(h[:, None], R, torch.zeros_like(R))
+    E = torch.where(h, E, torch.zeros_like(E))
+    return Nt, Dt, R, E
+
+
+def _theta(scene):
+    a = scene.arrays() if hasattr(scene, "arrays") else scene
+    return {k: torch.tensor(np.asarray(a[k], dtype=np.float64), requires_grad=(k in STAGE0_PARAMS))
+            for k in ("pos", "rot", "scale", "opacity", "albedo", "radiance", "emissive")}
+
+
+def _grads(th):
+    return {k: (th[k].grad.numpy().copy() if th[k].grad is not None else np.zeros(th[k].shape))
+            for k in STAGE0_PARAMS}
+
+
+def images_vjp(scene, cam, prm, d_images, fwd=None):
+    """Parameter gradients of sum over pixels of d_images . (Nt, Dt, R, E)
+    (d_images: dict of arrays shaped like the images)."""
+    sc = scene if isinstance(scene, Scene64) else Scene64(scene)
+    if fwd is None:
+        fwd = stage0_images(sc, cam, prm)
+    images, segs = fwd
+    th = _theta(scene)
+    O, Wd = _rays(cam, prm)
+    imgs = _images_t(th, segs, images, O, Wd)
+    total = sum((t * torch.as_tensor(np.asarray(d_images[k], dtype=np.float64))).sum()
+                for k, t in zip(("Nt", "Dt", "R", "E"), imgs))
+    total.backward()
+    return _grads(th)
+
+
 def stage0_objective(scene, cam, prm, targets, weights, fwd=None):
     """Loss (Eq. 4) of the camera's images, its gradient with respect to the
     surfel parameters (component-major numpy arrays, STAGE0_PARAMS) and
@@ -139,29 +185,15 @@ def stage0_objective(scene, cam, prm, targets, weights, fwd=None):
     if fwd is None:
         fwd = stage0_images(sc, cam, prm)
     images, segs = fwd
-    a = scene.arrays() if hasattr(scene, "arrays") else scene
-    th = {k: torch.tensor(np.asarray(a[k], dtype=np.float64), requires_grad=(k in STAGE0_PARAMS))
-          for k in ("pos", "rot", "scale", "opacity", "albedo", "radiance", "emissive")}
+    th = _theta(scene)
     O, Wd = _rays(cam, prm)
-    fr = _frames(th["rot"])
-    idx, mask = _pad([s.hits for s in segs])
-    den0 = (Wd[:, None, :] * fr[2].detach()[idx]).sum(-1)
-    sign = torch.where(mask, -torch.sign(den0), torch.zeros_like(den0))
-    N, D, R, E, _, A = _segment(th, fr, O, Wd, idx, mask, sign)
+    Nt, Dt, R, E = _images_t(th, segs, images, O, Wd)
     hit = np.asarray(images["hit"])
-    h = torch.as_tensor(hit)
-    one = torch.ones_like(A)
-    Nl = torch.linalg.norm(torch.where(h[:, None], N, torch.ones_like(N)), dim=1)   # (no 0/0 at misses)
-    Nt = torch.where(h[:, None], N / torch.where(h, Nl, one)[:, None], torch.zeros_like(N))
-    Dt = torch.where(h, D / torch.where(h, A, one), torch.zeros_like(D))
-    R = torch.where(h[:, None], R, torch.zeros_like(R))
-    E = torch.where(h, E, torch.zeros_like(E))
     for t_ in (Nt, Dt, R, E):
         t_.retain_grad()
     loss, _ = _objective(Nt, Dt, R, E, hit, O, Wd, targets, weights, cam)
     loss.backward()
-    grads = {k: (th[k].grad.numpy().copy() if th[k].grad is not None else np.zeros(th[k].shape))
-             for k in STAGE0_PARAMS}
+    grads = _grads(th)
     dimg = {k: (v.grad.numpy().copy() if v.grad is not None else np.zeros(v.shape))
             for k, v in (("Nt", Nt), ("Dt", Dt), ("R", R), ("E", E))}
     return float(loss.detach()), grads, dimg, fwd

@@ -138,3 +138,15 @@ def test_parameter_gradient_central_differences():
             assert abs(fd - g) <= 1e-5 * max(1.0, abs(g)) + 1e-7, (key, i, c, fd, g)
             checked += 1
     assert checked >= 12
+
+
+def test_objective_gradient_is_the_images_vjp_of_its_image_gradient():
+    from oracle.stage0 import images_vjp
+    scene, cam, targets = _room_case()
+    prm = Params(spp=1)
+    weights = (1.0, 0.5, 0.7, 0.3)
+    _, grads, dimg, fwd = stage0_objective(scene, cam, prm, targets, weights)
+    g2 = images_vjp(scene, cam, prm, dimg, fwd=fwd)
+    for k in grads:
+        np.testing.assert_allclose(g2[k], grads[k], rtol=1e-10, atol=1e-14)
+    assert np.abs(grads["pos"]).max() > 0 and np.abs(grads["emissive"]).max() > 0
