@@ -12,6 +12,8 @@
  *     and its gradient (Stage 1 objective)     Sec. 3.3, Eq. 8
  *   - multi-bounce path tracing                Sec. 3.4, Eq. 9
  *   - scene edits (relighting, recolouring)    Sec. 1 and Sec. 5 results
+ *   - Stage-0 objective: Nt, Dt, R, E images,
+ *     their loss terms and adjoint              Sec. 3.2, Eq. 4
  *   - light baking into r (0-bounce render,
  *     its radiance gradient, PQ-L1 loss, Adam)  Sec. 3.4 "Light Baking", Eq. 10
  *
@@ -291,6 +293,53 @@ typedef struct {
   float* emissive;              /* device [n]    */
 } eag_surfel_attrs;
 eag_status eag_apply_edit(const eag_edit* e, const eag_surfel_attrs* a, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Stage 0, the radiant scene (Sec. 3.2, Eq. 4). Per pixel, one camera ray
+ * (sample 0, the pixel centre unless EAG_JITTER) and its segment's images:
+ * Nt = N/|N|, Dt = D/A, R, E (Eq. 3), 8 floats per pixel in that order, all
+ * 0 for a pixel that blends nothing. The objective, with weights
+ * (lc, ln, ld, le):
+ *   lc * mean over pixels and channels of |PQ(R) - PQ(R_gt)|
+ *   ln * mean over hit pixels of (1 - Nt . N_mono)
+ *   ld * mean over valid pixels of (1 - N_d . N_mono)
+ *   le * mean over pixels of |E - M|
+ * with PQ as for light baking. N_d, the distance normal, is the normal of
+ * the points X = O + Dt W: normalize((X(x+1,y) - X(x-1,y)) x (X(x,y+1) -
+ * X(x,y-1))), turned to face the camera; a pixel is valid when it and its
+ * four neighbours are inside the image and hit.
+ * ------------------------------------------------------------------------ */
+/* Workspace of eag_render_stage0 and eag_stage0_backward: packed attributes,
+ * the persistent grid's hit list, double accumulators and per-hit gradient
+ * records (64 B for up to 20 hits per pixel of a batch of up to 8 cameras)
+ * and per-pixel scratch. 0 and the last error if the device cannot be
+ * queried. */
+size_t eag_stage0_workspace_bytes(int64_t n_surfels, const eag_camera* cams, int32_t n_cams);
+/* images: device [n_cams][H][W][8] (written). fwd_state: device, n_cams*H*W*
+ * EAG_FWD_PIXEL_FLOATS floats (written; the camera segments' totals, kept
+ * for eag_stage0_backward). */
+eag_status eag_render_stage0(const eag_bvh* bvh, const eag_surfels* s, const eag_camera* cams, int32_t n_cams,
+                             const eag_trace_params* p, float* images, float* fwd_state, void* ws, size_t ws_bytes,
+                             void* stream);
+/* Workspace of eag_stage0_loss (counters and per-pixel scratch; no scene). */
+size_t eag_stage0_loss_workspace_bytes(const eag_camera* cams, int32_t n_cams);
+/* The objective of images (as eag_render_stage0 writes them) against
+ * rgb_gt [n_cams][H][W][3], normal_mono [n_cams][H][W][3] (unit) and mask
+ * [n_cams][H][W] (device float arrays); weights: host float[4] = (lc, ln,
+ * ld, le). Writes loss (device double) and d_images [n_cams][H][W][8], its
+ * gradient in the images (the hit mask held fixed). */
+eag_status eag_stage0_loss(const float* images, const float* rgb_gt, const float* normal_mono, const float* mask,
+                           const eag_camera* cams, int32_t n_cams, const eag_trace_params* p, const float* weights,
+                           float* d_images, double* loss, void* ws, size_t ws_bytes, void* stream);
+/* Parameter gradients of sum(d_images * images), every discrete decision of
+ * the forward held fixed (hit lists, order, stopping hit, normal signs):
+ * grads->pos, rot, scale, opacity, radiance and grad_emissive [n] get +=
+ * (albedo is untouched; the caller zeroes the arrays for a fresh gradient).
+ * fwd_state: from eag_render_stage0 with the same arguments. */
+eag_status eag_stage0_backward(const eag_bvh* bvh, const eag_surfels* s, const eag_camera* cams, int32_t n_cams,
+                               const eag_trace_params* p, const float* d_images, const float* fwd_state,
+                               const eag_surfel_grads* grads, float* grad_emissive, void* ws, size_t ws_bytes,
+                               void* stream);
 
 /* ------------------------------------------------------------------------
  * Light baking (Sec. 3.4 "Light Baking", Eq. 10): the per-surfel radiance r

@@ -15,6 +15,7 @@ STATUS_NAMES = {0: "EAG_OK", 1: "EAG_NOT_READY", -1: "EAG_ERR_INVALID_ARGUMENT",
 JITTER, ADDITIVE_EMISSION, DETACH_BOUNCE = 1, 2, 4
 EDIT_SET_RADIANCE, EDIT_SCALE_RADIANCE, EDIT_SET_ALBEDO, EDIT_SET_EMISSIVE = 1, 2, 3, 4
 FWD_PIXEL_FLOATS = 28
+STAGE0_FLOATS = 8
 ACCUM_SCALE = 4294967296.0
 
 vp = C.c_void_p
@@ -100,6 +101,14 @@ SIGNATURES = {
                                  C.c_size_t, vp]),
     "eag_accum_resolve": (C.c_int, [vp, C.c_int64, C.c_int32, vp, vp]),
     "eag_apply_edit": (C.c_int, [P(Edit), P(SurfelAttrs), vp]),
+    "eag_stage0_workspace_bytes": (C.c_size_t, [C.c_int64, P(Camera), C.c_int32]),
+    "eag_render_stage0": (C.c_int, [vp, P(Surfels), P(Camera), C.c_int32, P(TraceParams), vp, vp, vp, C.c_size_t,
+                                    vp]),
+    "eag_stage0_loss_workspace_bytes": (C.c_size_t, [P(Camera), C.c_int32]),
+    "eag_stage0_loss": (C.c_int, [vp, vp, vp, vp, P(Camera), C.c_int32, P(TraceParams), P(C.c_float), vp, vp, vp,
+                                  C.c_size_t, vp]),
+    "eag_stage0_backward": (C.c_int, [vp, P(Surfels), P(Camera), C.c_int32, P(TraceParams), vp, vp, P(SurfelGrads),
+                                      vp, vp, C.c_size_t, vp]),
     "eag_bake_workspace_bytes": (C.c_size_t, [C.c_int64, P(Camera), C.c_int32]),
     "eag_render_zero_bounce": (C.c_int, [vp, P(Surfels), P(Camera), C.c_int32, P(TraceParams), vp, vp, C.c_size_t,
                                          vp]),

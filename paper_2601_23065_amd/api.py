@@ -293,6 +293,58 @@ def apply_edit(scene: Scene, kind: int, idx, value, stream=None):
     L.check(L.load().eag_apply_edit(C.byref(e), C.byref(a), _stream(stream)))
 
 
+def render_stage0(bvh: BVH, scene: Scene, cams, params: Params, ws=None, stream=None):
+    """Stage-0 images [n_cams, H, W, 8] (Nt, Dt, R, E) and the forward state
+    the backward needs."""
+    lib = L.load()
+    ca = _cams(cams)
+    H, W = cams[0].height, cams[0].width
+    images = torch.empty((len(cams), H, W, L.STAGE0_FLOATS), dtype=torch.float32, device=scene.device)
+    state = torch.empty(len(cams) * H * W * L.FWD_PIXEL_FLOATS, dtype=torch.float32, device=scene.device)
+    ws = _bytes(lib.eag_stage0_workspace_bytes(scene.n, ca, len(cams)), scene.device) if ws is None else ws
+    wp, wb = _aligned(ws)
+    sc = scene.c()
+    L.check(lib.eag_render_stage0(bvh.h, C.byref(sc), ca, len(cams), C.byref(params.c()), _ptr(images), _ptr(state),
+                                  wp, wb, _stream(stream)))
+    return images, state
+
+
+def stage0_loss(images, rgb_gt, normal_mono, mask, cams, params: Params, weights=(1.0, 1.0, 1.0, 1.0), stream=None):
+    """(loss as a device float64 scalar, d loss / d images) of Eq. 4."""
+    lib = L.load()
+    ca = _cams(cams)
+    ws = _bytes(lib.eag_stage0_loss_workspace_bytes(ca, len(cams)), images.device)
+    wp, wb = _aligned(ws)
+    d = torch.empty_like(images)
+    loss = torch.empty((), dtype=torch.float64, device=images.device)
+    w = (C.c_float * 4)(*[float(x) for x in weights])
+    L.check(lib.eag_stage0_loss(_ptr(images.contiguous()), _ptr(rgb_gt.contiguous()), _ptr(normal_mono.contiguous()),
+                                _ptr(mask.contiguous()), ca, len(cams), C.byref(params.c()), w, _ptr(d), _ptr(loss),
+                                wp, wb, _stream(stream)))
+    return loss, d
+
+
+def stage0_backward(bvh: BVH, scene: Scene, cams, params: Params, d_images, state, grads: dict | None = None, ws=None,
+                    stream=None):
+    """Accumulates d<d_images, images>/d(pos, rot, scale, opacity, radiance,
+    emissive) into `grads` (zeroed tensors are created if None)."""
+    lib = L.load()
+    ca = _cams(cams)
+    if grads is None:
+        grads = {k: torch.zeros_like(scene.t[k]) for k in ("pos", "rot", "scale", "opacity", "radiance", "emissive")}
+    g = L.SurfelGrads()
+    for k in ("pos", "rot", "scale", "opacity", "radiance"):
+        setattr(g, k, _ptr(grads[k]))
+    g.albedo = C.c_void_p(0)
+    ws = _bytes(lib.eag_stage0_workspace_bytes(scene.n, ca, len(cams)), scene.device) if ws is None else ws
+    wp, wb = _aligned(ws)
+    sc = scene.c()
+    L.check(lib.eag_stage0_backward(bvh.h, C.byref(sc), ca, len(cams), C.byref(params.c()),
+                                    _ptr(d_images.contiguous()), _ptr(state), C.byref(g), _ptr(grads["emissive"]), wp,
+                                    wb, _stream(stream)))
+    return grads
+
+
 def bake_workspace(scene: Scene, cams):
     return _bytes(L.load().eag_bake_workspace_bytes(scene.n, _cams(cams), len(cams)), scene.device)
 

@@ -273,6 +273,49 @@ void for_camera_batches(const eag_camera* cams, int32_t n_cams, const eag_trace_
   }
 }
 
+// Stage-0 workspace: packed attributes, work counters, hit list, double
+// gradient accumulators and gradient records, the camera pass's colour
+// output, the loss counters and the distance-normal contributions.
+struct Stage0Ws {
+  Attr* attrs;
+  unsigned long long* work;
+  uint64_t* hitlist;
+  double* gacc;
+  GradRecs grecs;
+  float* rgb;
+  unsigned long long* counts;
+  float* contrib;
+  size_t bytes;
+};
+
+Stage0Ws stage0_ws(void* base, int64_t n, int64_t n_pix, int64_t n_pix_batch, int64_t hl_lanes) {
+  Carver c(base, ~size_t(0));
+  Stage0Ws w;
+  w.attrs = c.take<Attr>(n);
+  w.work = c.take<unsigned long long>(8);
+  w.hitlist = c.take<uint64_t>((size_t)hl_lanes * HL_CAP);
+  w.gacc = c.take<double>(grad_accum_doubles(n));
+  GradRecs& g = w.grecs;
+  std::memset(&g, 0, sizeof(g));
+  const int64_t want = grad_rec_capacity(std::min<int64_t>(n_pix, n_pix_batch));
+  g.n_chunks = std::max<int64_t>(std::max<int64_t>(1, hl_lanes / 64), (want + REC_CHUNK - 1) / REC_CHUNK);
+  const int64_t cap = g.n_chunks * REC_CHUNK;
+  g.chunk_used = c.take<uint32_t>(g.n_chunks);
+  g.rec = c.take<float>((size_t)cap * 16);
+  g.idx = c.take<uint32_t>(cap);
+  g.order = c.take<uint32_t>(cap);
+  g.cnt = c.take<uint32_t>(n);
+  g.cursor = c.take<uint32_t>(n);
+  g.off = c.take<uint32_t>(n);
+  g.scan_bytes = grad_rec_scan_bytes(n);
+  g.scan_tmp = c.take<char>(g.scan_bytes);
+  w.rgb = c.take<float>(n_pix * 3);
+  w.counts = c.take<unsigned long long>(4);
+  w.contrib = c.take<float>(n_pix * 4);
+  w.bytes = c.bytes();
+  return w;
+}
+
 void check_adam(const eag_adam* a) {
   if (!a) fail(EAG_ERR_INVALID_ARGUMENT, "adam parameters are null");
   if (!(a->lr >= 0.0f) || !(a->beta1 >= 0.0f && a->beta1 < 1.0f) || !(a->beta2 >= 0.0f && a->beta2 < 1.0f) ||
@@ -652,6 +695,122 @@ eag_status eag_bake_step(const eag_bvh* b, const eag_surfels* s, const eag_camer
       launch_zero_bounce_adj_r(k.tc, cb, hw, nc, k.sp, w.dL + c0 * hw * 3, w.gacc, b->n, w.work, w.hitlist, st);
     });
     launch_adam(radiance, w.gacc, m, v, b->n * 3, *a, step, st);
+  });
+}
+
+size_t eag_stage0_workspace_bytes(int64_t n, const eag_camera* cams, int32_t n_cams) {
+  if (n < 1 || !cams || n_cams < 1) return 0;
+  try {
+    const int64_t hw = (int64_t)cams[0].width * cams[0].height;
+    return stage0_ws(nullptr, n, hw * n_cams, hw * MAX_CAMS_PER_LAUNCH, runner_lanes()).bytes;
+  } catch (const Error& e) {
+    set_error(e.status, e.msg);
+    return 0;
+  }
+}
+
+eag_status eag_render_stage0(const eag_bvh* b, const eag_surfels* s, const eag_camera* cams, int32_t n_cams,
+                             const eag_trace_params* p, float* images, float* fwd_state, void* ws, size_t ws_bytes,
+                             void* stream) {
+  return guarded([&] {
+    check_bvh(b, s);
+    validate_params(p);
+    check_cams(cams, n_cams);
+    if (!images || !fwd_state) fail(EAG_ERR_INVALID_ARGUMENT, "null argument");
+    const int64_t hw = (int64_t)cams[0].width * cams[0].height;
+    const Stage0Ws w = stage0_ws(ws, b->n, hw * n_cams, hw * MAX_CAMS_PER_LAUNCH, runner_lanes());
+    if (!ws || ws_bytes < w.bytes) fail(EAG_ERR_WORKSPACE_TOO_SMALL, "stage-0 workspace too small");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    float t_max = scene_t_max(b);
+    for (int i = 0; i < n_cams; ++i) t_max = std::fmax(t_max, camera_t_max(b, cams[i]));
+    const TraceSetup ts = trace_setup(b, p, t_max);
+    pack_attrs(s, b, w.attrs, st);
+    const TraceCtx tc = make_ctx(b, w.attrs, p, ts);
+    SbParams sp;
+    sp.spp = 1;
+    sp.flags = p->flags;
+    sp.k0 = (uint32_t)(p->seed & 0xffffffffu);
+    sp.k1 = (uint32_t)(p->seed >> 32);
+    sp.tau_E = p->tau_E;
+    for_camera_batches(cams, n_cams, p, [&](int c0, int nc, const CamBatch& cb) {
+      launch_camera_pass(tc, cb, hw, nc, sp, fwd_state + c0 * hw * EAG_FWD_PIXEL_FLOATS, w.rgb + c0 * hw * 3, w.work,
+                         w.hitlist, st);
+    });
+    launch_stage0_images(fwd_state, hw * n_cams, images, st);
+  });
+}
+
+eag_status eag_stage0_loss(const float* images, const float* rgb_gt, const float* normal_mono, const float* mask,
+                           const eag_camera* cams, int32_t n_cams, const eag_trace_params* p, const float* weights,
+                           float* d_images, double* loss, void* ws, size_t ws_bytes, void* stream) {
+  return guarded([&] {
+    validate_params(p);
+    check_cams(cams, n_cams);
+    if (!images || !rgb_gt || !normal_mono || !mask || !weights || !d_images || !loss)
+      fail(EAG_ERR_INVALID_ARGUMENT, "null argument");
+    const int64_t W = cams[0].width, H = cams[0].height, hw = W * H, np = hw * n_cams;
+    // (only the counters and contributions of the workspace are used: its size depends on no scene)
+    Carver c(ws, ~size_t(0));
+    unsigned long long* counts = c.take<unsigned long long>(4);
+    float* contrib = c.take<float>(np * 4);
+    if (!ws || ws_bytes < c.bytes()) fail(EAG_ERR_WORKSPACE_TOO_SMALL, "stage-0 loss workspace too small");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    SbParams sp;
+    sp.spp = 1;
+    sp.flags = p->flags;
+    sp.k0 = (uint32_t)(p->seed & 0xffffffffu);
+    sp.k1 = (uint32_t)(p->seed >> 32);
+    sp.tau_E = p->tau_E;
+    const double wt[4] = {weights[0], weights[1], weights[2], weights[3]};
+    launch_stage0_count(images, np, W, H, counts, loss, st);
+    for_camera_batches(cams, n_cams, p, [&](int c0, int nc, const CamBatch& cb) {
+      launch_stage0_loss_batch(images, rgb_gt, normal_mono, mask, cb, c0 * hw, nc * hw, W, H, sp, wt, counts,
+                               contrib, d_images, loss, st);
+    });
+    launch_stage0_gather(contrib, np, W, H, d_images, st);
+  });
+}
+
+size_t eag_stage0_loss_workspace_bytes(const eag_camera* cams, int32_t n_cams) {
+  if (!cams || n_cams < 1) return 0;
+  Carver c(nullptr, ~size_t(0));
+  c.take<unsigned long long>(4);
+  c.take<float>((int64_t)cams[0].width * cams[0].height * n_cams * 4);
+  return c.bytes();
+}
+
+eag_status eag_stage0_backward(const eag_bvh* b, const eag_surfels* s, const eag_camera* cams, int32_t n_cams,
+                               const eag_trace_params* p, const float* d_images, const float* fwd_state,
+                               const eag_surfel_grads* grads, float* grad_emissive, void* ws, size_t ws_bytes,
+                               void* stream) {
+  return guarded([&] {
+    check_bvh(b, s);
+    validate_params(p);
+    check_cams(cams, n_cams);
+    if (!d_images || !fwd_state || !grads || !grad_emissive) fail(EAG_ERR_INVALID_ARGUMENT, "null argument");
+    if (!grads->pos || !grads->rot || !grads->scale || !grads->opacity || !grads->radiance)
+      fail(EAG_ERR_INVALID_ARGUMENT, "a gradient pointer is null");
+    const int64_t hw = (int64_t)cams[0].width * cams[0].height;
+    const Stage0Ws w = stage0_ws(ws, b->n, hw * n_cams, hw * MAX_CAMS_PER_LAUNCH, runner_lanes());
+    if (!ws || ws_bytes < w.bytes) fail(EAG_ERR_WORKSPACE_TOO_SMALL, "stage-0 workspace too small");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    float t_max = scene_t_max(b);
+    for (int i = 0; i < n_cams; ++i) t_max = std::fmax(t_max, camera_t_max(b, cams[i]));
+    const TraceSetup ts = trace_setup(b, p, t_max);
+    pack_attrs(s, b, w.attrs, st);
+    const TraceCtx tc = make_ctx(b, w.attrs, p, ts);
+    SbParams sp;
+    sp.spp = 1;
+    sp.flags = p->flags;
+    sp.k0 = (uint32_t)(p->seed & 0xffffffffu);
+    sp.k1 = (uint32_t)(p->seed >> 32);
+    sp.tau_E = p->tau_E;
+    launch_grad_zero(w.gacc, b->n, st);
+    for_camera_batches(cams, n_cams, p, [&](int c0, int nc, const CamBatch& cb) {
+      launch_stage0_backward(tc, *s, cb, hw, nc, sp, fwd_state + c0 * hw * EAG_FWD_PIXEL_FLOATS,
+                             d_images + c0 * hw * STAGE0_FLOATS, w.gacc, w.grecs, w.work, w.hitlist, st);
+    });
+    launch_stage0_finalize(w.gacc, b->n, *grads, grad_emissive, st);
   });
 }
 

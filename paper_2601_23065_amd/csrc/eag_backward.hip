@@ -440,6 +440,116 @@ __global__ void __launch_bounds__(TRACE_BLOCK) __attribute__((amdgpu_waves_per_e
     gr.chunk_used[s_wcur[2 * wv + 1]] = s_wcur[2 * wv];
 }
 
+// Stage-0 adjoint (Sec. 3.2, Eq. 4): one work item per pixel on the
+// runner; the upstream gradient of the pixel's images (Nt, Dt, R, E; 8
+// floats) is reversed through Nt = N/|N| and Dt = D/A into dN, dD, dA, dR,
+// dE and then through the blended hits. Records carry the emissive gradient
+// w dE in row 10 (the albedo rows are otherwise unused here).
+struct Stage0AdjSource {
+  const Record* recs;
+  const Attr* attrs;
+  const CamBatch* cams;
+  int64_t hw;
+  SbParams sp;
+  const float* state;
+  const float* dimg;
+  GradPtrs gp;
+  GradRecs gr;
+  unsigned* wcur;
+  // per item
+  D3 gN, gR;
+  double gD, gA, gE, Tm, G, prefix;
+
+  __device__ __forceinline__ bool start(int64_t g, TraceCtx&, D3& O, D3& W) {
+    const FwdState st = load_state(state + g * EAG_FWD_PIXEL_FLOATS);
+    if (!(st.A > 0.0)) return false;   // a miss: every image is 0
+    const float* d = dimg + g * 8;
+    const D3 gNt = d3(d[0], d[1], d[2]);
+    const double gDt = d[3];
+    gR = d3(d[4], d[5], d[6]);
+    gE = d[7];
+    gN = (1.0 / st.Nlen) * (gNt - dot(st.Nt, gNt) * st.Nt);
+    gD = gDt / st.A;
+    gA = -gDt * st.Dt / st.A;
+    Tm = 1.0 - st.A;
+    G = dot(gN, st.Nlen * st.Nt) + gD * (st.Dt * st.A) + dot(gR, st.R) + gE * (double)st.E;
+    prefix = 0.0;
+    const CamDev& c = cams->c[g / hw];
+    W = pixel_dir(c, (uint32_t)(g % hw), 0, sp.flags, sp.k0, sp.k1);
+    O = d3(c.eye[0], c.eye[1], c.eye[2]);
+    return true;
+  }
+
+  __device__ __forceinline__ void operator()(uint32_t pos, double t, double alpha, double w, double Tb, D3 O, D3 W) {
+    const Record r = load_record(recs, pos);
+    const uint32_t idx = rec_index(r);
+    const Geo ge = surfel_geo(r);
+    const Attr at = attrs[pos];
+    const double sgn = dot(W, ge.n) > 0.0 ? -1.0 : 1.0;   // n' = sgn n faces the origin
+    const double c = sgn * dot(gN, ge.n) + gD * t + gR.x * at.r.x + gR.y * at.r.y + gR.z * at.r.z +
+                     gE * at.rho_e.w;
+    prefix += w * c;
+    const double g_alpha = Tb * c - (G - prefix - gA * Tm) / (1.0 - alpha);
+    D3 dummyO = d3(0.0, 0.0, 0.0), dummyW = d3(0.0, 0.0, 0.0);
+    double v[GRAD_ROWS];
+    double cv[10];
+    chain_values(ge, O, W, t, g_alpha, w * gD, (sgn * w) * gN, false, dummyO, dummyW, cv);
+#pragma unroll
+    for (int k = 0; k < 10; ++k) v[k] = cv[k];
+    v[10] = w * gE;
+    v[11] = v[12] = 0.0;
+    v[13] = w * gR.x;
+    v[14] = w * gR.y;
+    v[15] = w * gR.z;
+    emit_record(gr, gp, wcur, idx, v);
+  }
+
+  __device__ __forceinline__ bool finish(const Seg<true>&, D3&, D3&) { return false; }
+};
+
+__global__ void __launch_bounds__(TRACE_BLOCK) __attribute__((amdgpu_waves_per_eu(2)))
+k_stage0_bwd(TraceCtx tc, const CamBatch cams, int64_t hw, int32_t n_cams, SbParams sp, const float* state,
+             const float* dimg, GradPtrs gp, GradRecs gr, unsigned long long* work, uint64_t* hitlist) {
+  Stage0AdjSource src;
+  src.recs = tc.recs;
+  src.attrs = tc.attrs;
+  src.cams = &cams;
+  src.hw = hw;
+  src.sp = sp;
+  src.state = state;
+  src.dimg = dimg;
+  src.gp = gp;
+  __shared__ unsigned s_wcur[2 * (TRACE_BLOCK / 64)];
+  const int wv = (int)(threadIdx.x >> 6);
+  if ((threadIdx.x & 63) == 0) {
+    s_wcur[2 * wv] = 0u;
+    s_wcur[2 * wv + 1] = REC_NO_CHUNK;
+  }
+  src.gr = gr;
+  src.wcur = s_wcur + 2 * wv;
+  src.gN = src.gR = d3(0.0, 0.0, 0.0);
+  src.gD = src.gA = src.gE = src.Tm = src.G = src.prefix = 0.0;
+  run_segments<Q_ALL, true>(tc, src, work, hw * n_cams, hitlist, nullptr);
+  if ((threadIdx.x & 63) == 0 && s_wcur[2 * wv + 1] < (unsigned)gr.n_chunks)
+    gr.chunk_used[s_wcur[2 * wv + 1]] = s_wcur[2 * wv];
+}
+
+// Stage-0 gradients to the caller's arrays: rows 0-9 (pos, rot, scale,
+// opacity), row 10 (emissive), rows 13-15 (radiance).
+__global__ void k_stage0_finalize(const double* acc, int64_t n, eag_surfel_grads g, float* ge) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n * GRAD_ROWS) return;
+  const int64_t row = i / n, j = i - row * n;
+  float* dst = nullptr;
+  if (row < 3) dst = g.pos + row * n;
+  else if (row < 7) dst = g.rot + (row - 3) * n;
+  else if (row < 9) dst = g.scale + (row - 7) * n;
+  else if (row < 10) dst = g.opacity;
+  else if (row == 10) dst = ge;
+  else if (row >= 13) dst = g.radiance + (row - 13) * n;
+  if (dst) dst[j] += (float)acc[i];
+}
+
 __global__ void k_zero_u32(uint32_t* p, int64_t n) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0u;
@@ -569,6 +679,29 @@ void launch_single_bounce_backward(const TraceCtx& tc, const eag_surfels& s, con
                      reinterpret_cast<const double*>(scratch), dL, gp, gr, work, hitlist);
   reduce_records(gr, gacc, n, st);
   check_hip(hipGetLastError(), "single-bounce backward launch");
+}
+
+void launch_stage0_backward(const TraceCtx& tc, const eag_surfels& s, const CamBatch& cams, int64_t hw,
+                            int32_t n_cams, const SbParams& sp, const float* state, const float* dimg, double* gacc,
+                            const GradRecs& grecs, unsigned long long* work, uint64_t* hitlist, hipStream_t st) {
+  const int64_t n = s.n;
+  GradPtrs gp{gacc, gacc + 3 * n, gacc + 7 * n, gacc + 9 * n, gacc + 10 * n, gacc + 13 * n, n};
+  GradRecs gr = grecs;
+  gr.chunk_next = work + 1;
+  launch_zero_u64(work, 1, st);
+  zero_record_counts(gr, n, st);
+  hipLaunchKernelGGL(k_stage0_bwd, dim3((unsigned)(runner_lanes() / TRACE_BLOCK)), dim3(TRACE_BLOCK), 0, st, tc, cams,
+                     hw, n_cams, sp, state, dimg, gp, gr, work, hitlist);
+  reduce_records(gr, gacc, n, st);
+  check_hip(hipGetLastError(), "stage-0 backward launch");
+}
+
+void launch_stage0_finalize(const double* gacc, int64_t n, const eag_surfel_grads& g, float* grad_emissive,
+                            hipStream_t st) {
+  const int64_t m = n * GRAD_ROWS;
+  hipLaunchKernelGGL(k_stage0_finalize, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, gacc, n, g,
+                     grad_emissive);
+  check_hip(hipGetLastError(), "stage-0 finalize launch");
 }
 
 void launch_grad_zero(double* gacc, int64_t n, hipStream_t st) {

@@ -134,6 +134,29 @@ void launch_single_bounce_backward(const TraceCtx& tc, const eag_surfels& s, con
                                    int32_t n_cams, const SbParams& sp, const float* state, const double* r1,
                                    const float* dL, double* gacc, float* scratch, const GradRecs& grecs,
                                    unsigned long long* work, uint64_t* hitlist, hipStream_t st);
+// The camera segment of every pixel (forward state and emitter-branch colour).
+void launch_camera_pass(const TraceCtx& tc, const CamBatch& cams, int64_t hw, int32_t n_cams, const SbParams& sp,
+                        float* state, float* rgb, unsigned long long* work, uint64_t* hitlist, hipStream_t st);
+
+// Stage 0 (eag_stage0.hip, eag_backward.hip). images: [pixels][8] = Nt, Dt, R, E.
+constexpr int STAGE0_FLOATS = 8;
+void launch_stage0_images(const float* state, int64_t n_pix, float* images, hipStream_t st);
+// counts: 3 device counters (hit pixels, pixels valid for the distance normal, all pixels), set by the count
+// launch, which also zeroes loss; contrib: [pixels][4] floats; a loss batch covers pixels [g0, g0 + nb) of one
+// camera batch; the gather then completes dimg's Dt.
+void launch_stage0_count(const float* images, int64_t n_pix, int64_t W, int64_t H, unsigned long long* counts,
+                         double* loss, hipStream_t st);
+void launch_stage0_loss_batch(const float* images, const float* rgb_gt, const float* n_mono, const float* mask,
+                              const CamBatch& cams, int64_t g0, int64_t nb, int64_t W, int64_t H, const SbParams& sp,
+                              const double w[4], const unsigned long long* counts, float* contrib, float* dimg,
+                              double* loss, hipStream_t st);
+void launch_stage0_gather(const float* contrib, int64_t n_pix, int64_t W, int64_t H, float* dimg, hipStream_t st);
+void launch_stage0_backward(const TraceCtx& tc, const eag_surfels& s, const CamBatch& cams, int64_t hw,
+                            int32_t n_cams, const SbParams& sp, const float* state, const float* dimg, double* gacc,
+                            const GradRecs& grecs, unsigned long long* work, uint64_t* hitlist, hipStream_t st);
+void launch_stage0_finalize(const double* gacc, int64_t n, const eag_surfel_grads& g, float* grad_emissive,
+                            hipStream_t st);
+
 // Light baking (eag_bake.hip).
 void launch_zero_bounce(const TraceCtx& tc, const CamBatch& cams, int64_t hw, int32_t n_cams, const SbParams& sp,
                         float* rgb, unsigned long long* work, uint64_t* hitlist, hipStream_t st);

@@ -163,6 +163,14 @@ __global__ void k_sb_resolve(int64_t n_pix, SbParams sp, const float* state, con
 
 }  // namespace
 
+void launch_camera_pass(const TraceCtx& tc, const CamBatch& cams, int64_t hw, int32_t n_cams, const SbParams& sp,
+                        float* state, float* rgb, unsigned long long* work, uint64_t* hitlist, hipStream_t st) {
+  launch_zero_u64(work, 1, st);
+  hipLaunchKernelGGL(k_sb_camera, dim3((unsigned)(runner_lanes() / TRACE_BLOCK)), dim3(TRACE_BLOCK), 0, st, tc, cams,
+                     hw, n_cams, sp, state, rgb, work, hitlist);
+  check_hip(hipGetLastError(), "camera pass launch");
+}
+
 void launch_single_bounce(const TraceCtx& tc, const CamBatch& cams, int64_t hw, int32_t n_cams,
                           const SbParams& sp, float* state, double* r1, float* rgb, unsigned long long* work,
                           uint64_t* hitlist, hipStream_t st) {
