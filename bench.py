@@ -27,6 +27,10 @@ Further workloads print their own JSON line (not the default run):
                        6x4x3 m room with 12 boxes, 8 cameras at 256x256,
                        8 spp, forward render + adjoint of an L2 loss against
                        the render of a perturbed copy of the scene.
+  --workload stage0    Stage-0 step: the 100k-surfel room, 8 cameras at
+                       256x256; Nt, Dt, R, E render, the Eq. 4 objective
+                       against a perturbed scene's images, and the adjoint
+                       for every parameter.
   --workload bake      light baking: the 1M-surfel room with half its
                        emitters off, path-traced targets of 8 interior views
                        at 512x384 (64 spp, depth 5), one bake iteration
@@ -41,7 +45,7 @@ Further workloads print their own JSON line (not the default run):
                        percentiles per load.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
-                       [--workload room1m|rooms5m|sb100k|bake|serve]
+                       [--workload room1m|rooms5m|sb100k|stage0|bake|serve]
 """
 import argparse
 import hashlib
@@ -327,6 +331,80 @@ def bench_sb100k(torch, args):
 
 
 
+def bench_stage0(torch, args):
+    """Stage-0 step (one JSON line): the 100k-surfel room, 8 cameras at
+    256x256; targets are the Stage-0 images of a perturbed copy of the scene
+    (its R as the colour target, its Nt as the monocular normals, E > tau_E
+    as the emission mask); a step renders Nt, Dt, R, E, evaluates Eq. 4 with
+    unit weights and runs the adjoint for every parameter."""
+    import scenegen as sg
+    from paper_2601_23065_amd.api import BVH, Params, Scene, render_stage0, stage0_backward, stage0_loss
+
+    scene, cams, cfg = sg.config(2, n_override=args.surfels)
+    p = Params(spp=1, seed=0)
+    tgt = sg.perturb(scene)
+    gt = Scene(tgt.arrays())
+    ti, _ = render_stage0(BVH(gt), gt, cams, p)
+    rgb_gt = ti[..., 4:7].contiguous()
+    n_mono = ti[..., 0:3].contiguous()
+    mask = (ti[..., 7:8] > p.tau_E).float().contiguous()
+    gs = Scene(scene.arrays())
+    bvh = BVH(gs)
+    npix = len(cams) * cams[0].width * cams[0].height
+    _log(f"scene ready: {scene.n} surfels, {len(cams)} cameras {cams[0].width}x{cams[0].height}")
+    stream = torch.cuda.current_stream()
+    grads = {k: torch.zeros_like(gs.t[k]) for k in ("pos", "rot", "scale", "opacity", "radiance", "emissive")}
+
+    def step():
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        for v in grads.values():
+            v.zero_()
+        e[0].record(stream)
+        images, state = render_stage0(bvh, gs, cams, p)
+        e[1].record(stream)
+        loss, d = stage0_loss(images, rgb_gt, n_mono, mask, cams, p)
+        e[2].record(stream)
+        stage0_backward(bvh, gs, cams, p, d, state, grads)
+        e[3].record(stream)
+        return e, loss
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    evs = [step() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    fwd = float(np.mean([e[0].elapsed_time(e[1]) for e, _ in evs]))
+    lss = float(np.mean([e[1].elapsed_time(e[2]) for e, _ in evs]))
+    bwd = float(np.mean([e[2].elapsed_time(e[3]) for e, _ in evs]))
+    tot = float(np.mean([e[0].elapsed_time(e[3]) for e, _ in evs]))
+    rec = {
+        "metric": "Stage-0 steps per second",
+        "value": round(1e3 / tot, 3),
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"Stage-0 step, {scene.n} surfels in a 6x4x3 m room with 12 boxes, {len(cams)} cameras "
+                               f"{cams[0].width}x{cams[0].height}; step = Nt, Dt, R, E render + Eq. 4 (PQ-L1, normal, "
+                               f"distance normal, emission; unit weights) + adjoint for every parameter, against a "
+                               f"perturbed scene's images",
+                   "surfels": scene.n, "cameras": len(cams), "width": cams[0].width, "height": cams[0].height},
+        "detail": {"render_ms": round(fwd, 3), "loss_ms": round(lss, 3), "backward_ms": round(bwd, 3),
+                   "camera_rays_per_step": 2 * npix, "Mrays_per_s": round(2 * npix / (tot * 1e-3) / 1e6, 3),
+                   "loss": float(evs[-1][1]),
+                   "grad_norms": {k: float(v.norm()) for k, v in grads.items()}},
+    }
+    print(json.dumps(rec))
+
+
 def bench_bake(torch, args):
     """Light baking (one JSON line): the 1M-surfel room with half of its
     emitters switched off, path-traced targets (64 spp, depth 5, RR from 3)
@@ -524,7 +602,7 @@ def main():
                     help="serve workload request mix: small (128^2 or 256^2, 4 or 16 spp) or full "
                          "(256^2 .. 1920x1080, 16 .. 256 spp)")
     ap.add_argument("--spp", type=int, default=None, help="override the workload's 64 spp (diagnostics only)")
-    ap.add_argument("--workload", default="room1m", choices=["room1m", "rooms5m", "serve", "sb100k", "bake"])
+    ap.add_argument("--workload", default="room1m", choices=["room1m", "rooms5m", "serve", "sb100k", "bake", "stage0"])
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run an elementwise copy of MIB MiB three times (HBM counter calibration)")
     args = ap.parse_args()
@@ -549,6 +627,9 @@ def main():
         return
     if args.workload == "bake":
         bench_bake(torch, args)
+        return
+    if args.workload == "stage0":
+        bench_stage0(torch, args)
         return
 
     import scenegen as sg
