@@ -295,6 +295,40 @@ typedef struct {
 eag_status eag_apply_edit(const eag_edit* e, const eag_surfel_attrs* a, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Geometric edits (Sec. 1 and Sec. 5: moving, importing and deleting
+ * objects). Selection by box, rigid motions, deletion and duplication of
+ * surfels, and the surface-area cost of a tree, by which a caller chooses
+ * between eag_refit_bvh (same surfels, moved) and a new eag_build_bvh
+ * (after duplication the surfel count changes, and only a build will do).
+ * r: host float[4], a rotation quaternion (w, x, y, z), normalised here;
+ * pivot, t: host float[3]. A motion maps p to R(r) (p - pivot) + pivot + t
+ * and q to r (x) q (Hamilton product), computed in double precision.
+ * ------------------------------------------------------------------------ */
+typedef struct {                /* writable surfel arrays, shapes as eag_surfels */
+  int64_t n;
+  float *pos, *rot, *scale, *opacity, *albedo, *radiance, *emissive;
+} eag_surfels_out;
+size_t eag_select_workspace_bytes(int64_t n_surfels);
+/* The surfels whose centre lies in the closed box [lo, hi] (host float[3]
+ * each; compared in float32): idx (device int32 [n]) receives them in
+ * ascending order, count (device int64) their number. */
+eag_status eag_select_box(const eag_surfels* s, const float* lo, const float* hi, int32_t* idx, int64_t* count,
+                          void* ws, size_t ws_bytes, void* stream);
+/* Moves surfels idx[0..count) (device) of s in place (pos and rot only). */
+eag_status eag_move_surfels(const eag_surfels_out* s, const int32_t* idx, int64_t count, const float* r,
+                            const float* pivot, const float* t, void* stream);
+/* Deletes surfels idx[0..count) of s: their opacity becomes 0. */
+eag_status eag_delete_surfels(const eag_surfels_out* s, const int32_t* idx, int64_t count, void* stream);
+/* dst (n = src->n + count) receives src's surfels, then copies of
+ * src's surfels idx[0..count) moved by (r, pivot, t). */
+eag_status eag_duplicate_surfels(const eag_surfels* src, const int32_t* idx, int64_t count, const eag_surfels_out* dst,
+                                 const float* r, const float* pivot, const float* t, void* stream);
+/* cost (device double) = 1 + (sum over every node of the surface areas of
+ * its children's boxes) / (surface area of the root's box); 1 for a
+ * one-surfel scene. ws: eag_build_workspace_bytes(n) bytes suffice. */
+eag_status eag_bvh_sah_cost(const eag_bvh* bvh, double* cost, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
  * Stage 0, the radiant scene (Sec. 3.2, Eq. 4). Per pixel, one camera ray
  * (sample 0, the pixel centre unless EAG_JITTER) and its segment's images:
  * Nt = N/|N|, Dt = D/A, R, E (Eq. 3), 8 floats per pixel in that order, all

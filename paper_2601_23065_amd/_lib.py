@@ -57,6 +57,11 @@ class Adam(C.Structure):
     _fields_ = [("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float)]
 
 
+class SurfelsOut(C.Structure):
+    _fields_ = [("n", C.c_int64), ("pos", vp), ("rot", vp), ("scale", vp), ("opacity", vp), ("albedo", vp),
+                ("radiance", vp), ("emissive", vp)]
+
+
 class SurfelAttrs(C.Structure):
     _fields_ = [("n", C.c_int64), ("albedo", vp), ("radiance", vp), ("emissive", vp)]
 
@@ -101,6 +106,13 @@ SIGNATURES = {
                                  C.c_size_t, vp]),
     "eag_accum_resolve": (C.c_int, [vp, C.c_int64, C.c_int32, vp, vp]),
     "eag_apply_edit": (C.c_int, [P(Edit), P(SurfelAttrs), vp]),
+    "eag_select_workspace_bytes": (C.c_size_t, [C.c_int64]),
+    "eag_select_box": (C.c_int, [P(Surfels), P(C.c_float), P(C.c_float), vp, vp, vp, C.c_size_t, vp]),
+    "eag_move_surfels": (C.c_int, [P(SurfelsOut), vp, C.c_int64, P(C.c_float), P(C.c_float), P(C.c_float), vp]),
+    "eag_delete_surfels": (C.c_int, [P(SurfelsOut), vp, C.c_int64, vp]),
+    "eag_duplicate_surfels": (C.c_int, [P(Surfels), vp, C.c_int64, P(SurfelsOut), P(C.c_float), P(C.c_float),
+                                        P(C.c_float), vp]),
+    "eag_bvh_sah_cost": (C.c_int, [vp, vp, vp, C.c_size_t, vp]),
     "eag_stage0_workspace_bytes": (C.c_size_t, [C.c_int64, P(Camera), C.c_int32]),
     "eag_render_stage0": (C.c_int, [vp, P(Surfels), P(Camera), C.c_int32, P(TraceParams), vp, vp, vp, C.c_size_t,
                                     vp]),

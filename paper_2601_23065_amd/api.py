@@ -130,6 +130,7 @@ class BVH:
         L.check(lib.eag_build_bvh(C.byref(sc), mp, mb, wp, wb, _stream(stream), C.byref(h)))
         self.h = h
         self._ws = ws
+        self.cost_at_build = self.sah_cost(stream)   # for the refit-or-rebuild policy (update_bvh)
 
     def refit(self, scene: Scene | None = None, stream=None):
         lib = L.load()
@@ -137,6 +138,13 @@ class BVH:
         wp, wb = _aligned(self._ws)
         sc = scene.c()
         L.check(lib.eag_refit_bvh(self.h, C.byref(sc), wp, wb, _stream(stream)))
+
+    def sah_cost(self, stream=None):
+        """The tree's surface-area cost (a device float64 scalar)."""
+        cost = torch.empty((), dtype=torch.float64, device=self.scene.device)
+        wp, wb = _aligned(self._ws)
+        L.check(L.load().eag_bvh_sah_cost(self.h, _ptr(cost), wp, wb, _stream(stream)))
+        return cost
 
     def info(self):
         i = L.BvhInfo()
@@ -291,6 +299,75 @@ def apply_edit(scene: Scene, kind: int, idx, value, stream=None):
     e.value[:] = [float(v) for v in vals[:3]]
     a = scene.attrs_c()
     L.check(L.load().eag_apply_edit(C.byref(e), C.byref(a), _stream(stream)))
+
+
+def _f3(v, k=3):
+    return (C.c_float * k)(*[float(x) for x in v])
+
+
+def _out(scene: Scene):
+    o = L.SurfelsOut()
+    o.n = scene.n
+    for k in _GEOM + _ATTR:
+        setattr(o, k, _ptr(scene.t[k]))
+    return o
+
+
+def select_box(scene: Scene, lo, hi, stream=None):
+    """int32 device tensor of the surfels whose centre lies in [lo, hi]
+    (reads the count back: a synchronisation)."""
+    lib = L.load()
+    idx = torch.empty(scene.n, dtype=torch.int32, device=scene.device)
+    count = torch.zeros((), dtype=torch.int64, device=scene.device)
+    ws = _bytes(lib.eag_select_workspace_bytes(scene.n), scene.device)
+    wp, wb = _aligned(ws)
+    sc = scene.c()
+    L.check(lib.eag_select_box(C.byref(sc), _f3(lo), _f3(hi), _ptr(idx), _ptr(count), wp, wb, _stream(stream)))
+    return idx[:int(count)]
+
+
+def move_surfels(scene: Scene, idx, r=(1.0, 0.0, 0.0, 0.0), pivot=(0.0, 0.0, 0.0), t=(0.0, 0.0, 0.0), stream=None):
+    """In place: p -> R(r)(p - pivot) + pivot + t, q -> r (x) q for the surfels idx."""
+    idx = idx.to(torch.int32).contiguous()
+    o = _out(scene)
+    L.check(L.load().eag_move_surfels(C.byref(o), _ptr(idx), idx.numel(), _f3(r, 4), _f3(pivot), _f3(t),
+                                      _stream(stream)))
+
+
+def delete_surfels(scene: Scene, idx, stream=None):
+    """In place: opacity 0 for the surfels idx."""
+    idx = idx.to(torch.int32).contiguous()
+    o = _out(scene)
+    L.check(L.load().eag_delete_surfels(C.byref(o), _ptr(idx), idx.numel(), _stream(stream)))
+
+
+def duplicate_surfels(scene: Scene, idx, r=(1.0, 0.0, 0.0, 0.0), pivot=(0.0, 0.0, 0.0), t=(0.0, 0.0, 0.0),
+                      stream=None):
+    """A new Scene: the surfels of `scene`, then moved copies of the surfels idx."""
+    idx = idx.to(torch.int32).contiguous()
+    m = scene.n + idx.numel()
+    arrays = {k: torch.empty(((_SHAPES[k],) if _SHAPES[k] else ()) + (m,), dtype=torch.float32, device=scene.device)
+              for k in _GEOM + _ATTR}
+    dst = Scene(arrays, device=scene.device)
+    o = _out(dst)
+    sc = scene.c()
+    L.check(L.load().eag_duplicate_surfels(C.byref(sc), _ptr(idx), idx.numel(), C.byref(o), _f3(r, 4), _f3(pivot),
+                                           _f3(t), _stream(stream)))
+    return dst
+
+
+def update_bvh(bvh: BVH, scene: Scene, max_cost_ratio: float = 1.25, stream=None):
+    """Refit-or-rebuild policy after geometric edits: a changed surfel count
+    needs a build; otherwise the tree is refitted, and rebuilt when its
+    surface-area cost has grown past max_cost_ratio times the cost of its
+    last build. Returns (bvh, rebuilt)."""
+    if scene.n != bvh.scene.n:
+        return BVH(scene, stream), True
+    bvh.refit(scene, stream)
+    ratio = float(bvh.sah_cost(stream)) / float(bvh.cost_at_build)
+    if ratio > max_cost_ratio:
+        return BVH(scene, stream), True
+    return bvh, False
 
 
 def render_stage0(bvh: BVH, scene: Scene, cams, params: Params, ws=None, stream=None):

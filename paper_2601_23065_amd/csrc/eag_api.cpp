@@ -814,6 +814,84 @@ eag_status eag_stage0_backward(const eag_bvh* b, const eag_surfels* s, const eag
   });
 }
 
+size_t eag_select_workspace_bytes(int64_t n) {
+  if (n < 1) return 0;
+  try {
+    Carver c(nullptr, ~size_t(0));
+    c.take<uint32_t>(n);
+    c.take<uint32_t>(n);
+    c.take<char>(select_scan_bytes(n));
+    return c.bytes();
+  } catch (const Error& e) {
+    set_error(e.status, e.msg);
+    return 0;
+  }
+}
+
+eag_status eag_select_box(const eag_surfels* s, const float* lo, const float* hi, int32_t* idx, int64_t* count,
+                          void* ws, size_t ws_bytes, void* stream) {
+  return guarded([&] {
+    validate_surfels(s);
+    if (!lo || !hi || !idx || !count) fail(EAG_ERR_INVALID_ARGUMENT, "null argument");
+    if (s->n > INT32_MAX) fail(EAG_ERR_INVALID_ARGUMENT, "selection indices are int32");
+    Carver c(ws, ~size_t(0));
+    uint32_t* flags = c.take<uint32_t>(s->n);
+    uint32_t* scan = c.take<uint32_t>(s->n);
+    const size_t tb = select_scan_bytes(s->n);
+    void* tmp = c.take<char>(tb);
+    if (!ws || ws_bytes < c.bytes()) fail(EAG_ERR_WORKSPACE_TOO_SMALL, "selection workspace too small");
+    launch_select_box(s->pos, s->n, lo, hi, flags, scan, tmp, tb, idx, count, static_cast<hipStream_t>(stream));
+  });
+}
+
+static void check_motion(const float* r, const float* pivot, const float* t) {
+  if (!r || !pivot || !t) fail(EAG_ERR_INVALID_ARGUMENT, "null motion");
+  const double l = (double)r[0] * r[0] + (double)r[1] * r[1] + (double)r[2] * r[2] + (double)r[3] * r[3];
+  if (!(l > 1e-20) || !std::isfinite(l)) fail(EAG_ERR_INVALID_ARGUMENT, "rotation quaternion must be non-zero");
+  for (int k = 0; k < 3; ++k)
+    if (!std::isfinite(pivot[k]) || !std::isfinite(t[k])) fail(EAG_ERR_INVALID_ARGUMENT, "non-finite motion");
+}
+
+eag_status eag_move_surfels(const eag_surfels_out* s, const int32_t* idx, int64_t count, const float* r,
+                            const float* pivot, const float* t, void* stream) {
+  return guarded([&] {
+    if (!s || s->n < 1 || !s->pos || !s->rot) fail(EAG_ERR_INVALID_ARGUMENT, "bad surfel arrays");
+    if (count < 0 || (count > 0 && !idx)) fail(EAG_ERR_INVALID_ARGUMENT, "bad index list");
+    check_motion(r, pivot, t);
+    launch_move(s->pos, s->rot, s->n, idx, count, r, pivot, t, static_cast<hipStream_t>(stream));
+  });
+}
+
+eag_status eag_delete_surfels(const eag_surfels_out* s, const int32_t* idx, int64_t count, void* stream) {
+  return guarded([&] {
+    if (!s || s->n < 1 || !s->opacity) fail(EAG_ERR_INVALID_ARGUMENT, "bad surfel arrays");
+    if (count < 0 || (count > 0 && !idx)) fail(EAG_ERR_INVALID_ARGUMENT, "bad index list");
+    launch_delete(s->opacity, s->n, idx, count, static_cast<hipStream_t>(stream));
+  });
+}
+
+eag_status eag_duplicate_surfels(const eag_surfels* src, const int32_t* idx, int64_t count, const eag_surfels_out* dst,
+                                 const float* r, const float* pivot, const float* t, void* stream) {
+  return guarded([&] {
+    validate_surfels(src);
+    if (!dst || !dst->pos || !dst->rot || !dst->scale || !dst->opacity || !dst->albedo || !dst->radiance ||
+        !dst->emissive)
+      fail(EAG_ERR_INVALID_ARGUMENT, "bad destination arrays");
+    if (count < 0 || (count > 0 && !idx)) fail(EAG_ERR_INVALID_ARGUMENT, "bad index list");
+    if (dst->n != src->n + count) fail(EAG_ERR_INVALID_ARGUMENT, "destination must hold n + count surfels");
+    check_motion(r, pivot, t);
+    launch_append(*src, idx, count, *dst, r, pivot, t, static_cast<hipStream_t>(stream));
+  });
+}
+
+eag_status eag_bvh_sah_cost(const eag_bvh* b, double* cost, void* ws, size_t ws_bytes, void* stream) {
+  return guarded([&] {
+    if (!b || !cost) fail(EAG_ERR_INVALID_ARGUMENT, "null argument");
+    if (!ws || ws_bytes < 2 * sizeof(double)) fail(EAG_ERR_WORKSPACE_TOO_SMALL, "tree-cost workspace too small");
+    launch_sah_cost(b->nodes4, b->n_nodes4, b->root, static_cast<double*>(ws), cost, static_cast<hipStream_t>(stream));
+  });
+}
+
 eag_status eag_accum_resolve(const int64_t* accum, int64_t n_pixels, int32_t total_spp, float* rgb, void* stream) {
   return guarded([&] {
     if (!accum || !rgb || n_pixels < 0 || total_spp < 1) fail(EAG_ERR_INVALID_ARGUMENT, "bad resolve arguments");

@@ -157,6 +157,17 @@ void launch_stage0_backward(const TraceCtx& tc, const eag_surfels& s, const CamB
 void launch_stage0_finalize(const double* gacc, int64_t n, const eag_surfel_grads& g, float* grad_emissive,
                             hipStream_t st);
 
+// Geometric edits (eag_geom.hip).
+size_t select_scan_bytes(int64_t n);
+void launch_select_box(const float* pos, int64_t n, const float lo[3], const float hi[3], uint32_t* flags,
+                       uint32_t* scan, void* tmp, size_t tmp_bytes, int32_t* idx, int64_t* count, hipStream_t st);
+void launch_move(float* pos, float* rot, int64_t n, const int32_t* idx, int64_t count, const float r[4],
+                 const float pivot[3], const float t[3], hipStream_t st);
+void launch_delete(float* opacity, int64_t n, const int32_t* idx, int64_t count, hipStream_t st);
+void launch_append(const eag_surfels& src, const int32_t* idx, int64_t count, const eag_surfels_out& dst,
+                   const float r[4], const float pivot[3], const float t[3], hipStream_t st);
+void launch_sah_cost(const Node4* nodes, int32_t n_nodes, int32_t root, double* acc, double* cost, hipStream_t st);
+
 // Light baking (eag_bake.hip).
 void launch_zero_bounce(const TraceCtx& tc, const CamBatch& cams, int64_t hw, int32_t n_cams, const SbParams& sp,
                         float* rgb, unsigned long long* work, uint64_t* hitlist, hipStream_t st);

@@ -1,0 +1,121 @@
+"""Geometric edits against the oracle (Sec. 1 and Sec. 5: moving, importing
+and deleting objects): box selection bit-exact, rigid motions within one
+float32 rounding of the float64 motion, deletion and duplication traced
+bit-exactly against the brute-force oracle on the edited scene, the tree
+cost against the same definition evaluated on the tree's nodes, and the
+refit-or-rebuild policy."""
+import numpy as np
+import pytest
+import torch
+
+import scenegen as sg
+from oracle.edits import rigid, sah_cost, select_box as o_select
+from tests._util import gpu_scene
+from tests.test_gpu_trace import _compare
+
+pytestmark = pytest.mark.gpu
+
+
+def _room():
+    return sg.room_scene(16000, (3.0, 2.5, 2.5), 3, seed=31, emissive_frac=0.02)
+
+
+def _host(gs, k):
+    return gs.t[k].cpu().numpy()
+
+
+def test_select_and_move():
+    from paper_2601_23065_amd.api import move_surfels, select_box
+    scene = _room()
+    gs = gpu_scene(scene)
+    lo, hi = (0.5, 0.4, 0.0), (2.0, 1.8, 1.2)
+    idx = select_box(gs, lo, hi)
+    ref = o_select(scene.pos, lo, hi)
+    np.testing.assert_array_equal(idx.cpu().numpy(), ref)
+    assert 100 < ref.size < scene.n
+    r = np.array([0.9, 0.1, -0.3, 0.3])
+    pivot, t = (1.2, 1.1, 0.6), (0.3, -0.2, 0.1)
+    move_surfels(gs, idx, r, pivot, t)
+    p_ref, q_ref = rigid(scene.pos, scene.rot, ref, np.asarray(r, dtype=np.float32), np.float32(pivot),
+                         np.float32(t))
+    # one float32 rounding of the float64 motion (the kernel computes in double)
+    np.testing.assert_allclose(_host(gs, "pos"), p_ref, rtol=2 ** -23, atol=1e-7)
+    np.testing.assert_allclose(_host(gs, "rot"), q_ref, rtol=2 ** -23, atol=1e-7)
+    untouched = np.setdiff1d(np.arange(scene.n), ref)
+    np.testing.assert_array_equal(_host(gs, "pos")[:, untouched], scene.pos[:, untouched])
+    np.testing.assert_array_equal(_host(gs, "rot")[:, untouched], scene.rot[:, untouched])
+
+
+def _to_scene(gs, like):
+    s = like.copy()
+    for k in ("pos", "rot", "scale", "opacity", "albedo", "radiance", "emissive"):
+        setattr(s, k, np.ascontiguousarray(_host(gs, k)))
+    return s
+
+
+def test_delete_and_duplicate_trace_like_the_oracle():
+    from paper_2601_23065_amd.api import Params, delete_surfels, duplicate_surfels, select_box
+    scene = _room()
+    gs = gpu_scene(scene)
+    # delete the surfels of one box region, duplicate another region 0.6 m along y
+    delete_surfels(gs, select_box(gs, (0.0, 0.0, 0.0), (1.0, 1.0, 2.5)))
+    assert float(gs.t["opacity"][torch.from_numpy(o_select(scene.pos, (0, 0, 0), (1, 1, 2.5))).cuda()].abs().max()) == 0
+    sel = select_box(gs, (1.5, 1.0, 0.0), (2.5, 2.0, 1.0))
+    dup = duplicate_surfels(gs, sel, (1.0, 0.0, 0.0, 0.0), (0.0, 0.0, 0.0), (0.0, 0.6, 0.0))
+    assert dup.n == scene.n + sel.numel()
+    edited = _to_scene(dup, scene)
+    # originals copied bit for bit, copies moved
+    np.testing.assert_array_equal(edited.albedo[:, :scene.n], _host(gs, "albedo"))
+    np.testing.assert_array_equal(edited.albedo[:, scene.n:], _host(gs, "albedo")[:, sel.cpu().numpy()])
+    np.testing.assert_allclose(edited.pos[:, scene.n:], _host(gs, "pos")[:, sel.cpu().numpy()] +
+                               np.float32([[0.0], [0.6], [0.0]]), rtol=2 ** -23, atol=1e-7)
+    O, D = sg.random_rays(edited, 2500, seed=14)
+    _compare(edited, O, D, Params())
+
+
+def test_tree_cost_and_refit_or_rebuild():
+    from paper_2601_23065_amd.api import BVH, Params, move_surfels, select_box, update_bvh
+    scene = _room()
+    gs = gpu_scene(scene)
+    bvh = BVH(gs)
+    # the cost kernel against the definition evaluated on the tree's own nodes
+    info = bvh.info()
+    off = int(info.nodes4) - bvh.mem.data_ptr()
+    raw = bvh.mem[off:off + info.n_nodes4 * 128].cpu().numpy()
+    nodes = raw.view(np.float32).reshape(-1, 32)
+    refs = raw.view(np.int32).reshape(-1, 32)[:, 24:28]
+    b = nodes[:, :24]
+    lo_hi = [b[:, [0, 1, 2, 3, 4, 5]], b[:, [6, 7, 8, 9, 10, 11]], b[:, [12, 13, 14, 15, 16, 17]],
+             b[:, [18, 19, 20, 21, 22, 23]]]
+    boxes = np.stack(lo_hi, axis=1).reshape(-1, 4, 2, 3)
+    present = refs != 0x7fffffff
+    root = boxes[info.root][present[info.root]]
+    root_box = np.stack([root[:, 0].min(0), root[:, 1].max(0)])
+    ref = sah_cost(boxes[present], root_box)
+    got = float(bvh.sah_cost())
+    print(f"tree cost {got:.6f} oracle {ref:.6f}")
+    assert abs(got - ref) <= 1e-9 * ref and got > 1.0
+    # a small motion keeps the refitted tree
+    sel = select_box(gs, (0.5, 0.5, 0.0), (1.0, 1.0, 1.0))
+    move_surfels(gs, sel, t=(0.01, 0.0, 0.0))
+    bvh2, rebuilt = update_bvh(bvh, gs)
+    assert not rebuilt and bvh2 is bvh
+    # sending a large region across the room degrades it: rebuilt
+    big = select_box(gs, (0.0, 0.0, 0.0), (1.5, 2.5, 2.5))
+    move_surfels(gs, big, t=(1.5, 0.0, 0.0))
+    cost_refit = None
+    bvh3, rebuilt = update_bvh(bvh2, gs)
+    assert rebuilt and bvh3 is not bvh2
+    cost_refit = float(bvh2.sah_cost())
+    print(f"cost at build {float(bvh.cost_at_build):.4f}, refitted after the move {cost_refit:.4f}, "
+          f"rebuilt {float(bvh3.sah_cost()):.4f}")
+    assert float(bvh3.sah_cost()) < cost_refit
+    # both trees trace the edited scene alike
+    from paper_2601_23065_amd.api import trace_rays
+    edited = _to_scene(gs, scene)
+    O, D = sg.random_rays(edited, 2000, seed=15)
+    O, D = torch.from_numpy(O).cuda(), torch.from_numpy(D).cuda()
+    a = trace_rays(bvh2, gs, Params(), O, D, max_hits=256)
+    c = trace_rays(bvh3, gs, Params(), O, D, max_hits=256)
+    for x, y in zip(a, c):
+        assert torch.equal(x, y)
