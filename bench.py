@@ -31,6 +31,10 @@ Further workloads print their own JSON line (not the default run):
                        256x256; Nt, Dt, R, E render, the Eq. 4 objective
                        against a perturbed scene's images, and the adjoint
                        for every parameter.
+  --workload edits     geometric edit on the 1M-surfel room: select a box
+                       region, move it 1.5 m, refit; tree cost and path-
+                       tracing speed (16 spp) through the refitted and a
+                       rebuilt tree.
   --workload bake      light baking: the 1M-surfel room with half its
                        emitters off, path-traced targets of 8 interior views
                        at 512x384 (64 spp, depth 5), one bake iteration
@@ -45,7 +49,7 @@ Further workloads print their own JSON line (not the default run):
                        percentiles per load.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
-                       [--workload room1m|rooms5m|sb100k|stage0|bake|serve]
+                       [--workload room1m|rooms5m|sb100k|stage0|bake|edits|serve]
 """
 import argparse
 import hashlib
@@ -331,6 +335,75 @@ def bench_sb100k(torch, args):
 
 
 
+def bench_edits(torch, args):
+    """Geometric edit on the 1M-surfel room (one JSON line): select the
+    surfels of a box region (a corner of the room with its furniture), move
+    them 1.5 m, then refit the tree and, separately, rebuild it; the tree
+    cost of both and path-tracing speed (1024x768, 16 spp) through both."""
+    import scenegen as sg
+    from paper_2601_23065_amd.api import (BVH, Params, Scene, move_surfels, path_trace, path_trace_workspace,
+                                          select_box)
+
+    scene, cams, cfg = sg.config(3, n_override=args.surfels)
+    cam = cams[0]
+    gs = Scene(scene.arrays())
+    bvh = BVH(gs)
+    ws = path_trace_workspace(gs)
+    stream = torch.cuda.current_stream()
+
+    def timed(f):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        out = f()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return out, a.elapsed_time(b)
+
+    cost0 = float(bvh.cost_at_build)
+    idx, sel_ms = timed(lambda: select_box(gs, (0.0, 0.0, 0.0), (3.0, 3.0, 3.0)))
+    _, move_ms = timed(lambda: move_surfels(gs, idx, t=(1.5, 0.0, 0.0)))
+    _, refit_ms = timed(lambda: bvh.refit(gs))
+    cost_refit = float(bvh.sah_cost())
+    fresh, build_ms = timed(lambda: BVH(gs))
+    cost_fresh = float(fresh.cost_at_build)
+    p = Params(spp=args.spp or 16, max_depth=cfg["max_depth"], rr_start=cfg["rr_start"], seed=0)
+    counters = torch.zeros(6, dtype=torch.int64, device="cuda")
+
+    def pt(tree):
+        counters.zero_()
+        path_trace(tree, gs, cam, p, 0, p.spp, counters=counters, ws=ws)   # warm-up
+        counters.zero_()
+        _, ms = timed(lambda: path_trace(tree, gs, cam, p, 0, p.spp, counters=counters, ws=ws))
+        return float(counters[0]) / (ms * 1e-3) / 1e6, ms
+
+    rate_refit, ms_refit = pt(bvh)
+    rate_fresh, ms_fresh = pt(fresh)
+    rec = {
+        "metric": "path-tracing Mrays/s through the refitted tree after a geometric edit",
+        "value": round(rate_refit, 3),
+        "unit": "Mrays/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 1,
+        "ms_per_step": round(sel_ms + move_ms + refit_ms + ms_refit, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"geometric edit, {scene.n} surfels in an 8x6x3 m room with 40 boxes: the "
+                               f"{int(idx.numel())} surfels in the box [0,3]^3 moved 1.5 m along x; step = select + "
+                               f"move + refit + path tracing {cam.width}x{cam.height} at {p.spp} spp",
+                   "surfels": scene.n, "moved": int(idx.numel()), "spp": p.spp},
+        "detail": {"select_ms": round(sel_ms, 3), "move_ms": round(move_ms, 3), "refit_ms": round(refit_ms, 3),
+                   "rebuild_ms": round(build_ms, 3), "cost_at_build": round(cost0, 4),
+                   "cost_refitted": round(cost_refit, 4), "cost_rebuilt": round(cost_fresh, 4),
+                   "pt_ms_refitted": round(ms_refit, 3), "pt_ms_rebuilt": round(ms_fresh, 3),
+                   "Mrays_per_s_rebuilt": round(rate_fresh, 3)},
+    }
+    print(json.dumps(rec))
+
+
 def bench_stage0(torch, args):
     """Stage-0 step (one JSON line): the 100k-surfel room, 8 cameras at
     256x256; targets are the Stage-0 images of a perturbed copy of the scene
@@ -602,7 +675,7 @@ def main():
                     help="serve workload request mix: small (128^2 or 256^2, 4 or 16 spp) or full "
                          "(256^2 .. 1920x1080, 16 .. 256 spp)")
     ap.add_argument("--spp", type=int, default=None, help="override the workload's 64 spp (diagnostics only)")
-    ap.add_argument("--workload", default="room1m", choices=["room1m", "rooms5m", "serve", "sb100k", "bake", "stage0"])
+    ap.add_argument("--workload", default="room1m", choices=["room1m", "rooms5m", "serve", "sb100k", "bake", "stage0", "edits"])
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run an elementwise copy of MIB MiB three times (HBM counter calibration)")
     args = ap.parse_args()
@@ -630,6 +703,9 @@ def main():
         return
     if args.workload == "stage0":
         bench_stage0(torch, args)
+        return
+    if args.workload == "edits":
+        bench_edits(torch, args)
         return
 
     import scenegen as sg
