@@ -74,3 +74,49 @@ def test_host_validation_without_gpu(lib):
     a = _lib.SurfelAttrs()
     a.n = 10
     assert lib.eag_apply_edit(ctypes.byref(e), ctypes.byref(a), None) == -1
+
+
+def test_host_validation_of_the_baking_stage0_and_edit_calls(lib):
+    from paper_2601_23065_amd import _lib
+    C = ctypes
+    fake = C.c_void_p(0x1000)      # never dereferenced: every call below fails validation first
+    # Adam: the step counts from 1, the rates lie in [0, 1)
+    a = _lib.Adam(0.01, 0.9, 0.999, 1e-15)
+    assert lib.eag_adam_step(fake, fake, fake, fake, 10, C.byref(a), 0, None) == -1
+    assert b"step" in lib.eag_last_error()
+    bad = _lib.Adam(0.01, 1.0, 0.999, 1e-15)
+    assert lib.eag_adam_step(fake, fake, fake, fake, 10, C.byref(bad), 1, None) == -1
+    assert lib.eag_adam_step(None, fake, fake, fake, 10, C.byref(a), 1, None) == -1
+    # loss: null buffers, negative counts
+    assert lib.eag_bake_loss(None, fake, 10, fake, fake, None) == -1
+    assert lib.eag_bake_loss(fake, fake, -1, fake, fake, None) == -1
+    # motions: a zero quaternion, a non-finite pivot
+    g = _lib.SurfelsOut()
+    g.n = 10
+    g.pos = g.rot = fake
+    zero = (C.c_float * 4)(0, 0, 0, 0)
+    one = (C.c_float * 4)(1, 0, 0, 0)
+    z3 = (C.c_float * 3)(0, 0, 0)
+    nan3 = (C.c_float * 3)(float("nan"), 0, 0)
+    assert lib.eag_move_surfels(C.byref(g), fake, 1, zero, z3, z3, None) == -1
+    assert b"quaternion" in lib.eag_last_error()
+    assert lib.eag_move_surfels(C.byref(g), fake, 1, one, nan3, z3, None) == -1
+    assert lib.eag_move_surfels(C.byref(g), None, 3, one, z3, z3, None) == -1
+    assert lib.eag_delete_surfels(C.byref(g), fake, -2, None) == -1
+    # duplication: the destination must hold n + count surfels
+    s = _lib.Surfels()
+    s.n = 10
+    for k in ("pos", "rot", "scale", "opacity", "albedo", "radiance", "emissive"):
+        setattr(s, k, fake)
+    d = _lib.SurfelsOut()
+    d.n = 12
+    for k in ("pos", "rot", "scale", "opacity", "albedo", "radiance", "emissive"):
+        setattr(d, k, fake)
+    assert lib.eag_duplicate_surfels(C.byref(s), fake, 3, C.byref(d), one, z3, z3, None) == -1
+    assert b"n + count" in lib.eag_last_error()
+    # stage-0 loss workspace is a pure size query
+    cam = _lib.Camera()
+    cam.width, cam.height = 16, 8
+    assert lib.eag_stage0_loss_workspace_bytes(C.byref(cam), 2) >= 16 * 8 * 2 * 16
+    assert lib.eag_stage0_loss_workspace_bytes(None, 1) == 0
+    assert lib.eag_bake_workspace_bytes(0, C.byref(cam), 1) == 0

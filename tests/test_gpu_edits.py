@@ -119,3 +119,20 @@ def test_tree_cost_and_refit_or_rebuild():
     c = trace_rays(bvh3, gs, Params(), O, D, max_hits=256)
     for x, y in zip(a, c):
         assert torch.equal(x, y)
+
+
+def test_empty_selection_and_no_op_edits():
+    from paper_2601_23065_amd.api import delete_surfels, duplicate_surfels, move_surfels, select_box
+    scene = _room()
+    gs = gpu_scene(scene)
+    idx = select_box(gs, (10.0, 10.0, 10.0), (11.0, 11.0, 11.0))
+    assert idx.numel() == 0
+    move_surfels(gs, idx, (0.0, 1.0, 0.0, 0.0), (1.0, 1.0, 1.0), (5.0, 5.0, 5.0))
+    delete_surfels(gs, idx)
+    dup = duplicate_surfels(gs, idx, (0.0, 0.0, 1.0, 0.0), (0.0, 0.0, 0.0), (1.0, 0.0, 0.0))
+    assert dup.n == scene.n
+    for k in ("pos", "rot", "scale", "opacity", "albedo", "radiance", "emissive"):
+        np.testing.assert_array_equal(_host(gs, k), getattr(scene, k))
+        np.testing.assert_array_equal(_host(dup, k), getattr(scene, k))
+    # the whole scene selected
+    assert select_box(gs, (-1.0, -1.0, -1.0), (4.0, 4.0, 4.0)).numel() == scene.n

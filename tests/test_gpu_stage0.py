@@ -138,3 +138,25 @@ def test_stage0_render_loss_adjoint_chain():
         err = rel_err(got[k].cpu().numpy().astype(np.float64), ref[k])
         print(f"{k}: err {err.max():.2e}")
         assert err.max() <= 1e-3
+
+
+def test_stage0_on_an_empty_view():
+    """A camera looking out of the room's bounds from outside: every pixel
+    misses, the images are zero, only the colour and emission terms remain
+    (against constant targets, in closed form), and the adjoint is zero."""
+    from oracle.bake import pq
+    from paper_2601_23065_amd.api import BVH, Params, render_stage0, stage0_backward, stage0_loss
+    scene, _ = _room()
+    cam = sg.Camera((10.0, 10.0, 10.0), (20.0, 20.0, 20.0), (0.0, 0.0, 1.0), 30.0, 12, 9)
+    p = Params(spp=1)
+    gs = gpu_scene(scene)
+    bvh = BVH(gs)
+    images, state = render_stage0(bvh, gs, [cam], p)
+    assert float(images.abs().max()) == 0.0
+    M = cam.width * cam.height
+    tg = {"rgb": np.full((M, 3), 0.5), "normal": np.tile([0.0, 0.0, 1.0], (M, 1)), "mask": np.full(M, 1.0)}
+    loss, d = stage0_loss(images, *_gpu_targets(tg, [cam]), [cam], p, (1.0, 1.0, 1.0, 0.5))
+    ref = abs(float(pq(0.0) - pq(0.5))) + 0.5 * 1.0
+    assert abs(float(loss) - ref) <= 1e-12 * ref
+    g = stage0_backward(bvh, gs, [cam], p, d, state)
+    assert all(float(v.abs().max()) == 0.0 for v in g.values())
