@@ -23,6 +23,8 @@ Modules:
              every discrete decision fixed, differentiated by autograd
   bake     - light baking: the PQ-encoded L1 loss between 0-bounce and
              path-traced images, its radiance gradient, and the Adam step
+  nee      - emitter sampling on emissive surfels combined with cosine
+             sampling by multiple importance sampling, for path tracing
   stage0   - the Stage-0 objective (Eq. 4) on the camera segment's Nt, Dt,
              R, E images, with the distance normal, by autograd
 
