@@ -40,6 +40,11 @@ Further workloads print their own JSON line (not the default run):
                        at 512x384 (64 spp, depth 5), one bake iteration
                        (0-bounce render, PQ-L1 loss, radiance gradient, Adam)
                        per step.
+  --workload mis       emitter sampling combined with cosine sampling by
+                       multiple importance sampling on the default room:
+                       time per 64-spp image and image error of it and of
+                       the plain path tracer against a reference of 8x the
+                       spp (512), at equal spp and at equal time.
   --workload serve     continuous-batching server against one-at-a-time FIFO
                        on the same Poisson arrivals over a resident 3M-surfel
                        room (request mix scaled down by default: 128x128 or
@@ -49,7 +54,7 @@ Further workloads print their own JSON line (not the default run):
                        percentiles per load.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
-                       [--workload room1m|rooms5m|sb100k|stage0|bake|edits|serve]
+                       [--workload room1m|rooms5m|sb100k|stage0|bake|edits|mis|serve]
 """
 import argparse
 import hashlib
@@ -548,6 +553,99 @@ def bench_bake(torch, args):
     print(json.dumps(rec))
 
 
+def bench_mis(torch, args):
+    """Emitter sampling with multiple importance sampling against the plain
+    path tracer on the benchmark room: time per 64-spp image and image error
+    against a converged reference at equal spp and at equal time (one JSON
+    line)."""
+    import scenegen as sg
+    from paper_2601_23065_amd.api import BVH, Emitters, Params, Scene, path_trace, path_trace_mis, path_trace_workspace
+
+    scene, cams, cfg = sg.config(3, n_override=args.surfels)
+    cam = cams[0]
+    spp = args.spp or cfg["spp"]
+    params = Params(spp=spp, max_depth=cfg["max_depth"], rr_start=cfg["rr_start"], seed=0, camera_id=0)
+    gs = Scene(scene.arrays())
+    ws = path_trace_workspace(gs)
+    stream = torch.cuda.current_stream()
+    bvh = BVH(gs)
+    te0 = time.perf_counter()
+    em = Emitters(gs, params)
+    table_ms = (time.perf_counter() - te0) * 1e3
+    n_em, _ = em.info()
+    _log(f"scene ready: {scene.n} surfels, {n_em} emitters, {cam.width}x{cam.height}, {spp} spp")
+    counters = torch.zeros(6, dtype=torch.int64, device="cuda")
+
+    def image(fn, s0, count):
+        acc = fn(s0, count)
+        return acc.double() / (2.0 ** 32 * count)
+
+    def mis(s0, count, c=None):
+        return path_trace_mis(bvh, gs, em, cam, params, s0, count, counters=c, ws=ws)
+
+    def plain(s0, count, c=None):
+        return path_trace(bvh, gs, cam, params, s0, count, counters=c, ws=ws)
+
+    # converged reference: 8x the spp (512 at 64 spp) of the emitter-sampled estimator on sample indices
+    # disjoint from the tests
+    ref = None
+    per = max(1, spp // 2)
+    for k in range(16):
+        a = image(mis, 100000 + per * k, per)
+        ref = a if ref is None else ref + a
+        torch.cuda.synchronize()
+        _log(f"reference pass {k + 1}/16")
+    ref /= 16
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn(0, spp)
+        torch.cuda.synchronize()
+        counters.zero_()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        ev0.record(stream)
+        for _ in range(args.steps):
+            acc = fn(0, spp, counters)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / args.steps * 1e3
+        c = counters.cpu().numpy().astype(np.float64) / args.steps
+        img = acc.double() / (2.0 ** 32 * spp)
+        rmse = float(torch.sqrt(((img - ref) ** 2).mean()))
+        return wall, ev0.elapsed_time(ev1) / args.steps, c, rmse
+
+    ms_mis, kms_mis, c_mis, rmse_mis = timed(mis)
+    _log("emitter-sampled timing done")
+    ms_plain, kms_plain, c_plain, rmse_plain = timed(plain)
+    _log("plain timing done")
+    segments, paths, rounds, tests, blended, visits = c_mis
+    value = segments / (ms_mis * 1e-3) / 1e6
+    rec = {
+        "metric": "Mrays/s multi-bounce PT over 2D Gaussians with emitter sampling + MIS",
+        "value": round(value, 3), "unit": "Mrays/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_mis, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"path tracing with emitter sampling and MIS (power heuristic), {scene.n} surfels "
+                               f"({n_em} emitters) in an 8x6x3 m room with 40 boxes, {cam.width}x{cam.height}, "
+                               f"{spp} spp, max depth {params.max_depth}, RR from {params.rr_start}; step = the "
+                               f"path-tracing launch over all samples",
+                   "surfels": scene.n, "emitters": n_em, "width": cam.width, "height": cam.height, "spp": spp},
+        "roofline": _roofline(blended, segments, kms_mis),
+        "detail": {"segments_per_step": segments, "paths_per_step": paths,
+                   "light_pdf_note": "segments include one light segment per reflecting vertex whose sample "
+                                     "lies above the surface",
+                   "mis_image_ms": round(ms_mis, 3), "plain_image_ms": round(ms_plain, 3),
+                   "plain_segments_per_step": c_plain[0], "plain_mrays_s": round(c_plain[0] / (ms_plain * 1e-3) / 1e6, 3),
+                   "rmse_mis": rmse_mis, "rmse_plain": rmse_plain,
+                   "mse_ratio_equal_spp": round((rmse_plain / rmse_mis) ** 2, 3),
+                   "mse_ratio_equal_time": round((rmse_plain / rmse_mis) ** 2 * ms_plain / ms_mis, 3),
+                   "emitter_table_ms": round(table_ms, 3),
+                   "reference": f"{16 * per} spp of the emitter-sampled estimator on disjoint sample indices"},
+    }
+    print(json.dumps(rec))
+
+
 def bench_serve(torch, args):
     """Continuous batching against FIFO on the same arrivals (one JSON line)."""
     import scenegen as sg
@@ -675,7 +773,8 @@ def main():
                     help="serve workload request mix: small (128^2 or 256^2, 4 or 16 spp) or full "
                          "(256^2 .. 1920x1080, 16 .. 256 spp)")
     ap.add_argument("--spp", type=int, default=None, help="override the workload's 64 spp (diagnostics only)")
-    ap.add_argument("--workload", default="room1m", choices=["room1m", "rooms5m", "serve", "sb100k", "bake", "stage0", "edits"])
+    ap.add_argument("--workload", default="room1m",
+                    choices=["room1m", "rooms5m", "serve", "sb100k", "bake", "stage0", "edits", "mis"])
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run an elementwise copy of MIB MiB three times (HBM counter calibration)")
     args = ap.parse_args()
@@ -706,6 +805,9 @@ def main():
         return
     if args.workload == "edits":
         bench_edits(torch, args)
+        return
+    if args.workload == "mis":
+        bench_mis(torch, args)
         return
 
     import scenegen as sg

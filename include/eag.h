@@ -16,6 +16,10 @@
  *     their loss terms and adjoint              Sec. 3.2, Eq. 4
  *   - light baking into r (0-bounce render,
  *     its radiance gradient, PQ-L1 loss, Adam)  Sec. 3.4 "Light Baking", Eq. 10
+ *   - path tracing with emitter sampling and
+ *     multiple importance sampling             Sec. 5 and Appendix D (proposed there)
+ *   - geometric edits: selection, rigid
+ *     motion, deletion, duplication, tree cost  Sec. 1 and Sec. 5
  *
  * Conventions for every call:
  *   - Plain C. No exceptions cross the boundary; every entry point returns
@@ -269,6 +273,55 @@ eag_status eag_path_trace(const eag_bvh* bvh, const eag_surfels* s, const eag_ca
 /* rgb[i] = accum[i] / (EAG_ACCUM_SCALE * total_spp) for i < 3*n_pixels (device arrays). */
 eag_status eag_accum_resolve(const int64_t* accum, int64_t n_pixels, int32_t total_spp, float* rgb,
                              void* stream);
+
+/* ------------------------------------------------------------------------
+ * Path tracing with emitter sampling: next-event estimation on emissive
+ * surfels combined with the cosine sampling above by multiple importance
+ * sampling, the remedy for small emitters that Sec. 5 and Appendix D
+ * (Discussion) propose without fixing an estimator. The estimator built
+ * here has the expectation of eag_path_trace:
+ *   emitters    surfels with e > tau_E and opacity > 0;
+ *   selection   emitter j with probability w_j / W, w_j = opacity s_u s_v
+ *               (mean of r + e), by inversion of the inclusive prefix sums
+ *               on u0 (the first j whose sum exceeds u0 W);
+ *   point       uniform on the j's k_sigma ellipse from u1, u2 (radius
+ *               k sqrt(u1), angle 2 pi u2);
+ *   light pdf   p_l(X, w) = sum over the emitter ellipses the ray X + d w
+ *               crosses at d > 0 of rho_j d^2 / |w . n_j|, rho_j =
+ *               opacity (mean of r + e) / (pi k^2 W);
+ *   weights     power heuristic against p_b = max(0, w . Nt) / pi: at each
+ *               reflecting vertex the light segment from X towards the point
+ *               adds beta R p_b p_l / (p_b^2 + p_l^2) if it passes the emitter
+ *               test (beta after the vertex's P, before Russian roulette); a
+ *               cosine-sampled segment k >= 1 that passes it adds
+ *               beta R p_b^2 / (p_b^2 + p_l^2); the camera segment adds beta R.
+ * The light sample after segment k uses Philox counter (pixel, sample,
+ * 2^31 + k, camera_id); everything else is eag_path_trace's.
+ * ------------------------------------------------------------------------ */
+typedef struct eag_emitters eag_emitters;   /* opaque host handle; storage in caller memory */
+/* Device memory of a table for a scene of n_surfels (sized for every
+ * surfel being an emitter), and the workspace of its build. */
+size_t eag_emitters_bytes(int64_t n_surfels);
+size_t eag_emitters_workspace_bytes(int64_t n_surfels);
+/* Builds the table of s for p->tau_E (>= 0) and p->k_sigma (<= 3, the
+ * extent of the tree's boxes): compacted emitter attributes, prefix sums,
+ * densities and a tree over the emitters. mem (256-B aligned, >=
+ * eag_emitters_bytes) is referenced by the handle until
+ * eag_emitters_destroy; ws only during the call. Synchronises `stream`.
+ * The table is a copy: rebuild it after editing the scene. */
+eag_status eag_build_emitters(const eag_surfels* s, const eag_trace_params* p, void* mem, size_t mem_bytes,
+                              void* ws, size_t ws_bytes, void* stream, eag_emitters** out);
+/* count: emitters in the table; total_weight: W (0 when there are none). */
+eag_status eag_emitters_get_info(const eag_emitters* em, int64_t* count, double* total_weight);
+void eag_emitters_destroy(eag_emitters* em);
+/* As eag_path_trace (same accumulator, workspace and sample ranges) with the
+ * estimator above. em must come from the same scene (same surfel count) and
+ * the same tau_E and k_sigma as p; EAG_ADDITIVE_EMISSION is rejected. A table
+ * without emitters gives eag_path_trace's values. */
+eag_status eag_path_trace_mis(const eag_bvh* bvh, const eag_surfels* s, const eag_emitters* em,
+                              const eag_camera* cam, const eag_trace_params* p, uint32_t sample_begin,
+                              uint32_t sample_count, int64_t* accum, uint64_t* counters, void* ws,
+                              size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
  * Scene edits (the paper's relighting and material edits, Sec. 1, Sec. 5).

@@ -277,6 +277,61 @@ def path_trace(bvh: BVH, scene: Scene, cam, params: Params, sample_begin: int = 
     return accum
 
 
+class Emitters:
+    """Emitter table of a Scene for emitter sampling with multiple importance
+    sampling (built for params.tau_E and params.k_sigma); owns its device
+    memory. Rebuild it after editing the scene."""
+
+    def __init__(self, scene: Scene, params: Params, stream=None):
+        lib = L.load()
+        self.scene = scene
+        n = scene.n
+        self.mem = _bytes(lib.eag_emitters_bytes(n), scene.device)
+        ws = _bytes(lib.eag_emitters_workspace_bytes(n), scene.device)
+        h = C.c_void_p()
+        mp, mb = _aligned(self.mem)
+        wp, wb = _aligned(ws)
+        sc = scene.c()
+        p = params.c()
+        L.check(lib.eag_build_emitters(C.byref(sc), C.byref(p), mp, mb, wp, wb, _stream(stream), C.byref(h)))
+        self.h = h
+
+    def info(self):
+        """(number of emitters, total selection weight W)."""
+        n = C.c_int64()
+        w = C.c_double()
+        L.check(L.load().eag_emitters_get_info(self.h, C.byref(n), C.byref(w)))
+        return int(n.value), float(w.value)
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                L.load().eag_emitters_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+
+def path_trace_mis(bvh: BVH, scene: Scene, emitters: Emitters, cam, params: Params, sample_begin: int = 0,
+                   sample_count: int | None = None, accum=None, counters=None, stream=None, ws=None):
+    """path_trace with emitter sampling combined by multiple importance
+    sampling; same accumulator, sample ranges and workspace."""
+    lib = L.load()
+    dev = scene.device
+    sample_count = params.spp if sample_count is None else sample_count
+    if accum is None:
+        accum = torch.zeros((cam.height, cam.width, 3), dtype=torch.int64, device=dev)
+    if ws is None:
+        ws = _bytes(lib.eag_path_trace_workspace_bytes(scene.n), dev)
+    wp, wb = _aligned(ws)
+    c = camera_struct(cam)
+    p = params.c()
+    sc = scene.c()
+    L.check(lib.eag_path_trace_mis(bvh.h, C.byref(sc), emitters.h, C.byref(c), C.byref(p), sample_begin,
+                                   sample_count, _ptr(accum), _ptr(counters), wp, wb, _stream(stream)))
+    return accum
+
+
 def path_trace_workspace(scene: Scene):
     return _bytes(L.load().eag_path_trace_workspace_bytes(scene.n), scene.device)
 

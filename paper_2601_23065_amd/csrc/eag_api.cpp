@@ -602,6 +602,106 @@ eag_status eag_path_trace(const eag_bvh* b, const eag_surfels* s, const eag_came
   });
 }
 
+size_t eag_emitters_bytes(int64_t n) {
+  if (n < 1) return 0;
+  try {
+    return emitters_mem_bytes(n);
+  } catch (const Error& e) {
+    set_error(e.status, e.msg);
+    return 0;
+  }
+}
+
+size_t eag_emitters_workspace_bytes(int64_t n) {
+  if (n < 1) return 0;
+  try {
+    return emitters_ws_bytes(n);
+  } catch (const Error& e) {
+    set_error(e.status, e.msg);
+    return 0;
+  }
+}
+
+eag_status eag_build_emitters(const eag_surfels* s, const eag_trace_params* p, void* mem, size_t mem_bytes, void* ws,
+                              size_t ws_bytes, void* stream, eag_emitters** out) {
+  return guarded([&] {
+    validate_surfels(s);
+    validate_params(p);
+    if (!out) fail(EAG_ERR_INVALID_ARGUMENT, "out is null");
+    if (!(p->tau_E >= 0.0f)) fail(EAG_ERR_INVALID_ARGUMENT, "emitter sampling needs tau_E >= 0");
+    if (!(p->k_sigma <= 3.0f)) fail(EAG_ERR_INVALID_ARGUMENT, "emitter sampling needs k_sigma <= 3");
+    if (!mem || !ws) fail(EAG_ERR_INVALID_ARGUMENT, "mem and ws must be device buffers");
+    if ((reinterpret_cast<uintptr_t>(mem) & 255) || (reinterpret_cast<uintptr_t>(ws) & 255))
+      fail(EAG_ERR_INVALID_ARGUMENT, "mem and ws must be 256-byte aligned");
+    eag_emitters* e = new eag_emitters();
+    try {
+      build_emitters(s, p->tau_E, p->k_sigma, mem, mem_bytes, ws, ws_bytes, static_cast<hipStream_t>(stream), e);
+    } catch (...) {
+      delete e;
+      throw;
+    }
+    *out = e;
+  });
+}
+
+eag_status eag_emitters_get_info(const eag_emitters* em, int64_t* count, double* total_weight) {
+  return guarded([&] {
+    if (!em) fail(EAG_ERR_INVALID_ARGUMENT, "emitter table is null");
+    if (count) *count = em->dev.n;
+    if (total_weight) *total_weight = em->dev.W;
+  });
+}
+
+void eag_emitters_destroy(eag_emitters* em) {
+  if (!em) return;
+  delete em->bvh;
+  delete em;
+}
+
+eag_status eag_path_trace_mis(const eag_bvh* b, const eag_surfels* s, const eag_emitters* em, const eag_camera* cam,
+                              const eag_trace_params* p, uint32_t sample_begin, uint32_t sample_count,
+                              int64_t* accum, uint64_t* counters, void* ws, size_t ws_bytes, void* stream) {
+  return guarded([&] {
+    check_bvh(b, s);
+    validate_params(p);
+    if (!cam || !accum || !em) fail(EAG_ERR_INVALID_ARGUMENT, "null argument");
+    if (em->n_src != s->n) fail(EAG_ERR_INVALID_ARGUMENT, "emitter table built for another surfel count");
+    if (em->tau_E != p->tau_E || em->k_sigma != p->k_sigma)
+      fail(EAG_ERR_INVALID_ARGUMENT, "emitter table built for another tau_E or k_sigma");
+    if (p->flags & EAG_ADDITIVE_EMISSION)
+      fail(EAG_ERR_INVALID_ARGUMENT, "emitter sampling is defined for the emitter-terminated path tracer");
+    if ((uint64_t)sample_begin + sample_count > 0xffffffffull) fail(EAG_ERR_INVALID_ARGUMENT, "sample range overflow");
+    const RenderWs w = render_ws(ws, b->n, 0, 0, false, runner_lanes());
+    if (!ws || ws_bytes < w.bytes) fail(EAG_ERR_WORKSPACE_TOO_SMALL, "path-trace workspace too small");
+    const CamDev cd = make_cam(*cam, p->camera_id);
+    const TraceSetup ts = trace_setup(b, p, std::fmax(scene_t_max(b), camera_t_max(b, *cam)));
+    if (sample_count == 0) return;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    pack_attrs(s, b, w.attrs, st);
+    const TraceCtx tc = make_ctx(b, w.attrs, p, ts);
+    PtLaunch L;
+    std::memset(&L, 0, sizeof(L));
+    PtSlot& S = L.s[0];
+    S.cam = cd;
+    S.accum = accum;
+    S.attrs = w.attrs;
+    S.work_begin = 0;
+    S.tiles_x = (cam->width + 7) / 8;
+    S.tile_pixels = (int64_t)S.tiles_x * ((cam->height + 7) / 8) * 64;
+    S.global_end = (int64_t)sample_count * S.tile_pixels;
+    S.sample_begin = sample_begin;
+    S.max_depth = p->max_depth;
+    S.rr_start = p->rr_start;
+    S.flags = p->flags;
+    S.k0 = (uint32_t)(p->seed & 0xffffffffu);
+    S.k1 = (uint32_t)(p->seed >> 32);
+    S.tau_E = p->tau_E;
+    L.n_slots = 1;
+    L.n_work = S.global_end;
+    launch_path_trace_mis(tc, L, em->dev, w.work, reinterpret_cast<unsigned long long*>(counters), w.hitlist, st);
+  });
+}
+
 size_t eag_bake_workspace_bytes(int64_t n, const eag_camera* cams, int32_t n_cams) {
   if (n < 1 || !cams || n_cams < 1) return 0;
   try {

@@ -1,0 +1,471 @@
+// Emitter importance sampling on emissive surfels, combined with the cosine
+// sampling of the path tracer (Sec. 3.4, Eq. 9) by multiple importance
+// sampling; the paper proposes it for small emitters (Sec. 5, limitations;
+// Appendix D) and leaves the estimator open. The one built here:
+//
+//   emitters   surfels with e > tau_E and opacity > 0 (a segment passes the
+//              emitter test only if it blends one of them: its E is a sum of
+//              the hits' e with weights adding up to at most one);
+//   selection  emitter j with probability w_j / W, w_j = sigma s_u s_v
+//              (mean(r) + e), by inversion of the inclusive prefix sums;
+//   point      uniform on the j's k_sigma ellipse (area density rho_j =
+//              sigma (mean(r) + e) / (pi k^2 W));
+//   light pdf  p_l(X, w) = sum over the emitter ellipses the ray X + d w
+//              crosses at d > 0 of rho_j d^2 / |w . n_j|, evaluated by a
+//              traversal of a 4-wide tree over the emitters alone;
+//   weights    power heuristic against the cosine pdf p_b = max(0, w . Nt)
+//              / pi: a light segment that passes the emitter test adds
+//              beta R p_b p_l / (p_b^2 + p_l^2) (beta after the vertex's P,
+//              before Russian roulette), a cosine-sampled segment k >= 1 that
+//              passes it adds beta R p_b^2 / (p_b^2 + p_l^2); the camera
+//              segment is not weighted.
+// The light sample at the vertex after segment k draws Philox counter
+// (pixel, sample, 2^31 + k, id): u0 selects, u1 and u2 place the point.
+// Light segments are ordinary segments of the persistent runner: after a
+// reflecting vertex the lane traces the light segment first, then the
+// cosine-sampled continuation (if Russian roulette keeps the path).
+//
+// Table build: per-surfel flags, an exclusive scan and a compaction give the
+// emitters in ascending surfel order; their attributes are gathered into
+// arrays of their own, the weights' inclusive scan gives the prefix sums, and
+// the ordinary builder makes the tree over the compacted emitters.
+#include "eag_device.h"
+#include "eag_internal.h"
+#include "eag_render.h"
+#include "eag_runner.h"
+
+#include <cmath>
+#include <cstring>
+
+#include <rocprim/device/device_scan.hpp>
+
+namespace eag {
+
+namespace {
+
+constexpr uint32_t NEE_SEGMENT = 0x80000000u;
+constexpr double INV_PI = 0.3183098861837907;
+
+__device__ __forceinline__ void add_fixed(int64_t* acc, float v) {
+  if (v != 0.0f) {
+    const long long q = (long long)rint((double)v * EAG_ACCUM_SCALE);
+    atomicAdd(reinterpret_cast<unsigned long long*>(acc), (unsigned long long)q);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Light sampling and its density
+// ---------------------------------------------------------------------------
+// The term of one emitter ellipse in p_l (0 if the ray does not cross it at
+// d > 0), in double precision, with the tracer's acceptance test.
+__device__ __forceinline__ double pdf_term(const EmitterDev& E, uint32_t pos, D3 X, D3 W) {
+  const Record rec = load_record(E.recs, pos);
+  const Geo g = surfel_geo(rec);
+  const double den = dot(W, g.n);
+  if (!(fabs(den) > 1e-12)) return 0.0;
+  const D3 d = g.p - X;
+  const double t = dot(d, g.n) / den;
+  if (!(t > 0.0)) return 0.0;
+  const D3 y = t * W - d;
+  const double u = dot(y, g.tu) / g.su, v = dot(y, g.tv) / g.sv;
+  if (!(u * u + v * v <= E.k2)) return 0.0;
+  return E.rho[rec_index(rec)] * t * t / fabs(den);
+}
+
+// p_l(X, W): every emitter box the ray meets at t >= 0 is visited.
+__device__ double light_pdf(const EmitterDev& E, D3 X, D3 W) {
+  double sum = 0.0;
+  if (E.n == 0) return sum;
+  const V3 Of = v3((float)X.x, (float)X.y, (float)X.z);
+  const float wx = (float)W.x, wy = (float)W.y, wz = (float)W.z;
+  const V3 iW = v3(1.0f / (fabsf(wx) > 1e-30f ? wx : copysignf(1e-30f, wx)),
+                   1.0f / (fabsf(wy) > 1e-30f ? wy : copysignf(1e-30f, wy)),
+                   1.0f / (fabsf(wz) > 1e-30f ? wz : copysignf(1e-30f, wz)));
+  const float inf = __builtin_inff();
+  int stack[STACK_SIZE];
+  int sp = 0;
+  stack[sp++] = E.root;
+  while (sp > 0) {
+    const int ref = stack[--sp];
+    if (ref < 0) {
+      sum += pdf_term(E, (uint32_t)~ref, X, W);
+      continue;
+    }
+    const Node4* nd = E.nodes + ref;
+    const int4 cr = nd->ref;
+    const float4 b0 = nd->b[0], b1 = nd->b[1], b2 = nd->b[2], b3 = nd->b[3], b4 = nd->b[4], b5 = nd->b[5];
+    const float e0 = slab(b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, Of, iW, 0.0f, inf);
+    const float e1 = slab(b1.z, b1.w, b2.x, b2.y, b2.z, b2.w, Of, iW, 0.0f, inf);
+    const float e2 = slab(b3.x, b3.y, b3.z, b3.w, b4.x, b4.y, Of, iW, 0.0f, inf);
+    const float e3 = slab(b4.z, b4.w, b5.x, b5.y, b5.z, b5.w, Of, iW, 0.0f, inf);
+    // at most 3 * depth + 1 entries are ever held; the build checks that bound
+    if (cr.x != NODE4_EMPTY && e0 < inf && sp < STACK_SIZE) stack[sp++] = cr.x;
+    if (cr.y != NODE4_EMPTY && e1 < inf && sp < STACK_SIZE) stack[sp++] = cr.y;
+    if (cr.z != NODE4_EMPTY && e2 < inf && sp < STACK_SIZE) stack[sp++] = cr.z;
+    if (cr.w != NODE4_EMPTY && e3 < inf && sp < STACK_SIZE) stack[sp++] = cr.w;
+  }
+  return sum;
+}
+
+// The emitter selected by u0: the first j whose inclusive prefix sum exceeds
+// u0 W (u0 < 1, so j < n).
+__device__ __forceinline__ int64_t select_emitter(const EmitterDev& E, double u0) {
+  const double x = u0 * E.W;
+  int64_t lo = 0, hi = E.n - 1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (E.cdf[mid] > x) hi = mid;
+    else lo = mid + 1;
+  }
+  return lo;
+}
+
+// Uniform point on emitter j's k_sigma ellipse.
+__device__ __forceinline__ D3 emitter_point(const EmitterDev& E, int64_t j, double u1, double u2) {
+  const int64_t n = E.n;
+  Record rec;
+  rec.p_sigma = make_float4(E.pos[j], E.pos[n + j], E.pos[2 * n + j], 1.0f);
+  rec.q = make_float4(E.rot[j], E.rot[n + j], E.rot[2 * n + j], E.rot[3 * n + j]);
+  rec.s_idx = make_float4(E.scale[j], E.scale[n + j], 0.0f, 0.0f);
+  const Geo g = surfel_geo(rec);
+  const double r = E.k * sqrt(u1);
+  double s, c;
+  sincos(TWO_PI * u2, &s, &c);
+  const double a = r * c * g.su, b = r * s * g.sv;
+  return d3(g.p.x + a * g.tu.x + b * g.tv.x, g.p.y + a * g.tu.y + b * g.tv.y, g.p.z + a * g.tu.z + b * g.tv.z);
+}
+
+// ---------------------------------------------------------------------------
+// One lane's path with light segments
+// ---------------------------------------------------------------------------
+struct MisPathSource {
+  const PtLaunch* L;
+  const EmitterDev* E;
+  uint32_t pix, sample;
+  int depth;
+  V3 beta;
+  V3 lf;            // the pending light segment's factor beta * p_b p_l / (p_b^2 + p_l^2)
+  D3 X, Wb;         // the vertex and the cosine-sampled continuation
+  double pb;        // cosine pdf of the direction of the segment in flight (or the continuation)
+  bool light;       // the segment in flight is a light segment
+  bool cont;        // the continuation survived Russian roulette
+
+  __device__ __forceinline__ bool start(int64_t wid, TraceCtx& tcl, D3& O, D3& W) {
+    const PtSlot& S = L->s[0];
+    const int64_t s_rel = wid / S.tile_pixels;
+    const int64_t tp = wid - s_rel * S.tile_pixels;
+    const int64_t tile = tp >> 6;
+    const int within = (int)(tp & 63);
+    const int x = (int)(tile % S.tiles_x) * 8 + (within & 7);
+    const int y = (int)(tile / S.tiles_x) * 8 + (within >> 3);
+    if (x >= S.cam.width || y >= S.cam.height) return false;
+    pix = (uint32_t)(y * S.cam.width + x);
+    sample = S.sample_begin + (uint32_t)s_rel;
+    beta = v3(1.f, 1.f, 1.f);
+    depth = 0;
+    light = false;
+    cont = false;
+    pb = 0.0;
+    tcl.attrs = S.attrs;
+    O = d3(S.cam.eye[0], S.cam.eye[1], S.cam.eye[2]);
+    W = pixel_dir(S.cam, pix, sample, S.flags, S.k0, S.k1);
+    return true;
+  }
+
+  __device__ __forceinline__ void operator()(uint32_t, double, double, double, double, D3, D3) const {}
+
+  __device__ __forceinline__ bool finish(const Seg<false>& s, D3& O, D3& W) {
+    const PtSlot& S = L->s[0];
+    int64_t* acc = S.accum + (int64_t)pix * 3;
+    const double A = 1.0 - s.T;
+    const bool hit = s.nhits > 0 && A > 0.0;
+    if (light) {
+      light = false;
+      if (hit && s.E > S.tau_E) {
+        add_fixed(acc + 0, lf.x * s.R0);
+        add_fixed(acc + 1, lf.y * s.R1);
+        add_fixed(acc + 2, lf.z * s.R2);
+      }
+      if (!cont) return false;
+      O = X;
+      W = Wb;
+      return true;
+    }
+    if (!hit) return false;
+    if (s.E > S.tau_E) {
+      double wgt = 1.0;
+      if (depth >= 1 && E->n > 0) {
+        const double pl = light_pdf(*E, s.O, s.W);
+        const double den = pb * pb + pl * pl;
+        wgt = den > 0.0 ? pb * pb / den : 1.0;
+      }
+      add_fixed(acc + 0, (float)(beta.x * s.R0 * wgt));
+      add_fixed(acc + 1, (float)(beta.y * s.R1 * wgt));
+      add_fixed(acc + 2, (float)(beta.z * s.R2 * wgt));
+      return false;
+    }
+    if (depth >= S.max_depth) return false;
+    beta = v3(beta.x * s.P0, beta.y * s.P1, beta.z * s.P2);
+    const D3 Nt = (1.0 / sqrt(dot(s.N, s.N))) * s.N;
+    const double Dt = s.D / A;
+    X = d3(s.O.x + Dt * s.W.x, s.O.y + Dt * s.W.y, s.O.z + Dt * s.W.z);
+    // light sample, before Russian roulette
+    D3 Wl = d3(0.0, 0.0, 1.0);
+    if (E->n > 0) {
+      const uint4 wl = philox(make_uint4(pix, sample, NEE_SEGMENT + (uint32_t)depth, S.cam.id), S.k0, S.k1);
+      const int64_t j = select_emitter(*E, to_unit(wl.x));
+      const D3 y = emitter_point(*E, j, to_unit(wl.y), to_unit(wl.z));
+      const D3 dl = y - X;
+      Wl = (1.0 / sqrt(dot(dl, dl))) * dl;
+      const double cl = dot(Wl, Nt);
+      if (cl > 0.0) {
+        const double pbl = cl * INV_PI;
+        const double pl = light_pdf(*E, X, Wl);
+        const double den = pbl * pbl + pl * pl;
+        const float f = den > 0.0 ? (float)(pbl * pl / den) : 0.0f;
+        lf = v3(beta.x * f, beta.y * f, beta.z * f);
+        light = true;
+      }
+    }
+    // cosine sample and Russian roulette, as the plain path tracer
+    const uint4 w = philox(make_uint4(pix, sample, (uint32_t)depth, S.cam.id), S.k0, S.k1);
+    ++depth;
+    cont = true;
+    if (S.rr_start > 0 && depth >= S.rr_start) {
+      const float q = fminf(0.95f, fmaxf(fmaxf(beta.x, beta.y), beta.z));
+      if (!(to_unit(w.z) < q)) {
+        cont = false;
+      } else {
+        const float iq = 1.0f / q;
+        beta = v3(beta.x * iq, beta.y * iq, beta.z * iq);
+      }
+    }
+    Wb = cosine_dir(Nt, to_unit(w.x), to_unit(w.y));
+    pb = fmax(dot(Wb, Nt), 0.0) * INV_PI;
+    O = X;
+    if (light) {
+      W = Wl;
+      return true;
+    }
+    W = Wb;
+    return cont;
+  }
+};
+
+__global__ void __launch_bounds__(TRACE_BLOCK) __attribute__((amdgpu_waves_per_eu(2))) k_path_trace_mis(TraceCtx tc, PtLaunch L, EmitterDev E,
+                                                                unsigned long long* work_counter,
+                                                                unsigned long long* counters, uint64_t* hitlist) {
+  MisPathSource src;
+  src.L = &L;
+  src.E = &E;
+  src.pix = src.sample = 0;
+  src.depth = 0;
+  src.beta = src.lf = v3(0.f, 0.f, 0.f);
+  src.X = src.Wb = d3(0.0, 0.0, 0.0);
+  src.pb = 0.0;
+  src.light = src.cont = false;
+  run_segments<Q_ALL, false>(tc, src, work_counter, L.n_work, hitlist, counters);
+}
+
+// ---------------------------------------------------------------------------
+// Table build
+// ---------------------------------------------------------------------------
+__global__ void k_emit_flags(eag_surfels s, float tau_E, uint32_t* flags) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < s.n) flags[i] = (s.emissive[i] > tau_E && s.opacity[i] > 0.0f) ? 1u : 0u;
+}
+
+__global__ void k_emit_count(const uint32_t* flags, const uint32_t* scan, int64_t n, unsigned long long* count) {
+  *count = (unsigned long long)scan[n - 1] + flags[n - 1];
+}
+
+// Emitter off[i] takes surfel i's attributes (arrays of ne) and its weight.
+__global__ void k_emit_gather(eag_surfels s, const uint32_t* flags, const uint32_t* off, eag_surfels_out c,
+                              double* w) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= s.n || !flags[i]) return;
+  const int64_t n = s.n, ne = c.n, j = off[i];
+  for (int k = 0; k < 3; ++k) {
+    c.pos[k * ne + j] = s.pos[k * n + i];
+    c.albedo[k * ne + j] = s.albedo[k * n + i];
+    c.radiance[k * ne + j] = s.radiance[k * n + i];
+  }
+  for (int k = 0; k < 4; ++k) c.rot[k * ne + j] = s.rot[k * n + i];
+  for (int k = 0; k < 2; ++k) c.scale[k * ne + j] = s.scale[k * n + i];
+  c.opacity[j] = s.opacity[i];
+  c.emissive[j] = s.emissive[i];
+  const double rbar = ((double)s.radiance[i] + (double)s.radiance[n + i] + (double)s.radiance[2 * n + i]) / 3.0;
+  w[j] = (double)s.opacity[i] * (double)s.scale[i] * (double)s.scale[n + i] * (rbar + (double)s.emissive[i]);
+}
+
+__global__ void k_emit_rho(eag_surfels_out c, const double* cdf, double k, double* rho) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t ne = c.n;
+  if (j >= ne) return;
+  const double rbar = ((double)c.radiance[j] + (double)c.radiance[ne + j] + (double)c.radiance[2 * ne + j]) / 3.0;
+  rho[j] = (double)c.opacity[j] * (rbar + (double)c.emissive[j]) / (M_PI * k * k * cdf[ne - 1]);
+}
+
+unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+struct EmitWs {
+  uint32_t* flags;
+  uint32_t* off;
+  unsigned long long* count;
+  void* scan_tmp;
+  size_t scan_bytes;
+  void* build;
+  size_t build_bytes;
+  size_t bytes;
+};
+
+size_t emit_scan_bytes(int64_t n) {
+  size_t a = 0, b = 0;
+  check_hip(rocprim::exclusive_scan(nullptr, a, (const uint32_t*)nullptr, (uint32_t*)nullptr, 0u, (size_t)n,
+                                    rocprim::plus<uint32_t>(), (hipStream_t)0),
+            "emitter scan size");
+  check_hip(rocprim::inclusive_scan(nullptr, b, (const double*)nullptr, (double*)nullptr, (size_t)n,
+                                    rocprim::plus<double>(), (hipStream_t)0),
+            "emitter prefix size");
+  return std::max(a, b);
+}
+
+EmitWs emit_ws(void* base, int64_t n) {
+  Carver c(base, ~size_t(0));
+  EmitWs w;
+  w.flags = c.take<uint32_t>(n);
+  w.off = c.take<uint32_t>(n);
+  w.count = c.take<unsigned long long>(1);
+  w.scan_bytes = emit_scan_bytes(n);
+  w.scan_tmp = c.take<char>(w.scan_bytes);
+  w.build_bytes = build_ws_bytes(n);
+  w.build = c.take<char>(w.build_bytes);
+  w.bytes = c.bytes();
+  return w;
+}
+
+struct EmitMem {
+  float *pos, *rot, *scale, *opacity, *albedo, *radiance, *emissive;
+  double *w, *cdf, *rho;
+  void* bvh;
+  size_t bvh_bytes;
+  size_t bytes;
+};
+
+// Regions sized for n emitters; a table of ne <= n emitters uses strides ne.
+EmitMem emit_mem(void* base, int64_t n) {
+  Carver c(base, ~size_t(0));
+  EmitMem m;
+  m.pos = c.take<float>(3 * n);
+  m.rot = c.take<float>(4 * n);
+  m.scale = c.take<float>(2 * n);
+  m.opacity = c.take<float>(n);
+  m.albedo = c.take<float>(3 * n);
+  m.radiance = c.take<float>(3 * n);
+  m.emissive = c.take<float>(n);
+  m.w = c.take<double>(n);
+  m.cdf = c.take<double>(n);
+  m.rho = c.take<double>(n);
+  m.bvh_bytes = bvh_layout(nullptr, n).bytes;
+  m.bvh = c.take<char>(m.bvh_bytes);
+  m.bytes = c.bytes();
+  return m;
+}
+
+}  // namespace
+
+size_t emitters_mem_bytes(int64_t n) { return emit_mem(nullptr, n).bytes; }
+size_t emitters_ws_bytes(int64_t n) { return emit_ws(nullptr, n).bytes; }
+
+void build_emitters(const eag_surfels* s, float tau_E, float k_sigma, void* mem, size_t mem_bytes, void* ws,
+                    size_t ws_bytes, hipStream_t st, eag_emitters* out) {
+  const int64_t n = s->n;
+  const EmitMem m = emit_mem(mem, n);
+  const EmitWs w = emit_ws(ws, n);
+  if (mem_bytes < m.bytes) fail(EAG_ERR_WORKSPACE_TOO_SMALL, "emitter table memory too small");
+  if (ws_bytes < w.bytes) fail(EAG_ERR_WORKSPACE_TOO_SMALL, "emitter table workspace too small");
+  hipLaunchKernelGGL(k_emit_flags, dim3(blocks_for(n)), dim3(256), 0, st, *s, tau_E, w.flags);
+  size_t sb = w.scan_bytes;
+  check_hip(rocprim::exclusive_scan(w.scan_tmp, sb, w.flags, w.off, 0u, (size_t)n, rocprim::plus<uint32_t>(), st),
+            "emitter scan");
+  hipLaunchKernelGGL(k_emit_count, dim3(1), dim3(1), 0, st, w.flags, w.off, n, w.count);
+  unsigned long long ne = 0;
+  check_hip(hipMemcpyAsync(&ne, w.count, sizeof(ne), hipMemcpyDeviceToHost, st), "emitter count");
+  check_hip(hipStreamSynchronize(st), "emitter count sync");
+
+  std::memset(out, 0, sizeof(*out));
+  out->n_src = n;
+  out->tau_E = tau_E;
+  out->k_sigma = k_sigma;
+  EmitterDev& E = out->dev;
+  E.n = (int64_t)ne;
+  E.k = (double)k_sigma;
+  E.k2 = E.k * E.k;
+  if (ne == 0) return;
+
+  eag_surfels_out c;
+  c.n = (int64_t)ne;
+  c.pos = m.pos; c.rot = m.rot; c.scale = m.scale; c.opacity = m.opacity;
+  c.albedo = m.albedo; c.radiance = m.radiance; c.emissive = m.emissive;
+  hipLaunchKernelGGL(k_emit_gather, dim3(blocks_for(n)), dim3(256), 0, st, *s, w.flags, w.off, c, m.w);
+  sb = w.scan_bytes;
+  check_hip(rocprim::inclusive_scan(w.scan_tmp, sb, m.w, m.cdf, (size_t)ne, rocprim::plus<double>(), st),
+            "emitter prefix sums");
+  hipLaunchKernelGGL(k_emit_rho, dim3(blocks_for((int64_t)ne)), dim3(256), 0, st, c, m.cdf, E.k, m.rho);
+  check_hip(hipGetLastError(), "emitter table kernels");
+  check_hip(hipMemcpyAsync(&E.W, m.cdf + ne - 1, sizeof(double), hipMemcpyDeviceToHost, st), "emitter total");
+
+  // the tree over the compacted emitters
+  eag_surfels cs;
+  cs.n = (int64_t)ne;
+  cs.pos = m.pos; cs.rot = m.rot; cs.scale = m.scale; cs.opacity = m.opacity;
+  cs.albedo = m.albedo; cs.radiance = m.radiance; cs.emissive = m.emissive;
+  const BvhLayout l = bvh_layout(m.bvh, (int64_t)ne);
+  eag_bvh* b = new eag_bvh();
+  std::memset(b, 0, sizeof(*b));
+  b->n = (int64_t)ne;
+  int bits = 1;
+  while ((int64_t(1) << bits) < (int64_t)ne) ++bits;
+  b->idx_bits = bits;
+  b->mem = m.bvh;
+  b->mem_bytes = m.bvh_bytes;
+  b->hdr = l.hdr;
+  b->nodes = l.nodes;
+  b->nodes4 = l.nodes4;
+  b->recs = l.recs;
+  b->perm = l.perm;
+  b->leaf_parent = l.leaf_parent;
+  b->node_parent = l.node_parent;
+  try {
+    build_bvh(&cs, b, w.build, w.build_bytes, st);
+  } catch (...) {
+    delete b;
+    throw;
+  }
+  if (3 * b->depth4 + 1 > STACK_SIZE) {
+    delete b;
+    fail(EAG_ERR_INTERNAL, "emitter tree deeper than the density traversal's stack");
+  }
+  check_hip(hipStreamSynchronize(st), "emitter table sync");
+  out->bvh = b;
+  E.nodes = b->nodes4;
+  E.recs = b->recs;
+  E.root = b->root;
+  E.rho = m.rho;
+  E.cdf = m.cdf;
+  E.pos = m.pos;
+  E.rot = m.rot;
+  E.scale = m.scale;
+}
+
+void launch_path_trace_mis(const TraceCtx& tc, const PtLaunch& L, const EmitterDev& E,
+                           unsigned long long* work_counter, unsigned long long* counters, uint64_t* hitlist,
+                           hipStream_t st) {
+  const unsigned blocks = (unsigned)(runner_lanes() / TRACE_BLOCK);
+  launch_zero_u64(work_counter, 1, st);
+  hipLaunchKernelGGL(k_path_trace_mis, dim3(blocks), dim3(TRACE_BLOCK), 0, st, tc, L, E, work_counter, counters,
+                     hitlist);
+  check_hip(hipGetLastError(), "path_trace_mis launch");
+}
+
+}  // namespace eag

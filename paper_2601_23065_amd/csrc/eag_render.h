@@ -182,10 +182,44 @@ void launch_adam(float* r, const double* g, float* m, float* v, int64_t count, c
 void launch_adam(float* r, const float* g, float* m, float* v, int64_t count, const eag_adam& a, int32_t step,
                  hipStream_t st);
 
+// Emitter sampling with multiple importance sampling (eag_nee.hip).
+struct EmitterDev {
+  const Node4* nodes;        // 4-wide tree over the emitters
+  const Record* recs;        // their geometry records; the record index is the table position
+  const double* rho;         // [n] area density of the point sampler on each emitter's ellipse
+  const double* cdf;         // [n] inclusive prefix sums of the selection weights
+  const float* pos;          // [3][n] compacted centres
+  const float* rot;          // [4][n] compacted quaternions
+  const float* scale;        // [2][n] compacted scales
+  int64_t n;                 // emitters (0: no light samples, every weight 1)
+  double W;                  // total selection weight
+  double k, k2;              // k_sigma and its square
+  int32_t root;
+  int32_t pad;
+};
+size_t emitters_mem_bytes(int64_t n);
+size_t emitters_ws_bytes(int64_t n);
+void launch_path_trace_mis(const TraceCtx& tc, const PtLaunch& L, const EmitterDev& E,
+                           unsigned long long* work_counter, unsigned long long* counters, uint64_t* hitlist,
+                           hipStream_t st);
+
 size_t grad_accum_doubles(int64_t n);
 void launch_grad_zero(double* gacc, int64_t n, hipStream_t st);
 void launch_grad_finalize(const double* gacc, int64_t n, const eag_surfel_grads& g, hipStream_t st);
 void launch_apply_edit(const eag_edit& e, const eag_surfel_attrs& a, hipStream_t st);
 void launch_accum_resolve(const int64_t* accum, int64_t n_values, double scale, float* rgb, hipStream_t st);
 
+}  // namespace eag
+
+// Host handle of an emitter table (device storage in caller memory).
+struct eag_emitters {
+  eag::EmitterDev dev;
+  eag_bvh* bvh;              // tree over the emitters (null when there are none)
+  int64_t n_src;             // surfels of the scene it was built from
+  float tau_E, k_sigma;      // the parameters it was built for
+};
+
+namespace eag {
+void build_emitters(const eag_surfels* s, float tau_E, float k_sigma, void* mem, size_t mem_bytes, void* ws,
+                    size_t ws_bytes, hipStream_t st, eag_emitters* out);
 }  // namespace eag

@@ -120,3 +120,31 @@ def test_host_validation_of_the_baking_stage0_and_edit_calls(lib):
     assert lib.eag_stage0_loss_workspace_bytes(C.byref(cam), 2) >= 16 * 8 * 2 * 16
     assert lib.eag_stage0_loss_workspace_bytes(None, 1) == 0
     assert lib.eag_bake_workspace_bytes(0, C.byref(cam), 1) == 0
+
+
+def test_host_validation_of_the_emitter_sampling_calls(lib):
+    from paper_2601_23065_amd import _lib
+    C = ctypes
+    fake = C.c_void_p(0x1000)      # never dereferenced: every call below fails validation first
+    s = _lib.Surfels()
+    s.n = 10
+    for k in ("pos", "rot", "scale", "opacity", "albedo", "radiance", "emissive"):
+        setattr(s, k, fake)
+    p = _lib.TraceParams()
+    lib.eag_default_params(C.byref(p))
+    out = C.c_void_p()
+    assert lib.eag_emitters_bytes(0) == 0 and lib.eag_emitters_bytes(1000) > 1000 * 17 * 4
+    p.tau_E = -0.5
+    assert lib.eag_build_emitters(C.byref(s), C.byref(p), fake, 1 << 20, fake, 1 << 20, None, C.byref(out)) == -1
+    assert b"tau_E" in lib.eag_last_error()
+    lib.eag_default_params(C.byref(p))
+    p.k_sigma = 4.0
+    assert lib.eag_build_emitters(C.byref(s), C.byref(p), fake, 1 << 20, fake, 1 << 20, None, C.byref(out)) == -1
+    assert b"k_sigma" in lib.eag_last_error()
+    lib.eag_default_params(C.byref(p))
+    odd = C.c_void_p(0x1010)
+    assert lib.eag_build_emitters(C.byref(s), C.byref(p), odd, 1 << 20, fake, 1 << 20, None, C.byref(out)) == -1
+    assert b"aligned" in lib.eag_last_error()
+    assert lib.eag_emitters_get_info(None, None, None) == -1
+    assert lib.eag_path_trace_mis(None, C.byref(s), None, None, C.byref(p), 0, 1, None, None, None, 0, None) == -1
+    lib.eag_emitters_destroy(None)
