@@ -59,21 +59,25 @@ __device__ __forceinline__ void add_fixed(int64_t* acc, float v) {
 // The term of one emitter ellipse in p_l (0 if the ray does not cross it at
 // d > 0), in double precision, with the tracer's acceptance test.
 __device__ __forceinline__ double pdf_term(const EmitterDev& E, uint32_t pos, D3 X, D3 W) {
-  const Record rec = load_record(E.recs, pos);
-  const Geo g = surfel_geo(rec);
-  const double den = dot(W, g.n);
+  const EmitGeo* g = E.geo + pos;
+  const D3 n = d3(g->n[0], g->n[1], g->n[2]);
+  const double den = dot(W, n);
   if (!(fabs(den) > 1e-12)) return 0.0;
-  const D3 d = g.p - X;
-  const double t = dot(d, g.n) / den;
+  const D3 d = d3(g->p[0], g->p[1], g->p[2]) - X;
+  const double t = dot(d, n) / den;
   if (!(t > 0.0)) return 0.0;
   const D3 y = t * W - d;
-  const double u = dot(y, g.tu) / g.su, v = dot(y, g.tv) / g.sv;
+  const double u = dot(y, d3(g->tu[0], g->tu[1], g->tu[2])) / g->su;
+  const double v = dot(y, d3(g->tv[0], g->tv[1], g->tv[2])) / g->sv;
   if (!(u * u + v * v <= E.k2)) return 0.0;
-  return E.rho[rec_index(rec)] * t * t / fabs(den);
+  return g->rho * t * t / fabs(den);
 }
 
-// p_l(X, W): every emitter box the ray meets at t >= 0 is visited.
-__device__ double light_pdf(const EmitterDev& E, D3 X, D3 W) {
+// p_l(X, W): every emitter box the ray meets at t >= 0 is visited. The stack
+// lives in the lane's LDS column (lds, STACK_LDS entries) and spills to
+// private memory beyond; at most 3 * depth + 1 entries are ever held, a
+// bound the build checks against STACK_SIZE.
+__device__ double light_pdf(const EmitterDev& E, D3 X, D3 W, int* lds) {
   double sum = 0.0;
   if (E.n == 0) return sum;
   const V3 Of = v3((float)X.x, (float)X.y, (float)X.z);
@@ -82,11 +86,14 @@ __device__ double light_pdf(const EmitterDev& E, D3 X, D3 W) {
                    1.0f / (fabsf(wy) > 1e-30f ? wy : copysignf(1e-30f, wy)),
                    1.0f / (fabsf(wz) > 1e-30f ? wz : copysignf(1e-30f, wz)));
   const float inf = __builtin_inff();
-  int stack[STACK_SIZE];
-  int sp = 0;
-  stack[sp++] = E.root;
-  while (sp > 0) {
-    const int ref = stack[--sp];
+  int ovf[STACK_OVF];
+  TravStack st;
+  st.lds = lds;
+  st.ovf = ovf;
+  st.sp = 0;
+  st.push(E.root);
+  while (st.sp > 0) {
+    const int ref = st.pop();
     if (ref < 0) {
       sum += pdf_term(E, (uint32_t)~ref, X, W);
       continue;
@@ -98,11 +105,10 @@ __device__ double light_pdf(const EmitterDev& E, D3 X, D3 W) {
     const float e1 = slab(b1.z, b1.w, b2.x, b2.y, b2.z, b2.w, Of, iW, 0.0f, inf);
     const float e2 = slab(b3.x, b3.y, b3.z, b3.w, b4.x, b4.y, Of, iW, 0.0f, inf);
     const float e3 = slab(b4.z, b4.w, b5.x, b5.y, b5.z, b5.w, Of, iW, 0.0f, inf);
-    // at most 3 * depth + 1 entries are ever held; the build checks that bound
-    if (cr.x != NODE4_EMPTY && e0 < inf && sp < STACK_SIZE) stack[sp++] = cr.x;
-    if (cr.y != NODE4_EMPTY && e1 < inf && sp < STACK_SIZE) stack[sp++] = cr.y;
-    if (cr.z != NODE4_EMPTY && e2 < inf && sp < STACK_SIZE) stack[sp++] = cr.z;
-    if (cr.w != NODE4_EMPTY && e3 < inf && sp < STACK_SIZE) stack[sp++] = cr.w;
+    if (cr.x != NODE4_EMPTY && e0 < inf && st.sp < STACK_SIZE) st.push(cr.x);
+    if (cr.y != NODE4_EMPTY && e1 < inf && st.sp < STACK_SIZE) st.push(cr.y);
+    if (cr.z != NODE4_EMPTY && e2 < inf && st.sp < STACK_SIZE) st.push(cr.z);
+    if (cr.w != NODE4_EMPTY && e3 < inf && st.sp < STACK_SIZE) st.push(cr.w);
   }
   return sum;
 }
@@ -141,6 +147,7 @@ __device__ __forceinline__ D3 emitter_point(const EmitterDev& E, int64_t j, doub
 struct MisPathSource {
   const PtLaunch* L;
   const EmitterDev* E;
+  int* lds_stack;   // the lane's traversal-stack column, free while finishing
   uint32_t pix, sample;
   int depth;
   V3 beta;
@@ -195,7 +202,7 @@ struct MisPathSource {
     if (s.E > S.tau_E) {
       double wgt = 1.0;
       if (depth >= 1 && E->n > 0) {
-        const double pl = light_pdf(*E, s.O, s.W);
+        const double pl = light_pdf(*E, s.O, s.W, lds_stack);
         const double den = pb * pb + pl * pl;
         wgt = den > 0.0 ? pb * pb / den : 1.0;
       }
@@ -220,7 +227,7 @@ struct MisPathSource {
       const double cl = dot(Wl, Nt);
       if (cl > 0.0) {
         const double pbl = cl * INV_PI;
-        const double pl = light_pdf(*E, X, Wl);
+        const double pl = light_pdf(*E, X, Wl, lds_stack);
         const double den = pbl * pbl + pl * pl;
         const float f = den > 0.0 ? (float)(pbl * pl / den) : 0.0f;
         lf = v3(beta.x * f, beta.y * f, beta.z * f);
@@ -258,6 +265,7 @@ __global__ void __launch_bounds__(TRACE_BLOCK) __attribute__((amdgpu_waves_per_e
   MisPathSource src;
   src.L = &L;
   src.E = &E;
+  src.lds_stack = nullptr;
   src.pix = src.sample = 0;
   src.depth = 0;
   src.beta = src.lf = v3(0.f, 0.f, 0.f);
@@ -306,6 +314,24 @@ __global__ void k_emit_rho(eag_surfels_out c, const double* cdf, double k, doubl
   rho[j] = (double)c.opacity[j] * (rbar + (double)c.emissive[j]) / (M_PI * k * k * cdf[ne - 1]);
 }
 
+// Geometry of the emitter at leaf position pos, from its record.
+__global__ void k_emit_geo(const Record* recs, const double* rho, int64_t ne, EmitGeo* geo) {
+  const int64_t pos = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (pos >= ne) return;
+  const Record rec = load_record(recs, (uint32_t)pos);
+  const Geo g = surfel_geo(rec);
+  EmitGeo e;
+  e.p[0] = g.p.x; e.p[1] = g.p.y; e.p[2] = g.p.z;
+  e.tu[0] = g.tu.x; e.tu[1] = g.tu.y; e.tu[2] = g.tu.z;
+  e.tv[0] = g.tv.x; e.tv[1] = g.tv.y; e.tv[2] = g.tv.z;
+  e.n[0] = g.n.x; e.n[1] = g.n.y; e.n[2] = g.n.z;
+  e.su = g.su;
+  e.sv = g.sv;
+  e.rho = rho[rec_index(rec)];
+  e.pad = 0.0;
+  geo[pos] = e;
+}
+
 unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 struct EmitWs {
@@ -347,6 +373,7 @@ EmitWs emit_ws(void* base, int64_t n) {
 struct EmitMem {
   float *pos, *rot, *scale, *opacity, *albedo, *radiance, *emissive;
   double *w, *cdf, *rho;
+  EmitGeo* geo;
   void* bvh;
   size_t bvh_bytes;
   size_t bytes;
@@ -366,6 +393,7 @@ EmitMem emit_mem(void* base, int64_t n) {
   m.w = c.take<double>(n);
   m.cdf = c.take<double>(n);
   m.rho = c.take<double>(n);
+  m.geo = c.take<EmitGeo>(n);
   m.bvh_bytes = bvh_layout(nullptr, n).bytes;
   m.bvh = c.take<char>(m.bvh_bytes);
   m.bytes = c.bytes();
@@ -446,10 +474,12 @@ void build_emitters(const eag_surfels* s, float tau_E, float k_sigma, void* mem,
     delete b;
     fail(EAG_ERR_INTERNAL, "emitter tree deeper than the density traversal's stack");
   }
+  hipLaunchKernelGGL(k_emit_geo, dim3(blocks_for((int64_t)ne)), dim3(256), 0, st, b->recs, m.rho, (int64_t)ne, m.geo);
+  check_hip(hipGetLastError(), "emitter geometry");
   check_hip(hipStreamSynchronize(st), "emitter table sync");
   out->bvh = b;
   E.nodes = b->nodes4;
-  E.recs = b->recs;
+  E.geo = m.geo;
   E.root = b->root;
   E.rho = m.rho;
   E.cdf = m.cdf;

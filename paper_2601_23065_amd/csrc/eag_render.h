@@ -183,9 +183,16 @@ void launch_adam(float* r, const float* g, float* m, float* v, int64_t count, co
                  hipStream_t st);
 
 // Emitter sampling with multiple importance sampling (eag_nee.hip).
+// An emitter's geometry for the light pdf, in the tree's leaf order: centre,
+// frame (t_u, t_v, n from its normalised quaternion) and scales in double
+// precision, and rho, the area density of the point sampler on its ellipse.
+struct __align__(16) EmitGeo {
+  double p[3], tu[3], tv[3], n[3];
+  double su, sv, rho, pad;
+};
 struct EmitterDev {
   const Node4* nodes;        // 4-wide tree over the emitters
-  const Record* recs;        // their geometry records; the record index is the table position
+  const EmitGeo* geo;        // [n] geometry by leaf position
   const double* rho;         // [n] area density of the point sampler on each emitter's ellipse
   const double* cdf;         // [n] inclusive prefix sums of the selection weights
   const float* pos;          // [3][n] compacted centres

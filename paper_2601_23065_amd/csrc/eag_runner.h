@@ -57,6 +57,17 @@ struct RunStats {
   }
 };
 
+// A source that walks a tree of its own inside finish() (a light pdf, say)
+// may declare a member `int* lds_stack`: it receives the lane's column of the
+// traversal stack in LDS (entry i at lds_stack[i * TRACE_BLOCK], STACK_LDS
+// entries), which is empty whenever finish() runs.
+template <class Src>
+__device__ __forceinline__ auto bind_lds_stack(Src& src, int* col, int) -> decltype(src.lds_stack = col, void()) {
+  src.lds_stack = col;
+}
+template <class Src>
+__device__ __forceinline__ void bind_lds_stack(Src&, int*, long) {}
+
 template <int QMODE, bool DACC, class Src>
 __device__ __forceinline__ void run_segments(const TraceCtx& tc, Src& src, unsigned long long* work_counter,
                                              int64_t n_work, uint64_t* hitlist, unsigned long long* counters) {
@@ -68,6 +79,7 @@ __device__ __forceinline__ void run_segments(const TraceCtx& tc, Src& src, unsig
   st.lds = s_stack + threadIdx.x;
   st.ovf = s_ovf;
   st.sp = 0;
+  bind_lds_stack(src, st.lds, 0);
   int* const pend = s_pend + threadIdx.x;
   const int lane = (int)(threadIdx.x & 63);
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
