@@ -637,6 +637,10 @@ def bench_mis(torch, args):
                                      "lies above the surface",
                    "mis_image_ms": round(ms_mis, 3), "plain_image_ms": round(ms_plain, 3),
                    "plain_segments_per_step": c_plain[0], "plain_mrays_s": round(c_plain[0] / (ms_plain * 1e-3) / 1e6, 3),
+                   "per_segment_mis": {k: round(v / max(segments, 1), 3) for k, v in
+                                       zip(("rounds", "tests", "blended", "visits"), (rounds, tests, blended, visits))},
+                   "per_segment_plain": {k: round(v / max(c_plain[0], 1), 3) for k, v in
+                                         zip(("rounds", "tests", "blended", "visits"), c_plain[2:6])},
                    "rmse_mis": rmse_mis, "rmse_plain": rmse_plain,
                    "mse_ratio_equal_spp": round((rmse_plain / rmse_mis) ** 2, 3),
                    "mse_ratio_equal_time": round((rmse_plain / rmse_mis) ** 2 * ms_plain / ms_mis, 3),

@@ -151,9 +151,10 @@ struct MisPathSource {
   uint32_t pix, sample;
   int depth;
   V3 beta;
-  V3 lf;            // the pending light segment's factor beta * p_b p_l / (p_b^2 + p_l^2)
+  V3 lf;            // beta at the vertex of the pending light segment
   D3 X, Wb;         // the vertex and the cosine-sampled continuation
   double pb;        // cosine pdf of the direction of the segment in flight (or the continuation)
+  double pbl;       // cosine pdf of the pending light segment's direction
   bool light;       // the segment in flight is a light segment
   bool cont;        // the continuation survived Russian roulette
 
@@ -187,11 +188,15 @@ struct MisPathSource {
     const double A = 1.0 - s.T;
     const bool hit = s.nhits > 0 && A > 0.0;
     if (light) {
+      // the light pdf is needed only when the segment passes the emitter test
       light = false;
       if (hit && s.E > S.tau_E) {
-        add_fixed(acc + 0, lf.x * s.R0);
-        add_fixed(acc + 1, lf.y * s.R1);
-        add_fixed(acc + 2, lf.z * s.R2);
+        const double pl = light_pdf(*E, s.O, s.W, lds_stack);
+        const double den = pbl * pbl + pl * pl;
+        const float f = den > 0.0 ? (float)(pbl * pl / den) : 0.0f;
+        add_fixed(acc + 0, (lf.x * f) * s.R0);
+        add_fixed(acc + 1, (lf.y * f) * s.R1);
+        add_fixed(acc + 2, (lf.z * f) * s.R2);
       }
       if (!cont) return false;
       O = X;
@@ -226,11 +231,8 @@ struct MisPathSource {
       Wl = (1.0 / sqrt(dot(dl, dl))) * dl;
       const double cl = dot(Wl, Nt);
       if (cl > 0.0) {
-        const double pbl = cl * INV_PI;
-        const double pl = light_pdf(*E, X, Wl, lds_stack);
-        const double den = pbl * pbl + pl * pl;
-        const float f = den > 0.0 ? (float)(pbl * pl / den) : 0.0f;
-        lf = v3(beta.x * f, beta.y * f, beta.z * f);
+        pbl = cl * INV_PI;
+        lf = beta;
         light = true;
       }
     }
@@ -270,7 +272,7 @@ __global__ void __launch_bounds__(TRACE_BLOCK) __attribute__((amdgpu_waves_per_e
   src.depth = 0;
   src.beta = src.lf = v3(0.f, 0.f, 0.f);
   src.X = src.Wb = d3(0.0, 0.0, 0.0);
-  src.pb = 0.0;
+  src.pb = src.pbl = 0.0;
   src.light = src.cont = false;
   run_segments<Q_ALL, false>(tc, src, work_counter, L.n_work, hitlist, counters);
 }
