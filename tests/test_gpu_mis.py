@@ -1,8 +1,9 @@
 """Parity of path tracing with emitter sampling and multiple importance
 sampling against the oracle: the emitter table, every path of a room per
 sample, the camera-only case against the plain path tracer, equal means and
-lower variance than the plain path tracer, and sampled pixels of the
-benchmark's full-size configuration."""
+lower variance than the plain path tracer, a one-emitter table, an empty
+table, the table rebuilt after switching lights off, and sampled pixels of
+the benchmark's full-size configuration."""
 import multiprocessing as mp
 import os
 
@@ -100,6 +101,68 @@ def test_same_mean_lower_variance_than_plain():
           f"pass-to-pass pixel sd: mis {mis.std(axis=0).mean():.4f} plain {plain.std(axis=0).mean():.4f}")
     assert abs(sa.mean() - sb.mean()) < 5 * se
     assert mis.std(axis=0).mean() < 0.7 * plain.std(axis=0).mean()
+
+
+def test_single_emitter_over_a_receiver_per_sample():
+    """A one-emitter table (its tree is a single leaf), depth 1: every path
+    against the oracle."""
+    from paper_2601_23065_amd.api import BVH, Emitters, Params, path_trace_mis
+    from tests.test_oracle_render import _emitter_over_receiver
+    scene = _emitter_over_receiver()
+    cam = sg.Camera((3.0, 0.0, 0.5), (0.0, 0.0, 0.0), (0.0, 0.0, 1.0), 10.0, 3, 2)
+    p = Params(spp=64, max_depth=1, rr_start=0)
+    gs = gpu_scene(scene)
+    bvh = BVH(gs)
+    em = Emitters(gs, p)
+    assert em.info()[0] == 1
+    got = _per_sample(lambda s: path_trace_mis(bvh, gs, em, cam, p, sample_begin=s, sample_count=1), range(p.spp))
+    ref = path_trace_nee(Scene64(scene), cam, oracle_params(p))
+    ok = ref["flags"] == 0
+    err = rel_err(got, ref["value"], np.broadcast_to(ok[..., None], got.shape))
+    print(f"unflagged={ok.mean():.3f} err={err.max():.2e} nonzero={np.mean(ref['value'].sum(-1) > 0):.3f}")
+    assert ok.mean() > 0.9 and np.mean(ref["value"].sum(-1) > 0) > 0.3
+    assert err.max() <= 1e-4
+
+
+def test_no_emitters():
+    """A threshold above every e: an empty table, and the plain path
+    tracer's image (black: no segment passes the emitter test either)."""
+    from paper_2601_23065_amd.api import BVH, Emitters, Params, path_trace, path_trace_mis
+    scene, cam = _small_room()
+    p = Params(spp=2, max_depth=3, rr_start=2, tau_E=1.5)
+    gs = gpu_scene(scene)
+    bvh = BVH(gs)
+    em = Emitters(gs, p)
+    assert em.info() == (0, 0.0)
+    a = path_trace_mis(bvh, gs, em, cam, p)
+    assert torch.equal(a, path_trace(bvh, gs, cam, p)) and int(a.abs().sum()) == 0
+
+
+def test_lights_off_then_rebuilt_table():
+    """Half the emitters switched off (r = 0, e kept): they stay in the table
+    with the weight of their e; every path against the oracle on the edited
+    scene."""
+    from paper_2601_23065_amd import EDIT_SET_RADIANCE
+    from paper_2601_23065_amd.api import BVH, Emitters, Params, apply_edit, path_trace_mis
+    scene, cam = _small_room()
+    p = Params(spp=2, max_depth=4, rr_start=2, seed=5)
+    gs = gpu_scene(scene)
+    bvh = BVH(gs)
+    emit = np.nonzero(scene.arrays()["emissive"] > p.tau_E)[0]
+    off = np.random.default_rng(3).choice(emit, emit.size // 2, replace=False).astype(np.int32)
+    apply_edit(gs, EDIT_SET_RADIANCE, torch.from_numpy(off).cuda(), (0.0, 0.0, 0.0))
+    em = Emitters(gs, p)
+    arrays = {k: v.copy() for k, v in scene.arrays().items()}
+    arrays["radiance"][:, off] = 0.0
+    ref_em = OEmitters(Scene64(arrays), p.tau_E)
+    n, W = em.info()
+    assert n == ref_em.count and abs(W - ref_em.W) <= 1e-12 * ref_em.W
+    got = _per_sample(lambda s: path_trace_mis(bvh, gs, em, cam, p, sample_begin=s, sample_count=1), range(p.spp))
+    ref = path_trace_nee(Scene64(arrays), cam, oracle_params(p), em=ref_em)
+    ok = ref["flags"] == 0
+    err = rel_err(got, ref["value"], np.broadcast_to(ok[..., None], got.shape))
+    print(f"paths={ok.size} unflagged={ok.mean():.3f} err={err.max():.2e}")
+    assert ok.mean() > 0.4 and err.max() <= 1e-4
 
 
 _ORACLE = {}
