@@ -63,6 +63,22 @@ def test_path_trace_mis_room_per_sample():
     assert err.max() <= 1e-4
 
 
+def test_path_trace_mis_jittered_per_sample():
+    from paper_2601_23065_amd import JITTER
+    from paper_2601_23065_amd.api import BVH, Emitters, Params, path_trace_mis
+    scene, cam = _small_room()
+    p = Params(spp=2, max_depth=4, rr_start=2, camera_id=2, seed=11, flags=JITTER)
+    gs = gpu_scene(scene)
+    bvh = BVH(gs)
+    em = Emitters(gs, p)
+    got = _per_sample(lambda s: path_trace_mis(bvh, gs, em, cam, p, sample_begin=s, sample_count=1), range(p.spp))
+    ref = path_trace_nee(Scene64(scene), cam, oracle_params(p))
+    ok = ref["flags"] == 0
+    err = rel_err(got, ref["value"], np.broadcast_to(ok[..., None], got.shape))
+    print(f"paths={ok.size} unflagged={ok.mean():.3f} err={err.max():.2e}")
+    assert ok.mean() > 0.4 and err.max() <= 1e-4
+
+
 def test_camera_segments_only_equal_plain():
     """max_depth 0: no vertex, no light sample; bit-identical to path_trace."""
     from paper_2601_23065_amd.api import BVH, Emitters, Params, path_trace, path_trace_mis

@@ -39,10 +39,12 @@ def _small_room():
     return scene, cam
 
 
-def test_single_bounce_room_per_sample():
+@pytest.mark.parametrize("jitter", [False, True])
+def test_single_bounce_room_per_sample(jitter):
+    from paper_2601_23065_amd import JITTER
     from paper_2601_23065_amd.api import BVH, Params, render_single_bounce
     scene, cam = _small_room()
-    p = Params(spp=3, camera_id=7, seed=123)
+    p = Params(spp=3, camera_id=7, seed=123, flags=JITTER if jitter else 0)
     gs = gpu_scene(scene)
     bvh = BVH(gs)
     rgb, state = render_single_bounce(bvh, gs, [cam], p, keep_state=True)
@@ -81,6 +83,28 @@ def test_path_trace_room_per_sample():
     print(f"paths={ok.size} unflagged={ok.mean():.3f} err={err.max():.2e} nonzero={np.mean(ref['value'].sum(-1) > 0):.3f}")
     assert ok.mean() > 0.4
     assert err.max() <= 1e-4
+
+
+def test_path_trace_jittered_camera_rays_per_sample():
+    """EAG_JITTER: camera rays jittered inside the pixel by Philox segment
+    word 0xffffffff; every path against the oracle."""
+    from paper_2601_23065_amd import JITTER
+    from paper_2601_23065_amd.api import BVH, Params
+    scene, cam = _small_room()
+    p = Params(spp=3, max_depth=4, rr_start=2, camera_id=1, seed=7, flags=JITTER)
+    gs = gpu_scene(scene)
+    bvh = BVH(gs)
+    got = _pt_per_sample(bvh, gs, cam, p, range(p.spp))
+    prm = oracle_params(p)
+    assert prm.jitter
+    ref = o_path_trace(Scene64(scene), cam, prm)
+    ok = ref["flags"] == 0
+    err = rel_err(got, ref["value"], np.broadcast_to(ok[..., None], got.shape))
+    print(f"paths={ok.size} unflagged={ok.mean():.3f} err={err.max():.2e}")
+    assert ok.mean() > 0.4 and err.max() <= 1e-4
+    # the jitter moves the camera rays: sample 0 differs from the pixel-centre render
+    centre = _pt_per_sample(bvh, gs, cam, Params(spp=1, max_depth=4, rr_start=2, camera_id=1, seed=7), [0])
+    assert not np.array_equal(centre[:, 0], got[:, 0])
 
 
 def test_progressive_passes_are_exact():
