@@ -85,6 +85,38 @@ def test_path_trace_room_per_sample():
     assert err.max() <= 1e-4
 
 
+def _cloud():
+    return (sg.cloud_scene(2000, seed=1, emissive_frac=0.3),
+            sg.Camera((0.0, 0.0, -3.0), (0.0, 0.0, 0.0), (0.0, 1.0, 0.0), 60.0, 24, 18))
+
+
+@pytest.mark.parametrize("case", ["exact_t_order", "k2_Tmin1e-3_tmin1e-2"])
+def test_path_trace_other_readings_per_sample(case):
+    """The readings exposed as parameters: exact (t, index) order instead of
+    the depth quantum (on the cloud: coplanar walls would leave every order
+    to rounding); a 2-sigma extent with other stopping and minimum-hit
+    distances (on the room). Every path against the oracle with the same
+    parameters."""
+    from paper_2601_23065_amd.api import BVH, Params
+    if case == "exact_t_order":
+        scene, cam = _cloud()
+        kw = dict(depth_quantum=0.0)
+    else:
+        scene, cam = _small_room()
+        kw = dict(k_sigma=2.0, T_min=1e-3, t_min=1e-2)
+    p = Params(spp=2, max_depth=4, rr_start=2, seed=17, **kw)
+    gs = gpu_scene(scene)
+    bvh = BVH(gs)
+    got = _pt_per_sample(bvh, gs, cam, p, range(p.spp))
+    ref = o_path_trace(Scene64(scene), cam, oracle_params(p))
+    ok = ref["flags"] == 0
+    err = rel_err(got, ref["value"], np.broadcast_to(ok[..., None], got.shape))
+    print(f"{case}: paths={ok.size} unflagged={ok.mean():.3f} err={err.max():.2e} "
+          f"nonzero={np.mean(ref['value'].sum(-1) > 0):.3f}")
+    assert ok.mean() > 0.4 and err.max() <= 1e-4
+    assert np.mean(ref["value"].sum(-1) > 0) > 0.05
+
+
 def test_path_trace_jittered_camera_rays_per_sample():
     """EAG_JITTER: camera rays jittered inside the pixel by Philox segment
     word 0xffffffff; every path against the oracle."""
