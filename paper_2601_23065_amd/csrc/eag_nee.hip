@@ -261,9 +261,11 @@ struct MisPathSource {
   }
 };
 
-__global__ void __launch_bounds__(TRACE_BLOCK) __attribute__((amdgpu_waves_per_eu(2))) k_path_trace_mis(TraceCtx tc, PtLaunch L, EmitterDev E,
-                                                                unsigned long long* work_counter,
-                                                                unsigned long long* counters, uint64_t* hitlist) {
+// Two waves per SIMD, as the plain path tracer: without the bound the
+// allocator takes enough registers for one.
+__global__ void __launch_bounds__(TRACE_BLOCK) __attribute__((amdgpu_waves_per_eu(2)))
+k_path_trace_mis(TraceCtx tc, PtLaunch L, EmitterDev E, unsigned long long* work_counter, unsigned long long* counters,
+                 uint64_t* hitlist) {
   MisPathSource src;
   src.L = &L;
   src.E = &E;
