@@ -2,6 +2,8 @@
 reference values, derivatives against central differences, the adjoint
 identity that linearity in r gives, a hand-computed weight sum, and Adam's
 first step in closed form."""
+import os
+
 import numpy as np
 
 import scenegen as sg
@@ -12,10 +14,12 @@ from oracle.tracer import Scene64
 
 
 def test_pq_reference_values():
-    # ST 2084 code values for 1, 10, 100, 1000 and 10000 cd/m^2, and the
-    # curve's offset at zero, c1^m2
-    L = np.array([1.0, 10.0, 100.0, 1000.0, 10000.0])
-    np.testing.assert_allclose(pq(L), [0.1499, 0.2997, 0.5081, 0.7518, 1.0], atol=6e-5)
+    # ST 2084 code values for 1, 10, 100, 1000 and 10000 cd/m^2 (tests/golden),
+    # and the curve's offset at zero, c1^m2
+    ref = np.loadtxt(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "pq_st2084.txt"))
+    L, N = ref[:, 0], ref[:, 1]
+    assert L.size == 5
+    np.testing.assert_allclose(pq(L), N, atol=6e-5)
     assert abs(pq(10000.0) - 1.0) < 1e-15
     assert abs(pq(0.0) - (3424.0 / 4096.0) ** (2523.0 / 4096.0 * 128.0)) < 1e-20
     assert np.all(np.diff(pq(np.linspace(0.0, 20.0, 200))) > 0)

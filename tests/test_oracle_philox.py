@@ -11,6 +11,8 @@ import pytest
 
 from oracle import philox
 
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
 ROCRAND_PROG = r"""
 #include <rocrand/rocrand_philox4x32_10.h>
 #include <cstdio>
@@ -29,11 +31,14 @@ int main() {
 
 
 def test_published_kat_vectors():
-    # Random123 kat_vectors, philox4x32 with 10 rounds
-    w = philox.philox4x32_10(0, 0, 0, 0, 0)
-    assert [int(x) for x in w] == [0x6627E8D5, 0xE169C58D, 0xBC57AC4C, 0x9B00DBD8]
-    w = philox.philox4x32_10(0xFFFFFFFF, 0xFFFFFFFF, 0xFFFFFFFF, 0xFFFFFFFF, 0xFFFFFFFFFFFFFFFF)
-    assert [int(x) for x in w] == [0x408F276D, 0x41C83B0E, 0xA20BC7C6, 0x6D5451FD]
+    # Random123 kat_vectors, philox4x32 with 10 rounds (tests/golden)
+    rows = [line.split() for line in open(os.path.join(GOLDEN, "philox4x32_10_kat.txt"))
+            if line.strip() and not line.startswith("#")]
+    assert len(rows) == 3
+    for r in rows:
+        c0, c1, c2, c3, k0, k1, *want = (int(x, 16) for x in r)
+        w = philox.philox4x32_10(c0, c1, c2, c3, k0 | (k1 << 32))
+        assert [int(x) for x in w] == want
 
 
 @pytest.mark.skipif(shutil.which("hipcc") is None, reason="hipcc not available")
