@@ -44,7 +44,8 @@ Further workloads print their own JSON line (not the default run):
                        multiple importance sampling on the default room:
                        time per 64-spp image and image error of it and of
                        the plain path tracer against a reference of 8x the
-                       spp (512), at equal spp and at equal time.
+                       spp (512), at equal spp and at equal time
+                       (--mis-config 4: the three-room 5M scene at 64 spp).
   --workload serve     continuous-batching server against one-at-a-time FIFO
                        on the same Poisson arrivals over a resident 3M-surfel
                        room (request mix scaled down by default: 128x128 or
@@ -561,9 +562,9 @@ def bench_mis(torch, args):
     import scenegen as sg
     from paper_2601_23065_amd.api import BVH, Emitters, Params, Scene, path_trace, path_trace_mis, path_trace_workspace
 
-    scene, cams, cfg = sg.config(3, n_override=args.surfels)
+    scene, cams, cfg = sg.config(args.mis_config, n_override=args.surfels)
     cam = cams[0]
-    spp = args.spp or cfg["spp"]
+    spp = args.spp or (64 if args.mis_config == 4 else cfg["spp"])
     params = Params(spp=spp, max_depth=cfg["max_depth"], rr_start=cfg["rr_start"], seed=0, camera_id=0)
     gs = Scene(scene.arrays())
     ws = path_trace_workspace(gs)
@@ -627,7 +628,9 @@ def bench_mis(torch, args):
         "ms_per_step": round(ms_mis, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"path tracing with emitter sampling and MIS (power heuristic), {scene.n} surfels "
-                               f"({n_em} emitters) in an 8x6x3 m room with 40 boxes, {cam.width}x{cam.height}, "
+                               f"({n_em} emitters) in " + ("three 8x6x3 m rooms joined by doorways, 120 boxes"
+                                                           if args.mis_config == 4 else "an 8x6x3 m room with 40 boxes")
+                               + f", {cam.width}x{cam.height}, "
                                f"{spp} spp, max depth {params.max_depth}, RR from {params.rr_start}; step = the "
                                f"path-tracing launch over all samples",
                    "surfels": scene.n, "emitters": n_em, "width": cam.width, "height": cam.height, "spp": spp},
@@ -777,6 +780,8 @@ def main():
                     help="serve workload request mix: small (128^2 or 256^2, 4 or 16 spp) or full "
                          "(256^2 .. 1920x1080, 16 .. 256 spp)")
     ap.add_argument("--spp", type=int, default=None, help="override the workload's 64 spp (diagnostics only)")
+    ap.add_argument("--mis-config", type=int, default=3, choices=[3, 4],
+                    help="scene of the mis workload: 3 = the default room, 4 = the three rooms (64 spp)")
     ap.add_argument("--workload", default="room1m",
                     choices=["room1m", "rooms5m", "serve", "sb100k", "bake", "stage0", "edits", "mis"])
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
