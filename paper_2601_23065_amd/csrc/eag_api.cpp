@@ -563,6 +563,34 @@ size_t eag_path_trace_workspace_bytes(int64_t n) {
   }
 }
 
+namespace {
+// One request's path-tracing launch: all its work items (sample_count
+// samples of every pixel, in 8x8 tiles) in slot 0.
+PtLaunch single_request_launch(const CamDev& cd, const eag_camera& cam, const eag_trace_params* p, const Attr* attrs,
+                               int64_t* accum, uint32_t sample_begin, uint32_t sample_count) {
+  PtLaunch L;
+  std::memset(&L, 0, sizeof(L));
+  PtSlot& S = L.s[0];
+  S.cam = cd;
+  S.accum = accum;
+  S.attrs = attrs;
+  S.work_begin = 0;
+  S.tiles_x = (cam.width + 7) / 8;
+  S.tile_pixels = (int64_t)S.tiles_x * ((cam.height + 7) / 8) * 64;
+  S.global_end = (int64_t)sample_count * S.tile_pixels;
+  S.sample_begin = sample_begin;
+  S.max_depth = p->max_depth;
+  S.rr_start = p->rr_start;
+  S.flags = p->flags;
+  S.k0 = (uint32_t)(p->seed & 0xffffffffu);
+  S.k1 = (uint32_t)(p->seed >> 32);
+  S.tau_E = p->tau_E;
+  L.n_slots = 1;
+  L.n_work = S.global_end;
+  return L;
+}
+}  // namespace
+
 eag_status eag_path_trace(const eag_bvh* b, const eag_surfels* s, const eag_camera* cam, const eag_trace_params* p,
                           uint32_t sample_begin, uint32_t sample_count, int64_t* accum, uint64_t* counters, void* ws,
                           size_t ws_bytes, void* stream) {
@@ -579,25 +607,7 @@ eag_status eag_path_trace(const eag_bvh* b, const eag_surfels* s, const eag_came
     hipStream_t st = static_cast<hipStream_t>(stream);
     pack_attrs(s, b, w.attrs, st);
     const TraceCtx tc = make_ctx(b, w.attrs, p, ts);
-    PtLaunch L;
-    std::memset(&L, 0, sizeof(L));
-    PtSlot& S = L.s[0];
-    S.cam = cd;
-    S.accum = accum;
-    S.attrs = w.attrs;
-    S.work_begin = 0;
-    S.tiles_x = (cam->width + 7) / 8;
-    S.tile_pixels = (int64_t)S.tiles_x * ((cam->height + 7) / 8) * 64;
-    S.global_end = (int64_t)sample_count * S.tile_pixels;
-    S.sample_begin = sample_begin;
-    S.max_depth = p->max_depth;
-    S.rr_start = p->rr_start;
-    S.flags = p->flags;
-    S.k0 = (uint32_t)(p->seed & 0xffffffffu);
-    S.k1 = (uint32_t)(p->seed >> 32);
-    S.tau_E = p->tau_E;
-    L.n_slots = 1;
-    L.n_work = S.global_end;
+    const PtLaunch L = single_request_launch(cd, *cam, p, w.attrs, accum, sample_begin, sample_count);
     launch_path_trace(tc, L, w.work, reinterpret_cast<unsigned long long*>(counters), w.hitlist, st);
   });
 }
@@ -679,25 +689,7 @@ eag_status eag_path_trace_mis(const eag_bvh* b, const eag_surfels* s, const eag_
     hipStream_t st = static_cast<hipStream_t>(stream);
     pack_attrs(s, b, w.attrs, st);
     const TraceCtx tc = make_ctx(b, w.attrs, p, ts);
-    PtLaunch L;
-    std::memset(&L, 0, sizeof(L));
-    PtSlot& S = L.s[0];
-    S.cam = cd;
-    S.accum = accum;
-    S.attrs = w.attrs;
-    S.work_begin = 0;
-    S.tiles_x = (cam->width + 7) / 8;
-    S.tile_pixels = (int64_t)S.tiles_x * ((cam->height + 7) / 8) * 64;
-    S.global_end = (int64_t)sample_count * S.tile_pixels;
-    S.sample_begin = sample_begin;
-    S.max_depth = p->max_depth;
-    S.rr_start = p->rr_start;
-    S.flags = p->flags;
-    S.k0 = (uint32_t)(p->seed & 0xffffffffu);
-    S.k1 = (uint32_t)(p->seed >> 32);
-    S.tau_E = p->tau_E;
-    L.n_slots = 1;
-    L.n_work = S.global_end;
+    const PtLaunch L = single_request_launch(cd, *cam, p, w.attrs, accum, sample_begin, sample_count);
     launch_path_trace_mis(tc, L, em->dev, w.work, reinterpret_cast<unsigned long long*>(counters), w.hitlist, st);
   });
 }
