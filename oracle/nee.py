@@ -34,6 +34,15 @@ The reading built here:
 * Sample stream: the light sample at the vertex after segment k uses the
   Philox counter (pixel, sample, 2^31 + k, id); u0 selects, u1 and u2 place
   the point.
+* Selection by cells (an option, cell size c > 0, a power of two): the
+  emitters are grouped by the cube of side c holding their centre, in the
+  order (cell, surfel index); at the vertex X, a cell is chosen with
+  probability I_c / sum I over the cells, I_c = W_c / max(|X - m_c|^2, c^2)
+  (W_c the cell's summed w, m_c its centre), by inversion on u0, and an
+  emitter of the cell with probability w_j / W_c by inversion on u3 (the
+  counter's fourth word). The area density of emitter j becomes
+  (I_c(X) / sum I) sigma_j (rbar_j + e_j) / (pi k^2 W_c): emitters near the
+  vertex are drawn more often, and those of other rooms seldom.
 
 The two weights add up to one wherever one of the strategies can produce a
 direction, and p_l > 0 wherever the emitter part is not zero, so the
@@ -48,7 +57,8 @@ w_l.Nt, or count another crossing in p_l (u^2 + v^2 near k^2, d near 0).
 Pinned by tests/test_oracle_nee.py: p_l integrates to one over the sphere
 (uniform-sphere Monte Carlo), the mean of 1 / p_l over light samples is the
 solid angle the emitters cover (counted by uniform directions), the
-selection frequencies w_j / W and the uniform point density on the ellipse,
+selection frequencies w_j / W (and, with cells, I_c / sum I times w_j / W_c)
+and the uniform point density on the ellipse, for both selections,
 the single-bounce integral of one emitter over one receiver by quadrature
 (scipy dblquad), equal means of this estimator and the plain path tracer on a
 room, and per-sample equality with the plain path tracer when no vertex is
@@ -66,44 +76,111 @@ F_NEE = 1 << 9
 
 
 class Emitters:
-    """The emitter table of a scene for a threshold tau_E."""
+    """The emitter table of a scene for a threshold tau_E.
 
-    def __init__(self, sc: Scene64, tau_E: float, k_sigma: float = 3.0):
+    cell = 0: selection by power alone (w_j / W). cell = c > 0 (a power of
+    two): emitters are grouped by the cube of side c that holds their centre
+    (floor of the float32 centre / c per axis) and taken in the order (cell,
+    surfel index); at a vertex X a cell is chosen with probability
+    I_c / sum I, I_c = W_c / max(|X - m_c|^2, c^2), W_c the cell's summed w
+    and m_c its centre, by inversion on u0 over the cells in order, then an
+    emitter of the cell with probability w_j / W_c by inversion on u3."""
+
+    def __init__(self, sc: Scene64, tau_E: float, k_sigma: float = 3.0, cell: float = 0.0):
         self.tau_E = float(tau_E)
         self.k = float(k_sigma)
-        self.idx = np.nonzero((sc.e > np.float64(np.float32(tau_E))) & (sc.sigma > 0))[0]
-        j = self.idx
+        self.cell = float(cell)
+        j = np.nonzero((sc.e > np.float64(np.float32(tau_E))) & (sc.sigma > 0))[0]
+        if self.cell > 0 and j.size:
+            ic = np.floor(sc.p[j] / self.cell)
+            order = np.lexsort((j, ic[:, 2], ic[:, 1], ic[:, 0]))
+            j = j[order]
+        self.idx = j
         rbar = sc.r[j].sum(axis=1) / 3.0
         self.w = sc.sigma[j] * sc.su[j] * sc.sv[j] * (rbar + sc.e[j])
         self.cdf = np.cumsum(self.w)
         self.W = float(self.cdf[-1]) if j.size else 0.0
-        # area density of the point sampler on each ellipse
-        self.rho = (sc.sigma[j] * (rbar + sc.e[j]) / (np.pi * self.k * self.k * self.W)) if j.size else np.zeros(0)
         self.p, self.tu, self.tv, self.n = sc.p[j], sc.tu[j], sc.tv[j], sc.n[j]
         self.su, self.sv = sc.su[j], sc.sv[j]
         self.pmax = np.abs(self.p).max(axis=1) if j.size else np.zeros(0)
         self.smin = np.minimum(self.su, self.sv)
+        if self.cell > 0 and j.size:
+            ic = np.floor(self.p / self.cell)
+            first = np.ones(j.size, dtype=bool)
+            first[1:] = np.any(ic[1:] != ic[:-1], axis=1)
+            self.cell_of = np.cumsum(first) - 1
+            self.begin = np.nonzero(first)[0]
+            self.end = np.append(self.begin[1:], j.size)
+            self.ctr = (ic[self.begin] + 0.5) * self.cell
+            # per-cell sums and prefix sums, each summed in order within its cell
+            self.cdf_in = np.zeros(j.size)
+            self.Wc = np.zeros(self.begin.size)
+            for c, (b, e) in enumerate(zip(self.begin, self.end)):
+                self.cdf_in[b:e] = np.cumsum(self.w[b:e])
+                self.Wc[c] = self.cdf_in[e - 1]
+            # area density of the point sampler given the emitter's cell
+            self.rho = sc.sigma[j] * (rbar + sc.e[j]) / (np.pi * self.k * self.k * self.Wc[self.cell_of])
+        else:
+            # area density of the point sampler on each ellipse
+            self.rho = (sc.sigma[j] * (rbar + sc.e[j]) / (np.pi * self.k * self.k * self.W)) if j.size else np.zeros(0)
+
+    def importance(self, X):
+        """I_c(X) [M, cells] and their sums [M] (cell mode)."""
+        X = np.atleast_2d(X)
+        d = X[:, None, :] - self.ctr[None, :, :]
+        d2 = d[..., 0] * d[..., 0] + d[..., 1] * d[..., 1] + d[..., 2] * d[..., 2]
+        I = self.Wc[None, :] / np.maximum(d2, self.cell * self.cell)
+        return I, np.cumsum(I, axis=1)[:, -1]
 
     @property
     def count(self):
         return int(self.idx.size)
 
-    def sample(self, u0, u1, u2):
+    def sample(self, u0, u1, u2, u3=None, X=None, eX=None):
         """Emitter (position in the table), point y [M,3] and the selection
-        margin flag for uniforms u0, u1, u2 [M]."""
-        x = np.asarray(u0) * self.W
-        j = np.searchsorted(self.cdf, x, side="right")
-        j = np.minimum(j, self.count - 1)
-        # the prefix sums of another summation order differ by ~count * U * W
-        tol = 4.0 * self.count * 2.0 ** -53 * self.W
-        lo = np.where(j > 0, self.cdf[np.maximum(j - 1, 0)], -np.inf)
-        amb = (np.abs(x - self.cdf[j]) <= tol) | (np.abs(x - lo) <= tol)
+        margin flag for uniforms u0, u1, u2 (u3) [M] at vertices X [M,3]
+        (cell mode; eX their error bounds)."""
+        if self.cell > 0:
+            j, amb = self._select_cells(np.asarray(u0), np.asarray(u3), np.atleast_2d(X),
+                                        np.zeros(len(u0)) if eX is None else np.asarray(eX))
+        else:
+            x = np.asarray(u0) * self.W
+            j = np.searchsorted(self.cdf, x, side="right")
+            j = np.minimum(j, self.count - 1)
+            # the prefix sums of another summation order differ by ~count * U * W
+            tol = 4.0 * self.count * 2.0 ** -53 * self.W
+            lo = np.where(j > 0, self.cdf[np.maximum(j - 1, 0)], -np.inf)
+            amb = (np.abs(x - self.cdf[j]) <= tol) | (np.abs(x - lo) <= tol)
         r = self.k * np.sqrt(u1)
         phi = 2.0 * np.pi * np.asarray(u2)
         a = (r * np.cos(phi) * self.su[j])[:, None]
         b = (r * np.sin(phi) * self.sv[j])[:, None]
         y = self.p[j] + a * self.tu[j] + b * self.tv[j]
         return j, y, amb
+
+    def _select_cells(self, u0, u3, X, eX):
+        I, S = self.importance(X)
+        cum = np.cumsum(I, axis=1)
+        x = u0 * S
+        c = np.minimum((cum <= x[:, None]).sum(axis=1), self.Wc.size - 1)
+        # I moves with X by about 2 |dX| / distance, and another summation
+        # order by a few roundings per cell
+        d2min = np.maximum(np.min(np.sum((X[:, None, :] - self.ctr[None]) ** 2, axis=2), axis=1), self.cell ** 2)
+        tol = S * (4.0 * eX / np.sqrt(d2min) + 8.0 * self.Wc.size * 2.0 ** -53) + 1e-300
+        rows = np.arange(X.shape[0])
+        lo = np.where(c > 0, cum[rows, np.maximum(c - 1, 0)], -np.inf)
+        amb = (np.abs(x - cum[rows, c]) <= tol) | (np.abs(x - lo) <= tol)
+        # the emitter within the cell
+        b, e = self.begin[c], self.end[c]
+        y = u3 * self.Wc[c]
+        j = np.empty(c.size, dtype=np.int64)
+        for m in range(c.size):
+            k = b[m] + np.searchsorted(self.cdf_in[b[m]:e[m]], y[m], side="right")
+            j[m] = min(k, e[m] - 1)
+        tin = 4.0 * (e - b) * 2.0 ** -53 * self.Wc[c]
+        lo_in = np.where(j > b, self.cdf_in[np.maximum(j - 1, 0)], -np.inf)
+        amb |= (np.abs(y - self.cdf_in[j]) <= tin) | (np.abs(y - lo_in) <= tin)
+        return j, amb
 
     def pdf(self, X, W, eX=None, ew=None):
         """Solid-angle density p_l of the light sampler for rays X [M,3] + d W
@@ -130,6 +207,9 @@ class Emitters:
         cross = valid & (t > 0.0) & (q2 <= k2)
         with np.errstate(divide="ignore", invalid="ignore"):
             terms = np.where(cross, self.rho[None] * t * t / np.where(valid, np.abs(den), 1.0), 0.0)
+        if self.cell > 0:
+            I, S = self.importance(X)
+            terms = terms * (I[:, self.cell_of] / S[:, None])
         # margins, as the tracer takes them
         oinf = np.abs(X).max(axis=1)[:, None]
         tabs = np.minimum(np.where(valid, np.abs(t), 0.0), 1e6)
@@ -211,8 +291,8 @@ def path_trace_nee(scene, cam, prm, em=None, pixels=None, samples=None):
             Xo = O[ps] + Dt[:, None] * W[ps]
             # ---- light sample (before Russian roulette)
             if em.count:
-                v0, v1, v2, _ = philox.uniforms(P_pix[ps], P_smp[ps], NEE_SEGMENT + k, prm.camera_id, prm.seed)
-                _, y, amb = em.sample(v0, v1, v2)
+                v0, v1, v2, v3 = philox.uniforms(P_pix[ps], P_smp[ps], NEE_SEGMENT + k, prm.camera_id, prm.seed)
+                _, y, amb = em.sample(v0, v1, v2, v3, Xo, eX)
                 dl = y - Xo
                 dist = np.linalg.norm(dl, axis=1)
                 Wl = dl / dist[:, None]

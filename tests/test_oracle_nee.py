@@ -6,6 +6,7 @@ plain path tracer's mean on a room, and equals it when no vertex is reached."""
 import math
 
 import numpy as np
+import pytest
 from scipy import integrate
 
 import scenegen as sg
@@ -37,9 +38,10 @@ def _sphere(n, rng):
     return d / np.linalg.norm(d, axis=1, keepdims=True)
 
 
-def test_light_pdf_integrates_to_one():
-    em = Emitters(Scene64(_panel_scene()), 0.1)
-    assert em.count == 4
+@pytest.mark.parametrize("cell", [0.0, 0.5])
+def test_light_pdf_integrates_to_one(cell):
+    em = Emitters(Scene64(_panel_scene()), 0.1, cell=cell)
+    assert em.count == 4 and (cell == 0 or em.Wc.size == 3)
     rng = np.random.default_rng(1)
     for X in ([0.0, 0.0, 0.0], [0.3, -0.2, 0.8], [0.0, 0.0, 1.5]):
         vals = []
@@ -52,17 +54,26 @@ def test_light_pdf_integrates_to_one():
         assert abs(v.mean() - 1.0) < 5 * se + 1e-3
 
 
-def test_light_samples_cover_the_emitters_solid_angle():
+@pytest.mark.parametrize("cell", [0.0, 0.5])
+def test_light_samples_cover_the_emitters_solid_angle(cell):
     sc = Scene64(_panel_scene())
-    em = Emitters(sc, 0.1)
+    em = Emitters(sc, 0.1, cell=cell)
     rng = np.random.default_rng(2)
     X = np.array([0.2, -0.1, 0.1])
     n = 400000
-    u0, u1, u2 = rng.random(n), rng.random(n), rng.random(n)
-    j, y, _ = em.sample(u0, u1, u2)
-    # selection frequencies are w_j / W
+    u0, u1, u2, u3 = rng.random(n), rng.random(n), rng.random(n), rng.random(n)
+    j, y, _ = em.sample(u0, u1, u2, u3, np.tile(X, (n, 1)))
+    # selection frequencies: w_j / W, or with cells I_c(X) / sum I times w_j / W_c
     freq = np.bincount(j, minlength=em.count) / n
-    p = em.w / em.W
+    if cell > 0:
+        I, S = em.importance(X)
+        p = I[0, em.cell_of] / S[0] * em.w / em.Wc[em.cell_of]
+        # hand check of the importance: W_c over the squared distance to the cell centre, floored at c^2
+        m = (np.floor(em.p[0] / cell) + 0.5) * cell
+        assert abs(I[0, em.cell_of[0]] - em.Wc[em.cell_of[0]] / max(np.sum((X - m) ** 2), cell * cell)) < 1e-15
+    else:
+        p = em.w / em.W
+    assert abs(p.sum() - 1.0) < 1e-12
     assert np.all(np.abs(freq - p) <= 5 * np.sqrt(p * (1 - p) / n))
     # points are uniform on the k_sigma ellipse: (u^2 + v^2) / k^2 ~ U(0, 1)
     dy = y - em.p[j]
@@ -115,7 +126,8 @@ def test_single_bounce_quadrature_with_mis():
     assert v.std() < 0.7 * vp.std()
 
 
-def test_mis_mean_equals_plain_mean_on_a_room():
+@pytest.mark.parametrize("cell", [0.0, 1.0])
+def test_mis_mean_equals_plain_mean_on_a_room(cell):
     scene = sg.room_scene(3000, (3.0, 2.5, 2.5), 3, seed=31, emissive_frac=0.05)
     sc = Scene64(scene)
     cam = sg.Camera((0.4, 0.4, 1.0), (1.6, 1.3, 2.4), (0.0, 0.0, 1.0), 80.0, 8, 6)
@@ -124,7 +136,8 @@ def test_mis_mean_equals_plain_mean_on_a_room():
     # pixels whose camera segment reflects
     pix = np.array([i for i, g in enumerate(segs) if g.hit and g.E <= prm.tau_E and g.flags == 0])[[0, 15, 30]]
     S = 800
-    a = path_trace_nee(sc, cam, Params(spp=S, max_depth=3, rr_start=2, seed=4), pixels=pix)
+    em = Emitters(sc, 0.1, cell=cell)
+    a = path_trace_nee(sc, cam, Params(spp=S, max_depth=3, rr_start=2, seed=4), em=em, pixels=pix)
     b = path_trace(sc, cam, Params(spp=S, max_depth=3, rr_start=2, seed=4), pixels=pix)
     for i in range(pix.size):
         va, vb = a["value"][i].sum(-1), b["value"][i].sum(-1)
