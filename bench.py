@@ -40,7 +40,8 @@ Further workloads print their own JSON line (not the default run):
                        at 512x384 (64 spp, depth 5), one bake iteration
                        (0-bounce render, PQ-L1 loss, radiance gradient, Adam)
                        per step.
-  --workload mis       emitter sampling combined with cosine sampling by
+  --workload mis       emitter sampling (selection by 1 m cells; --mis-cell 0
+                       selects by power) combined with cosine sampling by
                        multiple importance sampling on the default room:
                        time per 64-spp image and image error of it and of
                        the plain path tracer against a reference of 8x the
@@ -571,7 +572,7 @@ def bench_mis(torch, args):
     stream = torch.cuda.current_stream()
     bvh = BVH(gs)
     te0 = time.perf_counter()
-    em = Emitters(gs, params)
+    em = Emitters(gs, params, cell=args.mis_cell)
     table_ms = (time.perf_counter() - te0) * 1e3
     n_em, _ = em.info()
     _log(f"scene ready: {scene.n} surfels, {n_em} emitters, {cam.width}x{cam.height}, {spp} spp")
@@ -627,13 +628,16 @@ def bench_mis(torch, args):
         "value": round(value, 3), "unit": "Mrays/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_mis, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"path tracing with emitter sampling and MIS (power heuristic), {scene.n} surfels "
+        "config": {"workload": f"path tracing with emitter sampling and MIS (power heuristic; selection "
+                               + (f"by {args.mis_cell} m cells" if args.mis_cell > 0 else "by power")
+                               + f"), {scene.n} surfels "
                                f"({n_em} emitters) in " + ("three 8x6x3 m rooms joined by doorways, 120 boxes"
                                                            if args.mis_config == 4 else "an 8x6x3 m room with 40 boxes")
                                + f", {cam.width}x{cam.height}, "
                                f"{spp} spp, max depth {params.max_depth}, RR from {params.rr_start}; step = the "
                                f"path-tracing launch over all samples",
-                   "surfels": scene.n, "emitters": n_em, "width": cam.width, "height": cam.height, "spp": spp},
+                   "surfels": scene.n, "emitters": n_em, "width": cam.width, "height": cam.height, "spp": spp,
+                   "selection_cell": args.mis_cell},
         "roofline": _roofline(blended, segments, kms_mis),
         "detail": {"segments_per_step": segments, "paths_per_step": paths,
                    "light_pdf_note": "segments include one light segment per reflecting vertex whose sample "
@@ -782,6 +786,8 @@ def main():
     ap.add_argument("--spp", type=int, default=None, help="override the workload's 64 spp (diagnostics only)")
     ap.add_argument("--mis-config", type=int, default=3, choices=[3, 4],
                     help="scene of the mis workload: 3 = the default room, 4 = the three rooms (64 spp)")
+    ap.add_argument("--mis-cell", type=float, default=1.0,
+                    help="emitter selection of the mis workload: 0 = by power, a power of two = by cells of that size")
     ap.add_argument("--workload", default="room1m",
                     choices=["room1m", "rooms5m", "serve", "sb100k", "bake", "stage0", "edits", "mis"])
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",

@@ -308,9 +308,20 @@ size_t eag_emitters_workspace_bytes(int64_t n_surfels);
  * densities and a tree over the emitters. mem (256-B aligned, >=
  * eag_emitters_bytes) is referenced by the handle until
  * eag_emitters_destroy; ws only during the call. Synchronises `stream`.
- * The table is a copy: rebuild it after editing the scene. */
-eag_status eag_build_emitters(const eag_surfels* s, const eag_trace_params* p, void* mem, size_t mem_bytes,
-                              void* ws, size_t ws_bytes, void* stream, eag_emitters** out);
+ * The table is a copy: rebuild it after editing the scene.
+ * cell: 0 selects emitters by power alone, as above. A power of two in
+ * [2^-10, 2^10] (scene units) selects by cells instead. Emitters are grouped
+ * by the cube of that side holding their centre (floor of the float32 centre
+ * over cell, per axis), in the order (cell, surfel index). At a vertex X, a
+ * cell is chosen with probability I_c / sum I over the cells, where
+ * I_c = W_c / max(|X - m_c|^2, cell^2), W_c is the cell's summed w_j and m_c
+ * its centre; inversion on u0 over the cells in order picks it. An emitter
+ * of the cell is then chosen with probability w_j / W_c, by inversion on u3
+ * (the fourth word of the light sample's Philox counter). rho_j becomes
+ * (I_c / sum I) opacity (mean of r + e) / (pi k^2 W_c). Emitters near the
+ * vertex are drawn more often, and those in other rooms seldom. */
+eag_status eag_build_emitters(const eag_surfels* s, const eag_trace_params* p, float cell, void* mem,
+                              size_t mem_bytes, void* ws, size_t ws_bytes, void* stream, eag_emitters** out);
 /* count: emitters in the table; total_weight: W (0 when there are none). */
 eag_status eag_emitters_get_info(const eag_emitters* em, int64_t* count, double* total_weight);
 void eag_emitters_destroy(eag_emitters* em);

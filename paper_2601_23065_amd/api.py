@@ -280,9 +280,11 @@ def path_trace(bvh: BVH, scene: Scene, cam, params: Params, sample_begin: int = 
 class Emitters:
     """Emitter table of a Scene for emitter sampling with multiple importance
     sampling (built for params.tau_E and params.k_sigma); owns its device
-    memory. Rebuild it after editing the scene."""
+    memory. Rebuild it after editing the scene. cell: 0 selects emitters by
+    power, a power of two selects by cells of that size weighted by their
+    power over the squared distance to the vertex."""
 
-    def __init__(self, scene: Scene, params: Params, stream=None):
+    def __init__(self, scene: Scene, params: Params, cell: float = 0.0, stream=None):
         lib = L.load()
         self.scene = scene
         n = scene.n
@@ -293,7 +295,8 @@ class Emitters:
         wp, wb = _aligned(ws)
         sc = scene.c()
         p = params.c()
-        L.check(lib.eag_build_emitters(C.byref(sc), C.byref(p), mp, mb, wp, wb, _stream(stream), C.byref(h)))
+        L.check(lib.eag_build_emitters(C.byref(sc), C.byref(p), float(cell), mp, mb, wp, wb, _stream(stream),
+                                       C.byref(h)))
         self.h = h
 
     def info(self):

@@ -632,20 +632,25 @@ size_t eag_emitters_workspace_bytes(int64_t n) {
   }
 }
 
-eag_status eag_build_emitters(const eag_surfels* s, const eag_trace_params* p, void* mem, size_t mem_bytes, void* ws,
-                              size_t ws_bytes, void* stream, eag_emitters** out) {
+eag_status eag_build_emitters(const eag_surfels* s, const eag_trace_params* p, float cell, void* mem, size_t mem_bytes,
+                              void* ws, size_t ws_bytes, void* stream, eag_emitters** out) {
   return guarded([&] {
     validate_surfels(s);
     validate_params(p);
     if (!out) fail(EAG_ERR_INVALID_ARGUMENT, "out is null");
     if (!(p->tau_E >= 0.0f)) fail(EAG_ERR_INVALID_ARGUMENT, "emitter sampling needs tau_E >= 0");
     if (!(p->k_sigma <= 3.0f)) fail(EAG_ERR_INVALID_ARGUMENT, "emitter sampling needs k_sigma <= 3");
+    if (cell != 0.0f) {
+      int e = 0;
+      if (!(cell >= 0x1p-10f && cell <= 0x1p10f) || std::frexp(cell, &e) != 0.5f)
+        fail(EAG_ERR_INVALID_ARGUMENT, "cell must be 0 or a power of two in [2^-10, 2^10]");
+    }
     if (!mem || !ws) fail(EAG_ERR_INVALID_ARGUMENT, "mem and ws must be device buffers");
     if ((reinterpret_cast<uintptr_t>(mem) & 255) || (reinterpret_cast<uintptr_t>(ws) & 255))
       fail(EAG_ERR_INVALID_ARGUMENT, "mem and ws must be 256-byte aligned");
     eag_emitters* e = new eag_emitters();
     try {
-      build_emitters(s, p->tau_E, p->k_sigma, mem, mem_bytes, ws, ws_bytes, static_cast<hipStream_t>(stream), e);
+      build_emitters(s, p->tau_E, p->k_sigma, cell, mem, mem_bytes, ws, ws_bytes, static_cast<hipStream_t>(stream), e);
     } catch (...) {
       delete e;
       throw;

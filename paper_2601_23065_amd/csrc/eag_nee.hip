@@ -37,6 +37,7 @@
 #include <cmath>
 #include <cstring>
 
+#include <rocprim/device/device_radix_sort.hpp>
 #include <rocprim/device/device_scan.hpp>
 
 namespace eag {
@@ -56,8 +57,46 @@ __device__ __forceinline__ void add_fixed(int64_t* acc, float v) {
 // ---------------------------------------------------------------------------
 // Light sampling and its density
 // ---------------------------------------------------------------------------
+// Selection by cells: I_c(X) = W_c / max(|X - m_c|^2, c^2), evaluated as
+// written (no fused multiply-add), and summed over the cells in order.
+__device__ __forceinline__ double cell_importance(const EmitterDev& E, int32_t c, D3 X) {
+#pragma clang fp contract(off)
+  const double4 q = E.cells[c];
+  const double dx = X.x - q.x, dy = X.y - q.y, dz = X.z - q.z;
+  const double d2 = dx * dx + dy * dy + dz * dz;
+  return q.w / fmax(d2, E.cell * E.cell);
+}
+
+__device__ double cell_total(const EmitterDev& E, D3 X) {
+  double S = 0.0;
+  for (int32_t c = 0; c < E.n_cells; ++c) S += cell_importance(E, c, X);
+  return S;
+}
+
+// The emitter selected at X: the first cell whose running sum of I exceeds
+// u0 S (S = cell_total(X)), then the first emitter of the cell whose prefix
+// sum within the cell exceeds u3 W_c.
+__device__ int64_t select_emitter_cells(const EmitterDev& E, D3 X, double S, double u0, double u3) {
+  const double x = u0 * S;
+  double cum = 0.0;
+  int32_t c = 0;
+  for (; c < E.n_cells - 1; ++c) {
+    cum += cell_importance(E, c, X);
+    if (cum > x) break;
+  }
+  const double y = u3 * E.cells[c].w;
+  int64_t lo = E.begin[c], hi = E.begin[c + 1] - 1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (E.cdf_in[mid] > y) hi = mid;
+    else lo = mid + 1;
+  }
+  return lo;
+}
+
 // The term of one emitter ellipse in p_l (0 if the ray does not cross it at
-// d > 0), in double precision, with the tracer's acceptance test.
+// d > 0), in double precision, with the tracer's acceptance test; with
+// cells, before the division by S(X).
 __device__ __forceinline__ double pdf_term(const EmitterDev& E, uint32_t pos, D3 X, D3 W) {
   const EmitGeo* g = E.geo + pos;
   const D3 n = d3(g->n[0], g->n[1], g->n[2]);
@@ -70,14 +109,15 @@ __device__ __forceinline__ double pdf_term(const EmitterDev& E, uint32_t pos, D3
   const double u = dot(y, d3(g->tu[0], g->tu[1], g->tu[2])) / g->su;
   const double v = dot(y, d3(g->tv[0], g->tv[1], g->tv[2])) / g->sv;
   if (!(u * u + v * v <= E.k2)) return 0.0;
-  return g->rho * t * t / fabs(den);
+  const double term = g->rho * t * t / fabs(den);
+  return E.n_cells > 0 ? term * cell_importance(E, g->cell, X) : term;
 }
 
 // p_l(X, W): every emitter box the ray meets at t >= 0 is visited. The stack
 // lives in the lane's LDS column (lds, STACK_LDS entries) and spills to
 // private memory beyond; at most 3 * depth + 1 entries are ever held, a
 // bound the build checks against STACK_SIZE.
-__device__ double light_pdf(const EmitterDev& E, D3 X, D3 W, int* lds) {
+__device__ double light_pdf(const EmitterDev& E, D3 X, D3 W, int* lds, double S) {
   double sum = 0.0;
   if (E.n == 0) return sum;
   const V3 Of = v3((float)X.x, (float)X.y, (float)X.z);
@@ -110,7 +150,7 @@ __device__ double light_pdf(const EmitterDev& E, D3 X, D3 W, int* lds) {
     if (cr.z != NODE4_EMPTY && e2 < inf && st.sp < STACK_SIZE) st.push(cr.z);
     if (cr.w != NODE4_EMPTY && e3 < inf && st.sp < STACK_SIZE) st.push(cr.w);
   }
-  return sum;
+  return E.n_cells > 0 ? sum / S : sum;
 }
 
 // The emitter selected by u0: the first j whose inclusive prefix sum exceeds
@@ -155,6 +195,7 @@ struct MisPathSource {
   D3 X, Wb;         // the vertex and the cosine-sampled continuation
   double pb;        // cosine pdf of the direction of the segment in flight (or the continuation)
   double pbl;       // cosine pdf of the pending light segment's direction
+  double Sx;        // selection by cells: S at the vertex the segment in flight started from
   bool light;       // the segment in flight is a light segment
   bool cont;        // the continuation survived Russian roulette
 
@@ -191,7 +232,7 @@ struct MisPathSource {
       // the light pdf is needed only when the segment passes the emitter test
       light = false;
       if (hit && s.E > S.tau_E) {
-        const double pl = light_pdf(*E, s.O, s.W, lds_stack);
+        const double pl = light_pdf(*E, s.O, s.W, lds_stack, Sx);
         const double den = pbl * pbl + pl * pl;
         const float f = den > 0.0 ? (float)(pbl * pl / den) : 0.0f;
         add_fixed(acc + 0, (lf.x * f) * s.R0);
@@ -207,7 +248,7 @@ struct MisPathSource {
     if (s.E > S.tau_E) {
       double wgt = 1.0;
       if (depth >= 1 && E->n > 0) {
-        const double pl = light_pdf(*E, s.O, s.W, lds_stack);
+        const double pl = light_pdf(*E, s.O, s.W, lds_stack, Sx);
         const double den = pb * pb + pl * pl;
         wgt = den > 0.0 ? pb * pb / den : 1.0;
       }
@@ -225,7 +266,13 @@ struct MisPathSource {
     D3 Wl = d3(0.0, 0.0, 1.0);
     if (E->n > 0) {
       const uint4 wl = philox(make_uint4(pix, sample, NEE_SEGMENT + (uint32_t)depth, S.cam.id), S.k0, S.k1);
-      const int64_t j = select_emitter(*E, to_unit(wl.x));
+      int64_t j;
+      if (E->n_cells > 0) {
+        Sx = cell_total(*E, X);
+        j = select_emitter_cells(*E, X, Sx, to_unit(wl.x), to_unit(wl.w));
+      } else {
+        j = select_emitter(*E, to_unit(wl.x));
+      }
       const D3 y = emitter_point(*E, j, to_unit(wl.y), to_unit(wl.z));
       const D3 dl = y - X;
       Wl = (1.0 / sqrt(dot(dl, dl))) * dl;
@@ -274,7 +321,7 @@ k_path_trace_mis(TraceCtx tc, PtLaunch L, EmitterDev E, unsigned long long* work
   src.depth = 0;
   src.beta = src.lf = v3(0.f, 0.f, 0.f);
   src.X = src.Wb = d3(0.0, 0.0, 0.0);
-  src.pb = src.pbl = 0.0;
+  src.pb = src.pbl = src.Sx = 0.0;
   src.light = src.cont = false;
   run_segments<Q_ALL, false>(tc, src, work_counter, L.n_work, hitlist, counters);
 }
@@ -291,12 +338,8 @@ __global__ void k_emit_count(const uint32_t* flags, const uint32_t* scan, int64_
   *count = (unsigned long long)scan[n - 1] + flags[n - 1];
 }
 
-// Emitter off[i] takes surfel i's attributes (arrays of ne) and its weight.
-__global__ void k_emit_gather(eag_surfels s, const uint32_t* flags, const uint32_t* off, eag_surfels_out c,
-                              double* w) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= s.n || !flags[i]) return;
-  const int64_t n = s.n, ne = c.n, j = off[i];
+__device__ __forceinline__ void copy_surfel(const eag_surfels& s, int64_t i, const eag_surfels_out& c, int64_t j) {
+  const int64_t n = s.n, ne = c.n;
   for (int k = 0; k < 3; ++k) {
     c.pos[k * ne + j] = s.pos[k * n + i];
     c.albedo[k * ne + j] = s.albedo[k * n + i];
@@ -306,20 +349,88 @@ __global__ void k_emit_gather(eag_surfels s, const uint32_t* flags, const uint32
   for (int k = 0; k < 2; ++k) c.scale[k * ne + j] = s.scale[k * n + i];
   c.opacity[j] = s.opacity[i];
   c.emissive[j] = s.emissive[i];
-  const double rbar = ((double)s.radiance[i] + (double)s.radiance[n + i] + (double)s.radiance[2 * n + i]) / 3.0;
-  w[j] = (double)s.opacity[i] * (double)s.scale[i] * (double)s.scale[n + i] * (rbar + (double)s.emissive[i]);
 }
 
-__global__ void k_emit_rho(eag_surfels_out c, const double* cdf, double k, double* rho) {
+// Emitter off[i] takes surfel i's attributes (arrays of ne), in surfel order.
+__global__ void k_emit_gather(eag_surfels s, const uint32_t* flags, const uint32_t* off, eag_surfels_out c) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= s.n || !flags[i]) return;
+  copy_surfel(s, i, c, off[i]);
+}
+
+// The cell key of each gathered emitter: floor(p / c) per axis (exact: c is
+// a power of two), offset by 2^20 and packed 21 bits per axis, x first.
+__global__ void k_emit_keys(eag_surfels_out c, float inv_cell, uint64_t* keys, uint32_t* vals) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t ne = c.n;
+  if (j >= ne) return;
+  uint64_t key = 0;
+  for (int a = 0; a < 3; ++a) key = (key << 21) | (uint64_t)((int64_t)floorf(c.pos[a * ne + j] * inv_cell) + (1 << 20));
+  keys[j] = key;
+  vals[j] = (uint32_t)j;
+}
+
+// Final order: entry j takes gathered emitter order[j] (identity when null)
+// and its weight.
+__global__ void k_emit_permute(eag_surfels g, const uint32_t* order, eag_surfels_out c, double* w) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t ne = c.n;
+  if (j >= ne) return;
+  const int64_t i = order ? (int64_t)order[j] : j;
+  copy_surfel(g, i, c, j);
+  const double rbar = ((double)g.radiance[i] + (double)g.radiance[ne + i] + (double)g.radiance[2 * ne + i]) / 3.0;
+  w[j] = (double)g.opacity[i] * (double)g.scale[i] * (double)g.scale[ne + i] * (rbar + (double)g.emissive[i]);
+}
+
+// First entry of each cell (keys sorted).
+__global__ void k_cell_flags(const uint64_t* keys, int64_t ne, uint32_t* flags) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j < ne) flags[j] = (j == 0 || keys[j] != keys[j - 1]) ? 1u : 0u;
+}
+
+// cell_of holds the inclusive scan of the flags (cell index + 1).
+__global__ void k_cell_begin(const uint32_t* flags, const uint32_t* cell_of, int64_t ne, int32_t* begin,
+                             unsigned long long* n_cells) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j >= ne) return;
+  if (flags[j]) begin[cell_of[j] - 1] = (int32_t)j;
+  if (j == ne - 1) {
+    begin[cell_of[j]] = (int32_t)ne;
+    *n_cells = cell_of[j];
+  }
+}
+
+// One thread per cell: its prefix sums in order, its total, its centre.
+__global__ void k_cell_sums(eag_surfels_out c, const double* w, const int32_t* begin, int32_t n_cells, double cell,
+                            double* cdf_in, double4* cells) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= n_cells) return;
+  const int32_t b = begin[k], e = begin[k + 1];
+  double sum = 0.0;
+  for (int32_t j = b; j < e; ++j) {
+    sum += w[j];
+    cdf_in[j] = sum;
+  }
+  const float inv = (float)(1.0 / cell);
+  const int64_t ne = c.n;
+  double m[3];
+  for (int a = 0; a < 3; ++a) m[a] = ((double)floorf(c.pos[a * ne + b] * inv) + 0.5) * cell;
+  cells[k] = make_double4(m[0], m[1], m[2], sum);
+}
+
+// rho_j against the total weight, or (cells) against the weight of j's cell.
+__global__ void k_emit_rho(eag_surfels_out c, const double* cdf, const double* cdf_in, const int32_t* begin,
+                           const uint32_t* cell_of, double k, double* rho) {
   const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int64_t ne = c.n;
   if (j >= ne) return;
   const double rbar = ((double)c.radiance[j] + (double)c.radiance[ne + j] + (double)c.radiance[2 * ne + j]) / 3.0;
-  rho[j] = (double)c.opacity[j] * (rbar + (double)c.emissive[j]) / (M_PI * k * k * cdf[ne - 1]);
+  const double W = cell_of ? cdf_in[begin[cell_of[j]] - 1] : cdf[ne - 1];
+  rho[j] = (double)c.opacity[j] * (rbar + (double)c.emissive[j]) / (M_PI * k * k * W);
 }
 
 // Geometry of the emitter at leaf position pos, from its record.
-__global__ void k_emit_geo(const Record* recs, const double* rho, int64_t ne, EmitGeo* geo) {
+__global__ void k_emit_geo(const Record* recs, const double* rho, const uint32_t* cell_of, int64_t ne, EmitGeo* geo) {
   const int64_t pos = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (pos >= ne) return;
   const Record rec = load_record(recs, (uint32_t)pos);
@@ -332,7 +443,8 @@ __global__ void k_emit_geo(const Record* recs, const double* rho, int64_t ne, Em
   e.su = g.su;
   e.sv = g.sv;
   e.rho = rho[rec_index(rec)];
-  e.pad = 0.0;
+  e.cell = cell_of ? (int32_t)cell_of[rec_index(rec)] - 1 : 0;
+  e.pad = 0;
   geo[pos] = e;
 }
 
@@ -342,6 +454,9 @@ struct EmitWs {
   uint32_t* flags;
   uint32_t* off;
   unsigned long long* count;
+  float* stage;            // gathered emitter attributes, 17 floats each
+  uint64_t *keys, *keys_sorted;
+  uint32_t *vals, *order;
   void* scan_tmp;
   size_t scan_bytes;
   void* build;
@@ -350,14 +465,20 @@ struct EmitWs {
 };
 
 size_t emit_scan_bytes(int64_t n) {
-  size_t a = 0, b = 0;
+  size_t a = 0, b = 0, c = 0, d = 0;
   check_hip(rocprim::exclusive_scan(nullptr, a, (const uint32_t*)nullptr, (uint32_t*)nullptr, 0u, (size_t)n,
                                     rocprim::plus<uint32_t>(), (hipStream_t)0),
             "emitter scan size");
   check_hip(rocprim::inclusive_scan(nullptr, b, (const double*)nullptr, (double*)nullptr, (size_t)n,
                                     rocprim::plus<double>(), (hipStream_t)0),
             "emitter prefix size");
-  return std::max(a, b);
+  check_hip(rocprim::inclusive_scan(nullptr, c, (const uint32_t*)nullptr, (uint32_t*)nullptr, (size_t)n,
+                                    rocprim::plus<uint32_t>(), (hipStream_t)0),
+            "emitter cell scan size");
+  check_hip(rocprim::radix_sort_pairs(nullptr, d, (const uint64_t*)nullptr, (uint64_t*)nullptr,
+                                      (const uint32_t*)nullptr, (uint32_t*)nullptr, (size_t)n, 0, 63, (hipStream_t)0),
+            "emitter sort size");
+  return std::max(std::max(a, b), std::max(c, d));
 }
 
 EmitWs emit_ws(void* base, int64_t n) {
@@ -365,7 +486,12 @@ EmitWs emit_ws(void* base, int64_t n) {
   EmitWs w;
   w.flags = c.take<uint32_t>(n);
   w.off = c.take<uint32_t>(n);
-  w.count = c.take<unsigned long long>(1);
+  w.count = c.take<unsigned long long>(2);
+  w.stage = c.take<float>(17 * n);
+  w.keys = c.take<uint64_t>(n);
+  w.keys_sorted = c.take<uint64_t>(n);
+  w.vals = c.take<uint32_t>(n);
+  w.order = c.take<uint32_t>(n);
   w.scan_bytes = emit_scan_bytes(n);
   w.scan_tmp = c.take<char>(w.scan_bytes);
   w.build_bytes = build_ws_bytes(n);
@@ -378,6 +504,10 @@ struct EmitMem {
   float *pos, *rot, *scale, *opacity, *albedo, *radiance, *emissive;
   double *w, *cdf, *rho;
   EmitGeo* geo;
+  double* cdf_in;          // prefix sums within each cell
+  double4* cells;          // centre, total weight
+  int32_t* begin;          // first entry of each cell, then ne
+  uint32_t* cell_of;       // cell index + 1 of each entry
   void* bvh;
   size_t bvh_bytes;
   size_t bytes;
@@ -398,6 +528,10 @@ EmitMem emit_mem(void* base, int64_t n) {
   m.cdf = c.take<double>(n);
   m.rho = c.take<double>(n);
   m.geo = c.take<EmitGeo>(n);
+  m.cdf_in = c.take<double>(n);
+  m.cells = c.take<double4>(n);
+  m.begin = c.take<int32_t>(n + 1);
+  m.cell_of = c.take<uint32_t>(n);
   m.bvh_bytes = bvh_layout(nullptr, n).bytes;
   m.bvh = c.take<char>(m.bvh_bytes);
   m.bytes = c.bytes();
@@ -409,8 +543,8 @@ EmitMem emit_mem(void* base, int64_t n) {
 size_t emitters_mem_bytes(int64_t n) { return emit_mem(nullptr, n).bytes; }
 size_t emitters_ws_bytes(int64_t n) { return emit_ws(nullptr, n).bytes; }
 
-void build_emitters(const eag_surfels* s, float tau_E, float k_sigma, void* mem, size_t mem_bytes, void* ws,
-                    size_t ws_bytes, hipStream_t st, eag_emitters* out) {
+void build_emitters(const eag_surfels* s, float tau_E, float k_sigma, float cell, void* mem, size_t mem_bytes,
+                    void* ws, size_t ws_bytes, hipStream_t st, eag_emitters* out) {
   const int64_t n = s->n;
   const EmitMem m = emit_mem(mem, n);
   const EmitWs w = emit_ws(ws, n);
@@ -429,21 +563,60 @@ void build_emitters(const eag_surfels* s, float tau_E, float k_sigma, void* mem,
   out->n_src = n;
   out->tau_E = tau_E;
   out->k_sigma = k_sigma;
+  out->cell = cell;
   EmitterDev& E = out->dev;
   E.n = (int64_t)ne;
   E.k = (double)k_sigma;
   E.k2 = E.k * E.k;
+  E.cell = (double)cell;
   if (ne == 0) return;
 
+  // gathered in surfel order, then (cells) sorted by (cell, surfel): the
+  // radix sort is stable
+  const unsigned bne = blocks_for((int64_t)ne);
+  eag_surfels_out g;
+  g.n = (int64_t)ne;
+  g.pos = w.stage; g.rot = w.stage + 3 * ne; g.scale = w.stage + 7 * ne; g.opacity = w.stage + 9 * ne;
+  g.albedo = w.stage + 10 * ne; g.radiance = w.stage + 13 * ne; g.emissive = w.stage + 16 * ne;
+  hipLaunchKernelGGL(k_emit_gather, dim3(blocks_for(n)), dim3(256), 0, st, *s, w.flags, w.off, g);
+  const uint32_t* order = nullptr;
+  if (cell > 0.0f) {
+    hipLaunchKernelGGL(k_emit_keys, dim3(bne), dim3(256), 0, st, g, 1.0f / cell, w.keys, w.vals);
+    sb = w.scan_bytes;
+    check_hip(rocprim::radix_sort_pairs(w.scan_tmp, sb, w.keys, w.keys_sorted, w.vals, w.order, (size_t)ne, 0, 63,
+                                        st),
+              "emitter cell sort");
+    order = w.order;
+  }
+  eag_surfels gs;
+  gs.n = (int64_t)ne;
+  gs.pos = g.pos; gs.rot = g.rot; gs.scale = g.scale; gs.opacity = g.opacity;
+  gs.albedo = g.albedo; gs.radiance = g.radiance; gs.emissive = g.emissive;
   eag_surfels_out c;
   c.n = (int64_t)ne;
   c.pos = m.pos; c.rot = m.rot; c.scale = m.scale; c.opacity = m.opacity;
   c.albedo = m.albedo; c.radiance = m.radiance; c.emissive = m.emissive;
-  hipLaunchKernelGGL(k_emit_gather, dim3(blocks_for(n)), dim3(256), 0, st, *s, w.flags, w.off, c, m.w);
+  hipLaunchKernelGGL(k_emit_permute, dim3(bne), dim3(256), 0, st, gs, order, c, m.w);
   sb = w.scan_bytes;
   check_hip(rocprim::inclusive_scan(w.scan_tmp, sb, m.w, m.cdf, (size_t)ne, rocprim::plus<double>(), st),
             "emitter prefix sums");
-  hipLaunchKernelGGL(k_emit_rho, dim3(blocks_for((int64_t)ne)), dim3(256), 0, st, c, m.cdf, E.k, m.rho);
+  const uint32_t* cell_of = nullptr;
+  if (cell > 0.0f) {
+    hipLaunchKernelGGL(k_cell_flags, dim3(bne), dim3(256), 0, st, w.keys_sorted, (int64_t)ne, w.vals);
+    sb = w.scan_bytes;
+    check_hip(rocprim::inclusive_scan(w.scan_tmp, sb, w.vals, m.cell_of, (size_t)ne, rocprim::plus<uint32_t>(), st),
+              "emitter cell scan");
+    hipLaunchKernelGGL(k_cell_begin, dim3(bne), dim3(256), 0, st, w.vals, m.cell_of, (int64_t)ne, m.begin,
+                       w.count + 1);
+    unsigned long long nc = 0;
+    check_hip(hipMemcpyAsync(&nc, w.count + 1, sizeof(nc), hipMemcpyDeviceToHost, st), "cell count");
+    check_hip(hipStreamSynchronize(st), "cell count sync");
+    E.n_cells = (int32_t)nc;
+    hipLaunchKernelGGL(k_cell_sums, dim3(blocks_for((int64_t)nc)), dim3(256), 0, st, c, m.w, m.begin, E.n_cells,
+                       E.cell, m.cdf_in, m.cells);
+    cell_of = m.cell_of;
+  }
+  hipLaunchKernelGGL(k_emit_rho, dim3(bne), dim3(256), 0, st, c, m.cdf, m.cdf_in, m.begin, cell_of, E.k, m.rho);
   check_hip(hipGetLastError(), "emitter table kernels");
   check_hip(hipMemcpyAsync(&E.W, m.cdf + ne - 1, sizeof(double), hipMemcpyDeviceToHost, st), "emitter total");
 
@@ -478,7 +651,7 @@ void build_emitters(const eag_surfels* s, float tau_E, float k_sigma, void* mem,
     delete b;
     fail(EAG_ERR_INTERNAL, "emitter tree deeper than the density traversal's stack");
   }
-  hipLaunchKernelGGL(k_emit_geo, dim3(blocks_for((int64_t)ne)), dim3(256), 0, st, b->recs, m.rho, (int64_t)ne, m.geo);
+  hipLaunchKernelGGL(k_emit_geo, dim3(bne), dim3(256), 0, st, b->recs, m.rho, cell_of, (int64_t)ne, m.geo);
   check_hip(hipGetLastError(), "emitter geometry");
   check_hip(hipStreamSynchronize(st), "emitter table sync");
   out->bvh = b;
@@ -490,6 +663,9 @@ void build_emitters(const eag_surfels* s, float tau_E, float k_sigma, void* mem,
   E.pos = m.pos;
   E.rot = m.rot;
   E.scale = m.scale;
+  E.cdf_in = m.cdf_in;
+  E.cells = m.cells;
+  E.begin = m.begin;
 }
 
 void launch_path_trace_mis(const TraceCtx& tc, const PtLaunch& L, const EmitterDev& E,

@@ -188,7 +188,8 @@ void launch_adam(float* r, const float* g, float* m, float* v, int64_t count, co
 // precision, and rho, the area density of the point sampler on its ellipse.
 struct __align__(16) EmitGeo {
   double p[3], tu[3], tv[3], n[3];
-  double su, sv, rho, pad;
+  double su, sv, rho;
+  int32_t cell, pad;         // the emitter's cell (selection by cells)
 };
 struct EmitterDev {
   const Node4* nodes;        // 4-wide tree over the emitters
@@ -202,7 +203,11 @@ struct EmitterDev {
   double W;                  // total selection weight
   double k, k2;              // k_sigma and its square
   int32_t root;
-  int32_t pad;
+  int32_t n_cells;           // selection by cells: cells (0: selection by power)
+  double cell;               // cell size (0: selection by power)
+  const double* cdf_in;      // [n] prefix sums of the weights within each cell
+  const double4* cells;      // [n_cells] centre and total weight
+  const int32_t* begin;      // [n_cells + 1] first entry of each cell, then n
 };
 size_t emitters_mem_bytes(int64_t n);
 size_t emitters_ws_bytes(int64_t n);
@@ -224,9 +229,10 @@ struct eag_emitters {
   eag_bvh* bvh;              // tree over the emitters (null when there are none)
   int64_t n_src;             // surfels of the scene it was built from
   float tau_E, k_sigma;      // the parameters it was built for
+  float cell;                // cell size of the selection (0: by power)
 };
 
 namespace eag {
-void build_emitters(const eag_surfels* s, float tau_E, float k_sigma, void* mem, size_t mem_bytes, void* ws,
-                    size_t ws_bytes, hipStream_t st, eag_emitters* out);
+void build_emitters(const eag_surfels* s, float tau_E, float k_sigma, float cell, void* mem, size_t mem_bytes,
+                    void* ws, size_t ws_bytes, hipStream_t st, eag_emitters* out);
 }  // namespace eag

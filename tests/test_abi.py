@@ -135,15 +135,19 @@ def test_host_validation_of_the_emitter_sampling_calls(lib):
     out = C.c_void_p()
     assert lib.eag_emitters_bytes(0) == 0 and lib.eag_emitters_bytes(1000) > 1000 * 17 * 4
     p.tau_E = -0.5
-    assert lib.eag_build_emitters(C.byref(s), C.byref(p), fake, 1 << 20, fake, 1 << 20, None, C.byref(out)) == -1
+    assert lib.eag_build_emitters(C.byref(s), C.byref(p), 0.0, fake, 1 << 20, fake, 1 << 20, None, C.byref(out)) == -1
     assert b"tau_E" in lib.eag_last_error()
     lib.eag_default_params(C.byref(p))
     p.k_sigma = 4.0
-    assert lib.eag_build_emitters(C.byref(s), C.byref(p), fake, 1 << 20, fake, 1 << 20, None, C.byref(out)) == -1
+    assert lib.eag_build_emitters(C.byref(s), C.byref(p), 0.0, fake, 1 << 20, fake, 1 << 20, None, C.byref(out)) == -1
     assert b"k_sigma" in lib.eag_last_error()
     lib.eag_default_params(C.byref(p))
+    for bad in (0.3, -1.0, 4096.0):
+        assert lib.eag_build_emitters(C.byref(s), C.byref(p), bad, fake, 1 << 20, fake, 1 << 20, None,
+                                      C.byref(out)) == -1
+        assert b"power of two" in lib.eag_last_error()
     odd = C.c_void_p(0x1010)
-    assert lib.eag_build_emitters(C.byref(s), C.byref(p), odd, 1 << 20, fake, 1 << 20, None, C.byref(out)) == -1
+    assert lib.eag_build_emitters(C.byref(s), C.byref(p), 0.5, odd, 1 << 20, fake, 1 << 20, None, C.byref(out)) == -1
     assert b"aligned" in lib.eag_last_error()
     assert lib.eag_emitters_get_info(None, None, None) == -1
     assert lib.eag_path_trace_mis(None, C.byref(s), None, None, C.byref(p), 0, 1, None, None, None, 0, None) == -1

@@ -79,6 +79,30 @@ def test_path_trace_mis_jittered_per_sample():
     assert ok.mean() > 0.4 and err.max() <= 1e-4
 
 
+@pytest.mark.parametrize("cell", [1.0, 0.25])
+def test_path_trace_mis_cells_per_sample(cell):
+    """Selection by cells (weighted by power over the squared distance to the
+    vertex): every path against the oracle with the same cells."""
+    from paper_2601_23065_amd.api import BVH, Emitters, Params, path_trace_mis
+    scene, cam = _small_room()
+    p = Params(spp=3, max_depth=5, rr_start=3, camera_id=4, seed=21)
+    gs = gpu_scene(scene)
+    bvh = BVH(gs)
+    em = Emitters(gs, p, cell=cell)
+    sc = Scene64(scene)
+    ref_em = OEmitters(sc, p.tau_E, cell=cell)
+    n, W = em.info()
+    assert n == ref_em.count and abs(W - ref_em.W) <= 1e-12 * ref_em.W
+    got = _per_sample(lambda s: path_trace_mis(bvh, gs, em, cam, p, sample_begin=s, sample_count=1), range(p.spp))
+    ref = path_trace_nee(sc, cam, oracle_params(p), em=ref_em)
+    ok = ref["flags"] == 0
+    err = rel_err(got, ref["value"], np.broadcast_to(ok[..., None], got.shape))
+    print(f"cell {cell} ({ref_em.Wc.size} cells): paths={ok.size} unflagged={ok.mean():.3f} err={err.max():.2e} "
+          f"nonzero={np.mean(ref['value'].sum(-1) > 0):.3f}")
+    assert ok.mean() > 0.4 and np.mean(ref["value"].sum(-1) > 0) > 0.5
+    assert err.max() <= 1e-4
+
+
 def test_camera_segments_only_equal_plain():
     """max_depth 0: no vertex, no light sample; bit-identical to path_trace."""
     from paper_2601_23065_amd.api import BVH, Emitters, Params, path_trace, path_trace_mis
