@@ -319,7 +319,9 @@ size_t eag_emitters_workspace_bytes(int64_t n_surfels);
  * of the cell is then chosen with probability w_j / W_c, by inversion on u3
  * (the fourth word of the light sample's Philox counter). rho_j becomes
  * (I_c / sum I) opacity (mean of r + e) / (pi k^2 W_c). Emitters near the
- * vertex are drawn more often, and those in other rooms seldom. */
+ * vertex are drawn more often, and those in other rooms seldom. Centres must
+ * satisfy |coordinate| / cell < 2^20 (cell keys hold 21 bits per axis); the
+ * selection at each vertex loops over all cells. */
 eag_status eag_build_emitters(const eag_surfels* s, const eag_trace_params* p, float cell, void* mem,
                               size_t mem_bytes, void* ws, size_t ws_bytes, void* stream, eag_emitters** out);
 /* count: emitters in the table; total_weight: W (0 when there are none). */
