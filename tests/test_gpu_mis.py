@@ -143,9 +143,10 @@ def test_same_mean_lower_variance_than_plain():
     assert mis.std(axis=0).mean() < 0.7 * plain.std(axis=0).mean()
 
 
-def test_single_emitter_over_a_receiver_per_sample():
-    """A one-emitter table (its tree is a single leaf), depth 1: every path
-    against the oracle."""
+@pytest.mark.parametrize("cell", [0.0, 1.0])
+def test_single_emitter_over_a_receiver_per_sample(cell):
+    """A one-emitter table (its tree is a single leaf; with cells, one cell),
+    depth 1: every path against the oracle."""
     from paper_2601_23065_amd.api import BVH, Emitters, Params, path_trace_mis
     from tests.test_oracle_render import _emitter_over_receiver
     scene = _emitter_over_receiver()
@@ -153,10 +154,11 @@ def test_single_emitter_over_a_receiver_per_sample():
     p = Params(spp=64, max_depth=1, rr_start=0)
     gs = gpu_scene(scene)
     bvh = BVH(gs)
-    em = Emitters(gs, p)
+    em = Emitters(gs, p, cell=cell)
     assert em.info()[0] == 1
     got = _per_sample(lambda s: path_trace_mis(bvh, gs, em, cam, p, sample_begin=s, sample_count=1), range(p.spp))
-    ref = path_trace_nee(Scene64(scene), cam, oracle_params(p))
+    sc = Scene64(scene)
+    ref = path_trace_nee(sc, cam, oracle_params(p), em=OEmitters(sc, p.tau_E, cell=cell))
     ok = ref["flags"] == 0
     err = rel_err(got, ref["value"], np.broadcast_to(ok[..., None], got.shape))
     print(f"unflagged={ok.mean():.3f} err={err.max():.2e} nonzero={np.mean(ref['value'].sum(-1) > 0):.3f}")
@@ -164,7 +166,8 @@ def test_single_emitter_over_a_receiver_per_sample():
     assert err.max() <= 1e-4
 
 
-def test_no_emitters():
+@pytest.mark.parametrize("cell", [0.0, 1.0])
+def test_no_emitters(cell):
     """A threshold above every e: an empty table, and the plain path
     tracer's image (black: no segment passes the emitter test either)."""
     from paper_2601_23065_amd.api import BVH, Emitters, Params, path_trace, path_trace_mis
@@ -172,7 +175,7 @@ def test_no_emitters():
     p = Params(spp=2, max_depth=3, rr_start=2, tau_E=1.5)
     gs = gpu_scene(scene)
     bvh = BVH(gs)
-    em = Emitters(gs, p)
+    em = Emitters(gs, p, cell=cell)
     assert em.info() == (0, 0.0)
     a = path_trace_mis(bvh, gs, em, cam, p)
     assert torch.equal(a, path_trace(bvh, gs, cam, p)) and int(a.abs().sum()) == 0
