@@ -97,7 +97,9 @@ __device__ int64_t select_emitter_cells(const EmitterDev& E, D3 X, double S, dou
 // The term of one emitter ellipse in p_l (0 if the ray does not cross it at
 // d > 0), in double precision, with the tracer's acceptance test; with
 // cells, before the division by S(X).
-__device__ __forceinline__ double pdf_term(const EmitterDev& E, uint32_t pos, D3 X, D3 W) {
+// lc, li: the last cell whose I_c(X) was evaluated, and that value (leaves
+// of one cell tend to come in a row).
+__device__ __forceinline__ double pdf_term(const EmitterDev& E, uint32_t pos, D3 X, D3 W, int32_t& lc, double& li) {
   const EmitGeo* g = E.geo + pos;
   const D3 n = d3(g->n[0], g->n[1], g->n[2]);
   const double den = dot(W, n);
@@ -110,7 +112,12 @@ __device__ __forceinline__ double pdf_term(const EmitterDev& E, uint32_t pos, D3
   const double v = dot(y, d3(g->tv[0], g->tv[1], g->tv[2])) / g->sv;
   if (!(u * u + v * v <= E.k2)) return 0.0;
   const double term = g->rho * t * t / fabs(den);
-  return E.n_cells > 0 ? term * cell_importance(E, g->cell, X) : term;
+  if (E.n_cells == 0) return term;
+  if (g->cell != lc) {
+    lc = g->cell;
+    li = cell_importance(E, lc, X);
+  }
+  return term * li;
 }
 
 // p_l(X, W): every emitter box the ray meets at t >= 0 is visited. The stack
@@ -132,10 +139,12 @@ __device__ double light_pdf(const EmitterDev& E, D3 X, D3 W, int* lds, double S)
   st.ovf = ovf;
   st.sp = 0;
   st.push(E.root);
+  int32_t lc = -1;
+  double li = 0.0;
   while (st.sp > 0) {
     const int ref = st.pop();
     if (ref < 0) {
-      sum += pdf_term(E, (uint32_t)~ref, X, W);
+      sum += pdf_term(E, (uint32_t)~ref, X, W, lc, li);
       continue;
     }
     const Node4* nd = E.nodes + ref;
