@@ -324,8 +324,10 @@ size_t eag_emitters_workspace_bytes(int64_t n_surfels);
  * selection at each vertex loops over all cells. */
 eag_status eag_build_emitters(const eag_surfels* s, const eag_trace_params* p, float cell, void* mem,
                               size_t mem_bytes, void* ws, size_t ws_bytes, void* stream, eag_emitters** out);
-/* count: emitters in the table; total_weight: W (0 when there are none). */
-eag_status eag_emitters_get_info(const eag_emitters* em, int64_t* count, double* total_weight);
+/* count: emitters in the table; total_weight: W (0 when there are none);
+ * n_cells: cells of the selection by cells (0 for selection by power). Each
+ * output is nullable. */
+eag_status eag_emitters_get_info(const eag_emitters* em, int64_t* count, double* total_weight, int32_t* n_cells);
 void eag_emitters_destroy(eag_emitters* em);
 /* As eag_path_trace (same accumulator, workspace and sample ranges) with the
  * estimator above. em must come from the same scene (same surfel count) and

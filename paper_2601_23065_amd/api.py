@@ -303,8 +303,14 @@ class Emitters:
         """(number of emitters, total selection weight W)."""
         n = C.c_int64()
         w = C.c_double()
-        L.check(L.load().eag_emitters_get_info(self.h, C.byref(n), C.byref(w)))
+        L.check(L.load().eag_emitters_get_info(self.h, C.byref(n), C.byref(w), None))
         return int(n.value), float(w.value)
+
+    def cells(self):
+        """Cells of the selection by cells (0 for selection by power)."""
+        c = C.c_int32()
+        L.check(L.load().eag_emitters_get_info(self.h, None, None, C.byref(c)))
+        return int(c.value)
 
     def __del__(self):
         try:

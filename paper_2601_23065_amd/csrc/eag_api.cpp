@@ -659,11 +659,12 @@ eag_status eag_build_emitters(const eag_surfels* s, const eag_trace_params* p, f
   });
 }
 
-eag_status eag_emitters_get_info(const eag_emitters* em, int64_t* count, double* total_weight) {
+eag_status eag_emitters_get_info(const eag_emitters* em, int64_t* count, double* total_weight, int32_t* n_cells) {
   return guarded([&] {
     if (!em) fail(EAG_ERR_INVALID_ARGUMENT, "emitter table is null");
     if (count) *count = em->dev.n;
     if (total_weight) *total_weight = em->dev.W;
+    if (n_cells) *n_cells = em->dev.n_cells;
   });
 }
 

@@ -149,6 +149,6 @@ def test_host_validation_of_the_emitter_sampling_calls(lib):
     odd = C.c_void_p(0x1010)
     assert lib.eag_build_emitters(C.byref(s), C.byref(p), 0.5, odd, 1 << 20, fake, 1 << 20, None, C.byref(out)) == -1
     assert b"aligned" in lib.eag_last_error()
-    assert lib.eag_emitters_get_info(None, None, None) == -1
+    assert lib.eag_emitters_get_info(None, None, None, None) == -1
     assert lib.eag_path_trace_mis(None, C.byref(s), None, None, C.byref(p), 0, 1, None, None, None, 0, None) == -1
     lib.eag_emitters_destroy(None)

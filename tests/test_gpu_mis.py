@@ -93,6 +93,7 @@ def test_path_trace_mis_cells_per_sample(cell):
     ref_em = OEmitters(sc, p.tau_E, cell=cell)
     n, W = em.info()
     assert n == ref_em.count and abs(W - ref_em.W) <= 1e-12 * ref_em.W
+    assert em.cells() == ref_em.Wc.size
     got = _per_sample(lambda s: path_trace_mis(bvh, gs, em, cam, p, sample_begin=s, sample_count=1), range(p.spp))
     ref = path_trace_nee(sc, cam, oracle_params(p), em=ref_em)
     ok = ref["flags"] == 0
