@@ -6,10 +6,15 @@
 //   emitters   surfels with e > tau_E and opacity > 0 (a segment passes the
 //              emitter test only if it blends one of them: its E is a sum of
 //              the hits' e with weights adding up to at most one);
-//   selection  emitter j with probability w_j / W, w_j = sigma s_u s_v
-//              (mean(r) + e), by inversion of the inclusive prefix sums;
+//   selection  by power: emitter j with probability w_j / W, w_j = sigma
+//              s_u s_v (mean(r) + e), by inversion of the inclusive prefix
+//              sums; or by cells: the emitters grouped by the cube of side c
+//              (a power of two) holding their centre, a cell chosen at the
+//              vertex X with probability I_c / sum I, I_c = W_c /
+//              max(|X - m_c|^2, c^2), then an emitter of it by power (u3);
 //   point      uniform on the j's k_sigma ellipse (area density rho_j =
-//              sigma (mean(r) + e) / (pi k^2 W));
+//              sigma (mean(r) + e) / (pi k^2 W), times I_c / sum I with W_c
+//              in place of W for cells);
 //   light pdf  p_l(X, w) = sum over the emitter ellipses the ray X + d w
 //              crosses at d > 0 of rho_j d^2 / |w . n_j|, evaluated by a
 //              traversal of a 4-wide tree over the emitters alone;
@@ -26,9 +31,12 @@
 // cosine-sampled continuation (if Russian roulette keeps the path).
 //
 // Table build: per-surfel flags, an exclusive scan and a compaction give the
-// emitters in ascending surfel order; their attributes are gathered into
-// arrays of their own, the weights' inclusive scan gives the prefix sums, and
-// the ordinary builder makes the tree over the compacted emitters.
+// emitters in ascending surfel order; with cells, a stable radix sort by cell
+// key reorders them to (cell, surfel) order, flags at key changes and their
+// scan number the cells, and one thread per cell sums its weights in order.
+// The attributes are gathered into arrays of their own, the weights'
+// inclusive scan gives the prefix sums, and the ordinary builder makes the
+// tree over the compacted emitters.
 #include "eag_device.h"
 #include "eag_internal.h"
 #include "eag_render.h"
