@@ -561,7 +561,8 @@ def bench_mis(torch, args):
     against a converged reference at equal spp and at equal time (one JSON
     line)."""
     import scenegen as sg
-    from paper_2601_23065_amd.api import BVH, Emitters, Params, Scene, path_trace, path_trace_mis, path_trace_workspace
+    from paper_2601_23065_amd.api import (BVH, Emitters, Params, Scene, path_trace, path_trace_mis,
+                                          path_trace_mis_workspace, path_trace_workspace)
 
     scene, cams, cfg = sg.config(args.mis_config, n_override=args.surfels)
     cam = cams[0]
@@ -569,6 +570,7 @@ def bench_mis(torch, args):
     params = Params(spp=spp, max_depth=cfg["max_depth"], rr_start=cfg["rr_start"], seed=0, camera_id=0)
     gs = Scene(scene.arrays())
     ws = path_trace_workspace(gs)
+    ws_mis = path_trace_mis_workspace(gs, cam, params)
     stream = torch.cuda.current_stream()
     bvh = BVH(gs)
     te0 = time.perf_counter()
@@ -583,7 +585,7 @@ def bench_mis(torch, args):
         return acc.double() / (2.0 ** 32 * count)
 
     def mis(s0, count, c=None):
-        return path_trace_mis(bvh, gs, em, cam, params, s0, count, counters=c, ws=ws)
+        return path_trace_mis(bvh, gs, em, cam, params, s0, count, counters=c, ws=ws_mis)
 
     def plain(s0, count, c=None):
         return path_trace(bvh, gs, cam, params, s0, count, counters=c, ws=ws)

@@ -329,10 +329,16 @@ eag_status eag_build_emitters(const eag_surfels* s, const eag_trace_params* p, f
  * output is nullable. */
 eag_status eag_emitters_get_info(const eag_emitters* em, int64_t* count, double* total_weight, int32_t* n_cells);
 void eag_emitters_destroy(eag_emitters* em);
-/* As eag_path_trace (same accumulator, workspace and sample ranges) with the
- * estimator above. em must come from the same scene (same surfel count) and
- * the same tau_E and k_sigma as p; EAG_ADDITIVE_EMISSION is rejected. A table
- * without emitters gives eag_path_trace's values. */
+/* Workspace of eag_path_trace_mis: eag_path_trace's, plus a queue for the
+ * contributions that wait for their light pdf (96 B per entry, W H (max_depth
+ * + 1) entries per 4 samples: the calls launch 4 samples at a time). 0 for
+ * invalid arguments. */
+size_t eag_path_trace_mis_workspace_bytes(int64_t n_surfels, const eag_camera* cam, const eag_trace_params* p);
+/* As eag_path_trace (same accumulator and sample ranges) with the estimator
+ * above; ws: eag_path_trace_mis_workspace_bytes. em must come from the same
+ * scene (same surfel count) and the same tau_E and k_sigma as p;
+ * EAG_ADDITIVE_EMISSION is rejected. A table without emitters gives
+ * eag_path_trace's values. */
 eag_status eag_path_trace_mis(const eag_bvh* bvh, const eag_surfels* s, const eag_emitters* em,
                               const eag_camera* cam, const eag_trace_params* p, uint32_t sample_begin,
                               uint32_t sample_count, int64_t* accum, uint64_t* counters, void* ws,

@@ -111,6 +111,7 @@ SIGNATURES = {
                                      P(vp)]),
     "eag_emitters_get_info": (C.c_int, [vp, P(C.c_int64), P(C.c_double), P(C.c_int32)]),
     "eag_emitters_destroy": (None, [vp]),
+    "eag_path_trace_mis_workspace_bytes": (C.c_size_t, [C.c_int64, P(Camera), P(TraceParams)]),
     "eag_path_trace_mis": (C.c_int, [vp, P(Surfels), vp, P(Camera), P(TraceParams), C.c_uint32, C.c_uint32, vp, vp,
                                      vp, C.c_size_t, vp]),
     "eag_apply_edit": (C.c_int, [P(Edit), P(SurfelAttrs), vp]),

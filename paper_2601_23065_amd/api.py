@@ -324,21 +324,27 @@ class Emitters:
 def path_trace_mis(bvh: BVH, scene: Scene, emitters: Emitters, cam, params: Params, sample_begin: int = 0,
                    sample_count: int | None = None, accum=None, counters=None, stream=None, ws=None):
     """path_trace with emitter sampling combined by multiple importance
-    sampling; same accumulator, sample ranges and workspace."""
+    sampling; same accumulator and sample ranges (ws: path_trace_mis_workspace)."""
     lib = L.load()
     dev = scene.device
     sample_count = params.spp if sample_count is None else sample_count
     if accum is None:
         accum = torch.zeros((cam.height, cam.width, 3), dtype=torch.int64, device=dev)
-    if ws is None:
-        ws = _bytes(lib.eag_path_trace_workspace_bytes(scene.n), dev)
-    wp, wb = _aligned(ws)
     c = camera_struct(cam)
     p = params.c()
+    if ws is None:
+        ws = _bytes(lib.eag_path_trace_mis_workspace_bytes(scene.n, C.byref(c), C.byref(p)), dev)
+    wp, wb = _aligned(ws)
     sc = scene.c()
     L.check(lib.eag_path_trace_mis(bvh.h, C.byref(sc), emitters.h, C.byref(c), C.byref(p), sample_begin,
                                    sample_count, _ptr(accum), _ptr(counters), wp, wb, _stream(stream)))
     return accum
+
+
+def path_trace_mis_workspace(scene: Scene, cam, params: Params):
+    c = camera_struct(cam)
+    p = params.c()
+    return _bytes(L.load().eag_path_trace_mis_workspace_bytes(scene.n, C.byref(c), C.byref(p)), scene.device)
 
 
 def path_trace_workspace(scene: Scene):

@@ -674,6 +674,17 @@ void eag_emitters_destroy(eag_emitters* em) {
   delete em;
 }
 
+size_t eag_path_trace_mis_workspace_bytes(int64_t n, const eag_camera* cam, const eag_trace_params* p) {
+  if (n < 1 || !cam || !p || cam->width < 1 || cam->height < 1 || p->max_depth < 0) return 0;
+  try {
+    const int64_t entries = pdf_queue_entries((int64_t)cam->width * cam->height, p->max_depth, MIS_CHUNK_SPP);
+    return render_ws(nullptr, n, 0, 0, false, runner_lanes()).bytes + align_up(pdf_queue_bytes(entries));
+  } catch (const Error& e) {
+    set_error(e.status, e.msg);
+    return 0;
+  }
+}
+
 eag_status eag_path_trace_mis(const eag_bvh* b, const eag_surfels* s, const eag_emitters* em, const eag_camera* cam,
                               const eag_trace_params* p, uint32_t sample_begin, uint32_t sample_count,
                               int64_t* accum, uint64_t* counters, void* ws, size_t ws_bytes, void* stream) {
@@ -688,15 +699,23 @@ eag_status eag_path_trace_mis(const eag_bvh* b, const eag_surfels* s, const eag_
       fail(EAG_ERR_INVALID_ARGUMENT, "emitter sampling is defined for the emitter-terminated path tracer");
     if ((uint64_t)sample_begin + sample_count > 0xffffffffull) fail(EAG_ERR_INVALID_ARGUMENT, "sample range overflow");
     const RenderWs w = render_ws(ws, b->n, 0, 0, false, runner_lanes());
-    if (!ws || ws_bytes < w.bytes) fail(EAG_ERR_WORKSPACE_TOO_SMALL, "path-trace workspace too small");
+    const int64_t entries = pdf_queue_entries((int64_t)cam->width * cam->height, p->max_depth, MIS_CHUNK_SPP);
+    if (!ws || ws_bytes < w.bytes + align_up(pdf_queue_bytes(entries)))
+      fail(EAG_ERR_WORKSPACE_TOO_SMALL, "path-trace workspace too small (eag_path_trace_mis_workspace_bytes)");
+    void* queue = static_cast<char*>(ws) + w.bytes;
     const CamDev cd = make_cam(*cam, p->camera_id);
     const TraceSetup ts = trace_setup(b, p, std::fmax(scene_t_max(b), camera_t_max(b, *cam)));
     if (sample_count == 0) return;
     hipStream_t st = static_cast<hipStream_t>(stream);
     pack_attrs(s, b, w.attrs, st);
     const TraceCtx tc = make_ctx(b, w.attrs, p, ts);
-    const PtLaunch L = single_request_launch(cd, *cam, p, w.attrs, accum, sample_begin, sample_count);
-    launch_path_trace_mis(tc, L, em->dev, w.work, reinterpret_cast<unsigned long long*>(counters), w.hitlist, st);
+    // launches of at most MIS_CHUNK_SPP samples, each followed by its light pdfs
+    for (uint32_t c0 = 0; c0 < sample_count; c0 += MIS_CHUNK_SPP) {
+      const uint32_t cnt = std::min<uint32_t>(MIS_CHUNK_SPP, sample_count - c0);
+      const PtLaunch L = single_request_launch(cd, *cam, p, w.attrs, accum, sample_begin + c0, cnt);
+      launch_path_trace_mis(tc, L, em->dev, queue, entries, w.work, reinterpret_cast<unsigned long long*>(counters),
+                            w.hitlist, st);
+    }
   });
 }
 

@@ -199,11 +199,37 @@ __device__ __forceinline__ D3 emitter_point(const EmitterDev& E, int64_t j, doub
 }
 
 // ---------------------------------------------------------------------------
+// Contributions that wait for their light pdf
+// ---------------------------------------------------------------------------
+// The tree walk of the light pdf would run inside finish() for the few lanes
+// that end a segment together, with the rest of the wave waiting. Instead the
+// path kernel queues each contribution that needs it, and a second kernel
+// walks the tree once per entry with every lane busy. A path queues at most
+// one entry per reflecting vertex and one at its end, so a launch of P paths
+// at max depth D needs at most P (D + 1) entries; the host launches sample
+// chunks that fit. Integer accumulation makes the image independent of the
+// order in which contributions arrive.
+struct __align__(16) PdfEntry {
+  double o[3], w[3];   // the segment's ray
+  double pbx;          // cosine pdf of its direction at o
+  double S;            // selection by cells: S at o
+  float a[3], b[3];    // light segment: beta at o and R; cosine-sampled: beta R in a
+  uint32_t pix;
+  uint32_t light;
+};
+struct PdfQueue {
+  PdfEntry* e;
+  unsigned long long* count;
+  int64_t cap;
+};
+
+// ---------------------------------------------------------------------------
 // One lane's path with light segments
 // ---------------------------------------------------------------------------
 struct MisPathSource {
   const PtLaunch* L;
   const EmitterDev* E;
+  const PdfQueue* Q;
   int* lds_stack;   // the lane's traversal-stack column, free while finishing
   uint32_t pix, sample;
   int depth;
@@ -240,6 +266,29 @@ struct MisPathSource {
 
   __device__ __forceinline__ void operator()(uint32_t, double, double, double, double, D3, D3) const {}
 
+  // Queue a contribution; the lanes that call this together claim their
+  // slots with one atomic.
+  __device__ __forceinline__ void defer(bool is_light, D3 o, D3 w, double pbx, V3 a, V3 b) {
+    const int lane = (int)(threadIdx.x & 63);
+    const uint64_t m = __ballot(true);
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    unsigned long long base = 0;
+    if (lane == leader) base = atomicAdd(Q->count, (unsigned long long)__popcll(m));
+    base = __shfl(base, leader);
+    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    const unsigned long long slot = base + (unsigned long long)__popcll(m & below);
+    if (slot >= (unsigned long long)Q->cap) return;   // the host sizes chunks so that this never happens
+    PdfEntry& e = Q->e[slot];
+    e.o[0] = o.x; e.o[1] = o.y; e.o[2] = o.z;
+    e.w[0] = w.x; e.w[1] = w.y; e.w[2] = w.z;
+    e.pbx = pbx;
+    e.S = Sx;
+    e.a[0] = a.x; e.a[1] = a.y; e.a[2] = a.z;
+    e.b[0] = b.x; e.b[1] = b.y; e.b[2] = b.z;
+    e.pix = pix;
+    e.light = is_light ? 1u : 0u;
+  }
+
   __device__ __forceinline__ bool finish(const Seg<false>& s, D3& O, D3& W) {
     const PtSlot& S = L->s[0];
     int64_t* acc = S.accum + (int64_t)pix * 3;
@@ -248,14 +297,7 @@ struct MisPathSource {
     if (light) {
       // the light pdf is needed only when the segment passes the emitter test
       light = false;
-      if (hit && s.E > S.tau_E) {
-        const double pl = light_pdf(*E, s.O, s.W, lds_stack, Sx);
-        const double den = pbl * pbl + pl * pl;
-        const float f = den > 0.0 ? (float)(pbl * pl / den) : 0.0f;
-        add_fixed(acc + 0, (lf.x * f) * s.R0);
-        add_fixed(acc + 1, (lf.y * f) * s.R1);
-        add_fixed(acc + 2, (lf.z * f) * s.R2);
-      }
+      if (hit && s.E > S.tau_E) defer(true, s.O, s.W, pbl, lf, v3(s.R0, s.R1, s.R2));
       if (!cont) return false;
       O = X;
       W = Wb;
@@ -263,15 +305,14 @@ struct MisPathSource {
     }
     if (!hit) return false;
     if (s.E > S.tau_E) {
-      double wgt = 1.0;
+      const V3 bR = v3(beta.x * s.R0, beta.y * s.R1, beta.z * s.R2);
       if (depth >= 1 && E->n > 0) {
-        const double pl = light_pdf(*E, s.O, s.W, lds_stack, Sx);
-        const double den = pb * pb + pl * pl;
-        wgt = den > 0.0 ? pb * pb / den : 1.0;
+        defer(false, s.O, s.W, pb, bR, bR);
+      } else {
+        add_fixed(acc + 0, bR.x);
+        add_fixed(acc + 1, bR.y);
+        add_fixed(acc + 2, bR.z);
       }
-      add_fixed(acc + 0, (float)(beta.x * s.R0 * wgt));
-      add_fixed(acc + 1, (float)(beta.y * s.R1 * wgt));
-      add_fixed(acc + 2, (float)(beta.z * s.R2 * wgt));
       return false;
     }
     if (depth >= S.max_depth) return false;
@@ -328,11 +369,12 @@ struct MisPathSource {
 // Two waves per SIMD, as the plain path tracer: without the bound the
 // allocator takes enough registers for one.
 __global__ void __launch_bounds__(TRACE_BLOCK) __attribute__((amdgpu_waves_per_eu(2)))
-k_path_trace_mis(TraceCtx tc, PtLaunch L, EmitterDev E, unsigned long long* work_counter, unsigned long long* counters,
-                 uint64_t* hitlist) {
+k_path_trace_mis(TraceCtx tc, PtLaunch L, EmitterDev E, PdfQueue Q, unsigned long long* work_counter,
+                 unsigned long long* counters, uint64_t* hitlist) {
   MisPathSource src;
   src.L = &L;
   src.E = &E;
+  src.Q = &Q;
   src.lds_stack = nullptr;
   src.pix = src.sample = 0;
   src.depth = 0;
@@ -341,6 +383,33 @@ k_path_trace_mis(TraceCtx tc, PtLaunch L, EmitterDev E, unsigned long long* work
   src.pb = src.pbl = src.Sx = 0.0;
   src.light = src.cont = false;
   run_segments<Q_ALL, false>(tc, src, work_counter, L.n_work, hitlist, counters);
+}
+
+// One queued contribution per thread (grid-stride): its light pdf, its MIS
+// weight, and the weighted value into the pixel's accumulator.
+__global__ void __launch_bounds__(TRACE_BLOCK) k_settle_pdfs(EmitterDev E, PdfQueue Q, int64_t* accum) {
+  __shared__ int s_stack[STACK_LDS * TRACE_BLOCK];
+  const unsigned long long n = *Q.count < (unsigned long long)Q.cap ? *Q.count : (unsigned long long)Q.cap;
+  for (unsigned long long i = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x; i < n;
+       i += (unsigned long long)gridDim.x * blockDim.x) {
+    const PdfEntry& e = Q.e[i];
+    const D3 o = d3(e.o[0], e.o[1], e.o[2]), w = d3(e.w[0], e.w[1], e.w[2]);
+    const double pl = light_pdf(E, o, w, s_stack + threadIdx.x, e.S);
+    const double pbx = e.pbx;
+    const double den = pbx * pbx + pl * pl;
+    int64_t* acc = accum + (int64_t)e.pix * 3;
+    if (e.light) {
+      const float f = den > 0.0 ? (float)(pbx * pl / den) : 0.0f;
+      add_fixed(acc + 0, (e.a[0] * f) * e.b[0]);
+      add_fixed(acc + 1, (e.a[1] * f) * e.b[1]);
+      add_fixed(acc + 2, (e.a[2] * f) * e.b[2]);
+    } else {
+      const double wgt = den > 0.0 ? pbx * pbx / den : 1.0;
+      add_fixed(acc + 0, (float)(e.a[0] * wgt));
+      add_fixed(acc + 1, (float)(e.a[1] * wgt));
+      add_fixed(acc + 2, (float)(e.a[2] * wgt));
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -685,14 +754,29 @@ void build_emitters(const eag_surfels* s, float tau_E, float k_sigma, float cell
   E.begin = m.begin;
 }
 
-void launch_path_trace_mis(const TraceCtx& tc, const PtLaunch& L, const EmitterDev& E,
-                           unsigned long long* work_counter, unsigned long long* counters, uint64_t* hitlist,
-                           hipStream_t st) {
+size_t pdf_queue_bytes(int64_t entries) { return (size_t)entries * sizeof(PdfEntry) + 256; }
+
+int64_t pdf_queue_entries(int64_t pixels, int32_t max_depth, uint32_t chunk) {
+  return pixels * (int64_t)chunk * (int64_t)(max_depth + 1);
+}
+
+void launch_path_trace_mis(const TraceCtx& tc, const PtLaunch& L, const EmitterDev& E, void* queue,
+                           int64_t queue_entries, unsigned long long* work_counter, unsigned long long* counters,
+                           uint64_t* hitlist, hipStream_t st) {
   const unsigned blocks = (unsigned)(runner_lanes() / TRACE_BLOCK);
+  PdfQueue Q;
+  Q.count = reinterpret_cast<unsigned long long*>(queue);
+  Q.e = reinterpret_cast<PdfEntry*>(static_cast<char*>(queue) + 256);
+  Q.cap = queue_entries;
   launch_zero_u64(work_counter, 1, st);
-  hipLaunchKernelGGL(k_path_trace_mis, dim3(blocks), dim3(TRACE_BLOCK), 0, st, tc, L, E, work_counter, counters,
+  launch_zero_u64(Q.count, 1, st);
+  hipLaunchKernelGGL(k_path_trace_mis, dim3(blocks), dim3(TRACE_BLOCK), 0, st, tc, L, E, Q, work_counter, counters,
                      hitlist);
   check_hip(hipGetLastError(), "path_trace_mis launch");
+  if (E.n > 0) {
+    hipLaunchKernelGGL(k_settle_pdfs, dim3(blocks), dim3(TRACE_BLOCK), 0, st, E, Q, L.s[0].accum);
+    check_hip(hipGetLastError(), "settle launch");
+  }
 }
 
 }  // namespace eag

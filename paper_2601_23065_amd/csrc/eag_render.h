@@ -211,9 +211,15 @@ struct EmitterDev {
 };
 size_t emitters_mem_bytes(int64_t n);
 size_t emitters_ws_bytes(int64_t n);
-void launch_path_trace_mis(const TraceCtx& tc, const PtLaunch& L, const EmitterDev& E,
-                           unsigned long long* work_counter, unsigned long long* counters, uint64_t* hitlist,
-                           hipStream_t st);
+// queue: pdf_queue_bytes(queue_entries) bytes of device memory for the
+// contributions that wait for their light pdf; a launch of P paths at max
+// depth D needs pdf_queue_entries = P (D + 1).
+constexpr uint32_t MIS_CHUNK_SPP = 4;   // samples per launch of eag_path_trace_mis
+size_t pdf_queue_bytes(int64_t entries);
+int64_t pdf_queue_entries(int64_t pixels, int32_t max_depth, uint32_t chunk);
+void launch_path_trace_mis(const TraceCtx& tc, const PtLaunch& L, const EmitterDev& E, void* queue,
+                           int64_t queue_entries, unsigned long long* work_counter, unsigned long long* counters,
+                           uint64_t* hitlist, hipStream_t st);
 
 size_t grad_accum_doubles(int64_t n);
 void launch_grad_zero(double* gacc, int64_t n, hipStream_t st);
