@@ -578,7 +578,7 @@ def bench_mis(torch, args):
     table_ms = (time.perf_counter() - te0) * 1e3
     n_em, _ = em.info()
     _log(f"scene ready: {scene.n} surfels, {n_em} emitters, {cam.width}x{cam.height}, {spp} spp")
-    counters = torch.zeros(6, dtype=torch.int64, device="cuda")
+    counters = torch.zeros(7, dtype=torch.int64, device="cuda")
 
     def image(fn, s0, count):
         acc = fn(s0, count)
@@ -623,7 +623,8 @@ def bench_mis(torch, args):
     _log("emitter-sampled timing done")
     ms_plain, kms_plain, c_plain, rmse_plain = timed(plain)
     _log("plain timing done")
-    segments, paths, rounds, tests, blended, visits = c_mis
+    segments, paths, rounds, tests, blended, visits, dropped = c_mis
+    assert dropped == 0, f"{dropped} light-pdf queue entries dropped"
     value = segments / (ms_mis * 1e-3) / 1e6
     rec = {
         "metric": "Mrays/s multi-bounce PT over 2D Gaussians with emitter sampling + MIS",
@@ -650,6 +651,7 @@ def bench_mis(torch, args):
                                        zip(("rounds", "tests", "blended", "visits"), (rounds, tests, blended, visits))},
                    "per_segment_plain": {k: round(v / max(c_plain[0], 1), 3) for k, v in
                                          zip(("rounds", "tests", "blended", "visits"), c_plain[2:6])},
+                   "light_pdf_queue_dropped": int(dropped),
                    "rmse_mis": rmse_mis, "rmse_plain": rmse_plain,
                    "mse_ratio_equal_spp": round((rmse_plain / rmse_mis) ** 2, 3),
                    "mse_ratio_equal_time": round((rmse_plain / rmse_mis) ** 2 * ms_plain / ms_mis, 3),

@@ -49,7 +49,7 @@
 extern "C" {
 #endif
 
-#define EAG_ABI_VERSION 1u
+#define EAG_ABI_VERSION 2u
 
 typedef enum {
   EAG_OK = 0,
@@ -329,16 +329,21 @@ eag_status eag_build_emitters(const eag_surfels* s, const eag_trace_params* p, f
  * output is nullable. */
 eag_status eag_emitters_get_info(const eag_emitters* em, int64_t* count, double* total_weight, int32_t* n_cells);
 void eag_emitters_destroy(eag_emitters* em);
-/* Workspace of eag_path_trace_mis: eag_path_trace's, plus a queue for the
- * contributions that wait for their light pdf (96 B per entry, W H (max_depth
- * + 1) entries per 4 samples: the calls launch 4 samples at a time). 0 for
- * invalid arguments. */
+/* Workspace of eag_path_trace_mis for its fastest launches: eag_path_trace's,
+ * plus a queue for the contributions that wait for their light pdf (96 B per
+ * entry, W H (max_depth + 1) entries per sample, for 4 samples per launch).
+ * A smaller workspace also works: the call then launches as many samples at
+ * a time as its queue holds, and fails only when one sample does not fit.
+ * 0 for invalid arguments. */
 size_t eag_path_trace_mis_workspace_bytes(int64_t n_surfels, const eag_camera* cam, const eag_trace_params* p);
 /* As eag_path_trace (same accumulator and sample ranges) with the estimator
  * above; ws: eag_path_trace_mis_workspace_bytes. em must come from the same
  * scene (same surfel count) and the same tau_E and k_sigma as p;
  * EAG_ADDITIVE_EMISSION is rejected. A table without emitters gives
- * eag_path_trace's values. */
+ * eag_path_trace's values. counters: nullable device uint64 [7]: the six of
+ * eag_path_trace, then the number of queued contributions dropped because
+ * the queue was full (0 unless a launch queues more than one entry per
+ * segment: the image then lacks them). */
 eag_status eag_path_trace_mis(const eag_bvh* bvh, const eag_surfels* s, const eag_emitters* em,
                               const eag_camera* cam, const eag_trace_params* p, uint32_t sample_begin,
                               uint32_t sample_count, int64_t* accum, uint64_t* counters, void* ws,
@@ -352,13 +357,19 @@ enum {
   EAG_EDIT_SET_RADIANCE = 1,    /* r[i] = value[0..2]                         */
   EAG_EDIT_SCALE_RADIANCE = 2,  /* r[i] *= value[0..2] (0 switches lights off) */
   EAG_EDIT_SET_ALBEDO = 3,      /* rho[i] = value[0..2]                       */
-  EAG_EDIT_SET_EMISSIVE = 4     /* e[i] = value[0]                            */
+  EAG_EDIT_SET_EMISSIVE = 4,    /* e[i] = value[0]                            */
+  EAG_EDIT_TRANSFORM = 5        /* rigid motion (server only; eag_move_surfels
+                                   applies it to caller arrays): value[0..3] =
+                                   unit quaternion r (w, x, y, z), value[4..6] =
+                                   pivot, value[7..9] = translation t;
+                                   p -> R(r)(p - pivot) + pivot + t, q -> r (x) q */
 };
 typedef struct {
   int32_t kind;
-  const int32_t* idx;           /* device [count] surfel indices, each < n */
+  const int32_t* idx;           /* device [count] surfel indices; indices outside
+                                   [0, n) are skipped */
   int64_t count;
-  float value[3];
+  float value[12];              /* per kind, as above; the rest unused */
 } eag_edit;
 typedef struct {
   int64_t n;
@@ -510,7 +521,8 @@ eag_status eag_bake_step(const eag_bvh* bvh, const eag_surfels* s, const eag_cam
  * requests that arrive while others run join the next launch. Edits are
  * ordered with respect to later submits: each request renders the scene
  * version current at its submit; attribute edits create a new version
- * (copy-on-write attributes), geometry is shared.
+ * (copy-on-write attributes); geometry is shared, so a geometric edit
+ * (a rigid motion with a BVH refit) first lets earlier requests finish.
  * ------------------------------------------------------------------------ */
 typedef struct eag_server eag_server;
 typedef struct {
@@ -539,7 +551,15 @@ size_t eag_serve_arena_bytes(int64_t n, int32_t versions, size_t request_bytes);
 /* Copies the scene into the arena and builds the BVH (synchronous). */
 eag_status eag_serve_create(const eag_surfels* s, const eag_server_config* cfg, eag_server** out);
 eag_status eag_serve_submit(eag_server* srv, const eag_request* req, uint64_t* ticket);  /* non-blocking */
-eag_status eag_serve_edit(eag_server* srv, const eag_edit* e, uint64_t* ticket);        /* idx: host */
+/* Queues an edit, ordered with respect to earlier and later submits (non-
+ * blocking). e->idx is a device array that the server reads when it applies
+ * the edit, on its stream: the caller keeps it unchanged until the ticket
+ * reports done. Attribute kinds make a new copy-on-write attribute version.
+ * EAG_EDIT_TRANSFORM moves the resident geometry, which all versions share,
+ * and refits the BVH: it waits until every request submitted before it has
+ * completed (requests submitted after it wait behind it), then applies the
+ * motion, refits, and makes a new version. */
+eag_status eag_serve_edit(eag_server* srv, const eag_edit* e, uint64_t* ticket);
 eag_status eag_serve_poll(eag_server* srv, uint64_t ticket, eag_result* out);           /* non-blocking */
 eag_status eag_serve_cancel(eag_server* srv, uint64_t ticket);
 eag_status eag_serve_destroy(eag_server* srv);  /* drains, stops the scheduler thread */

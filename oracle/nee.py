@@ -69,7 +69,7 @@ import numpy as np
 from . import philox
 from .frames import cosine_direction
 from .render import _camera, _pixels
-from .tracer import KAPPA, U32, F_RR, UF32, Scene64, trace
+from .tracer import KAPPA, UGEOM, F_RR, UF32, Scene64, trace
 
 NEE_SEGMENT = 1 << 31
 F_NEE = 1 << 9
@@ -213,10 +213,10 @@ class Emitters:
         # margins, as the tracer takes them
         oinf = np.abs(X).max(axis=1)[:, None]
         tabs = np.minimum(np.where(valid, np.abs(t), 0.0), 1e6)
-        dxe = eX[:, None] + tabs * ew[:, None] + KAPPA * U32 * (oinf + self.pmax[None, :] + tabs)
+        dxe = eX[:, None] + tabs * ew[:, None] + KAPPA * UGEOM * (oinf + self.pmax[None, :] + tabs)
         dte = np.minimum(dxe / np.maximum(np.abs(den), 1e-12), 1e6)
         duv = dte / self.smin[None, :]
-        dq2 = 2.0 * np.sqrt(q2) * duv + duv * duv + KAPPA * U32 * k2
+        dq2 = 2.0 * np.sqrt(q2) * duv + duv * duv + KAPPA * UGEOM * k2
         amb = np.any(valid & (t > -dte) & (np.abs(q2 - k2) <= dq2), axis=1)
         amb |= np.any(valid & (q2 <= k2 + dq2) & (np.abs(t) <= dte), axis=1)
         return terms.sum(axis=1), amb
@@ -297,8 +297,8 @@ def path_trace_nee(scene, cam, prm, em=None, pixels=None, samples=None):
                 dist = np.linalg.norm(dl, axis=1)
                 Wl = dl / dist[:, None]
                 cl = np.einsum("mc,mc->m", Wl, Nt)
-                ewl = (eX + KAPPA * U32 * (np.abs(y).max(axis=1) + np.abs(Xo).max(axis=1))) / dist + KAPPA * U32
-                amb |= np.abs(cl) <= ewb + ewl + KAPPA * U32
+                ewl = (eX + KAPPA * UGEOM * (np.abs(y).max(axis=1) + np.abs(Xo).max(axis=1))) / dist + KAPPA * UGEOM
+                amb |= np.abs(cl) <= ewb + ewl + KAPPA * UGEOM
                 flags[ps[amb]] |= F_NEE
                 up = np.nonzero(cl > 0.0)[0]
                 if up.size:

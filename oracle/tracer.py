@@ -44,7 +44,6 @@ from .frames import quat_frames, hemisphere_frame
 UGEOM = 2.0 ** -53      # ray geometry evaluated in double precision
 UF32 = 2.0 ** -24       # quantities stored in float32 (E against tau_E, throughput)
 KAPPA = 64.0
-U32 = UGEOM
 
 F_RIM, F_TMIN, F_BUCKET, F_TERM, F_EMIT, F_THIN, F_FRAME, F_PAR, F_RR = (1 << i for i in range(9))
 FLAG_NAMES = {F_RIM: "rim", F_TMIN: "tmin", F_BUCKET: "bucket", F_TERM: "term", F_EMIT: "emit",
@@ -143,16 +142,17 @@ def _trace_batch(sc, O, W, prm, eO, ew, seg_k):
     q2 = u * u + v * v
     acc = valid & (t > prm.t_min) & (q2 <= k2)
 
-    # float32 error model for the margin flags: dxe bounds the absolute error
+    # rounding-error model for the margin flags (UGEOM: ray geometry in double
+    # precision, times KAPPA): dxe bounds the absolute error
     # of a hit point, dte its distance along the ray, duv its tangent-plane
     # coordinates (the hit point slides by dxe / |cos| within the plane)
     oinf = np.abs(O).max(axis=1)[:, None]
     tabs = np.minimum(np.where(valid, np.abs(t), 0.0), 1e6)
-    dxe = eO[:, None] + tabs * ew[:, None] + KAPPA * U32 * (oinf + sc.pmax[None, :] + tabs)
+    dxe = eO[:, None] + tabs * ew[:, None] + KAPPA * UGEOM * (oinf + sc.pmax[None, :] + tabs)
     acos = np.maximum(np.abs(den), 1e-12)
     dte = np.minimum(dxe / acos, 1e6)
     duv = dte / sc.smin[None, :]
-    dq2 = 2.0 * np.sqrt(q2) * duv + duv * duv + KAPPA * U32 * k2
+    dq2 = 2.0 * np.sqrt(q2) * duv + duv * duv + KAPPA * UGEOM * k2
     near_t = valid & (t > prm.t_min - dte)
     rim = np.any(near_t & (np.abs(q2 - k2) <= dq2), axis=1)
     tmin = np.any(valid & (q2 <= k2 + dq2) & (np.abs(t - prm.t_min) <= dte), axis=1)
@@ -226,9 +226,9 @@ def _trace_batch(sc, O, W, prm, eO, ew, seg_k):
             if tw.size > 1 and np.any(np.diff(tw) <= ew_[1:] + ew_[:-1]):
                 flags |= F_BUCKET
         # --- termination margin: relative alpha error ea, weight error dw
-        ea = np.sqrt(q2[b, hi]) * duv[b, hi] + 4 * KAPPA * U32
+        ea = np.sqrt(q2[b, hi]) * duv[b, hi] + 4 * KAPPA * UGEOM
         lt = alpha[:m + 1] / (1.0 - alpha[:m + 1]) * ea
-        dlnT = float(np.sum(lt)) + (m + 1) * KAPPA * U32
+        dlnT = float(np.sum(lt)) + (m + 1) * KAPPA * UGEOM
         lnTmin = np.log(prm.T_min)
         if terminated:
             if abs(np.log(T[m]) - lnTmin) <= dlnT or (m >= 1 and abs(np.log(T[m - 1]) - lnTmin) <= dlnT):
@@ -249,9 +249,9 @@ def _trace_batch(sc, O, W, prm, eO, ew, seg_k):
         # so weight errors move them by the spread of the averaged values
         dDt = float(np.sum(wts * (np.abs(seg.t - seg.Dt) * dw + dte[b, hi]))) / seg.A
         eN = float(np.sum(wts * np.linalg.norm(nprime - seg.Nt[None, :], axis=1) * dw)) / max(seg.Nlen, 1e-300)
-        eN += KAPPA * U32
-        seg.eX = eO[b] + abs(seg.Dt) * ew[b] + dDt + KAPPA * U32 * (oinf[b, 0] + 2 * abs(seg.Dt))
-        seg.ew = eN * (1.0 + 2.0 / max(seg.mlen, 1e-3)) + KAPPA * U32
+        eN += KAPPA * UGEOM
+        seg.eX = eO[b] + abs(seg.Dt) * ew[b] + dDt + KAPPA * UGEOM * (oinf[b, 0] + 2 * abs(seg.Dt))
+        seg.ew = eN * (1.0 + 2.0 / max(seg.mlen, 1e-3)) + KAPPA * UGEOM
         seg.flags = flags
         res.append(seg)
     return res

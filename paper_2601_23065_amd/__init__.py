@@ -6,7 +6,7 @@ package does not load the library; the first call does, and raises if it has
 not been built.
 """
 from ._lib import (ADDITIVE_EMISSION, DETACH_BOUNCE, EDIT_SCALE_RADIANCE, EDIT_SET_ALBEDO,  # noqa: F401
-                   EDIT_SET_EMISSIVE, EDIT_SET_RADIANCE, JITTER, EagError, load)
+                   EDIT_SET_EMISSIVE, EDIT_SET_RADIANCE, EDIT_TRANSFORM, JITTER, EagError, load)
 
 
 def __getattr__(name):

@@ -13,7 +13,7 @@ STATUS_NAMES = {0: "EAG_OK", 1: "EAG_NOT_READY", -1: "EAG_ERR_INVALID_ARGUMENT",
                 -6: "EAG_ERR_UNKNOWN_TICKET", -7: "EAG_ERR_INTERNAL"}
 
 JITTER, ADDITIVE_EMISSION, DETACH_BOUNCE = 1, 2, 4
-EDIT_SET_RADIANCE, EDIT_SCALE_RADIANCE, EDIT_SET_ALBEDO, EDIT_SET_EMISSIVE = 1, 2, 3, 4
+EDIT_SET_RADIANCE, EDIT_SCALE_RADIANCE, EDIT_SET_ALBEDO, EDIT_SET_EMISSIVE, EDIT_TRANSFORM = 1, 2, 3, 4, 5
 FWD_PIXEL_FLOATS = 28
 STAGE0_FLOATS = 8
 ACCUM_SCALE = 4294967296.0
@@ -50,7 +50,7 @@ class BvhInfo(C.Structure):
 
 
 class Edit(C.Structure):
-    _fields_ = [("kind", C.c_int32), ("idx", vp), ("count", C.c_int64), ("value", C.c_float * 3)]
+    _fields_ = [("kind", C.c_int32), ("idx", vp), ("count", C.c_int64), ("value", C.c_float * 12)]
 
 
 class Adam(C.Structure):

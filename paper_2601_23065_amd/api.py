@@ -8,6 +8,8 @@ failing library raises.
 from __future__ import annotations
 
 import ctypes as C
+import functools
+import inspect
 from dataclasses import dataclass, fields
 
 import torch
@@ -22,6 +24,30 @@ _SHAPES = {"pos": 3, "rot": 4, "scale": 2, "opacity": 0, "albedo": 3, "radiance"
 def _stream(stream=None):
     s = stream if stream is not None else torch.cuda.current_stream()
     return C.c_void_p(s.cuda_stream)
+
+
+def _streamed(fn):
+    """Run a binding function on its `stream` argument when one is given.
+
+    The library launches on that stream, so the work torch has queued on its
+    current stream (the caller's inputs, and the zero fills of tensors made
+    here) must come first: the stream waits for the current one. The body
+    then runs with the stream current, so workspaces, accumulators and
+    temporaries made here are allocated and cleared on it, and the caching
+    allocator does not hand their memory to other streams while the
+    library's kernels may still use it. Without a stream, everything runs on
+    torch's current stream."""
+    sig = inspect.signature(fn)
+
+    @functools.wraps(fn)
+    def run(*args, **kwargs):
+        stream = sig.bind_partial(*args, **kwargs).arguments.get("stream")
+        if stream is None:
+            return fn(*args, **kwargs)
+        stream.wait_stream(torch.cuda.current_stream(stream.device))
+        with torch.cuda.stream(stream):
+            return fn(*args, **kwargs)
+    return run
 
 
 def _ptr(t):
@@ -117,6 +143,7 @@ class Scene:
 class BVH:
     """Linear BVH over a Scene; owns its device memory as a torch tensor."""
 
+    @_streamed
     def __init__(self, scene: Scene, stream=None):
         lib = L.load()
         self.scene = scene
@@ -132,6 +159,7 @@ class BVH:
         self._ws = ws
         self.cost_at_build = self.sah_cost(stream)   # for the refit-or-rebuild policy (update_bvh)
 
+    @_streamed
     def refit(self, scene: Scene | None = None, stream=None):
         lib = L.load()
         scene = scene or self.scene
@@ -139,6 +167,7 @@ class BVH:
         sc = scene.c()
         L.check(lib.eag_refit_bvh(self.h, C.byref(sc), wp, wb, _stream(stream)))
 
+    @_streamed
     def sah_cost(self, stream=None):
         """The tree's surface-area cost (a device float64 scalar)."""
         cost = torch.empty((), dtype=torch.float64, device=self.scene.device)
@@ -160,6 +189,7 @@ class BVH:
             pass
 
 
+@_streamed
 def trace_rays(bvh: BVH, scene: Scene, params: Params, origins, dirs, max_hits: int = 0, stream=None,
                stats=None):
     """origins, dirs: [3, M] float32 device tensors. Returns out [12, M]
@@ -191,6 +221,7 @@ def _cams(cams):
     return arr
 
 
+@_streamed
 def render_single_bounce(bvh: BVH, scene: Scene, cams, params: Params, keep_state: bool = False, stream=None,
                          overrides=None):
     """Returns rgb [n_cams, H, W, 3] and, if keep_state, the forward state."""
@@ -211,6 +242,7 @@ def render_single_bounce(bvh: BVH, scene: Scene, cams, params: Params, keep_stat
     return (rgb, state) if keep_state else rgb
 
 
+@_streamed
 def single_bounce_backward(bvh: BVH, scene: Scene, cams, params: Params, dL_drgb, state, grads: dict | None = None,
                            stream=None, overrides=None):
     """Accumulates gradients into `grads` (zeroed tensors are created if
@@ -257,6 +289,7 @@ class SingleBounceRender(torch.autograd.Function):
                 None, None, None, None, None)
 
 
+@_streamed
 def path_trace(bvh: BVH, scene: Scene, cam, params: Params, sample_begin: int = 0, sample_count: int | None = None,
                accum=None, counters=None, stream=None, ws=None):
     """Adds samples [sample_begin, sample_begin + sample_count) into the int64
@@ -284,6 +317,7 @@ class Emitters:
     power, a power of two selects by cells of that size weighted by their
     power over the squared distance to the vertex."""
 
+    @_streamed
     def __init__(self, scene: Scene, params: Params, cell: float = 0.0, stream=None):
         lib = L.load()
         self.scene = scene
@@ -321,6 +355,7 @@ class Emitters:
             pass
 
 
+@_streamed
 def path_trace_mis(bvh: BVH, scene: Scene, emitters: Emitters, cam, params: Params, sample_begin: int = 0,
                    sample_count: int | None = None, accum=None, counters=None, stream=None, ws=None):
     """path_trace with emitter sampling combined by multiple importance
@@ -351,6 +386,7 @@ def path_trace_workspace(scene: Scene):
     return _bytes(L.load().eag_path_trace_workspace_bytes(scene.n), scene.device)
 
 
+@_streamed
 def resolve(accum, total_spp: int, stream=None):
     """float32 image [H, W, 3] = accum / (2^32 * total_spp)."""
     rgb = torch.empty(accum.shape, dtype=torch.float32, device=accum.device)
@@ -358,6 +394,7 @@ def resolve(accum, total_spp: int, stream=None):
     return rgb
 
 
+@_streamed
 def apply_edit(scene: Scene, kind: int, idx, value, stream=None):
     """In-place attribute edit of the scene's arrays; idx: int32 device tensor."""
     e = L.Edit()
@@ -365,8 +402,8 @@ def apply_edit(scene: Scene, kind: int, idx, value, stream=None):
     idx = idx.to(torch.int32).contiguous()
     e.idx = _ptr(idx)
     e.count = idx.numel()
-    vals = list(value) + [0.0] * (3 - len(list(value)))
-    e.value[:] = [float(v) for v in vals[:3]]
+    vals = [float(v) for v in value]
+    e.value[:] = vals + [0.0] * (12 - len(vals))
     a = scene.attrs_c()
     L.check(L.load().eag_apply_edit(C.byref(e), C.byref(a), _stream(stream)))
 
@@ -383,6 +420,7 @@ def _out(scene: Scene):
     return o
 
 
+@_streamed
 def select_box(scene: Scene, lo, hi, stream=None):
     """int32 device tensor of the surfels whose centre lies in [lo, hi]
     (reads the count back: a synchronisation)."""
@@ -396,6 +434,7 @@ def select_box(scene: Scene, lo, hi, stream=None):
     return idx[:int(count)]
 
 
+@_streamed
 def move_surfels(scene: Scene, idx, r=(1.0, 0.0, 0.0, 0.0), pivot=(0.0, 0.0, 0.0), t=(0.0, 0.0, 0.0), stream=None):
     """In place: p -> R(r)(p - pivot) + pivot + t, q -> r (x) q for the surfels idx."""
     idx = idx.to(torch.int32).contiguous()
@@ -404,6 +443,7 @@ def move_surfels(scene: Scene, idx, r=(1.0, 0.0, 0.0, 0.0), pivot=(0.0, 0.0, 0.0
                                       _stream(stream)))
 
 
+@_streamed
 def delete_surfels(scene: Scene, idx, stream=None):
     """In place: opacity 0 for the surfels idx."""
     idx = idx.to(torch.int32).contiguous()
@@ -411,6 +451,7 @@ def delete_surfels(scene: Scene, idx, stream=None):
     L.check(L.load().eag_delete_surfels(C.byref(o), _ptr(idx), idx.numel(), _stream(stream)))
 
 
+@_streamed
 def duplicate_surfels(scene: Scene, idx, r=(1.0, 0.0, 0.0, 0.0), pivot=(0.0, 0.0, 0.0), t=(0.0, 0.0, 0.0),
                       stream=None):
     """A new Scene: the surfels of `scene`, then moved copies of the surfels idx."""
@@ -426,6 +467,7 @@ def duplicate_surfels(scene: Scene, idx, r=(1.0, 0.0, 0.0, 0.0), pivot=(0.0, 0.0
     return dst
 
 
+@_streamed
 def update_bvh(bvh: BVH, scene: Scene, max_cost_ratio: float = 1.25, stream=None):
     """Refit-or-rebuild policy after geometric edits: a changed surfel count
     needs a build; otherwise the tree is refitted, and rebuilt when its
@@ -440,6 +482,7 @@ def update_bvh(bvh: BVH, scene: Scene, max_cost_ratio: float = 1.25, stream=None
     return bvh, False
 
 
+@_streamed
 def render_stage0(bvh: BVH, scene: Scene, cams, params: Params, ws=None, stream=None):
     """Stage-0 images [n_cams, H, W, 8] (Nt, Dt, R, E) and the forward state
     the backward needs."""
@@ -456,6 +499,7 @@ def render_stage0(bvh: BVH, scene: Scene, cams, params: Params, ws=None, stream=
     return images, state
 
 
+@_streamed
 def stage0_loss(images, rgb_gt, normal_mono, mask, cams, params: Params, weights=(1.0, 1.0, 1.0, 1.0), stream=None):
     """(loss as a device float64 scalar, d loss / d images) of Eq. 4."""
     lib = L.load()
@@ -471,6 +515,7 @@ def stage0_loss(images, rgb_gt, normal_mono, mask, cams, params: Params, weights
     return loss, d
 
 
+@_streamed
 def stage0_backward(bvh: BVH, scene: Scene, cams, params: Params, d_images, state, grads: dict | None = None, ws=None,
                     stream=None):
     """Accumulates d<d_images, images>/d(pos, rot, scale, opacity, radiance,
@@ -496,6 +541,7 @@ def bake_workspace(scene: Scene, cams):
     return _bytes(L.load().eag_bake_workspace_bytes(scene.n, _cams(cams), len(cams)), scene.device)
 
 
+@_streamed
 def render_zero_bounce(bvh: BVH, scene: Scene, cams, params: Params, ws=None, stream=None):
     """0-bounce images [n_cams, H, W, 3]: R composited along each camera ray."""
     lib = L.load()
@@ -509,6 +555,7 @@ def render_zero_bounce(bvh: BVH, scene: Scene, cams, params: Params, ws=None, st
     return rgb
 
 
+@_streamed
 def zero_bounce_backward(bvh: BVH, scene: Scene, cams, params: Params, dL_drgb, grad_radiance=None, ws=None,
                          stream=None):
     """grad_radiance [3, n] += d<dL_drgb, 0-bounce image>/d radiance."""
@@ -524,6 +571,7 @@ def zero_bounce_backward(bvh: BVH, scene: Scene, cams, params: Params, dL_drgb, 
     return grad_radiance
 
 
+@_streamed
 def bake_loss(rgb, target, stream=None):
     """(loss as a device float64 scalar, dloss/drgb) of mean |PQ(rgb) - PQ(target)|."""
     rgb, target = rgb.contiguous(), target.contiguous()
@@ -547,6 +595,7 @@ class Adam:
         return a
 
 
+@_streamed
 def adam_step(param, grad, m, v, adam: Adam, step: int, stream=None):
     """In-place projected Adam update of param (m, v: moment tensors)."""
     L.check(L.load().eag_adam_step(_ptr(param), _ptr(grad), _ptr(m), _ptr(v), param.numel(), C.byref(adam.c()),
@@ -569,6 +618,7 @@ class Baker:
         self.loss = torch.zeros((), dtype=torch.float64, device=scene.device)
         self.steps = 0
 
+    @_streamed
     def step(self, stream=None):
         lib = L.load()
         self.steps += 1
@@ -620,18 +670,30 @@ class Server:
         return t.value, out
 
     def edit(self, kind: int, idx, value):
-        """Queue an attribute edit (host index list); returns its ticket."""
-        import numpy as np
-        idx = np.ascontiguousarray(np.asarray(idx, dtype=np.int32))
+        """Queue an attribute edit, or EDIT_TRANSFORM with value = r (4),
+        pivot (3), t (3); idx: surfel indices (any int sequence or tensor),
+        held on the device until the edit is done. Returns its ticket."""
+        idx = torch.as_tensor(idx, dtype=torch.int32).to(self.device).contiguous()
+        # the server reads idx on its stream: the upload must come first
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        idx.record_stream(self.stream)
         e = L.Edit()
         e.kind = int(kind)
-        e.idx = C.c_void_p(idx.ctypes.data)
-        e.count = idx.size
-        vals = list(value) + [0.0] * (3 - len(list(value)))
-        e.value[:] = [float(v) for v in vals[:3]]
+        e.idx = _ptr(idx)
+        e.count = idx.numel()
+        vals = [float(v) for v in value]
+        e.value[:] = vals + [0.0] * (12 - len(vals))
         t = C.c_uint64()
         L.check(L.load().eag_serve_edit(self.h, C.byref(e), C.byref(t)))
+        self._keep[t.value] = idx
         return t.value
+
+    def transform(self, idx, r=(1.0, 0.0, 0.0, 0.0), pivot=(0.0, 0.0, 0.0), t=(0.0, 0.0, 0.0)):
+        """Queue a rigid motion of the surfels idx (p -> R(r)(p - pivot) +
+        pivot + t, q -> r (x) q) with a BVH refit; it waits for the requests
+        submitted before it. Returns its ticket."""
+        from ._lib import EDIT_TRANSFORM
+        return self.edit(EDIT_TRANSFORM, idx, list(r) + list(pivot) + list(t))
 
     def poll(self, ticket: int):
         """Returns None while running, else a dict with status and times."""
@@ -639,6 +701,7 @@ class Server:
         st = L.load().eag_serve_poll(self.h, ticket, C.byref(res))
         if st == L.EAG_NOT_READY:
             return None
+        self._keep.pop(ticket, None)   # the server no longer reads the buffers it was given
         return dict(status=st, version=res.scene_version, t_submit=res.t_submit, t_admit=res.t_admit,
                     t_done=res.t_done, paths=res.paths)
 

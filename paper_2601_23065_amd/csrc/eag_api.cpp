@@ -699,9 +699,18 @@ eag_status eag_path_trace_mis(const eag_bvh* b, const eag_surfels* s, const eag_
       fail(EAG_ERR_INVALID_ARGUMENT, "emitter sampling is defined for the emitter-terminated path tracer");
     if ((uint64_t)sample_begin + sample_count > 0xffffffffull) fail(EAG_ERR_INVALID_ARGUMENT, "sample range overflow");
     const RenderWs w = render_ws(ws, b->n, 0, 0, false, runner_lanes());
-    const int64_t entries = pdf_queue_entries((int64_t)cam->width * cam->height, p->max_depth, MIS_CHUNK_SPP);
-    if (!ws || ws_bytes < w.bytes + align_up(pdf_queue_bytes(entries)))
-      fail(EAG_ERR_WORKSPACE_TOO_SMALL, "path-trace workspace too small (eag_path_trace_mis_workspace_bytes)");
+    // Samples per launch: as many as the caller's queue holds, up to
+    // MIS_CHUNK_SPP (the size eag_path_trace_mis_workspace_bytes returns).
+    const int64_t per_sample = pdf_queue_entries((int64_t)cam->width * cam->height, p->max_depth, 1);
+    uint32_t chunk = 0;
+    if (ws && ws_bytes >= w.bytes) {
+      for (uint32_t c = MIS_CHUNK_SPP; c >= 1 && !chunk; --c)
+        if (ws_bytes - w.bytes >= align_up(pdf_queue_bytes(per_sample * c))) chunk = c;
+    }
+    if (!chunk)
+      fail(EAG_ERR_WORKSPACE_TOO_SMALL, "path-trace workspace too small for one sample's light-pdf queue "
+                                        "(eag_path_trace_mis_workspace_bytes)");
+    const int64_t entries = per_sample * chunk;
     void* queue = static_cast<char*>(ws) + w.bytes;
     const CamDev cd = make_cam(*cam, p->camera_id);
     const TraceSetup ts = trace_setup(b, p, std::fmax(scene_t_max(b), camera_t_max(b, *cam)));
@@ -709,10 +718,10 @@ eag_status eag_path_trace_mis(const eag_bvh* b, const eag_surfels* s, const eag_
     hipStream_t st = static_cast<hipStream_t>(stream);
     pack_attrs(s, b, w.attrs, st);
     const TraceCtx tc = make_ctx(b, w.attrs, p, ts);
-    // launches of at most MIS_CHUNK_SPP samples, each followed by its light pdfs
-    for (uint32_t c0 = 0; c0 < sample_count; c0 += MIS_CHUNK_SPP) {
-      const uint32_t cnt = std::min<uint32_t>(MIS_CHUNK_SPP, sample_count - c0);
-      const PtLaunch L = single_request_launch(cd, *cam, p, w.attrs, accum, sample_begin + c0, cnt);
+    // launches of at most `chunk` samples, each followed by its light pdfs
+    for (uint64_t c0 = 0; c0 < sample_count; c0 += chunk) {
+      const uint32_t cnt = (uint32_t)std::min<uint64_t>(chunk, sample_count - c0);
+      const PtLaunch L = single_request_launch(cd, *cam, p, w.attrs, accum, sample_begin + (uint32_t)c0, cnt);
       launch_path_trace_mis(tc, L, em->dev, queue, entries, w.work, reinterpret_cast<unsigned long long*>(counters),
                             w.hitlist, st);
     }
@@ -1023,7 +1032,8 @@ eag_status eag_apply_edit(const eag_edit* e, const eag_surfel_attrs* a, void* st
     if (!e || !a) fail(EAG_ERR_INVALID_ARGUMENT, "null argument");
     if (a->n < 1 || !a->albedo || !a->radiance || !a->emissive) fail(EAG_ERR_INVALID_ARGUMENT, "bad attribute arrays");
     if (e->count < 0 || (e->count > 0 && !e->idx)) fail(EAG_ERR_INVALID_ARGUMENT, "bad edit index list");
-    if (e->kind < EAG_EDIT_SET_RADIANCE || e->kind > EAG_EDIT_SET_EMISSIVE) fail(EAG_ERR_INVALID_ARGUMENT, "bad edit kind");
+    if (e->kind < EAG_EDIT_SET_RADIANCE || e->kind > EAG_EDIT_SET_EMISSIVE)
+      fail(EAG_ERR_INVALID_ARGUMENT, "bad edit kind (attribute kinds only; eag_move_surfels applies motions)");
     if (e->count == 0) return;
     launch_apply_edit(*e, *a, static_cast<hipStream_t>(stream));
   });

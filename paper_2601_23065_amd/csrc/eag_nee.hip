@@ -277,7 +277,8 @@ struct MisPathSource {
     base = __shfl(base, leader);
     const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
     const unsigned long long slot = base + (unsigned long long)__popcll(m & below);
-    if (slot >= (unsigned long long)Q->cap) return;   // the host sizes chunks so that this never happens
+    // the host sizes launches so that this never happens; the settle kernel counts any claim past the end
+    if (slot >= (unsigned long long)Q->cap) return;
     PdfEntry& e = Q->e[slot];
     e.o[0] = o.x; e.o[1] = o.y; e.o[2] = o.z;
     e.w[0] = w.x; e.w[1] = w.y; e.w[2] = w.z;
@@ -387,9 +388,14 @@ k_path_trace_mis(TraceCtx tc, PtLaunch L, EmitterDev E, PdfQueue Q, unsigned lon
 
 // One queued contribution per thread (grid-stride): its light pdf, its MIS
 // weight, and the weighted value into the pixel's accumulator.
-__global__ void __launch_bounds__(TRACE_BLOCK) k_settle_pdfs(EmitterDev E, PdfQueue Q, int64_t* accum) {
+__global__ void __launch_bounds__(TRACE_BLOCK) k_settle_pdfs(EmitterDev E, PdfQueue Q, int64_t* accum,
+                                                             unsigned long long* counters) {
   __shared__ int s_stack[STACK_LDS * TRACE_BLOCK];
-  const unsigned long long n = *Q.count < (unsigned long long)Q.cap ? *Q.count : (unsigned long long)Q.cap;
+  const unsigned long long claimed = *Q.count;
+  const unsigned long long n = claimed < (unsigned long long)Q.cap ? claimed : (unsigned long long)Q.cap;
+  // Claims past the queue's end were dropped by the path kernel: counted, so
+  // that a caller can see that the image lacks them.
+  if (counters && blockIdx.x == 0 && threadIdx.x == 0 && claimed > n) atomicAdd(&counters[6], claimed - n);
   for (unsigned long long i = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x; i < n;
        i += (unsigned long long)gridDim.x * blockDim.x) {
     const PdfEntry& e = Q.e[i];
@@ -774,7 +780,7 @@ void launch_path_trace_mis(const TraceCtx& tc, const PtLaunch& L, const EmitterD
                      hitlist);
   check_hip(hipGetLastError(), "path_trace_mis launch");
   if (E.n > 0) {
-    hipLaunchKernelGGL(k_settle_pdfs, dim3(blocks), dim3(TRACE_BLOCK), 0, st, E, Q, L.s[0].accum);
+    hipLaunchKernelGGL(k_settle_pdfs, dim3(blocks), dim3(TRACE_BLOCK), 0, st, E, Q, L.s[0].accum, counters);
     check_hip(hipGetLastError(), "settle launch");
   }
 }

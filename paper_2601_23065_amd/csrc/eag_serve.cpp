@@ -23,6 +23,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <cmath>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -73,8 +74,7 @@ struct Op {
   bool is_edit = false;
   uint64_t ticket = 0;
   std::shared_ptr<Req> req;
-  eag_edit edit{};
-  std::vector<int32_t> idx;
+  eag_edit edit{};          // idx: the caller's device array, read when the edit is applied
   double t_submit = 0;
 };
 
@@ -170,6 +170,15 @@ struct eag_server {
     return s;
   }
 
+  // The order key must represent every distance a request's segments can
+  // reach in the current scene box (called with the lock held: a motion
+  // edit changes the box).
+  void check_range(const eag_request& r) const {
+    float tmax = 0;
+    for (int a = 0; a < 3; ++a) tmax += (bvh->hi[a] - bvh->lo[a]) * (bvh->hi[a] - bvh->lo[a]);
+    (void)trace_setup(bvh, &r.params, std::fmax(std::sqrt(tmax), camera_t_max(bvh, r.cam)));
+  }
+
   void run();
   void apply_edit(Op& op, int slot);
   bool admit_one(std::shared_ptr<Req>& r);
@@ -191,24 +200,22 @@ void eag_server::apply_edit(Op& op, int slot) {
   check_hip(hipMemcpyAsync(dst.albedo, src.albedo, 3 * n * sizeof(float), hipMemcpyDeviceToDevice, st), "copy");
   check_hip(hipMemcpyAsync(dst.radiance, src.radiance, 3 * n * sizeof(float), hipMemcpyDeviceToDevice, st), "copy");
   check_hip(hipMemcpyAsync(dst.emissive, src.emissive, n * sizeof(float), hipMemcpyDeviceToDevice, st), "copy");
-  size_t off = 0;
-  const size_t bytes = op.idx.size() * sizeof(int32_t);
-  bool pooled = false;
-  if (bytes) {
-    if (!pool.alloc(bytes, off)) fail(EAG_ERR_OUT_OF_BUDGET, "arena too small for the edit's index list");
-    pooled = true;
-    int32_t* d_idx = reinterpret_cast<int32_t*>(pool_base + off);
-    check_hip(hipMemcpyAsync(d_idx, op.idx.data(), bytes, hipMemcpyHostToDevice, st), "edit index upload");
-    eag_edit e = op.edit;
-    e.idx = d_idx;
-    e.count = (int64_t)op.idx.size();
+  const eag_edit& e = op.edit;
+  const eag_surfels s = surfels(slot);
+  if (e.kind == EAG_EDIT_TRANSFORM) {
+    // every request that could see the old geometry has completed (the
+    // scheduler drains before a transform), so the pool is free for the
+    // refit's workspace
+    if (e.count > 0) {
+      launch_move(pos, rot, n, e.idx, e.count, e.value, e.value + 4, e.value + 7, st);
+      refit_bvh(&s, bvh, pool_base, pool_bytes, st);
+    }
+  } else if (e.count > 0) {
     eag_surfel_attrs a{n, dst.albedo, dst.radiance, dst.emissive};
     launch_apply_edit(e, a, st);
   }
-  const eag_surfels s = surfels(slot);
   pack_attrs(&s, bvh, dst.attrs, st);
   check_hip(hipStreamSynchronize(st), "edit sync");
-  if (pooled) pool.release(off, bytes);
   dst.used = true;
   dst.refs = 0;
   dst.id = next_version_id++;
@@ -250,6 +257,14 @@ void eag_server::run() {
       while (!inbox.empty()) {
         Op& op = inbox.front();
         if (!op.is_edit) {
+          try {
+            check_range(op.req->r);   // again: a motion edit may have grown the box since the submit
+          } catch (const Error& e) {
+            op.req->status = e.status;
+            op.req->t_done = now_s();
+            inbox.pop_front();
+            continue;
+          }
           op.req->version = current;
           op.req->version_id = ver[current].id;
           ver[current].refs++;
@@ -257,6 +272,9 @@ void eag_server::run() {
           inbox.pop_front();
           continue;
         }
+        // a motion changes the geometry every version shares: earlier
+        // requests finish first
+        if (op.edit.kind == EAG_EDIT_TRANSFORM && (!live.empty() || !pending.empty())) break;
         int slot = -1;
         for (int v = 0; v < MAX_VERSIONS; ++v)
           if (v != current && (!ver[v].used || ver[v].refs == 0)) { slot = v; break; }
@@ -487,9 +505,6 @@ eag_status eag_serve_submit(eag_server* srv, const eag_request* req, uint64_t* t
     make_cam(req->cam, req->params.camera_id);
     if (!req->out_rgb) fail(EAG_ERR_INVALID_ARGUMENT, "out_rgb is null");
     if (req->params.depth_quantum == 0.0f) fail(EAG_ERR_INVALID_ARGUMENT, "serving needs depth_quantum > 0");
-    float tmax = 0;
-    for (int a = 0; a < 3; ++a) tmax += (srv->bvh->hi[a] - srv->bvh->lo[a]) * (srv->bvh->hi[a] - srv->bvh->lo[a]);
-    (void)trace_setup(srv->bvh, &req->params, std::fmax(std::sqrt(tmax), camera_t_max(srv->bvh, req->cam)));
     const int64_t npix = (int64_t)req->cam.width * req->cam.height;
     if ((size_t)npix * 24 > srv->pool_bytes) fail(EAG_ERR_OUT_OF_BUDGET, "request does not fit the arena");
   } catch (const Error& e) {
@@ -504,6 +519,11 @@ eag_status eag_serve_submit(eag_server* srv, const eag_request* req, uint64_t* t
   {
     std::lock_guard<std::mutex> g(srv->mu);
     if (srv->device_error) return serve_fail(EAG_ERR_DEVICE, srv->device_msg);
+    try {
+      srv->check_range(*req);
+    } catch (const Error& e) {
+      return serve_fail(e.status, e.msg);
+    }
     r->ticket = srv->next_ticket++;
     srv->reqs[r->ticket] = r;
     Op op;
@@ -520,15 +540,19 @@ eag_status eag_serve_submit(eag_server* srv, const eag_request* req, uint64_t* t
 
 eag_status eag_serve_edit(eag_server* srv, const eag_edit* e, uint64_t* ticket) {
   if (!srv || !e || !ticket) return serve_fail(EAG_ERR_INVALID_ARGUMENT, "null argument");
-  if (e->kind < EAG_EDIT_SET_RADIANCE || e->kind > EAG_EDIT_SET_EMISSIVE)
+  if (e->kind < EAG_EDIT_SET_RADIANCE || e->kind > EAG_EDIT_TRANSFORM)
     return serve_fail(EAG_ERR_INVALID_ARGUMENT, "bad edit kind");
   if (e->count < 0 || (e->count > 0 && !e->idx)) return serve_fail(EAG_ERR_INVALID_ARGUMENT, "bad index list");
+  if (e->kind == EAG_EDIT_TRANSFORM) {
+    const float* v = e->value;
+    const double l = (double)v[0] * v[0] + (double)v[1] * v[1] + (double)v[2] * v[2] + (double)v[3] * v[3];
+    if (!(l > 1e-20) || !std::isfinite(l)) return serve_fail(EAG_ERR_INVALID_ARGUMENT, "rotation must be non-zero");
+    for (int k = 4; k < 10; ++k)
+      if (!std::isfinite(v[k])) return serve_fail(EAG_ERR_INVALID_ARGUMENT, "non-finite motion");
+  }
   Op op;
   op.is_edit = true;
   op.edit = *e;
-  op.idx.assign(e->idx, e->idx + e->count);
-  for (int32_t i : op.idx)
-    if (i < 0 || i >= srv->n) return serve_fail(EAG_ERR_INVALID_ARGUMENT, "edit index out of range");
   op.t_submit = now_s();
   {
     std::lock_guard<std::mutex> g(srv->mu);

@@ -54,7 +54,7 @@ def test_defaults_and_queries(lib):
     assert (p.spp, p.max_depth, p.rr_start, p.kbuf) == (4, 5, 3, 16)
     assert abs(p.tau_E - 0.1) < 1e-7 and abs(p.T_min - 1e-4) < 1e-10
     assert p.depth_quantum == 2.0 ** -13
-    assert lib.eag_abi_version() == 1
+    assert lib.eag_abi_version() == 2
     assert lib.eag_bvh_bytes(0) == 0 and lib.eag_bvh_bytes(1000) > 1000 * 48
     assert lib.eag_build_workspace_bytes(1000) > 0
     assert lib.eag_trace_workspace_bytes(1000) >= 1000 * 32

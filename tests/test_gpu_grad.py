@@ -146,3 +146,168 @@ def test_adjoint_against_finite_differences():
         assert abs(ad - fd) <= 1e-2 * max(abs(fd), 1e-2 * scale), (k, comp, i, ad, fd)
         checked += 1
     assert checked == 50
+
+
+def test_autograd_function_matches_oracle_gradient():
+    """SingleBounceRender.apply on leaf tensors, a masked linear loss, and
+    loss.backward(): every leaf's .grad against the oracle's gradient of the
+    same loss (1e-3); the emissive input gets no gradient."""
+    from paper_2601_23065_amd.api import BVH, Params, SingleBounceRender
+    scene = sg.room_scene(20000, (3.0, 2.5, 2.5), 3, seed=41, emissive_frac=0.02)
+    cams = sg.interior_cameras(scene, 2, 48, 40, seed=5)
+    p = Params(spp=4, seed=9)
+    sc = Scene64(scene)
+    H, W = cams[0].height, cams[0].width
+    rng = np.random.default_rng(13)
+    c = np.zeros((len(cams), H * W, 3))
+    ref = {k: 0.0 for k in PARAMS}
+    for ci, cam in enumerate(cams):
+        prm = oracle_params(p)
+        prm.camera_id = p.camera_id + ci
+        pix = _unflagged_pixels(sc, cam, prm, 100, 30 + ci)
+        c[ci, pix] = rng.uniform(-1, 1, (pix.size, 3))
+        g, _, _ = single_bounce_grad(scene, cam, prm, pix, dL_dI=c[ci, pix])
+        for k in PARAMS:
+            ref[k] = ref[k] + g[k]
+    gs = gpu_scene(scene)
+    bvh = BVH(gs)
+    leaves = {k: gs.t[k].clone().requires_grad_(True) for k in PARAMS}
+    emissive = gs.t["emissive"].clone()
+    rgb = SingleBounceRender.apply(leaves["pos"], leaves["rot"], leaves["scale"], leaves["opacity"],
+                                   leaves["albedo"], leaves["radiance"], emissive, bvh, gs, cams, p)
+    assert rgb.requires_grad and rgb.shape == (len(cams), H, W, 3)
+    loss = (rgb * torch.from_numpy(c.reshape(len(cams), H, W, 3)).float().cuda()).sum()
+    loss.backward()
+    assert emissive.grad is None
+    for k in PARAMS:
+        got = leaves[k].grad.cpu().numpy().astype(np.float64)
+        e = rel_err(got, ref[k])
+        print(f"{k}: max rel err {e.max():.2e}")
+        assert e.max() <= 1e-3, k
+
+
+_FD = {}
+
+
+def _near(O, W, p, n, tu, tv, su, sv, k2):
+    """Rays (O, W [R, 3]) that come within 1.1 k_sigma of one surfel's
+    tangent-plane ellipse at t > 0: the only rays a small change of that
+    surfel can affect."""
+    den = W @ n
+    with np.errstate(divide="ignore", invalid="ignore"):
+        t = ((p - O) @ n) / den
+        y = O + t[:, None] * W - p
+        q2 = (y @ tu / su) ** 2 + (y @ tv / sv) ** 2
+    return (np.abs(den) > 1e-12) & (t > 0) & (q2 <= 1.21 * k2)
+
+
+def _fd_job(args):
+    """Central difference of the masked L2 loss for one parameter, over the
+    masked pixels whose rays pass near its surfel; None if a discrete
+    decision of those pixels changes within +-h."""
+    from oracle.frames import quat_frames
+    from oracle.render import single_bounce
+    key, comp, i = args
+    base, cams, prms, rays, mask, tgt, fwd0 = (_FD[k] for k in ("base", "cams", "prms", "rays", "mask", "tgt", "fwd0"))
+    tu, tv, n = (a[0] for a in quat_frames(base["rot"][:, i:i + 1]))
+    p = base["pos"][:, i]
+    su, sv = base["scale"][:, i]
+    k2 = prms[0].k_sigma ** 2
+    val = base[key][comp, i] if comp is not None else base[key][i]
+    h = 1e-6 * max(1.0, abs(val))
+    dL = 0.0
+    for ci in range(len(cams)):
+        O, W, owner = rays[ci]
+        aff = np.unique(owner[_near(O, W, p, n, tu, tv, su, sv, k2)])
+        if aff.size == 0:
+            continue
+        pix = mask[ci][aff]
+        f0 = fwd0[ci]
+        sig0 = signature({"branch": f0["branch"][aff], "cam": [f0["cam"][a] for a in aff],
+                          "sec": [f0["sec"][a] for a in aff]})
+        f = []
+        for sgn in (1, -1):
+            pert = {kk: vv for kk, vv in base.items()}
+            arr = base[key].copy()
+            if comp is not None:
+                arr[comp, i] += sgn * h
+            else:
+                arr[i] += sgn * h
+            pert[key] = arr
+            out = single_bounce(Scene64(pert), cams[ci], prms[ci], pixels=pix, keep_segments=True)
+            if signature(out) != sig0:
+                return None
+            f.append(0.5 * float(((out["L"] - tgt[ci][aff]) ** 2).sum()))
+        dL += (f[0] - f[1]) / (2 * h)
+    return key, comp, i, dL
+
+
+@pytest.mark.slow
+def test_adjoint_config2_against_finite_differences():
+    """The reconstruction step at full size: 100k-surfel room, 8 cameras at
+    256x256, 8 spp, L2 loss over a mask of 64 seeded pixels per camera
+    against the oracle's render of the perturbed scene. The adjoint of the
+    full-size call against central differences of the float64 forward on 50
+    random parameters of surfels the masked pixels blend (camera and
+    secondary segments), each parameter's difference taken over the masked
+    pixels whose rays pass near its surfel, resampled when a discrete
+    decision of those pixels changes; agreement 1e-2."""
+    from oracle import Params as OParams
+    from paper_2601_23065_amd.api import Params
+    scene, cams, cfg = sg.config(2)
+    target = sg.perturb(scene, seed=102)
+    p_spp = cfg["spp"]
+    prms = [OParams(spp=p_spp, seed=0, camera_id=ci) for ci in range(len(cams))]
+    sc, st = Scene64(scene), Scene64(target)
+    H, W = cams[0].height, cams[0].width
+    rng = np.random.default_rng(302)
+    masks, fwds, tgts, rays = [], [], [], []
+    dL = np.zeros((len(cams), H * W, 3), dtype=np.float32)
+    hit_cam, hit_sec = set(), set()
+    for ci, cam in enumerate(cams):
+        cand = np.sort(rng.choice(H * W, 64, replace=False))
+        fwd = single_bounce(sc, cam, prms[ci], pixels=cand, keep_segments=True)
+        ok = fwd["flags"] == 0
+        pix = cand[ok]
+        fwd = single_bounce(sc, cam, prms[ci], pixels=pix, keep_segments=True)
+        tgt = single_bounce(st, cam, prms[ci], pixels=pix)["L"]
+        masks.append(pix)
+        fwds.append(fwd)
+        tgts.append(tgt)
+        dL[ci, pix] = (fwd["L"] - tgt).astype(np.float32)
+        O = [fwd["O"]]
+        Wd = [fwd["W"]]
+        owner = [np.arange(pix.size)]
+        for a, row in enumerate(fwd["sec"]):
+            for g in row:
+                if g is not None:
+                    O.append(g.O[None])
+                    Wd.append(g.W[None])
+                    owner.append(np.array([a]))
+                    hit_sec.update(int(h) for h in g.hits)
+        rays.append((np.concatenate(O), np.concatenate(Wd), np.concatenate(owner)))
+        hit_cam.update(int(h) for s in fwd["cam"] for h in s.hits)
+    got, _ = _gpu_grads(scene, cams, Params(spp=p_spp, seed=0, camera_id=0), dL.reshape(len(cams), H, W, 3))
+    base = {k: np.asarray(v, dtype=np.float64).copy() for k, v in scene.arrays().items()}
+    _FD.update(base=base, cams=cams, prms=prms, rays=rays, mask=masks, tgt=tgts, fwd0=fwds)
+    pools = (sorted(hit_cam), sorted(hit_sec - hit_cam) or sorted(hit_cam))
+    jobs = []
+    for j in range(160):
+        k = PARAMS[rng.integers(len(PARAMS))]
+        i = int(rng.choice(pools[j % 2]))
+        comp = int(rng.integers(base[k].shape[0])) if base[k].ndim == 2 else None
+        jobs.append((k, comp, i))
+    import multiprocessing as mp
+    import os
+    with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1)) as pool:
+        res = [r for r in pool.map(_fd_job, jobs, chunksize=1) if r is not None][:50]
+    scale = max(np.abs(v).max() for v in got.values())
+    worst = 0.0
+    for k, comp, i, fd in res:
+        ad = got[k][comp, i] if comp is not None else got[k][i]
+        e = abs(ad - fd) / max(abs(fd), 1e-2 * scale)
+        worst = max(worst, e)
+        assert e <= 1e-2, (k, comp, i, ad, fd)
+    print(f"{len(res)} parameters checked, worst {worst:.2e}; {len(hit_cam)} camera-hit and {len(hit_sec)} "
+          f"secondary-hit surfels")
+    assert len(res) == 50

@@ -58,7 +58,7 @@ def test_path_trace_mis_room_per_sample():
     err = rel_err(got, ref["value"], np.broadcast_to(ok[..., None], got.shape))
     print(f"paths={ok.size} unflagged={ok.mean():.3f} err={err.max():.2e} "
           f"nonzero={np.mean(ref['value'].sum(-1) > 0):.3f}")
-    assert ok.mean() > 0.4
+    assert ok.mean() >= 0.98
     assert np.mean(ref["value"].sum(-1) > 0) > 0.5
     assert err.max() <= 1e-4
 
@@ -76,7 +76,7 @@ def test_path_trace_mis_jittered_per_sample():
     ok = ref["flags"] == 0
     err = rel_err(got, ref["value"], np.broadcast_to(ok[..., None], got.shape))
     print(f"paths={ok.size} unflagged={ok.mean():.3f} err={err.max():.2e}")
-    assert ok.mean() > 0.4 and err.max() <= 1e-4
+    assert ok.mean() >= 0.98 and err.max() <= 1e-4
 
 
 @pytest.mark.parametrize("cell", [1.0, 0.25])
@@ -100,7 +100,7 @@ def test_path_trace_mis_cells_per_sample(cell):
     err = rel_err(got, ref["value"], np.broadcast_to(ok[..., None], got.shape))
     print(f"cell {cell} ({ref_em.Wc.size} cells): paths={ok.size} unflagged={ok.mean():.3f} err={err.max():.2e} "
           f"nonzero={np.mean(ref['value'].sum(-1) > 0):.3f}")
-    assert ok.mean() > 0.4 and np.mean(ref["value"].sum(-1) > 0) > 0.5
+    assert ok.mean() >= 0.98 and np.mean(ref["value"].sum(-1) > 0) > 0.5
     assert err.max() <= 1e-4
 
 
@@ -163,7 +163,7 @@ def test_single_emitter_over_a_receiver_per_sample(cell):
     ok = ref["flags"] == 0
     err = rel_err(got, ref["value"], np.broadcast_to(ok[..., None], got.shape))
     print(f"unflagged={ok.mean():.3f} err={err.max():.2e} nonzero={np.mean(ref['value'].sum(-1) > 0):.3f}")
-    assert ok.mean() > 0.9 and np.mean(ref["value"].sum(-1) > 0) > 0.3
+    assert ok.mean() >= 0.98 and np.mean(ref["value"].sum(-1) > 0) > 0.3
     assert err.max() <= 1e-4
 
 
@@ -206,7 +206,7 @@ def test_lights_off_then_rebuilt_table():
     ok = ref["flags"] == 0
     err = rel_err(got, ref["value"], np.broadcast_to(ok[..., None], got.shape))
     print(f"paths={ok.size} unflagged={ok.mean():.3f} err={err.max():.2e}")
-    assert ok.mean() > 0.4 and err.max() <= 1e-4
+    assert ok.mean() >= 0.98 and err.max() <= 1e-4
 
 
 _ORACLE = {}
@@ -232,11 +232,11 @@ def test_path_trace_mis_full_size_sampled_pixels():
     gs = gpu_scene(scene)
     bvh = BVH(gs)
     em = Emitters(gs, p)
-    acc = path_trace_mis(bvh, gs, em, cam, p, 0, p.spp)
+    counters = torch.zeros(7, dtype=torch.int64, device="cuda")
+    acc = path_trace_mis(bvh, gs, em, cam, p, 0, p.spp, counters=counters)
     got = acc.cpu().numpy().reshape(-1, 3).astype(np.float64) / 2.0 ** 32
 
-    rng = np.random.default_rng(12)
-    pixels = rng.choice(cam.width * cam.height, 3, replace=False)
+    pixels = np.random.default_rng(12).choice(cam.width * cam.height, 36, replace=False)
     sc = Scene64(scene)
     prm = OParams(spp=p.spp, max_depth=p.max_depth, rr_start=p.rr_start, seed=0, camera_id=0)
     _ORACLE.update(sc=sc, cam=cam, prm=prm, em=OEmitters(sc, prm.tau_E))
@@ -249,7 +249,42 @@ def test_path_trace_mis_full_size_sampled_pixels():
         ref[px] += v
         flagged[px] |= f
     ok = [px for px in ref if not flagged[px]]
-    print(f"pixels {list(ref)} flagged {flagged} gpu {[got[px] for px in ok]} oracle {[ref[px] for px in ok]}")
-    assert len(ok) >= 2
+    nz = [px for px in ok if np.any(ref[px] != 0)]
+    print(f"{len(ref)} pixels: {len(ok)} unflagged, {len(nz)} nonzero; gpu {[got[px] for px in nz[:3]]} "
+          f"oracle {[ref[px] for px in nz[:3]]}")
+    assert len(ok) >= 32 and len(nz) >= 32
     err = rel_err(np.stack([got[px] for px in ok]), np.stack([ref[px] for px in ok]))
+    print(f"max rel err {err.max():.2e}")
     assert err.max() <= 1e-4
+    assert int(counters[6]) == 0
+
+
+@pytest.mark.parametrize("cell", [0.0, 1.0])
+def test_launch_chunks_and_small_workspace_are_exact(cell):
+    """One call over samples 2-10 spans launches of four samples (2-5, 6-9,
+    10), each with its own light-pdf queue and settle pass. Its fixed-point
+    accumulator equals the sum of nine one-sample calls bit for bit, with
+    selection by power and by cells; so does the same call with a workspace
+    whose queue holds one sample (nine launches). No queued contribution is
+    dropped."""
+    from paper_2601_23065_amd.api import BVH, Emitters, Params, _bytes, path_trace_mis, path_trace_mis_workspace
+    from paper_2601_23065_amd import load
+    scene, cam = _small_room()
+    p = Params(spp=16, max_depth=5, rr_start=3, camera_id=5, seed=77)
+    gs = gpu_scene(scene)
+    bvh = BVH(gs)
+    em = Emitters(gs, p, cell=cell)
+    c = torch.zeros(7, dtype=torch.int64, device="cuda")
+    whole = path_trace_mis(bvh, gs, em, cam, p, sample_begin=2, sample_count=9, counters=c)
+    acc = None
+    for s in range(2, 11):
+        acc = path_trace_mis(bvh, gs, em, cam, p, sample_begin=s, sample_count=1, accum=acc, counters=c)
+    full = path_trace_mis_workspace(gs, cam, p)
+    queue_4 = full.numel() - load().eag_path_trace_workspace_bytes(scene.n)
+    small = _bytes(full.numel() - queue_4 * 3 // 4 + 1024, gs.device)   # room for one sample's queue
+    chunked = path_trace_mis(bvh, gs, em, cam, p, sample_begin=2, sample_count=9, ws=small, counters=c)
+    torch.cuda.synchronize()
+    print(f"cell {cell}: image sum {int(whole.sum())}; counters {c.tolist()}")
+    assert torch.equal(whole, acc) and torch.equal(whole, chunked)
+    assert int(whole.abs().sum()) > 0
+    assert int(c[6]) == 0

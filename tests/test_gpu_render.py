@@ -26,7 +26,7 @@ def test_single_bounce_config1_full_image():
     ok = ref["flags"] == 0
     err = rel_err(rgb, ref["L"], np.broadcast_to(ok[:, None], rgb.shape))
     print(f"pixels={ok.size} unflagged={ok.mean():.3f} max_err={err.max():.2e} branches={np.bincount(ref['branch'])}")
-    assert ok.mean() > 0.5
+    assert ok.mean() >= 0.98
     assert err.max() <= 1e-4
     # miss pixels are exactly zero, emitter pixels carry R
     miss = ref["branch"] == 0
@@ -53,7 +53,7 @@ def test_single_bounce_room_per_sample(jitter):
     st = state[:npix * 28].view(npix, 28).cpu().numpy()
     ref = o_single_bounce(Scene64(scene), cam, oracle_params(p))
     ok = ref["flags"] == 0
-    assert ok.mean() > 0.5
+    assert ok.mean() >= 0.98
     np.testing.assert_array_equal(st[:, 25].astype(int)[ok], ref["branch"][ok])
     e1 = rel_err(r1, ref["R1"], np.broadcast_to(ok[:, None, None], r1.shape))
     eL = rel_err(rgb[0].cpu().numpy().reshape(-1, 3), ref["L"], np.broadcast_to(ok[:, None], (npix, 3)))
@@ -81,7 +81,7 @@ def test_path_trace_room_per_sample():
     ok = ref["flags"] == 0
     err = rel_err(got, ref["value"], np.broadcast_to(ok[..., None], got.shape))
     print(f"paths={ok.size} unflagged={ok.mean():.3f} err={err.max():.2e} nonzero={np.mean(ref['value'].sum(-1) > 0):.3f}")
-    assert ok.mean() > 0.4
+    assert ok.mean() >= 0.98
     assert err.max() <= 1e-4
 
 
@@ -113,7 +113,7 @@ def test_path_trace_other_readings_per_sample(case):
     err = rel_err(got, ref["value"], np.broadcast_to(ok[..., None], got.shape))
     print(f"{case}: paths={ok.size} unflagged={ok.mean():.3f} err={err.max():.2e} "
           f"nonzero={np.mean(ref['value'].sum(-1) > 0):.3f}")
-    assert ok.mean() > 0.4 and err.max() <= 1e-4
+    assert ok.mean() >= 0.98 and err.max() <= 1e-4
     assert np.mean(ref["value"].sum(-1) > 0) > 0.05
 
 
@@ -133,7 +133,7 @@ def test_path_trace_jittered_camera_rays_per_sample():
     ok = ref["flags"] == 0
     err = rel_err(got, ref["value"], np.broadcast_to(ok[..., None], got.shape))
     print(f"paths={ok.size} unflagged={ok.mean():.3f} err={err.max():.2e}")
-    assert ok.mean() > 0.4 and err.max() <= 1e-4
+    assert ok.mean() >= 0.98 and err.max() <= 1e-4
     # the jitter moves the camera rays: sample 0 differs from the pixel-centre render
     centre = _pt_per_sample(bvh, gs, cam, Params(spp=1, max_depth=4, rr_start=2, camera_id=1, seed=7), [0])
     assert not np.array_equal(centre[:, 0], got[:, 0])
@@ -191,7 +191,7 @@ def test_path_trace_deep_coplanar_stack(layers):
     err = rel_err(got, ref["value"], np.broadcast_to(ok[..., None], got.shape))
     print(f"layers={layers} paths={ok.size} unflagged={ok.mean():.3f} err={err.max():.2e} "
           f"mean={ref['value'].mean():.3f}")
-    assert ok.mean() > 0.5
+    assert ok.mean() >= 0.98
     assert err.max() <= 1e-4
     # every camera ray blends the whole stack, 16 keys per k-buffer round
     from paper_2601_23065_amd.api import path_trace
@@ -201,3 +201,25 @@ def test_path_trace_deep_coplanar_stack(layers):
     assert seg == ok.size
     assert hits == seg * layers
     assert rounds >= seg * -(-layers // 16)
+
+
+def test_side_stream_equals_current_stream():
+    """Every call given a stream other than torch's current one: the BVH
+    built, the accumulator created and cleared, and the paths traced on a
+    side stream, and a single-bounce render there, equal the same calls on
+    the current stream bit for bit."""
+    from paper_2601_23065_amd.api import BVH, Params, path_trace, render_single_bounce
+    scene, cam = _small_room()
+    p = Params(spp=4, max_depth=4, rr_start=2, seed=12)
+    gs = gpu_scene(scene)
+    bvh = BVH(gs)
+    ref_pt = path_trace(bvh, gs, cam, p)
+    ref_sb = render_single_bounce(bvh, gs, [cam], p)
+    side = torch.cuda.Stream()
+    bvh_side = BVH(gs, stream=side)
+    pt = path_trace(bvh_side, gs, cam, p, stream=side)
+    sb = render_single_bounce(bvh_side, gs, [cam], p, stream=side)
+    side.synchronize()
+    torch.cuda.synchronize()
+    assert torch.equal(pt, ref_pt) and int(pt.abs().sum()) > 0
+    assert torch.equal(sb, ref_sb)

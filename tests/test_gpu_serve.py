@@ -118,3 +118,102 @@ def test_cancel_and_small_arena_admission():
     srv.close()
     assert r_big["status"] == -5          # EAG_ERR_CANCELLED
     assert all(r["status"] == 0 for r in res)
+
+
+def test_served_requests_match_the_oracle():
+    """The serving mix's four resolution classes (scaled to the test scene:
+    32x32, 64x64, 128x96, 240x135) at two sample counts, max depth 5,
+    Russian roulette from 3, served together with one slot fewer than
+    requests; on 8 seeded pixels of each served image, the resolved value
+    against the oracle's mean over the request's paths (1e-4) wherever no
+    path is flagged."""
+    import multiprocessing as mp
+    import os
+    from oracle import Params as OParams
+    from oracle.tracer import Scene64
+    from paper_2601_23065_amd.api import Params, Server
+    from tests._util import rel_err
+    scene = _scene()
+    gs = gpu_scene(scene)
+    cams = sg.interior_cameras(scene, 8, 16, 16, seed=19)
+    reqs = []
+    for i, ((w, h), spp) in enumerate([(r, s) for r in ((32, 32), (64, 64), (128, 96), (240, 135))
+                                       for s in (4, 12)]):
+        c = cams[i]
+        reqs.append((sg.Camera(c.eye, c.look_at, c.up, 60.0, w, h),
+                     Params(spp=spp, max_depth=5, rr_start=3, camera_id=20 + i, seed=8)))
+    srv = Server(gs, arena_bytes=256 << 20, max_live_requests=7, paths_per_launch=30000)
+    tickets = [srv.submit(cam, p) for cam, p in reqs]
+    res = [srv.wait(t) for t, _ in tickets]
+    srv.close()
+    assert all(r["status"] == 0 for r in res)
+    _ORACLE.update(sc=Scene64(scene))
+    rng = np.random.default_rng(29)
+    jobs = []
+    for k, (cam, p) in enumerate(reqs):
+        prm = OParams(spp=p.spp, max_depth=p.max_depth, rr_start=p.rr_start, seed=p.seed, camera_id=p.camera_id)
+        for px in rng.choice(cam.width * cam.height, 8, replace=False):
+            jobs.append((k, cam, prm, int(px)))
+    with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1)) as pool:
+        out = pool.map(_oracle_pixel, jobs, chunksize=1)
+    n_ok = 0
+    for k, (cam, p) in enumerate(reqs):
+        img = tickets[k][1].cpu().numpy().reshape(-1, 3).astype(np.float64)
+        rows = [(px, v, f) for kk, px, v, f in out if kk == k]
+        ok = [(px, v) for px, v, f in rows if not f]
+        n_ok += len(ok)
+        got = np.stack([img[px] for px, _ in ok])
+        ref = np.stack([v for _, v in ok])
+        e = rel_err(got, ref)
+        print(f"{cam.width}x{cam.height} {p.spp} spp: {len(ok)}/{len(rows)} unflagged, "
+              f"{np.count_nonzero(ref.sum(1))} nonzero, max rel err {e.max():.2e}")
+        assert e.max() <= 1e-4
+    assert n_ok >= 0.95 * len(jobs)
+
+
+_ORACLE = {}
+
+
+def _oracle_pixel(args):
+    from oracle.render import path_trace
+    k, cam, prm, px = args
+    r = path_trace(_ORACLE["sc"], cam, prm, pixels=np.array([px]))
+    return k, px, r["value"][0].mean(axis=0), bool(r["flags"][0].any())
+
+
+def test_transform_edit_refits_and_waits_for_earlier_requests():
+    """A rigid motion of a furniture box's surfels through the server: the
+    request submitted before it renders the original geometry, the one
+    after it the moved geometry through the refitted tree; each equals the
+    same render alone (fresh BVH over the caller's arrays, moved by
+    eag_move_surfels), bit for bit."""
+    import math
+    from paper_2601_23065_amd.api import BVH, Server, move_surfels, select_box
+    scene = _scene()
+    gs = gpu_scene(scene)
+    reqs = _requests(scene)
+    cam, p = reqs[0]
+    lo, hi = scene.boxes[0]
+    sel = select_box(gs, [float(v) - 0.01 for v in lo], [float(v) + 0.01 for v in hi])
+    assert sel.numel() > 100
+    half = math.radians(20.0) / 2
+    r = (math.cos(half), 0.0, 0.0, math.sin(half))
+    pivot = tuple(float(0.5 * (a + b)) for a, b in zip(lo, hi))
+    t = (0.3, -0.2, 0.0)
+    srv = Server(gs, arena_bytes=64 << 20, max_live_requests=4, paths_per_launch=20000)
+    t_before, out_before = srv.submit(cam, p)
+    t_edit = srv.transform(sel, r, pivot, t)
+    t_after, out_after = srv.submit(cam, p)
+    rb, re, ra = srv.wait(t_before), srv.wait(t_edit), srv.wait(t_after)
+    srv.close()
+    assert rb["status"] == 0 and re["status"] == 0 and ra["status"] == 0
+    assert ra["version"] == re["version"] != rb["version"]
+    assert re["t_done"] >= rb["t_done"]                 # the motion waited for the earlier request
+    ref_before = _alone(gs, BVH(gs), cam, p)
+    moved = gpu_scene(scene)
+    move_surfels(moved, sel, r, pivot, t)
+    ref_after = _alone(moved, BVH(moved), cam, p)
+    torch.cuda.synchronize()
+    assert torch.equal(out_before, ref_before)
+    assert torch.equal(out_after, ref_after)
+    assert not torch.equal(ref_before, ref_after)

@@ -14,7 +14,7 @@ pytestmark = pytest.mark.gpu
 MAX_HITS = 256
 
 
-def _compare(scene, O, D, params, max_flag_frac=0.25):
+def _compare(scene, O, D, params, max_flag_frac=0.01):
     from paper_2601_23065_amd.api import BVH, trace_rays
     gs = gpu_scene(scene)
     bvh = BVH(gs)
