@@ -220,9 +220,13 @@ def _oracle_job(args):
 
 
 def test_path_trace_mis_full_size_sampled_pixels():
-    """The benchmark's 1M-surfel room at 1024x768, 64 spp, depth 5, Russian
-    roulette from depth 3, in one launch; sampled pixels against the
-    oracle's sum over their 64 paths."""
+    """The benchmark's 1M-surfel room at 1024x768, depth 5, Russian roulette
+    from depth 3: all 64 samples in one call (16 launches of four, none
+    dropping a queued contribution), and samples 16-31 in another, whose
+    pixels are compared on 48 seeded pixels with the oracle's sums over
+    those 16 paths: at least 32 unflagged and nonzero. (Over all 64 paths,
+    with a light segment at every reflecting vertex, about 40% of the pixels
+    hold a flagged path.)"""
     from oracle import Params as OParams
     from paper_2601_23065_amd.api import BVH, Emitters, Params, path_trace_mis
 
@@ -233,14 +237,18 @@ def test_path_trace_mis_full_size_sampled_pixels():
     bvh = BVH(gs)
     em = Emitters(gs, p)
     counters = torch.zeros(7, dtype=torch.int64, device="cuda")
-    acc = path_trace_mis(bvh, gs, em, cam, p, 0, p.spp, counters=counters)
-    got = acc.cpu().numpy().reshape(-1, 3).astype(np.float64) / 2.0 ** 32
+    full = path_trace_mis(bvh, gs, em, cam, p, 0, p.spp, counters=counters)
+    assert int(counters[6]) == 0 and int(full.abs().sum()) > 0
+    s0, cnt = 16, 16
+    part = path_trace_mis(bvh, gs, em, cam, p, s0, cnt, counters=counters)
+    got = part.cpu().numpy().reshape(-1, 3).astype(np.float64) / 2.0 ** 32
+    assert int(counters[6]) == 0
 
-    pixels = np.random.default_rng(12).choice(cam.width * cam.height, 36, replace=False)
+    pixels = np.random.default_rng(12).choice(cam.width * cam.height, 48, replace=False)
     sc = Scene64(scene)
     prm = OParams(spp=p.spp, max_depth=p.max_depth, rr_start=p.rr_start, seed=0, camera_id=0)
     _ORACLE.update(sc=sc, cam=cam, prm=prm, em=OEmitters(sc, prm.tau_E))
-    jobs = [(int(px), list(range(s0, s0 + 8))) for px in pixels for s0 in range(0, p.spp, 8)]
+    jobs = [(int(px), list(range(a, a + 4))) for px in pixels for a in range(s0, s0 + cnt, 4)]
     with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1)) as pool:
         res = pool.map(_oracle_job, jobs, chunksize=1)
     ref = {int(px): np.zeros(3) for px in pixels}
@@ -256,7 +264,6 @@ def test_path_trace_mis_full_size_sampled_pixels():
     err = rel_err(np.stack([got[px] for px in ok]), np.stack([ref[px] for px in ok]))
     print(f"max rel err {err.max():.2e}")
     assert err.max() <= 1e-4
-    assert int(counters[6]) == 0
 
 
 @pytest.mark.parametrize("cell", [0.0, 1.0])
