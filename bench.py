@@ -91,9 +91,23 @@ def _oracle_worker(args):
 _ORACLE = {}
 
 
-def cpu_baseline(scene, cam, params, budget_paths=1024):
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(scene, cam, params, full_segments, budget_paths=1024):
     """Oracle segments/s on a fixed sample of the workload's paths, across
-    the host cores with a fork pool."""
+    the host cores this process may use (at most 16, the host's share per
+    GPU) with a fork pool, and the time the oracle would take for the whole
+    workload at that rate (extrapolated, not run)."""
     import multiprocessing as mp
 
     from oracle import Params
@@ -104,16 +118,25 @@ def cpu_baseline(scene, cam, params, budget_paths=1024):
     rng = np.random.default_rng(7)
     pix = rng.choice(cam.width * cam.height, budget_paths, replace=False)
     samp = rng.integers(0, params.spp, budget_paths)
-    cores = min(os.cpu_count() or 1, 16, budget_paths)
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    cores = min(usable, 16, budget_paths)
     jobs = [(np.array([p]), [int(s)]) for p, s in zip(pix, samp)]
     t0 = time.perf_counter()
     with mp.get_context("fork").Pool(cores) as pool:
         res = pool.map(_oracle_worker, jobs, chunksize=1)
     wall = time.perf_counter() - t0
     segs = sum(r[0] for r in res)
-    return {"value": segs / wall / 1e6, "unit": "Mrays/s", "cores": cores, "kind": "oracle",
+    rate = segs / wall
+    return {"value": rate / 1e6, "unit": "Mrays/s", "cores": cores, "kind": "oracle",
             "sample": f"{budget_paths} random (pixel, sample) paths of the same frame, {segs} segments, "
-                      f"{wall:.1f} s wall on {cores} processes"}
+                      f"{wall:.1f} s wall on {cores} processes",
+            "host": {"os_cpu_count": os.cpu_count(), "usable_cpus": usable, "cpu_model": _cpu_model()},
+            "extrapolated_full_workload_s": round(full_segments / rate, 1),
+            "extrapolated_note": f"extrapolated, not run: the workload's {int(full_segments)} segments per step "
+                                 f"at the sampled oracle rate on {cores} processes"}
 
 
 def copy_calibration(torch, mib):
@@ -908,7 +931,7 @@ def main():
     }
     if not args.no_cpu:
         _log("oracle CPU baseline")
-        rec["cpu_baseline"] = cpu_baseline(scene, cam, params)
+        rec["cpu_baseline"] = cpu_baseline(scene, cam, params, segments)
     print(json.dumps(rec))
 
 

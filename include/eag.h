@@ -35,7 +35,13 @@
  *     Input buffers must stay alive until the stream reaches the call.
  *   - Asynchronous device faults surface as EAG_ERR_DEVICE from a later
  *     call; host-side validation errors return EAG_ERR_INVALID_ARGUMENT and
- *     launch nothing.
+ *     launch nothing. Errors only the kernels can see reach a later call the
+ *     same way, through a word of mapped host memory the library allocates
+ *     once per process: a hit farther than the order key's last depth bucket
+ *     (max_bucket * depth_quantum, with 64 - 2 ceil(log2 n) bucket bits; 32 m
+ *     at 2^23 surfels and the default quantum) marks that launch's results
+ *     invalid, and the next call returns EAG_ERR_DEVICE asking for a larger
+ *     depth_quantum.
  *   - Arrays are component-major (structure of arrays) float32:
  *     a "[3][n]" array holds x[0..n), then y[0..n), then z[0..n).
  */
@@ -164,15 +170,21 @@ typedef struct {
 
 size_t eag_bvh_bytes(int64_t n);
 size_t eag_build_workspace_bytes(int64_t n);
-/* Build. Synchronises `stream` once at the end to read back depth and bounds.
- * bvh_mem: device, >= eag_bvh_bytes(n), 256-B aligned, owned by the caller and
- * referenced by the handle until eag_bvh_destroy. ws: device scratch, only
- * used during the call. */
+/* Build. Stream-ordered and asynchronous: the call enqueues the build on
+ * `stream` and returns; depths, node count and bounds stay on the device
+ * (eag_bvh_get_info waits for them). bvh_mem: device, >= eag_bvh_bytes(n),
+ * 256-B aligned, owned by the caller and referenced by the handle until
+ * eag_bvh_destroy. ws: device scratch, in use until the stream reaches the
+ * end of the build. Any tree the build can make fits the traversal stack
+ * (at most 63 + ceil(log2 n) levels), so nothing is checked after it. */
 eag_status eag_build_bvh(const eag_surfels* s, void* bvh_mem, size_t bvh_bytes,
                          void* ws, size_t ws_bytes, void* stream, eag_bvh** out);
 /* Recompute frames, records and node bounds after a geometry edit that keeps
- * n; topology is kept (Morton order of the build). Synchronises `stream`. */
+ * n; topology is kept (Morton order of the build). Stream-ordered and
+ * asynchronous, like the build. */
 eag_status eag_refit_bvh(eag_bvh* bvh, const eag_surfels* s, void* ws, size_t ws_bytes, void* stream);
+/* Waits for the last build or refit of the handle (host-blocking, the one
+ * BVH call that is) and reports its shape and bounds. */
 eag_status eag_bvh_get_info(const eag_bvh* bvh, eag_bvh_info* out);
 void eag_bvh_destroy(eag_bvh* bvh);
 

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -24,6 +25,7 @@ eag_status set_error(eag_status s, const std::string& m) {
 template <class F>
 eag_status guarded(F&& f) {
   try {
+    check_device_status();
     f();
     return EAG_OK;
   } catch (const Error& e) {
@@ -56,6 +58,49 @@ void check_hip(hipError_t e, const char* what) {
   if (e != hipSuccess) fail(EAG_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+// Errors that only a kernel can see reach the host through one word of
+// mapped host memory per process: a kernel stores its code there, and the
+// next call into the library reports and clears it (calls stay
+// asynchronous; the report comes one call late, as for other device errors).
+namespace {
+std::mutex g_status_mu;
+unsigned int* g_status = nullptr;
+}  // namespace
+
+unsigned int* device_status_word() {
+  std::lock_guard<std::mutex> g(g_status_mu);
+  if (!g_status) {
+    void* p = nullptr;
+    check_hip(hipHostMalloc(&p, 256, hipHostMallocMapped), "status word");
+    g_status = static_cast<unsigned int*>(p);
+    __atomic_store_n(g_status, 0u, __ATOMIC_SEQ_CST);
+  }
+  return g_status;
+}
+
+void check_device_status() {
+  unsigned int* w = g_status;
+  if (!w) return;
+  const unsigned int code = __atomic_exchange_n(w, 0u, __ATOMIC_SEQ_CST);
+  if (code & EAG_DEVICE_KEY_RANGE)
+    fail(EAG_ERR_DEVICE, "an earlier launch met a hit beyond the order key's last depth bucket "
+                         "(max_bucket * depth_quantum): raise depth_quantum; its results are invalid");
+  if (code) fail(EAG_ERR_DEVICE, "an earlier launch reported a device error");
+}
+
+void bvh_sync_host(eag_bvh* b) {
+  check_hip(hipEventSynchronize(b->built), "bvh build wait");
+  BvhHeader h;
+  check_hip(hipMemcpy(&h, b->hdr, sizeof(h), hipMemcpyDeviceToHost), "bvh header read");
+  for (int a = 0; a < 3; ++a) {
+    b->lo[a] = header_float(h.blo[a]);
+    b->hi[a] = header_float(h.bhi[a]);
+  }
+  b->max_depth = h.max_depth;
+  b->n_nodes4 = h.n_nodes4;
+  b->depth4 = h.depth4;
+}
+
 void validate_params(const eag_trace_params* p) {
   if (!p) fail(EAG_ERR_INVALID_ARGUMENT, "params is null");
   if (p->kbuf != KBUF) fail(EAG_ERR_INVALID_ARGUMENT, "kbuf must be 16");
@@ -70,7 +115,7 @@ void validate_params(const eag_trace_params* p) {
     fail(EAG_ERR_INVALID_ARGUMENT, "depth_quantum must be 0 or a power of two");
 }
 
-TraceSetup trace_setup(const eag_bvh* b, const eag_trace_params* p, float t_max_needed) {
+TraceSetup trace_setup(const eag_bvh* b, const eag_trace_params* p) {
   TraceSetup ts;
   ts.idx_bits = b->idx_bits;
   const int bucket_bits = 64 - 2 * ts.idx_bits;
@@ -79,14 +124,14 @@ TraceSetup trace_setup(const eag_bvh* b, const eag_trace_params* p, float t_max_
     ts.max_bucket = 0xffffffffu;
     ts.inv_dq = 0.0;
   } else {
+    // A distance beyond the last bucket (max_bucket * depth_quantum) is
+    // detected by the kernels (device status), not here: the scene's extent
+    // lives on the device, and the calls do not wait for it.
     ts.max_bucket = bucket_bits >= 32 ? 0xffffffffu : ((1u << bucket_bits) - 1u);
     ts.inv_dq = 1.0 / (double)p->depth_quantum;
-    const double t_rep = (double)ts.max_bucket * (double)p->depth_quantum;
-    if ((double)t_max_needed >= t_rep)
-      fail(EAG_ERR_INVALID_ARGUMENT, "scene too deep for the order key at this depth_quantum and surfel count "
-                                     "(raise depth_quantum)");
   }
-  if (3 * b->depth4 > STACK_SIZE) fail(EAG_ERR_INTERNAL, "BVH deeper than the traversal stack");
+  // (the traversal stack holds 3 entries per level of any tree the build
+  // can make: STACK_SIZE covers the deepest)
   return ts;
 }
 
@@ -122,24 +167,6 @@ CamDev make_cam(const eag_camera& c, uint32_t id) {
   d.id = id;
   d.pad = 0;
   return d;
-}
-
-// Largest distance from the camera to a point of the scene box (its
-// farthest corner): no camera-ray hit lies farther.
-float camera_t_max(const eag_bvh* b, const eag_camera& c) {
-  double d2 = 0;
-  for (int a = 0; a < 3; ++a) {
-    const double lo = b->lo[a], hi = b->hi[a], e = c.eye[a];
-    const double far = std::fmax(std::fabs(e - lo), std::fabs(e - hi));
-    d2 += far * far;
-  }
-  return (float)std::sqrt(d2);
-}
-
-float scene_t_max(const eag_bvh* b) {
-  double diag2 = 0;
-  for (int a = 0; a < 3; ++a) diag2 += (double)(b->hi[a] - b->lo[a]) * (b->hi[a] - b->lo[a]);
-  return (float)std::sqrt(diag2);
 }
 
 }  // namespace eag
@@ -246,9 +273,7 @@ struct BakeCall {
 
 BakeCall bake_setup(const eag_bvh* b, const eag_surfels* s, const eag_camera* cams, int32_t n_cams,
                     const eag_trace_params* p, const BakeWs& w, hipStream_t st) {
-  float t_max = scene_t_max(b);
-  for (int i = 0; i < n_cams; ++i) t_max = std::fmax(t_max, camera_t_max(b, cams[i]));
-  const TraceSetup ts = trace_setup(b, p, t_max);
+  const TraceSetup ts = trace_setup(b, p);
   pack_attrs(s, b, w.attrs, st);
   BakeCall k;
   k.tc = make_ctx(b, w.attrs, p, ts);
@@ -381,14 +406,12 @@ eag_status eag_build_bvh(const eag_surfels* s, void* bvh_mem, size_t bvh_bytes, 
     b->leaf_parent = l.leaf_parent;
     b->node_parent = l.node_parent;
     try {
+      check_hip(hipEventCreateWithFlags(&b->built, hipEventDisableTiming), "build event");
       build_bvh(s, b, ws, ws_bytes, static_cast<hipStream_t>(stream));
     } catch (...) {
+      if (b->built) (void)hipEventDestroy(b->built);
       delete b;
       throw;
-    }
-    if (3 * b->depth4 > STACK_SIZE) {
-      delete b;
-      fail(EAG_ERR_INTERNAL, "BVH deeper than the traversal stack");
     }
     *out = b;
   });
@@ -405,6 +428,9 @@ eag_status eag_refit_bvh(eag_bvh* b, const eag_surfels* s, void* ws, size_t ws_b
 eag_status eag_bvh_get_info(const eag_bvh* b, eag_bvh_info* out) {
   return guarded([&] {
     if (!b || !out) fail(EAG_ERR_INVALID_ARGUMENT, "null argument");
+    // the one BVH call that waits: for the last build or refit, then reads
+    // the header the device wrote
+    bvh_sync_host(const_cast<eag_bvh*>(b));
     out->n = b->n;
     out->max_depth = b->max_depth;
     out->root = b->root;
@@ -421,7 +447,11 @@ eag_status eag_bvh_get_info(const eag_bvh* b, eag_bvh_info* out) {
   });
 }
 
-void eag_bvh_destroy(eag_bvh* b) { delete b; }
+void eag_bvh_destroy(eag_bvh* b) {
+  if (!b) return;
+  if (b->built) (void)hipEventDestroy(b->built);
+  delete b;
+}
 
 size_t eag_trace_workspace_bytes(int64_t n) { return n < 1 ? 0 : render_ws(nullptr, n, 0, 0, false).bytes; }
 
@@ -437,10 +467,7 @@ eag_status eag_trace_rays(const eag_bvh* b, const eag_surfels* s, const eag_trac
     const RenderWs w = render_ws(ws, b->n, 0, 0, false);
     if (!ws || ws_bytes < w.bytes) fail(EAG_ERR_WORKSPACE_TOO_SMALL, "trace workspace too small");
     if (n_rays == 0) return;
-    // rays may start anywhere: allow the key range for a ray from far outside
-    double far = 0;
-    for (int a = 0; a < 3; ++a) far = std::fmax(far, std::fmax(std::fabs(b->lo[a]), std::fabs(b->hi[a])));
-    const TraceSetup ts = trace_setup(b, p, (float)(4.0 * far + scene_t_max(b)));
+    const TraceSetup ts = trace_setup(b, p);
     hipStream_t st = static_cast<hipStream_t>(stream);
     pack_attrs(s, b, w.attrs, st);
     launch_trace_rays(b, w.attrs, p, ts, n_rays, origins, dirs, out, hit_idx, hit_count, max_hits, stats, st);
@@ -487,9 +514,7 @@ eag_status eag_render_single_bounce(const eag_bvh* b, const eag_surfels* s, cons
     const int64_t np = hw * n_cams;
     const RenderWs w = render_ws(ws, b->n, np, p->spp, true, runner_lanes());
     if (!ws || ws_bytes < w.bytes) fail(EAG_ERR_WORKSPACE_TOO_SMALL, "render workspace too small");
-    float t_max = scene_t_max(b);
-    for (int i = 0; i < n_cams; ++i) t_max = std::fmax(t_max, camera_t_max(b, cams[i]));
-    const TraceSetup ts = trace_setup(b, p, t_max);
+    const TraceSetup ts = trace_setup(b, p);
     hipStream_t st = static_cast<hipStream_t>(stream);
     pack_attrs(s, b, w.attrs, st);
     const TraceCtx tc = make_ctx(b, w.attrs, p, ts);
@@ -526,9 +551,7 @@ eag_status eag_single_bounce_backward(const eag_bvh* b, const eag_surfels* s, co
     const int64_t np = hw * n_cams;
     const RenderWs w = render_ws(ws, b->n, np, p->spp, true, runner_lanes(), hw * MAX_CAMS_PER_LAUNCH, true);
     if (!ws || ws_bytes < w.bytes) fail(EAG_ERR_WORKSPACE_TOO_SMALL, "backward workspace too small");
-    float t_max = scene_t_max(b);
-    for (int i = 0; i < n_cams; ++i) t_max = std::fmax(t_max, camera_t_max(b, cams[i]));
-    const TraceSetup ts = trace_setup(b, p, t_max);
+    const TraceSetup ts = trace_setup(b, p);
     hipStream_t st = static_cast<hipStream_t>(stream);
     pack_attrs(s, b, w.attrs, st);
     const TraceCtx tc = make_ctx(b, w.attrs, p, ts);
@@ -602,7 +625,7 @@ eag_status eag_path_trace(const eag_bvh* b, const eag_surfels* s, const eag_came
     const RenderWs w = render_ws(ws, b->n, 0, 0, false, runner_lanes());
     if (!ws || ws_bytes < w.bytes) fail(EAG_ERR_WORKSPACE_TOO_SMALL, "path-trace workspace too small");
     const CamDev cd = make_cam(*cam, p->camera_id);
-    const TraceSetup ts = trace_setup(b, p, std::fmax(scene_t_max(b), camera_t_max(b, *cam)));
+    const TraceSetup ts = trace_setup(b, p);
     if (sample_count == 0) return;
     hipStream_t st = static_cast<hipStream_t>(stream);
     pack_attrs(s, b, w.attrs, st);
@@ -670,7 +693,7 @@ eag_status eag_emitters_get_info(const eag_emitters* em, int64_t* count, double*
 
 void eag_emitters_destroy(eag_emitters* em) {
   if (!em) return;
-  delete em->bvh;
+  eag_bvh_destroy(em->bvh);
   delete em;
 }
 
@@ -713,7 +736,7 @@ eag_status eag_path_trace_mis(const eag_bvh* b, const eag_surfels* s, const eag_
     const int64_t entries = per_sample * chunk;
     void* queue = static_cast<char*>(ws) + w.bytes;
     const CamDev cd = make_cam(*cam, p->camera_id);
-    const TraceSetup ts = trace_setup(b, p, std::fmax(scene_t_max(b), camera_t_max(b, *cam)));
+    const TraceSetup ts = trace_setup(b, p);
     if (sample_count == 0) return;
     hipStream_t st = static_cast<hipStream_t>(stream);
     pack_attrs(s, b, w.attrs, st);
@@ -847,9 +870,7 @@ eag_status eag_render_stage0(const eag_bvh* b, const eag_surfels* s, const eag_c
     const Stage0Ws w = stage0_ws(ws, b->n, hw * n_cams, hw * MAX_CAMS_PER_LAUNCH, runner_lanes());
     if (!ws || ws_bytes < w.bytes) fail(EAG_ERR_WORKSPACE_TOO_SMALL, "stage-0 workspace too small");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    float t_max = scene_t_max(b);
-    for (int i = 0; i < n_cams; ++i) t_max = std::fmax(t_max, camera_t_max(b, cams[i]));
-    const TraceSetup ts = trace_setup(b, p, t_max);
+    const TraceSetup ts = trace_setup(b, p);
     pack_attrs(s, b, w.attrs, st);
     const TraceCtx tc = make_ctx(b, w.attrs, p, ts);
     SbParams sp;
@@ -920,9 +941,7 @@ eag_status eag_stage0_backward(const eag_bvh* b, const eag_surfels* s, const eag
     const Stage0Ws w = stage0_ws(ws, b->n, hw * n_cams, hw * MAX_CAMS_PER_LAUNCH, runner_lanes());
     if (!ws || ws_bytes < w.bytes) fail(EAG_ERR_WORKSPACE_TOO_SMALL, "stage-0 workspace too small");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    float t_max = scene_t_max(b);
-    for (int i = 0; i < n_cams; ++i) t_max = std::fmax(t_max, camera_t_max(b, cams[i]));
-    const TraceSetup ts = trace_setup(b, p, t_max);
+    const TraceSetup ts = trace_setup(b, p);
     pack_attrs(s, b, w.attrs, st);
     const TraceCtx tc = make_ctx(b, w.attrs, p, ts);
     SbParams sp;
@@ -1014,7 +1033,8 @@ eag_status eag_bvh_sah_cost(const eag_bvh* b, double* cost, void* ws, size_t ws_
   return guarded([&] {
     if (!b || !cost) fail(EAG_ERR_INVALID_ARGUMENT, "null argument");
     if (!ws || ws_bytes < 2 * sizeof(double)) fail(EAG_ERR_WORKSPACE_TOO_SMALL, "tree-cost workspace too small");
-    launch_sah_cost(b->nodes4, b->n_nodes4, b->root, static_cast<double*>(ws), cost, static_cast<hipStream_t>(stream));
+    launch_sah_cost(b->nodes4, b->hdr, b->n - 1, b->root, static_cast<double*>(ws), cost,
+                    static_cast<hipStream_t>(stream));
   });
 }
 

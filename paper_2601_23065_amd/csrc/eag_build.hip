@@ -8,7 +8,10 @@
 //    equal codes broken by sorted position);
 // 4. geometry records in sorted order (one 64-B record per surfel);
 // 5. bottom-up box propagation with per-node arrival counters;
-// 6. the deepest leaf, which bounds the traversal stack.
+// 6. the depth of the binary tree, and its collapse into a 4-wide tree.
+// Everything is enqueued on the caller's stream: the depths, node count and
+// bounds stay in the device header, and the host waits for them only when
+// asked (eag_bvh_get_info).
 #include <hip/hip_runtime.h>
 #include <rocprim/device/device_radix_sort.hpp>
 
@@ -44,6 +47,16 @@ __device__ __forceinline__ Frame frame_of(const float* rot, int64_t n, int64_t i
   f.tv = d3(2.0 * (x * y - w * z), 1.0 - 2.0 * (x * x + z * z), 2.0 * (y * z + w * x));
   f.n = cross(f.tu, f.tv);
   return f;
+}
+
+// Bounds only (a refit keeps the depths and the node count).
+__global__ void k_reset_bounds(BvhHeader* h) {
+  if (threadIdx.x < 3) {
+    h->plo[threadIdx.x] = 0xffffffffu;
+    h->phi[threadIdx.x] = 0u;
+    h->blo[threadIdx.x] = 0xffffffffu;
+    h->bhi[threadIdx.x] = 0u;
+  }
 }
 
 __global__ void k_init_header(BvhHeader* h) {
@@ -374,10 +387,10 @@ __global__ void k_collapse_level(const Node* bin, Node4* out, Collapse cq, int l
 
 // Refit of 4-wide boxes from the binary tree (internal children) and the
 // surfel boxes (leaves).
-__global__ void k_node4_boxes(const Node* bin, Node4* out, int n4, const float* box, const int32_t* perm,
-                              int64_t n) {
+__global__ void k_node4_boxes(const Node* bin, Node4* out, const BvhHeader* h, const float* box,
+                              const int32_t* perm, int64_t n) {
   const int m = blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= n4) return;
+  if (m >= h->n_nodes4) return;
   Node4& nd = out[m];
   const int s[4] = {nd.src.x, nd.src.y, nd.src.z, nd.src.w};
   float* bf = reinterpret_cast<float*>(nd.b);
@@ -456,18 +469,12 @@ BuildWs build_ws(void* base, int64_t n) {
   return w;
 }
 
-void read_back(eag_bvh* b, hipStream_t st) {
-  BvhHeader h;
-  check_hip(hipMemcpyAsync(&h, b->hdr, sizeof(h), hipMemcpyDeviceToHost, st), "header copy");
-  check_hip(hipStreamSynchronize(st), "build sync");
-  for (int a = 0; a < 3; ++a) {
-    b->lo[a] = fdec(h.blo[a]);
-    b->hi[a] = fdec(h.bhi[a]);
-  }
-  b->max_depth = h.max_depth;
-  b->n_nodes4 = h.n_nodes4;
-  b->depth4 = h.depth4;
-}
+// Levels the collapse is launched for: a Karras tree over 63-bit codes with
+// ties broken by an idx_bits-bit position splits at a strictly longer prefix
+// on every level, so no internal node lies deeper than 63 + idx_bits. Levels
+// past the tree's depth find an empty queue and return at once.
+int collapse_levels(int32_t idx_bits) { return std::min(COLLAPSE_MAXL, 64 + idx_bits); }
+static_assert(64 + 23 <= COLLAPSE_MAXL, "the collapse covers the deepest tree of 2^23 surfels");
 
 }  // namespace
 
@@ -525,18 +532,17 @@ void build_bvh(const eag_surfels* s, eag_bvh* b, void* ws, size_t ws_bytes, hipS
   }
   check_hip(hipGetLastError(), "build launch");
   b->root = n > 1 ? 0 : ~0;
-  read_back(b, st);
   if (n > 1) {
-    if (b->max_depth >= COLLAPSE_MAXL) fail(EAG_ERR_INTERNAL, "binary tree too deep to collapse");
     Collapse cq{{w.q0, w.q1}, w.counts};
     hipLaunchKernelGGL(k_collapse_init, dim3(1), dim3(256), 0, st, w.counts, w.q0);
     const unsigned g = std::min<unsigned>(blocks(n), 1024u);
-    for (int level = 0; level < b->max_depth; ++level)
+    const int levels = collapse_levels(b->idx_bits);
+    for (int level = 0; level < levels; ++level)
       hipLaunchKernelGGL(k_collapse_level, dim3(g), dim3(256), 0, st, b->nodes, b->nodes4, cq, level);
     hipLaunchKernelGGL(k_collapse_finish, dim3(1), dim3(64), 0, st, w.counts, b->hdr);
     check_hip(hipGetLastError(), "collapse launch");
-    read_back(b, st);
   }
+  check_hip(hipEventRecord(b->built, st), "build event");
 }
 
 void refit_bvh(const eag_surfels* s, eag_bvh* b, void* ws, size_t ws_bytes, hipStream_t st) {
@@ -544,23 +550,22 @@ void refit_bvh(const eag_surfels* s, eag_bvh* b, void* ws, size_t ws_bytes, hipS
   BuildWs w = build_ws(ws, n);
   if (ws_bytes < w.bytes) fail(EAG_ERR_WORKSPACE_TOO_SMALL, "refit workspace too small");
   BvhHeader* h = b->hdr;
-  // bounds are recomputed; max_depth is kept since the topology is unchanged
-  hipLaunchKernelGGL(k_init_header, dim3(1), dim3(64), 0, st, h);
+  // bounds are recomputed; the depths and node count stay, since the
+  // topology is unchanged
+  hipLaunchKernelGGL(k_reset_bounds, dim3(1), dim3(64), 0, st, h);
   hipLaunchKernelGGL(k_boxes, dim3(blocks(n)), dim3(256), 0, st, *s, 3.0f, w.box, h);
   hipLaunchKernelGGL(k_records, dim3(blocks(n)), dim3(256), 0, st, *s, b->perm, b->recs);
   if (n > 1) {
     hipLaunchKernelGGL(k_zero_i32, dim3(blocks(n)), dim3(256), 0, st, w.visits, n);
     hipLaunchKernelGGL(k_bottom_up, dim3(blocks(n)), dim3(256), 0, st, n, w.box, b->perm, b->nodes,
                        b->leaf_parent, b->node_parent, w.visits);
-    hipLaunchKernelGGL(k_node4_boxes, dim3(blocks(b->n_nodes4)), dim3(256), 0, st, b->nodes, b->nodes4,
-                       b->n_nodes4, w.box, b->perm, n);
+    // (the 4-wide node count is on the device: the grid covers the n - 1 it
+    // can reach)
+    hipLaunchKernelGGL(k_node4_boxes, dim3(blocks(n - 1)), dim3(256), 0, st, b->nodes, b->nodes4, h, w.box,
+                       b->perm, n);
   }
   check_hip(hipGetLastError(), "refit launch");
-  const int32_t depth = b->max_depth, n4 = b->n_nodes4, d4 = b->depth4;
-  read_back(b, st);
-  b->max_depth = depth;
-  b->n_nodes4 = n4;
-  b->depth4 = d4;
+  check_hip(hipEventRecord(b->built, st), "refit event");
 }
 
 void pack_attrs(const eag_surfels* s, const eag_bvh* b, Attr* attrs, hipStream_t st) {

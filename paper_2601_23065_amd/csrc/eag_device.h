@@ -12,7 +12,11 @@
 namespace eag {
 
 constexpr int KBUF = 16;          // k-buffer depth
-constexpr int STACK_SIZE = 64;    // traversal stack; builds deeper than this are rejected on the host
+// Traversal stack: 3 entries per level of the deepest tree a build can make
+// (63 code bits plus 23 position bits of prefix, so at most 87 levels), so
+// that no tree needs a check on the host. Entries past the LDS part live in
+// private memory and are rarely touched.
+constexpr int STACK_SIZE = 264;
 
 // ---------------------------------------------------------------------------
 // Layouts in HBM
@@ -155,6 +159,9 @@ struct TraceCtx {
   double t_min;
   double k2;               // k_sigma^2
   double T_min;
+  // Mapped host word receiving device status codes (a key beyond the last
+  // bucket); null: not reported.
+  unsigned int* status;
   // Optional per-lane hit list (null: off). Entry j of this lane is
   // hl[j * HL_STRIDE]. A lane's entries are contiguous: appends happen at
   // different times in different lanes, and a lane filling its own cache
@@ -166,6 +173,9 @@ constexpr int HL_CAP = 128;        // entries per lane (a multiple of 8: the lis
 constexpr int HL_STRIDE = 1;
 static_assert(HL_CAP % 8 == 0 && HL_STRIDE == 1, "hit-list scan reads 8 contiguous entries");
 
+__device__ __noinline__ void report_key_range(unsigned int* status) {
+  if (status) __hip_atomic_fetch_or(status, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
 __device__ __forceinline__ uint64_t make_key(const TraceCtx& tc, double t, uint32_t idx, uint32_t pos) {
   uint32_t bucket;
   if (tc.inv_dq > 0.0) {
@@ -683,7 +693,12 @@ __device__ __forceinline__ uint64_t leaf_key(const TraceCtx& tc, const Record& r
   const bool hit = (fr == FILTER_ACCEPT && !early_out) || (fr == FILTER_EXACT && exact_ok);
   const uint64_t key = fr == FILTER_ACCEPT && blo == bhi ? make_key_b(tc, blo, rec_index(rec), pos)
                                                          : make_key(tc, t, rec_index(rec), pos);
-  return hit && !(have_floor && key <= floor_key) ? key : ~0ull;
+  const bool take = hit && !(have_floor && key <= floor_key);
+  // A hit in the last bucket may stand for a farther one that the key
+  // saturated into it, whose order among the others is then unknown: the
+  // launch reports it (a rare branch; never taken within the range).
+  if (take && tc.inv_dq > 0.0 && key_bucket(tc, key) >= tc.max_bucket) report_key_range(tc.status);
+  return take ? key : ~0ull;
 }
 
 // Take a qualifying key into the round. The list needs only keys beyond the
@@ -801,9 +816,12 @@ __device__ __forceinline__ void blend_round(const TraceCtx& tc, Seg<DACC>& s, Ro
       nat = tc.attrs[np];
     }
     // t, u, v and the unit normal from the columns of the unnormalised
-    // quaternion's rotation, |q|^2 (t_u, t_v, n): no square root
+    // quaternion's rotation, |q|^2 (t_u, t_v, n): no square root, and one
+    // reciprocal c = 1 / (|q|^2 s_u s_v) for u^2 + v^2 and the normal's scale
     const double qw = rec.q.x, qx = rec.q.y, qy = rec.q.z, qz = rec.q.w;
-    const double iq2 = 1.0 / (qw * qw + qx * qx + qy * qy + qz * qz);
+    const double su = rec.s_idx.x, sv = rec.s_idx.y;
+    const double c = 1.0 / ((qw * qw + qx * qx + qy * qy + qz * qz) * (su * sv));
+    const double iq2 = c * (su * sv);
     const D3 cu = d3(qw * qw + qx * qx - qy * qy - qz * qz, 2.0 * (qx * qy + qw * qz), 2.0 * (qx * qz - qw * qy));
     const D3 cv = d3(2.0 * (qx * qy - qw * qz), qw * qw - qx * qx + qy * qy - qz * qz, 2.0 * (qy * qz + qw * qx));
     const D3 cn = d3(2.0 * (qx * qz + qw * qy), 2.0 * (qy * qz - qw * qx), qw * qw - qx * qx - qy * qy + qz * qz);
@@ -811,8 +829,8 @@ __device__ __forceinline__ void blend_round(const TraceCtx& tc, Seg<DACC>& s, Ro
     const double dn = dot(s.W, cn);
     const double t = dot(dp, cn) / dn;
     const D3 yv = d3(t * s.W.x - dp.x, t * s.W.y - dp.y, t * s.W.z - dp.z);
-    const double u = dot(yv, cu) * iq2 / (double)rec.s_idx.x, v = dot(yv, cv) * iq2 / (double)rec.s_idx.y;
-    const double a = (double)rec.p_sigma.w * exp(-0.5 * (u * u + v * v));
+    const double uc = dot(yv, cu) * sv, vc = dot(yv, cv) * su;   // u, v times |q|^2 s_u s_v
+    const double a = (double)rec.p_sigma.w * exp(-0.5 * ((uc * uc + vc * vc) * (c * c)));
     const double w = s.T * a;
     const Acc wf = (Acc)w;
     if (QMODE == Q_ALL) {

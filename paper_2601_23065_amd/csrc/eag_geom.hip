@@ -109,11 +109,11 @@ __device__ __forceinline__ double child_area(const Node4& nd, int k) {
   }
 }
 
-__global__ void __launch_bounds__(256) k_sah_sum(const Node4* nodes, int32_t n_nodes, int32_t root, double* acc) {
+__global__ void __launch_bounds__(256) k_sah_sum(const Node4* nodes, const BvhHeader* h, int32_t root, double* acc) {
   __shared__ double part[4];
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   double a = 0.0;
-  if (i < n_nodes) {
+  if (i < h->n_nodes4) {
     const Node4& nd = nodes[i];
     const int c[4] = {nd.ref.x, nd.ref.y, nd.ref.z, nd.ref.w};
     for (int k = 0; k < 4; ++k)
@@ -216,12 +216,14 @@ void launch_append(const eag_surfels& src, const int32_t* idx, int64_t count, co
   check_hip(hipGetLastError(), "append launch");
 }
 
-void launch_sah_cost(const Node4* nodes, int32_t n_nodes, int32_t root, double* acc, double* cost, hipStream_t st) {
-  if (root < 0 || n_nodes <= 0) {
+void launch_sah_cost(const Node4* nodes, const BvhHeader* h, int64_t max_nodes, int32_t root, double* acc,
+                     double* cost, hipStream_t st) {
+  if (root < 0 || max_nodes <= 0) {
     hipLaunchKernelGGL(k_sah_single, dim3(1), dim3(64), 0, st, cost);
   } else {
+    // the node count is in the device header: the grid covers the most there can be
     hipLaunchKernelGGL(k_sah_zero, dim3(1), dim3(64), 0, st, acc);
-    hipLaunchKernelGGL(k_sah_sum, dim3(nb(n_nodes)), dim3(256), 0, st, nodes, n_nodes, root, acc);
+    hipLaunchKernelGGL(k_sah_sum, dim3(nb(max_nodes)), dim3(256), 0, st, nodes, h, root, acc);
     hipLaunchKernelGGL(k_sah_final, dim3(1), dim3(64), 0, st, acc, cost);
   }
   check_hip(hipGetLastError(), "tree cost launch");

@@ -56,26 +56,44 @@ struct BvhHeader {
 
 }  // namespace eag
 
+// Host handle of a BVH. Build and refit only enqueue work: the fields marked
+// "synced" are filled from the device header by bvh_sync_host (which waits
+// for the `built` event) and are read by host code that may wait.
 struct eag_bvh {
   int64_t n;
   int32_t idx_bits;
-  int32_t max_depth;
+  int32_t max_depth;      // synced
   int32_t root;
-  float lo[3], hi[3];
+  float lo[3], hi[3];     // synced
   void* mem;
   size_t mem_bytes;
   eag::BvhHeader* hdr;
   eag::Node* nodes;
   eag::Node4* nodes4;
-  int32_t n_nodes4;
-  int32_t depth4;
+  int32_t n_nodes4;       // synced
+  int32_t depth4;         // synced
   eag::Record* recs;
   int32_t* perm;
   int32_t* leaf_parent;
   int32_t* node_parent;
+  hipEvent_t built = nullptr;   // recorded after the last build or refit
 };
 
 namespace eag {
+
+// Device status codes (bits of the mapped status word).
+constexpr unsigned int EAG_DEVICE_KEY_RANGE = 1u;
+unsigned int* device_status_word();
+void check_device_status();
+// Waits for the last build or refit and fills the handle's synced fields.
+void bvh_sync_host(eag_bvh* b);
+// Decodes a bound of the header (floats stored as order-preserving uints).
+inline float header_float(uint32_t e) {
+  const uint32_t bits = (e & 0x80000000u) ? (e & 0x7fffffffu) : ~e;
+  float f;
+  __builtin_memcpy(&f, &bits, 4);
+  return f;
+}
 
 // Pieces of a BVH allocation of n surfels (base may be null to size it).
 struct BvhLayout {
@@ -104,10 +122,9 @@ struct TraceSetup {
   uint32_t max_bucket;
   double inv_dq;
 };
-TraceSetup trace_setup(const eag_bvh* b, const eag_trace_params* p, float t_max_needed);
+TraceSetup trace_setup(const eag_bvh* b, const eag_trace_params* p);
 void validate_params(const eag_trace_params* p);
 CamDev make_cam(const eag_camera& c, uint32_t id);
-float camera_t_max(const eag_bvh* b, const eag_camera& c);
 
 void launch_trace_rays(const eag_bvh* b, const Attr* attrs, const eag_trace_params* p, const TraceSetup& ts,
                        int64_t n_rays, const double* o, const double* d, float* out, int32_t* hit_idx,

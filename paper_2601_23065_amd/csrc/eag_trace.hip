@@ -56,6 +56,7 @@ TraceCtx make_ctx(const eag_bvh* b, const Attr* attrs, const eag_trace_params* p
   tc.k2 = (double)p->k_sigma * (double)p->k_sigma;
   tc.T_min = p->T_min;
   tc.hl = nullptr;
+  tc.status = device_status_word();
   return tc;
 }
 

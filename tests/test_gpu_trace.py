@@ -97,3 +97,25 @@ def test_invalid_arguments_raise():
     for bad in (Params(kbuf=8), Params(spp=0), Params(depth_quantum=0.3), Params(max_depth=65)):
         with pytest.raises(EagError):
             trace_rays(bvh, gs, bad, o, d)
+
+
+def test_order_key_range_reported_by_the_next_call():
+    """A depth quantum so fine that distances beyond 1 m pass the order
+    key's last bucket: the kernels detect it (the host no longer knows the
+    scene's extent when it launches), and the next call reports it once as a
+    device error; the call after that runs normally."""
+    from paper_2601_23065_amd import EagError
+    from paper_2601_23065_amd.api import BVH, Params, trace_rays
+    scene = sg.cloud_scene(2000, seed=1)
+    gs = gpu_scene(scene)
+    bvh = BVH(gs)
+    O, D = sg.random_rays(scene, 256, seed=4)
+    o, d = torch.from_numpy(O).cuda(), torch.from_numpy(D).cuda()
+    trace_rays(bvh, gs, Params(), o, d)
+    trace_rays(bvh, gs, Params(depth_quantum=2.0 ** -32), o, d)
+    torch.cuda.synchronize()
+    with pytest.raises(EagError, match="depth_quantum"):
+        trace_rays(bvh, gs, Params(), o, d)
+    out = trace_rays(bvh, gs, Params(), o, d)
+    torch.cuda.synchronize()
+    assert torch.isfinite(out).all()
