@@ -208,6 +208,26 @@ eag_status eag_trace_rays(const eag_bvh* bvh, const eag_surfels* s, const eag_tr
                           int32_t* hit_idx, int32_t* hit_count, int32_t max_hits, int32_t* stats,
                           void* ws, size_t ws_bytes, void* stream);
 
+/* Set-up for callers that cannot allocate: allocates the library's status
+ * word (once per process) and looks up the no-allocation scratch of the
+ * current device. Call it once on each device, with that device current,
+ * before eag_trace_rays_noalloc; idempotent. */
+eag_status eag_init(void);
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): eag_trace_rays without
+ * a workspace, allocating nothing. Its scratch (the scene's packed attribute
+ * records) is a static device array of EAG_NOALLOC_MAX_SURFELS records per
+ * device: scenes of more surfels are rejected with EAG_ERR_INVALID_ARGUMENT,
+ * and so are calls on a device eag_init has not set up. Every call on a
+ * device shares that device's array, so calls that overlap on one device
+ * (other streams, other threads) race; each call rewrites the records it
+ * reads. Arguments and results as eag_trace_rays. */
+#define EAG_NOALLOC_MAX_SURFELS (1 << 18)
+eag_status eag_trace_rays_noalloc(const eag_bvh* bvh, const eag_surfels* s, const eag_trace_params* p,
+                                  int64_t n_rays, const double* origins, const double* dirs, float* out,
+                                  int32_t* hit_idx, int32_t* hit_count, int32_t max_hits, int32_t* stats,
+                                  void* stream);
+
 /* ------------------------------------------------------------------------
  * Single-bounce emission-aware render (Sec. 3.3, Eq. 5-7): per pixel, the
  * camera segment through the pixel centre gives (Nt, Dt, R, E, P, A); a miss

@@ -94,6 +94,9 @@ SIGNATURES = {
     "eag_trace_workspace_bytes": (C.c_size_t, [C.c_int64]),
     "eag_trace_rays": (C.c_int, [vp, P(Surfels), P(TraceParams), C.c_int64, vp, vp, vp, vp, vp, C.c_int32, vp, vp,
                                  C.c_size_t, vp]),
+    "eag_init": (C.c_int, []),
+    "eag_trace_rays_noalloc": (C.c_int, [vp, P(Surfels), P(TraceParams), C.c_int64, vp, vp, vp, vp, vp, C.c_int32,
+                                         vp, vp]),
     "eag_fwd_state_floats": (C.c_int64, [P(Camera), C.c_int32, P(TraceParams)]),
     "eag_render_workspace_bytes": (C.c_size_t, [C.c_int64, P(Camera), C.c_int32, P(TraceParams)]),
     "eag_backward_workspace_bytes": (C.c_size_t, [C.c_int64, P(Camera), C.c_int32, P(TraceParams)]),

@@ -214,6 +214,28 @@ def trace_rays(bvh: BVH, scene: Scene, params: Params, origins, dirs, max_hits: 
     return (out, hits, cnt) if max_hits > 0 else out
 
 
+def init():
+    """eag_init on the current device: set-up for trace_rays_noalloc."""
+    L.check(L.load().eag_init())
+
+
+def trace_rays_noalloc(bvh: BVH, scene: Scene, params: Params, origins, dirs, out, hits=None, counts=None,
+                       stats=None, stream=None):
+    """eag_trace_rays_noalloc: as trace_rays, with every buffer the caller's
+    (origins, dirs: contiguous float64 [3, M]; out: float32 [12, M]; hits:
+    optional int32 [M, max_hits]; counts: int32 [M]; stats: int32 [M, 3])
+    and nothing allocated, here or in the library (after init() on this
+    device). At most 2^18 surfels."""
+    p = params.c()
+    sc = scene.c()
+    max_hits = hits.shape[1] if hits is not None else 0
+    s = stream if stream is not None else torch.cuda.current_stream()
+    L.check(L.load().eag_trace_rays_noalloc(bvh.h, C.byref(sc), C.byref(p), origins.shape[1], _ptr(origins),
+                                            _ptr(dirs), _ptr(out), _ptr(hits), _ptr(counts), max_hits, _ptr(stats),
+                                            C.c_void_p(s.cuda_stream)))
+    return out
+
+
 def _cams(cams):
     arr = (L.Camera * len(cams))()
     for i, c in enumerate(cams):

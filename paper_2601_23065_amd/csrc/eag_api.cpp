@@ -78,6 +78,11 @@ unsigned int* device_status_word() {
   return g_status;
 }
 
+bool device_status_allocated() {
+  std::lock_guard<std::mutex> g(g_status_mu);
+  return g_status != nullptr;
+}
+
 void check_device_status() {
   unsigned int* w = g_status;
   if (!w) return;
@@ -471,6 +476,35 @@ eag_status eag_trace_rays(const eag_bvh* b, const eag_surfels* s, const eag_trac
     hipStream_t st = static_cast<hipStream_t>(stream);
     pack_attrs(s, b, w.attrs, st);
     launch_trace_rays(b, w.attrs, p, ts, n_rays, origins, dirs, out, hit_idx, hit_count, max_hits, stats, st);
+  });
+}
+
+eag_status eag_init(void) {
+  return guarded([&] {
+    (void)device_status_word();
+    noalloc_setup_current_device();
+  });
+}
+
+eag_status eag_trace_rays_noalloc(const eag_bvh* b, const eag_surfels* s, const eag_trace_params* p, int64_t n_rays,
+                                  const double* origins, const double* dirs, float* out, int32_t* hit_idx,
+                                  int32_t* hit_count, int32_t max_hits, int32_t* stats, void* stream) {
+  return guarded([&] {
+    check_bvh(b, s);
+    validate_params(p);
+    if (n_rays < 0) fail(EAG_ERR_INVALID_ARGUMENT, "n_rays < 0");
+    if (n_rays > 0 && (!origins || !dirs || !out)) fail(EAG_ERR_INVALID_ARGUMENT, "ray or output pointer is null");
+    if (hit_idx && max_hits < 1) fail(EAG_ERR_INVALID_ARGUMENT, "max_hits must be >= 1 with hit_idx");
+    if (b->n > EAG_NOALLOC_MAX_SURFELS)
+      fail(EAG_ERR_INVALID_ARGUMENT, "eag_trace_rays_noalloc takes at most EAG_NOALLOC_MAX_SURFELS (2^18) surfels");
+    Attr* attrs = noalloc_scratch_current_device();
+    if (!attrs || !device_status_allocated())
+      fail(EAG_ERR_INVALID_ARGUMENT, "eag_trace_rays_noalloc needs eag_init on this device first");
+    if (n_rays == 0) return;
+    const TraceSetup ts = trace_setup(b, p);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    pack_attrs(s, b, attrs, st);   // all n records rewritten: nothing left from an earlier call is read
+    launch_trace_rays(b, attrs, p, ts, n_rays, origins, dirs, out, hit_idx, hit_count, max_hits, stats, st);
   });
 }
 

@@ -83,8 +83,14 @@ namespace eag {
 
 // Device status codes (bits of the mapped status word).
 constexpr unsigned int EAG_DEVICE_KEY_RANGE = 1u;
-unsigned int* device_status_word();
+unsigned int* device_status_word();     // allocates the word on first use
+bool device_status_allocated();
 void check_device_status();
+// The no-allocation entry point's static scratch on the current device:
+// setup looks its address up (once per device), the other returns it, or
+// null before setup.
+void noalloc_setup_current_device();
+Attr* noalloc_scratch_current_device();
 // Waits for the last build or refit and fills the handle's synced fields.
 void bvh_sync_host(eag_bvh* b);
 // Decodes a bound of the header (floats stored as order-preserving uints).

@@ -4,7 +4,42 @@
 #include "eag_device.h"
 #include "eag_internal.h"
 
+#include <mutex>
+
+// Scratch of eag_trace_rays_noalloc: the packed attribute records of a scene
+// of at most EAG_NOALLOC_MAX_SURFELS surfels (32 B each, 8 MiB in all).
+// Static device memory: every device the library runs on holds its own copy
+// until the process ends, at its own address (looked up per device by
+// eag_init), and the calls on one device share it.
+static __device__ __align__(256) eag::Attr scratch[EAG_NOALLOC_MAX_SURFELS];
+
 namespace eag {
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+Attr* g_scratch[MAX_DEVICES] = {};   // the array's device address on each device, once looked up
+}  // namespace
+
+void noalloc_setup_current_device() {
+  int dev = 0;
+  check_hip(hipGetDevice(&dev), "hipGetDevice");
+  if (dev < 0 || dev >= MAX_DEVICES) fail(EAG_ERR_INVALID_ARGUMENT, "device index beyond the library's table");
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (g_scratch[dev]) return;
+  void* ptr = nullptr;
+  check_hip(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "no-alloc scratch address");
+  if (!ptr) fail(EAG_ERR_DEVICE, "no-alloc scratch has no device address");
+  g_scratch[dev] = static_cast<Attr*>(ptr);
+}
+
+Attr* noalloc_scratch_current_device() {
+  int dev = 0;
+  check_hip(hipGetDevice(&dev), "hipGetDevice");
+  if (dev < 0 || dev >= MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  return g_scratch[dev];
+}
 
 namespace {
 
