@@ -702,13 +702,15 @@ def bench_serve(torch, args):
     def params_of(i, r):
         return Params(spp=r["spp"], max_depth=cfg["max_depth"], rr_start=cfg["rr_start"], seed=0, camera_id=i)
 
-    def fifo(reqs, realtime):
+    def fifo(reqs, realtime, keep=False):
         """One request at a time through the plain path tracer, in arrival
-        order; returns (latencies or service times in s, renders)."""
+        order; returns latencies (or service times) in s, and the images
+        when keep."""
         gs = Scene(scene.arrays())
         bvh = BVH(gs)
         torch.cuda.synchronize()
         out = []
+        images = []
         t_start = time.perf_counter()
         for i, r in enumerate(reqs):
             if realtime:
@@ -720,15 +722,17 @@ def bench_serve(torch, args):
                 apply_edit(gs, kinds[r["op"]], torch.from_numpy(r["idx"]).cuda(), r["value"])
                 continue
             acc = path_trace(bvh, gs, r["camera"], params_of(i, r))
-            resolve(acc, r["spp"])
+            img = resolve(acc, r["spp"])
             torch.cuda.synchronize()
             done = time.perf_counter()
             out.append(done - (t_start + r["t"]) if realtime else done - t_req)
-            if i % 10 == 9:
-                _log(f"fifo: {i + 1} of {len(reqs)} requests")
-        return np.array(out)
+            if keep:
+                images.append(img)
+            _log(f"fifo: {i + 1} of {len(reqs)} requests ({r['camera'].width}x{r['camera'].height}, {r['spp']} spp)")
+        out = np.array(out)
+        return (out, images) if keep else out
 
-    def batched(reqs):
+    def batched(reqs, keep=False):
         gs = Scene(scene.arrays())
         need = L_arena(scene.n)
         srv = Server(gs, arena_bytes=need, max_live_requests=8,
@@ -742,19 +746,18 @@ def bench_serve(torch, args):
             if r["kind"] == "edit":
                 srv.edit(kinds[r["op"]], r["idx"], r["value"])
             else:
-                tickets.append(srv.submit(r["camera"], params_of(i, r))[0])
-            if i % 10 == 9:
-                _log(f"batched: {i + 1} of {len(reqs)} requests submitted")
+                tickets.append(srv.submit(r["camera"], params_of(i, r)))
+            _log(f"batched: {i + 1} of {len(reqs)} requests submitted")
         _log("batched: all requests submitted")
         lat = []
-        for k, t in enumerate(tickets):
-            res = srv.wait(t, timeout=600.0)
+        for k, (t, img) in enumerate(tickets):
+            res = srv.wait(t, timeout=1200.0)
             assert res["status"] == 0, res
             lat.append(res["t_done"] - res["t_submit"])
-            if k % 10 == 9:
-                _log(f"batched: {k + 1} of {len(tickets)} requests done")
+            _log(f"batched: {k + 1} of {len(tickets)} requests done")
         srv.close()
-        return np.array(lat)
+        lat = np.array(lat)
+        return (lat, [img for _, img in tickets]) if keep else lat
 
     def L_arena(n):
         from paper_2601_23065_amd import _lib
@@ -762,22 +765,32 @@ def bench_serve(torch, args):
         return int(_lib.load().eag_serve_arena_bytes(n, 3, 8 * w * h * 24)) + (64 << 20)
 
     cal = sg.arrivals(scene, n_req, 1.0, **mix)
-    fifo(cal[:4], False)   # warm-up: code objects, allocator
-    service = fifo(cal, False)
-    mu = service.size / service.sum()
-    _log(f"FIFO service rate {mu:.2f} requests/s (mean {service.mean() * 1e3:.1f} ms)")
+    fifo(cal[:2], False)   # warm-up: code objects, allocator
+    if args.serve_rate > 0:
+        mu = args.serve_rate
+        service = np.array([1.0 / mu])
+        _log(f"FIFO service rate given: {mu:.4f} requests/s")
+    else:
+        service = fifo(cal, False)
+        mu = service.size / service.sum()
+        _log(f"FIFO service rate {mu:.4f} requests/s (mean {service.mean() * 1e3:.1f} ms over {service.size})")
     loads = {}
-    for rho in (0.5, 0.8, 0.95):
+    identical = {}
+    for rho in (float(x) for x in args.serve_loads.split(",") if x):
         reqs = sg.arrivals(scene, n_req, rho * mu, **mix)
-        lf = fifo(reqs, True)
-        lb = batched(reqs)
+        lf, imf = fifo(reqs, True, keep=True)
+        lb, imb = batched(reqs, keep=True)
+        identical[str(rho)] = all(torch.equal(a, b) for a, b in zip(imf, imb)) and len(imf) == len(imb)
+        del imf, imb
         loads[str(rho)] = {k: {"p50_ms": round(float(np.percentile(v, 50)) * 1e3, 2),
                                "p99_ms": round(float(np.percentile(v, 99)) * 1e3, 2),
                                "mean_ms": round(float(v.mean()) * 1e3, 2)} for k, v in (("batched", lb), ("fifo", lf))}
-        _log(f"load {rho}: {loads[str(rho)]}")
+        _log(f"load {rho}: {loads[str(rho)]}; served images equal FIFO's: {identical[str(rho)]}")
+    errors = serve_oracle_check(torch, scene, cfg, mix, args) if args.serve_check else None
+    key = "0.8" if "0.8" in loads else (next(iter(loads)) if loads else None)
     rec = {
-        "metric": "p99 request latency at 0.8 load, continuous batching",
-        "value": loads["0.8"]["batched"]["p99_ms"],
+        "metric": f"p99 request latency at {key} load, continuous batching",
+        "value": loads[key]["batched"]["p99_ms"] if key else None,
         "unit": "ms",
         "n_gpus": 1,
         "steps": n_req,
@@ -789,14 +802,76 @@ def bench_serve(torch, args):
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"render server over a resident {scene.n}-surfel 8x6x3 m room, Poisson arrivals of "
-                               f"{n_req} requests (resolutions {mix['resolutions']}, spp {mix['spps']}, depth 5, "
-                               f"5% attribute edits) at 0.5/0.8/0.95 of the FIFO service rate",
-                   "surfels": scene.n, "requests": n_req},
-        "detail": {"fifo_service_rate_per_s": round(mu, 3), "fifo_mean_service_ms": round(service.mean() * 1e3, 3),
-                   "loads": loads},
+                               f"{n_req} requests per load (resolutions {mix['resolutions']}, spp {mix['spps']}, "
+                               f"depth 5, 5% attribute edits) at {args.serve_loads} of the FIFO service rate",
+                   "surfels": scene.n, "requests": n_req, "mix": args.mix},
+        "detail": {"fifo_service_rate_per_s": round(mu, 4), "fifo_mean_service_ms": round(service.mean() * 1e3, 3),
+                   "service_rate_measured": args.serve_rate <= 0, "loads": loads,
+                   "served_images_equal_fifo": identical, "oracle_error_per_class": errors},
     }
     print(json.dumps(rec))
 
+
+
+def _serve_oracle_job(args):
+    import oracle.render as R
+    k, cam, prm, pixels, sample = args
+    out = R.path_trace(_ORACLE["sc"], cam, prm, pixels=pixels, samples=[sample])
+    return k, out["value"][:, 0], out["flags"][:, 0]
+
+
+def serve_oracle_check(torch, scene, cfg, mix, args, per_class=256):
+    """Image error against the oracle for each request class of the mix
+    (resolution x spp): a request of the class (camera and parameters as the
+    served ones) renders one of its samples alone through the same kernel,
+    and per_class seeded pixels of that sample are compared path by path
+    with the oracle (the served image is a fixed-point sum of such paths,
+    identical whether served in a mix or alone). Max relative error over
+    unflagged paths, |a - b| / max(|b|, 1e-2 RMS(b))."""
+    import multiprocessing as mp
+
+    import scenegen as sg
+    from oracle import Params as OParams
+    from oracle.tracer import Scene64
+    from paper_2601_23065_amd.api import BVH, Params, Scene, path_trace
+    gs = Scene(scene.arrays())
+    bvh = BVH(gs)
+    cams = sg.interior_cameras(scene, len(mix["resolutions"]) * len(mix["spps"]), 16, 16, seed=606)
+    rng = np.random.default_rng(607)
+    jobs, gpu = [], {}
+    k = 0
+    for (w, h) in mix["resolutions"]:
+        for spp in mix["spps"]:
+            c = cams[k]
+            cam = sg.Camera(c.eye, c.look_at, c.up, c.vfov_deg, w, h)
+            p = Params(spp=spp, max_depth=cfg["max_depth"], rr_start=cfg["rr_start"], seed=0, camera_id=1000 + k)
+            sample = int(rng.integers(spp))
+            acc = path_trace(bvh, gs, cam, p, sample, 1)
+            pix = np.sort(rng.choice(w * h, per_class, replace=False))
+            gpu[k] = (f"{w}x{h} {spp} spp", acc.cpu().numpy().reshape(-1, 3)[pix].astype(np.float64) / 2.0 ** 32)
+            prm = OParams(spp=spp, max_depth=cfg["max_depth"], rr_start=cfg["rr_start"], seed=0, camera_id=1000 + k)
+            jobs += [(k, cam, prm, pix[i:i + 16], sample) for i in range(0, per_class, 16)]
+            k += 1
+    _log(f"serve oracle check: {len(jobs)} jobs of 16 paths")
+    _ORACLE.update(sc=Scene64(scene))
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    with mp.get_context("fork").Pool(min(usable, 16)) as pool:
+        res = pool.map(_serve_oracle_job, jobs, chunksize=1)
+    out = {}
+    for kk, (name, got) in gpu.items():
+        ref = np.concatenate([v for j, v, f in res if j == kk])
+        flags = np.concatenate([f for j, v, f in res if j == kk])
+        ok = flags == 0
+        a, b = got[ok], ref[ok]
+        rms = np.sqrt(np.mean(b * b)) if b.size else 0.0
+        err = np.abs(a - b) / np.maximum(np.abs(b), 1e-2 * rms + 1e-30)
+        out[name] = {"paths": int(ok.size), "unflagged": int(ok.sum()), "nonzero": int(np.count_nonzero(b.sum(1))),
+                     "max_rel_err": float(err.max()) if err.size else None}
+        _log(f"serve oracle check {name}: {out[name]}")
+    return out
 
 
 def main():
@@ -811,6 +886,12 @@ def main():
                     help="serve workload request mix: small (128^2 or 256^2, 4 or 16 spp) or full "
                          "(256^2 .. 1920x1080, 16 .. 256 spp)")
     ap.add_argument("--spp", type=int, default=None, help="override the workload's 64 spp (diagnostics only)")
+    ap.add_argument("--serve-loads", default="0.5,0.8,0.95", help="serve workload: loads to run (fractions of the "
+                    "FIFO service rate)")
+    ap.add_argument("--serve-rate", type=float, default=0.0, help="serve workload: FIFO service rate (requests/s) "
+                    "from an earlier calibration; 0 measures it")
+    ap.add_argument("--serve-check", action="store_true", help="serve workload: image error of each request class "
+                    "against the oracle (host cores)")
     ap.add_argument("--mis-config", type=int, default=3, choices=[3, 4],
                     help="scene of the mis workload: 3 = the default room, 4 = the three rooms (64 spp)")
     ap.add_argument("--mis-cell", type=float, default=1.0,
