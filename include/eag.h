@@ -549,8 +549,9 @@ eag_status eag_bake_step(const eag_bvh* bvh, const eag_surfels* s, const eag_cam
  * Serving: a resident scene answering path-tracing requests with continuous
  * batching. A host scheduler thread admits requests while their fixed-point
  * accumulators fit the arena and a slot is free, and each launch of the
- * multi-request persistent kernel draws paths from every live request, so
- * requests that arrive while others run join the next launch. Edits are
+ * multi-request persistent kernel draws paths from the live requests, the
+ * one with the least work left first, so requests that arrive while others
+ * run join the next launch and short ones do not wait behind long ones. Edits are
  * ordered with respect to later submits: each request renders the scene
  * version current at its submit; attribute edits create a new version
  * (copy-on-write attributes); geometry is shared, so a geometric edit

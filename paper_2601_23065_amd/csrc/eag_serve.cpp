@@ -10,10 +10,10 @@
 //     free and their fixed-point accumulator fits the arena's request pool
 //     (first fit);
 //   * each iteration launches the multi-request path-tracing kernel over a
-//     budget of paths taken by the live requests oldest first, so the order
-//     is FIFO's while requests that arrive meanwhile fill the rest of the
-//     GPU from the next launch on (requests whose ray-segment parameters
-//     differ from the oldest one's wait for a launch of their own);
+//     budget of paths taken by the live requests with the least work left
+//     first, so that short requests do not queue behind long ones, and the
+//     rest of the budget goes to the others (requests whose ray-segment
+//     parameters differ from the first one's wait for a launch of their own);
 //   * a request whose work is complete is resolved into its output image and
 //     retired; latency = completion - submit.
 // Results do not depend on batching: each path's random numbers come from
@@ -327,20 +327,26 @@ void eag_server::run() {
         cv.wait_for(lk, std::chrono::milliseconds(2));
         continue;
       }
-      // ---- one launch: live requests in arrival order take work until the
-      // launch's path budget is spent (the oldest first, so the order is
-      // FIFO's, and younger requests fill what the older ones leave). One
-      // launch traces with one set of ray-segment parameters, so it takes
-      // only requests whose T_min, t_min, k_sigma and depth_quantum equal
-      // the oldest live request's.
+      // ---- one launch: live requests take work until the launch's path
+      // budget is spent, the one with the least work left first (arrival
+      // order among equals), so that a short request that arrives while a
+      // long one runs finishes in the next launches instead of queueing
+      // behind it, and the rest of the budget goes to the others. One launch
+      // traces with one set of ray-segment parameters, so it takes only
+      // requests whose T_min, t_min, k_sigma and depth_quantum equal those
+      // of the first request in that order.
+      std::vector<Req*> order;
+      for (auto& r : live) order.push_back(r.get());
+      std::stable_sort(order.begin(), order.end(),
+                       [](const Req* a, const Req* b) { return a->total - a->done < b->total - b->done; });
       PtLaunch L;
       std::memset(&L, 0, sizeof(L));
-      const eag_trace_params& p0 = live[0]->r.params;
+      const eag_trace_params& p0 = order[0]->r.params;
       int64_t budget = std::max<int64_t>(cfg.paths_per_launch, 1);
       int64_t total = 0;
       std::vector<std::pair<Req*, int64_t>> take;
-      for (size_t i = 0; i < live.size() && budget > 0; ++i) {
-        Req& r = *live[i];
+      for (size_t i = 0; i < order.size() && budget > 0; ++i) {
+        Req& r = *order[i];
         const eag_trace_params& q = r.r.params;
         if (q.T_min != p0.T_min || q.t_min != p0.t_min || q.k_sigma != p0.k_sigma ||
             q.depth_quantum != p0.depth_quantum)

@@ -217,3 +217,30 @@ def test_transform_edit_refits_and_waits_for_earlier_requests():
     assert torch.equal(out_before, ref_before)
     assert torch.equal(out_after, ref_after)
     assert not torch.equal(ref_before, ref_after)
+
+
+def test_short_request_overtakes_a_long_one():
+    """Launches take the live requests with the least work left first: a
+    short request submitted after a long one finishes first, and both equal
+    their renders alone."""
+    from paper_2601_23065_amd.api import BVH, Params, Server
+    scene = _scene()
+    gs = gpu_scene(scene)
+    cams = sg.interior_cameras(scene, 2, 16, 16, seed=33)
+    long_cam = sg.Camera(cams[0].eye, cams[0].look_at, cams[0].up, 70.0, 96, 72)
+    short_cam = sg.Camera(cams[1].eye, cams[1].look_at, cams[1].up, 70.0, 16, 16)
+    p_long = Params(spp=64, max_depth=4, rr_start=2, camera_id=40, seed=3)
+    p_short = Params(spp=2, max_depth=4, rr_start=2, camera_id=41, seed=3)
+    srv = Server(gs, arena_bytes=64 << 20, max_live_requests=4, paths_per_launch=8192)
+    t_long, out_long = srv.submit(long_cam, p_long)
+    t_short, out_short = srv.submit(short_cam, p_short)
+    r_long, r_short = srv.wait(t_long), srv.wait(t_short)
+    srv.close()
+    assert r_long["status"] == 0 and r_short["status"] == 0
+    print(f"long done after {r_long['t_done'] - r_long['t_submit']:.3f} s, short after "
+          f"{r_short['t_done'] - r_short['t_submit']:.3f} s")
+    assert r_short["t_done"] < r_long["t_done"]
+    bvh = BVH(gs)
+    torch.cuda.synchronize()
+    assert torch.equal(out_long, _alone(gs, bvh, long_cam, p_long))
+    assert torch.equal(out_short, _alone(gs, bvh, short_cam, p_short))
