@@ -4,7 +4,7 @@ Workload (one step): a 1M-surfel 8x6x3 m room with 40 furniture boxes and
 ~0.5% emissive ceiling-panel surfels (scene seed 3), one 1024x768 camera at
 (1.0, 3.0, 1.6) looking at (8.0, 3.0, 1.2), 64 spp, max depth 5, Russian
 roulette from depth 3, 16-entry k-buffer. A step is the whole hot path on
-resident inputs: LBVH build over the surfels, the persistent path-tracing
+resident inputs: BVH build over the surfels, the persistent path-tracing
 kernel over all 50.3M paths, and the resolve of the fixed-point image.
 
 Metric: ray segments traced per second (Mrays/s), counted on the device.
@@ -997,7 +997,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"path tracing, {scene.n} surfels in an 8x6x3 m room with 40 boxes, "
                                f"{cam.width}x{cam.height}, {params.spp} spp, max depth {params.max_depth}, "
-                               f"RR from {params.rr_start}, k-buffer 16; step = LBVH build + path tracing + resolve",
+                               f"RR from {params.rr_start}, k-buffer 16; step = BVH build + path tracing + resolve",
                    "surfels": scene.n, "width": cam.width, "height": cam.height, "spp": params.spp,
                    "max_depth": params.max_depth},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": PEAK_HBM_GBS, "unit": "GB/s",

@@ -137,9 +137,9 @@ typedef struct {
 void eag_default_params(eag_trace_params* p);
 
 /* ------------------------------------------------------------------------
- * Acceleration structure: a linear BVH over the surfels' k_sigma ellipse
- * bounds (63-bit Morton order, Karras hierarchy), collapsed into a 4-wide
- * tree for traversal. The paper's implementation
+ * Acceleration structure: a BVH over the surfels' k_sigma ellipse bounds
+ * (63-bit Morton order, then locally-ordered agglomerative clustering of
+ * the sorted boxes), collapsed into a 4-wide tree for traversal. The paper's implementation
  * uses an OptiX acceleration structure (Sec. 5 "Implementation Details");
  * gfx950 has no ray-tracing units, so this one is built and traversed by
  * hand-written kernels.

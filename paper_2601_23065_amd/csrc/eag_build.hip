@@ -4,11 +4,13 @@
 //    Sec. 3.1: centre p, tangent axes t_u, t_v from the normalised
 //    quaternion, scales s_u, s_v), and the scene bounds;
 // 2. 63-bit Morton codes of the centres, radix-sorted with rocPRIM;
-// 3. Karras' radix-tree construction (one thread per internal node, ties of
-//    equal codes broken by sorted position);
-// 4. geometry records in sorted order (one 64-B record per surfel);
-// 5. bottom-up box propagation with per-node arrival counters;
-// 6. the depth of the binary tree, and its collapse into a 4-wide tree.
+// 3. a binary hierarchy by locally-ordered agglomerative clustering of the
+//    sorted boxes (below), which writes each node's child boxes as it makes
+//    the node;
+// 4. geometry records in sorted order (one 48-B record per surfel);
+// 5. the depth of the binary tree, and its collapse into a 4-wide tree.
+// A refit keeps the topology and propagates boxes bottom-up with per-node
+// arrival counters.
 // Everything is enqueued on the caller's stream: the depths, node count and
 // bounds stay in the device header, and the host waits for them only when
 // asked (eag_bvh_get_info).
@@ -159,40 +161,264 @@ __global__ void k_morton(eag_surfels s, const BvhHeader* h, uint64_t* codes, uin
   ids[i] = (uint32_t)i;
 }
 
-__device__ __forceinline__ int common_prefix(const uint64_t* c, int n, int i, int j) {
-  if (j < 0 || j >= n) return -1;
-  const uint64_t a = c[i], b = c[j];
-  if (a == b) return 64 + __clz((uint32_t)(i ^ j));
-  return __clzll(a ^ b);
+// ---------------------------------------------------------------------------
+// Binary hierarchy by locally-ordered agglomerative clustering (PLOC, Meister
+// and Bittner, TVCG 2018). The clusters start as the leaves in Morton order.
+// Each iteration finds every cluster's nearest neighbour among the PLOC_R
+// clusters on either side in the current order, by the surface area of the
+// union of their boxes (ties to the lower position), merges every mutual pair
+// into a new internal node at the lower position, and compacts the order.
+// A cluster made in iteration t is at most t levels high, so iterations are
+// launched a fixed number of times: PLOC_ITERS of them, then at most
+// ceil(log2 n) halving iterations that pair positions 2k and 2k + 1, which
+// bound the tree's height by PLOC_ITERS + ceil(log2 n) whatever the input.
+// Every launch reads the cluster count from the device and returns at once
+// when one cluster is left. Internal nodes are numbered from the top: the
+// k-th node made is n - 2 - k, so the last (the root) is node 0.
+// ---------------------------------------------------------------------------
+constexpr int PLOC_R = 8;          // search radius
+constexpr int PLOC_ITERS = 64;     // iterations before the halving fallback
+constexpr int PLOC_GRID = 1024;    // blocks of every clustering launch
+constexpr int PLOC_TILE = 256;
+
+struct PlocState {
+  int32_t n;          // clusters now
+  int32_t n_prev;     // clusters before the last merge step
+  int32_t cur;        // buffer holding the current clusters
+  int32_t active;     // the last scan found work to merge
+  int32_t made;       // internal nodes made so far
+  int32_t made_base;  // nodes made before the last merge step
+  int32_t pad[2];
+};
+
+struct Ploc {
+  int32_t* cl[2];     // cluster references (node >= 0, leaf ~position)
+  float4* cb[2];      // cluster boxes: [2i] lo.xyz, [2i + 1] hi.xyz
+  int32_t* nn;        // nearest neighbour of each cluster
+  int32_t* bsum;      // per block: clusters kept, nodes made
+  int32_t* boff;      // exclusive offsets of bsum
+  PlocState* st;
+};
+
+__device__ __forceinline__ float union_area(float4 al, float4 ah, float4 bl, float4 bh) {
+  const float dx = fmaxf(ah.x, bh.x) - fminf(al.x, bl.x);
+  const float dy = fmaxf(ah.y, bh.y) - fminf(al.y, bl.y);
+  const float dz = fmaxf(ah.z, bh.z) - fminf(al.z, bl.z);
+  return dx * dy + dy * dz + dz * dx;
 }
 
-// Karras (HPG 2012), Algorithm for one internal node i of n-1.
-__global__ void k_karras(const uint64_t* c, int n, Node* nodes, int32_t* leaf_parent, int32_t* node_parent) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n - 1) return;
-  const int d = (common_prefix(c, n, i, i + 1) - common_prefix(c, n, i, i - 1)) >= 0 ? 1 : -1;
-  const int dmin = common_prefix(c, n, i, i - d);
-  int lmax = 2;
-  while (common_prefix(c, n, i, i + lmax * d) > dmin) lmax *= 2;
-  int l = 0;
-  for (int t = lmax / 2; t >= 1; t /= 2)
-    if (common_prefix(c, n, i, i + (l + t) * d) > dmin) l += t;
-  const int j = i + l * d;
-  const int dnode = common_prefix(c, n, i, j);
-  int s = 0;
-  for (int div = 2;; div *= 2) {
-    const int t = (l + div - 1) / div;
-    if (common_prefix(c, n, i, i + (s + t) * d) > dnode) s += t;
-    if (t <= 1) break;
+__global__ void k_ploc_init(int64_t n, const float* box, const int32_t* perm, Ploc P, int32_t* node_parent) {
+  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (j == 0) {
+    PlocState s = {};
+    s.n = (int32_t)n;
+    *P.st = s;
+    node_parent[0] = -1;
   }
-  const int g = i + s * d + min(d, 0);
-  const int lo = min(i, j), hi = max(i, j);
-  const int left = (lo == g) ? ~g : g;
-  const int right = (hi == g + 1) ? ~(g + 1) : (g + 1);
-  nodes[i].d = make_int4(left, right, 0, 0);
-  if (left < 0) leaf_parent[~left] = i; else node_parent[left] = i;
-  if (right < 0) leaf_parent[~right] = i; else node_parent[right] = i;
-  if (i == 0) node_parent[0] = -1;
+  if (j >= n) return;
+  const int64_t i = perm[j];
+  P.cl[0][j] = ~(int32_t)j;
+  P.cb[0][2 * j] = make_float4(box[i], box[n + i], box[2 * n + i], 0.0f);
+  P.cb[0][2 * j + 1] = make_float4(box[3 * n + i], box[4 * n + i], box[5 * n + i], 0.0f);
+}
+
+// Nearest neighbour of every cluster (halving: the other of its pair).
+__global__ void __launch_bounds__(PLOC_TILE) k_ploc_nn(Ploc P, int halving) {
+  __shared__ float4 slo[PLOC_TILE + 2 * PLOC_R], shi[PLOC_TILE + 2 * PLOC_R];
+  const int n = P.st->n;
+  if (n <= 1) return;
+  const int p = P.st->cur;
+  const float4* cb = P.cb[p];
+  for (int base = blockIdx.x * PLOC_TILE; base < n; base += gridDim.x * PLOC_TILE) {
+    const int i = base + (int)threadIdx.x;
+    if (halving) {
+      if (i < n) P.nn[i] = (i ^ 1) < n ? (i ^ 1) : i;
+      continue;
+    }
+    for (int k = threadIdx.x; k < PLOC_TILE + 2 * PLOC_R; k += PLOC_TILE) {
+      const int g = base - PLOC_R + k;
+      if (g >= 0 && g < n) {
+        slo[k] = cb[2 * g];
+        shi[k] = cb[2 * g + 1];
+      }
+    }
+    __syncthreads();
+    if (i < n) {
+      const int li = (int)threadIdx.x + PLOC_R;
+      const float4 al = slo[li], ah = shi[li];
+      float best = INFINITY;
+      int bj = i;
+      for (int d = -PLOC_R; d <= PLOC_R; ++d) {
+        const int g = i + d;
+        if (d == 0 || g < 0 || g >= n) continue;
+        const float a = union_area(al, ah, slo[li + d], shi[li + d]);
+        if (a < best) {   // ascending g: ties keep the lower position
+          best = a;
+          bj = g;
+        }
+      }
+      P.nn[i] = bj;
+    }
+    __syncthreads();
+  }
+}
+
+// Per position: kept (a cluster survives there) and made (a node is made
+// there, at the lower position of a mutual pair).
+__device__ __forceinline__ void ploc_decide(const int32_t* nn, int i, int& j, bool& keep, bool& made) {
+  j = nn[i];
+  const bool mutual = j != i && nn[j] == i;
+  keep = !mutual || i < j;
+  made = mutual && i < j;
+}
+
+// Exclusive block scan of two counts (each at most PLOC_TILE per tile),
+// packed in one int; returns the block's totals in *tot.
+__device__ __forceinline__ int scan_pair(int v, int* lds, int* tot) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(x, o);
+    if (lane >= o) x += t;
+  }
+  if (lane == 63) lds[w] = x;
+  __syncthreads();
+  int before = 0;
+  for (int k = 0; k < w; ++k) before += lds[k];
+  *tot = lds[0] + lds[1] + lds[2] + lds[3];
+  __syncthreads();
+  return before + x - v;
+}
+
+__device__ __forceinline__ void ploc_chunk(int n, int& lo, int& hi) {
+  const int chunk = (n + gridDim.x - 1) / gridDim.x;
+  lo = min(n, (int)blockIdx.x * chunk);
+  hi = min(n, lo + chunk);
+}
+
+__global__ void __launch_bounds__(PLOC_TILE) k_ploc_count(Ploc P) {
+  __shared__ int lds[4];
+  const int n = P.st->n;
+  if (n <= 1) return;
+  int lo, hi;
+  ploc_chunk(n, lo, hi);
+  int keep_sum = 0, made_sum = 0;
+  for (int base = lo; base < hi; base += PLOC_TILE) {
+    const int i = base + (int)threadIdx.x;
+    int v = 0;
+    if (i < hi) {
+      int j;
+      bool keep, made;
+      ploc_decide(P.nn, i, j, keep, made);
+      v = (keep ? 1 : 0) | (made ? 1 << 16 : 0);
+    }
+    int tot;
+    scan_pair(v, lds, &tot);
+    keep_sum += tot & 0xffff;
+    made_sum += tot >> 16;
+  }
+  if (threadIdx.x == 0) {
+    P.bsum[2 * blockIdx.x] = keep_sum;
+    P.bsum[2 * blockIdx.x + 1] = made_sum;
+  }
+}
+
+// One block: offsets of the blocks' kept clusters and made nodes, and the
+// state for the write step.
+__global__ void __launch_bounds__(PLOC_GRID) k_ploc_scan(Ploc P, int blocks) {
+  __shared__ int lk[PLOC_GRID / 64], lm[PLOC_GRID / 64];
+  PlocState* st = P.st;
+  const int n = st->n;
+  if (n <= 1) {
+    if (threadIdx.x == 0) st->active = 0;
+    return;
+  }
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int k0 = t < blocks ? P.bsum[2 * t] : 0, m0 = t < blocks ? P.bsum[2 * t + 1] : 0;
+  int k = k0, m = m0;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int a = __shfl_up(k, o), b = __shfl_up(m, o);
+    if (lane >= o) {
+      k += a;
+      m += b;
+    }
+  }
+  if (lane == 63) {
+    lk[w] = k;
+    lm[w] = m;
+  }
+  __syncthreads();
+  int kb = 0, mb = 0, kt = 0, mt = 0;
+  for (int q = 0; q < PLOC_GRID / 64; ++q) {
+    if (q < w) {
+      kb += lk[q];
+      mb += lm[q];
+    }
+    kt += lk[q];
+    mt += lm[q];
+  }
+  if (t < blocks) {
+    P.boff[2 * t] = kb + k - k0;
+    P.boff[2 * t + 1] = mb + m - m0;
+  }
+  if (t == 0) {
+    st->n_prev = n;
+    st->n = kt;
+    st->cur ^= 1;
+    st->active = 1;
+    st->made_base = st->made;
+    st->made += mt;
+  }
+}
+
+__global__ void __launch_bounds__(PLOC_TILE) k_ploc_write(Ploc P, int64_t n_leaves, Node* nodes,
+                                                         int32_t* leaf_parent, int32_t* node_parent) {
+  __shared__ int lds[4];
+  const PlocState* st = P.st;
+  if (!st->active) return;
+  const int n = st->n_prev;
+  const int out = st->cur, in = out ^ 1;
+  const int32_t* cl = P.cl[in];
+  const float4* cb = P.cb[in];
+  int lo, hi;
+  ploc_chunk(n, lo, hi);
+  int keep_at = P.boff[2 * blockIdx.x];
+  int made_at = st->made_base + P.boff[2 * blockIdx.x + 1];
+  for (int base = lo; base < hi; base += PLOC_TILE) {
+    const int i = base + (int)threadIdx.x;
+    int j = i;
+    bool keep = false, made = false;
+    if (i < hi) ploc_decide(P.nn, i, j, keep, made);
+    int tot;
+    const int off = scan_pair((keep ? 1 : 0) | (made ? 1 << 16 : 0), lds, &tot);
+    if (keep) {
+      const int o = keep_at + (off & 0xffff);
+      if (made) {
+        const int id = (int)(n_leaves - 2) - (made_at + (off >> 16));
+        const int c0 = cl[i], c1 = cl[j];
+        const float4 l0 = cb[2 * i], h0 = cb[2 * i + 1], l1 = cb[2 * j], h1 = cb[2 * j + 1];
+        Node nd;
+        nd.a = make_float4(l0.x, l0.y, l0.z, h0.x);
+        nd.b = make_float4(h0.y, h0.z, l1.x, l1.y);
+        nd.c = make_float4(l1.z, h1.x, h1.y, h1.z);
+        nd.d = make_int4(c0, c1, 0, 0);
+        nodes[id] = nd;
+        if (c0 < 0) leaf_parent[~c0] = id; else node_parent[c0] = id;
+        if (c1 < 0) leaf_parent[~c1] = id; else node_parent[c1] = id;
+        P.cl[out][o] = id;
+        P.cb[out][2 * o] = make_float4(fminf(l0.x, l1.x), fminf(l0.y, l1.y), fminf(l0.z, l1.z), 0.0f);
+        P.cb[out][2 * o + 1] = make_float4(fmaxf(h0.x, h1.x), fmaxf(h0.y, h1.y), fmaxf(h0.z, h1.z), 0.0f);
+      } else {
+        P.cl[out][o] = cl[i];
+        P.cb[out][2 * o] = cb[2 * i];
+        P.cb[out][2 * o + 1] = cb[2 * i + 1];
+      }
+    }
+    keep_at += tot & 0xffff;
+    made_at += tot >> 16;
+  }
 }
 
 __global__ void k_records(eag_surfels s, const int32_t* perm, Record* recs) {
@@ -439,6 +665,10 @@ struct BuildWs {
   uint64_t* codes_out;
   uint32_t* ids_in;
   int32_t* visits;
+  float4* cbox[2];
+  int32_t* bsum;
+  int32_t* boff;
+  PlocState* ploc;
   void* sort_tmp;
   size_t sort_bytes;
   size_t bytes;
@@ -463,18 +693,39 @@ BuildWs build_ws(void* base, int64_t n) {
   w.codes_out = c.take<uint64_t>(n);
   w.ids_in = c.take<uint32_t>(n);
   w.visits = c.take<int32_t>(n);
+  w.cbox[0] = c.take<float4>(2 * n);
+  w.cbox[1] = c.take<float4>(2 * n);
+  w.bsum = c.take<int32_t>(2 * PLOC_GRID);
+  w.boff = c.take<int32_t>(2 * PLOC_GRID);
+  w.ploc = c.take<PlocState>(1);
   w.sort_bytes = sort_tmp_bytes(n);
   w.sort_tmp = c.take<char>(w.sort_bytes);
   w.bytes = c.bytes();
   return w;
 }
 
-// Levels the collapse is launched for: a Karras tree over 63-bit codes with
-// ties broken by an idx_bits-bit position splits at a strictly longer prefix
-// on every level, so no internal node lies deeper than 63 + idx_bits. Levels
-// past the tree's depth find an empty queue and return at once.
-int collapse_levels(int32_t idx_bits) { return std::min(COLLAPSE_MAXL, 64 + idx_bits); }
-static_assert(64 + 23 <= COLLAPSE_MAXL, "the collapse covers the deepest tree of 2^23 surfels");
+// The clustering's state in the build workspace. The collapse queues are
+// free while it runs and hold the two cluster orders; the bottom-up arrival
+// counters (used by refits only) hold the nearest neighbours.
+Ploc ploc_ws(const BuildWs& w) {
+  Ploc P;
+  P.cl[0] = reinterpret_cast<int32_t*>(w.q0);
+  P.cl[1] = reinterpret_cast<int32_t*>(w.q1);
+  P.cb[0] = w.cbox[0];
+  P.cb[1] = w.cbox[1];
+  P.nn = w.visits;
+  P.bsum = w.bsum;
+  P.boff = w.boff;
+  P.st = w.ploc;
+  return P;
+}
+
+// Levels the collapse is launched for: the clustering's tree is at most
+// PLOC_ITERS + ceil(log2 n) <= PLOC_ITERS + idx_bits levels high, and a
+// 4-wide level spans at least one binary level. Levels past the tree's depth
+// find an empty queue and return at once.
+int collapse_levels(int32_t idx_bits) { return std::min(COLLAPSE_MAXL, PLOC_ITERS + idx_bits); }
+static_assert(PLOC_ITERS + 23 <= COLLAPSE_MAXL, "the collapse covers the deepest tree of 2^23 surfels");
 
 }  // namespace
 
@@ -518,18 +769,23 @@ void build_bvh(const eag_surfels* s, eag_bvh* b, void* ws, size_t ws_bytes, hipS
                                       reinterpret_cast<uint32_t*>(b->perm), (size_t)n, 0, 63, st),
             "radix_sort_pairs");
   if (n > 1) {
-    hipLaunchKernelGGL(k_karras, dim3(blocks(n - 1)), dim3(256), 0, st, w.codes_out, (int)n, b->nodes,
-                       b->leaf_parent, b->node_parent);
+    const Ploc P = ploc_ws(w);
+    hipLaunchKernelGGL(k_ploc_init, dim3(blocks(n)), dim3(256), 0, st, n, w.box, b->perm, P, b->node_parent);
+    const unsigned g = std::min<unsigned>(blocks(n, PLOC_TILE), (unsigned)PLOC_GRID);
+    const int iters = PLOC_ITERS + b->idx_bits;
+    for (int t = 0; t < iters; ++t) {
+      hipLaunchKernelGGL(k_ploc_nn, dim3(g), dim3(PLOC_TILE), 0, st, P, t >= PLOC_ITERS ? 1 : 0);
+      hipLaunchKernelGGL(k_ploc_count, dim3(g), dim3(PLOC_TILE), 0, st, P);
+      hipLaunchKernelGGL(k_ploc_scan, dim3(1), dim3(PLOC_GRID), 0, st, P, (int)g);
+      hipLaunchKernelGGL(k_ploc_write, dim3(g), dim3(PLOC_TILE), 0, st, P, n, b->nodes, b->leaf_parent,
+                         b->node_parent);
+    }
   } else {
     hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, b->leaf_parent, (int64_t)1);
   }
   hipLaunchKernelGGL(k_records, dim3(blocks(n)), dim3(256), 0, st, *s, b->perm, b->recs);
-  if (n > 1) {
-    hipLaunchKernelGGL(k_zero_i32, dim3(blocks(n)), dim3(256), 0, st, w.visits, n);
-    hipLaunchKernelGGL(k_bottom_up, dim3(blocks(n)), dim3(256), 0, st, n, w.box, b->perm, b->nodes,
-                       b->leaf_parent, b->node_parent, w.visits);
+  if (n > 1)
     hipLaunchKernelGGL(k_depth, dim3(blocks(n)), dim3(256), 0, st, n, b->leaf_parent, b->node_parent, b->hdr);
-  }
   check_hip(hipGetLastError(), "build launch");
   b->root = n > 1 ? 0 : ~0;
   if (n > 1) {

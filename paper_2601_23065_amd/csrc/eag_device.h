@@ -13,8 +13,9 @@ namespace eag {
 
 constexpr int KBUF = 16;          // k-buffer depth
 // Traversal stack: 3 entries per level of the deepest tree a build can make
-// (63 code bits plus 23 position bits of prefix, so at most 87 levels), so
-// that no tree needs a check on the host. Entries past the LDS part live in
+// (64 clustering iterations plus at most 23 halving iterations, each adding
+// at most one level, so at most 87 levels), so that no tree needs a check on
+// the host. Entries past the LDS part live in
 // private memory and are rarely touched.
 constexpr int STACK_SIZE = 264;
 

@@ -1,4 +1,4 @@
-"""LBVH invariants on the device-built tree: every surfel in exactly one
+"""BVH invariants on the device-built tree: every surfel in exactly one
 leaf, every child box inside its parent's box, each leaf's box contains its
 surfel's k_sigma ellipse, and the stack bound (max depth) is consistent."""
 import numpy as np

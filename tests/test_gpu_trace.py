@@ -1,4 +1,4 @@
-"""Parity of the GPU tracer (LBVH traversal, tangent-plane intersection,
+"""Parity of the GPU tracer (BVH traversal, tangent-plane intersection,
 16-entry k-buffer, front-to-back blending) with the FP64 brute-force oracle
 on identical float32 rays: blended hit lists bit-exact on rays the oracle
 does not flag as float32-ambiguous, traced quantities within 1e-4."""
