@@ -161,7 +161,7 @@ def _code_tokens(text):
 
 # what the path-tracing kernel is compiled from, and the BVH build it traverses
 KERNEL_SOURCES = ["paper_2601_23065_amd/csrc/eag_pt.hip", "paper_2601_23065_amd/csrc/eag_build.hip",
-                  "paper_2601_23065_amd/csrc/eag_runner.h",
+                  "paper_2601_23065_amd/csrc/eag_prim.hip", "paper_2601_23065_amd/csrc/eag_runner.h",
                   "paper_2601_23065_amd/csrc/eag_device.h", "paper_2601_23065_amd/csrc/eag_render.h",
                   "paper_2601_23065_amd/csrc/eag_internal.h", "include/eag.h", "paper_2601_23065_amd/build.py"]
 

@@ -16,7 +16,8 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libeag.so")
 SOURCES = ["eag_api.cpp", "eag_build.hip", "eag_trace.hip", "eag_render.hip", "eag_backward.hip", "eag_pt.hip",
-           "eag_edit.hip", "eag_serve.cpp", "eag_bake.hip", "eag_stage0.hip", "eag_geom.hip", "eag_nee.hip"]
+           "eag_edit.hip", "eag_serve.cpp", "eag_bake.hip", "eag_stage0.hip", "eag_geom.hip", "eag_nee.hip",
+           "eag_prim.hip"]
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 ARCH = os.environ.get("EAG_OFFLOAD_ARCH", "gfx950")

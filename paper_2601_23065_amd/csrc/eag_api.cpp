@@ -90,6 +90,9 @@ void check_device_status() {
   if (code & EAG_DEVICE_KEY_RANGE)
     fail(EAG_ERR_DEVICE, "an earlier launch met a hit beyond the order key's last depth bucket "
                          "(max_bucket * depth_quantum): raise depth_quantum; its results are invalid");
+  if (code & EAG_DEVICE_SORT_RANGE)
+    fail(EAG_ERR_DEVICE, "an earlier radix sort computed an output position out of range (an internal error); "
+                         "its results are invalid");
   if (code) fail(EAG_ERR_DEVICE, "an earlier launch reported a device error");
 }
 

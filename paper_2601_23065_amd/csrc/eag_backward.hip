@@ -27,7 +27,6 @@
 #include "eag_render.h"
 #include "eag_runner.h"
 
-#include <rocprim/device/device_scan.hpp>
 
 namespace eag {
 
@@ -632,13 +631,7 @@ int64_t grad_rec_capacity(int64_t n_items) {
   return c < GRAD_RECS_MAX ? c : GRAD_RECS_MAX;
 }
 
-size_t grad_rec_scan_bytes(int64_t n) {
-  size_t b = 0;
-  check_hip(rocprim::exclusive_scan(nullptr, b, (const uint32_t*)nullptr, (uint32_t*)nullptr, 0u, (size_t)n,
-                                    rocprim::plus<uint32_t>(), (hipStream_t)0),
-            "exclusive_scan size query");
-  return b;
-}
+size_t grad_rec_scan_bytes(int64_t n) { return scan_u32_bytes(n); }
 
 void zero_record_counts(const GradRecs& gr, int64_t n, hipStream_t st) {
   if (gr.n_chunks <= 0) return;
@@ -652,9 +645,7 @@ void zero_record_counts(const GradRecs& gr, int64_t n, hipStream_t st) {
 // Group the records of the pass just run by surfel and add their sums.
 void reduce_records(const GradRecs& gr, double* gacc, int64_t n, hipStream_t st) {
   if (gr.n_chunks <= 0) return;
-  size_t tb = gr.scan_bytes;
-  check_hip(rocprim::exclusive_scan(gr.scan_tmp, tb, gr.cnt, gr.off, 0u, (size_t)n, rocprim::plus<uint32_t>(), st),
-            "record count scan");
+  scan_u32(gr.cnt, gr.off, n, false, gr.scan_tmp, gr.scan_bytes, st);
   hipLaunchKernelGGL(k_rec_place, dim3(4096), dim3(256), 0, st, gr);
   hipLaunchKernelGGL(k_rec_reduce, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st, gr, gacc, n);
 }

@@ -3,7 +3,7 @@
 // 1. frames and k_sigma-ellipse boxes of every surfel (the surfel of
 //    Sec. 3.1: centre p, tangent axes t_u, t_v from the normalised
 //    quaternion, scales s_u, s_v), and the scene bounds;
-// 2. 63-bit Morton codes of the centres, radix-sorted with rocPRIM;
+// 2. 63-bit Morton codes of the centres, radix-sorted (eag_prim.hip);
 // 3. a binary hierarchy by locally-ordered agglomerative clustering of the
 //    sorted boxes (below), which writes each node's child boxes as it makes
 //    the node;
@@ -15,7 +15,6 @@
 // bounds stay in the device header, and the host waits for them only when
 // asked (eag_bvh_get_info).
 #include <hip/hip_runtime.h>
-#include <rocprim/device/device_radix_sort.hpp>
 
 #include "eag_device.h"
 #include "eag_internal.h"
@@ -674,14 +673,6 @@ struct BuildWs {
   size_t bytes;
 };
 
-size_t sort_tmp_bytes(int64_t n) {
-  size_t b = 0;
-  hipError_t e = rocprim::radix_sort_pairs(nullptr, b, (uint64_t*)nullptr, (uint64_t*)nullptr, (uint32_t*)nullptr,
-                                           (uint32_t*)nullptr, (size_t)n, 0, 63, (hipStream_t)0);
-  check_hip(e, "radix_sort_pairs size query");
-  return b;
-}
-
 BuildWs build_ws(void* base, int64_t n) {
   Carver c(base, ~size_t(0));
   BuildWs w;
@@ -698,7 +689,7 @@ BuildWs build_ws(void* base, int64_t n) {
   w.bsum = c.take<int32_t>(2 * PLOC_GRID);
   w.boff = c.take<int32_t>(2 * PLOC_GRID);
   w.ploc = c.take<PlocState>(1);
-  w.sort_bytes = sort_tmp_bytes(n);
+  w.sort_bytes = sort_pairs_bytes(n);
   w.sort_tmp = c.take<char>(w.sort_bytes);
   w.bytes = c.bytes();
   return w;
@@ -764,10 +755,8 @@ void build_bvh(const eag_surfels* s, eag_bvh* b, void* ws, size_t ws_bytes, hipS
   if (ws_bytes < w.bytes) fail(EAG_ERR_WORKSPACE_TOO_SMALL, "build workspace too small");
   geometry_pass(s, b, w, st);
   hipLaunchKernelGGL(k_morton, dim3(blocks(n)), dim3(256), 0, st, *s, b->hdr, w.codes_in, w.ids_in);
-  size_t sb = w.sort_bytes;
-  check_hip(rocprim::radix_sort_pairs(w.sort_tmp, sb, w.codes_in, w.codes_out, w.ids_in,
-                                      reinterpret_cast<uint32_t*>(b->perm), (size_t)n, 0, 63, st),
-            "radix_sort_pairs");
+  sort_pairs_u64(w.codes_in, w.codes_out, w.ids_in, reinterpret_cast<uint32_t*>(b->perm), n, 63, w.sort_tmp,
+                 w.sort_bytes, st);
   if (n > 1) {
     const Ploc P = ploc_ws(w);
     hipLaunchKernelGGL(k_ploc_init, dim3(blocks(n)), dim3(256), 0, st, n, w.box, b->perm, P, b->node_parent);

@@ -17,7 +17,6 @@
 
 #include <cmath>
 
-#include <rocprim/device/device_scan.hpp>
 
 namespace eag {
 
@@ -179,20 +178,13 @@ Rigid make_rigid(const float r[4], const float pivot[3], const float t[3]) {
 
 }  // namespace
 
-size_t select_scan_bytes(int64_t n) {
-  size_t b = 0;
-  check_hip(rocprim::exclusive_scan(nullptr, b, (const uint32_t*)nullptr, (uint32_t*)nullptr, 0u, (size_t)n,
-                                    rocprim::plus<uint32_t>(), (hipStream_t)0),
-            "exclusive_scan size query");
-  return b;
-}
+size_t select_scan_bytes(int64_t n) { return scan_u32_bytes(n); }
 
 void launch_select_box(const float* pos, int64_t n, const float lo[3], const float hi[3], uint32_t* flags,
                        uint32_t* scan, void* tmp, size_t tmp_bytes, int32_t* idx, int64_t* count, hipStream_t st) {
   hipLaunchKernelGGL(k_box_flags, dim3(nb(n)), dim3(256), 0, st, pos, n, make_float3(lo[0], lo[1], lo[2]),
                      make_float3(hi[0], hi[1], hi[2]), flags);
-  check_hip(rocprim::exclusive_scan(tmp, tmp_bytes, flags, scan, 0u, (size_t)n, rocprim::plus<uint32_t>(), st),
-            "selection scan");
+  scan_u32(flags, scan, n, false, tmp, tmp_bytes, st);
   hipLaunchKernelGGL(k_box_compact, dim3(nb(n)), dim3(256), 0, st, flags, scan, n, idx, count);
   check_hip(hipGetLastError(), "selection launch");
 }

@@ -83,6 +83,7 @@ namespace eag {
 
 // Device status codes (bits of the mapped status word).
 constexpr unsigned int EAG_DEVICE_KEY_RANGE = 1u;
+constexpr unsigned int EAG_DEVICE_SORT_RANGE = 2u;
 unsigned int* device_status_word();     // allocates the word on first use
 bool device_status_allocated();
 void check_device_status();
@@ -100,6 +101,20 @@ inline float header_float(uint32_t e) {
   __builtin_memcpy(&f, &bits, 4);
   return f;
 }
+
+// Device-wide primitives (eag_prim.hip), deterministic, enqueued on the
+// stream; tmp is a workspace of at least the size the *_bytes function
+// gives for n. A scan may run in place (out == in). The sort is stable,
+// orders by the keys' low end_bit bits and leaves its inputs unchanged.
+size_t scan_u32_bytes(int64_t n);
+size_t scan_f64_bytes(int64_t n);
+void scan_u32(const uint32_t* in, uint32_t* out, int64_t n, bool inclusive, void* tmp, size_t tmp_bytes,
+              hipStream_t st);
+void scan_f64(const double* in, double* out, int64_t n, bool inclusive, void* tmp, size_t tmp_bytes,
+              hipStream_t st);
+size_t sort_pairs_bytes(int64_t n);
+void sort_pairs_u64(const uint64_t* keys_in, uint64_t* keys_out, const uint32_t* vals_in, uint32_t* vals_out,
+                    int64_t n, int end_bit, void* tmp, size_t tmp_bytes, hipStream_t st);
 
 // Pieces of a BVH allocation of n surfels (base may be null to size it).
 struct BvhLayout {

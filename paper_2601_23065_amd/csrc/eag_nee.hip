@@ -45,8 +45,6 @@
 #include <cmath>
 #include <cstring>
 
-#include <rocprim/device/device_radix_sort.hpp>
-#include <rocprim/device/device_scan.hpp>
 
 namespace eag {
 
@@ -557,20 +555,7 @@ struct EmitWs {
 };
 
 size_t emit_scan_bytes(int64_t n) {
-  size_t a = 0, b = 0, c = 0, d = 0;
-  check_hip(rocprim::exclusive_scan(nullptr, a, (const uint32_t*)nullptr, (uint32_t*)nullptr, 0u, (size_t)n,
-                                    rocprim::plus<uint32_t>(), (hipStream_t)0),
-            "emitter scan size");
-  check_hip(rocprim::inclusive_scan(nullptr, b, (const double*)nullptr, (double*)nullptr, (size_t)n,
-                                    rocprim::plus<double>(), (hipStream_t)0),
-            "emitter prefix size");
-  check_hip(rocprim::inclusive_scan(nullptr, c, (const uint32_t*)nullptr, (uint32_t*)nullptr, (size_t)n,
-                                    rocprim::plus<uint32_t>(), (hipStream_t)0),
-            "emitter cell scan size");
-  check_hip(rocprim::radix_sort_pairs(nullptr, d, (const uint64_t*)nullptr, (uint64_t*)nullptr,
-                                      (const uint32_t*)nullptr, (uint32_t*)nullptr, (size_t)n, 0, 63, (hipStream_t)0),
-            "emitter sort size");
-  return std::max(std::max(a, b), std::max(c, d));
+  return std::max(std::max(scan_u32_bytes(n), scan_f64_bytes(n)), sort_pairs_bytes(n));
 }
 
 EmitWs emit_ws(void* base, int64_t n) {
@@ -643,9 +628,7 @@ void build_emitters(const eag_surfels* s, float tau_E, float k_sigma, float cell
   if (mem_bytes < m.bytes) fail(EAG_ERR_WORKSPACE_TOO_SMALL, "emitter table memory too small");
   if (ws_bytes < w.bytes) fail(EAG_ERR_WORKSPACE_TOO_SMALL, "emitter table workspace too small");
   hipLaunchKernelGGL(k_emit_flags, dim3(blocks_for(n)), dim3(256), 0, st, *s, tau_E, w.flags);
-  size_t sb = w.scan_bytes;
-  check_hip(rocprim::exclusive_scan(w.scan_tmp, sb, w.flags, w.off, 0u, (size_t)n, rocprim::plus<uint32_t>(), st),
-            "emitter scan");
+  scan_u32(w.flags, w.off, n, false, w.scan_tmp, w.scan_bytes, st);
   hipLaunchKernelGGL(k_emit_count, dim3(1), dim3(1), 0, st, w.flags, w.off, n, w.count);
   unsigned long long ne = 0;
   check_hip(hipMemcpyAsync(&ne, w.count, sizeof(ne), hipMemcpyDeviceToHost, st), "emitter count");
@@ -674,10 +657,7 @@ void build_emitters(const eag_surfels* s, float tau_E, float k_sigma, float cell
   const uint32_t* order = nullptr;
   if (cell > 0.0f) {
     hipLaunchKernelGGL(k_emit_keys, dim3(bne), dim3(256), 0, st, g, 1.0f / cell, w.keys, w.vals);
-    sb = w.scan_bytes;
-    check_hip(rocprim::radix_sort_pairs(w.scan_tmp, sb, w.keys, w.keys_sorted, w.vals, w.order, (size_t)ne, 0, 63,
-                                        st),
-              "emitter cell sort");
+    sort_pairs_u64(w.keys, w.keys_sorted, w.vals, w.order, (int64_t)ne, 63, w.scan_tmp, w.scan_bytes, st);
     order = w.order;
   }
   eag_surfels gs;
@@ -689,15 +669,11 @@ void build_emitters(const eag_surfels* s, float tau_E, float k_sigma, float cell
   c.pos = m.pos; c.rot = m.rot; c.scale = m.scale; c.opacity = m.opacity;
   c.albedo = m.albedo; c.radiance = m.radiance; c.emissive = m.emissive;
   hipLaunchKernelGGL(k_emit_permute, dim3(bne), dim3(256), 0, st, gs, order, c, m.w);
-  sb = w.scan_bytes;
-  check_hip(rocprim::inclusive_scan(w.scan_tmp, sb, m.w, m.cdf, (size_t)ne, rocprim::plus<double>(), st),
-            "emitter prefix sums");
+  scan_f64(m.w, m.cdf, (int64_t)ne, true, w.scan_tmp, w.scan_bytes, st);
   const uint32_t* cell_of = nullptr;
   if (cell > 0.0f) {
     hipLaunchKernelGGL(k_cell_flags, dim3(bne), dim3(256), 0, st, w.keys_sorted, (int64_t)ne, w.vals);
-    sb = w.scan_bytes;
-    check_hip(rocprim::inclusive_scan(w.scan_tmp, sb, w.vals, m.cell_of, (size_t)ne, rocprim::plus<uint32_t>(), st),
-              "emitter cell scan");
+    scan_u32(w.vals, m.cell_of, (int64_t)ne, true, w.scan_tmp, w.scan_bytes, st);
     hipLaunchKernelGGL(k_cell_begin, dim3(bne), dim3(256), 0, st, w.vals, m.cell_of, (int64_t)ne, m.begin,
                        w.count + 1);
     unsigned long long nc = 0;
