@@ -170,7 +170,7 @@ struct TraceCtx {
   uint64_t* hl;
 };
 
-constexpr int HL_CAP = 128;        // entries per lane (a multiple of 8: the list is scanned 8 at a time)
+constexpr int HL_CAP = 256;        // entries per lane (a multiple of 8: the list is scanned 8 at a time)
 constexpr int HL_STRIDE = 1;
 static_assert(HL_CAP % 8 == 0 && HL_STRIDE == 1, "hit-list scan reads 8 contiguous entries");
 
