@@ -413,6 +413,7 @@ eag_status eag_build_bvh(const eag_surfels* s, void* bvh_mem, size_t bvh_bytes, 
     b->perm = l.perm;
     b->leaf_parent = l.leaf_parent;
     b->node_parent = l.node_parent;
+    b->levels = l.levels;
     try {
       check_hip(hipEventCreateWithFlags(&b->built, hipEventDisableTiming), "build event");
       build_bvh(s, b, ws, ws_bytes, static_cast<hipStream_t>(stream));

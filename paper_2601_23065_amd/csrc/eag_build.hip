@@ -9,8 +9,8 @@
 //    the node;
 // 4. geometry records in sorted order (one 48-B record per surfel);
 // 5. the depth of the binary tree, and its collapse into a 4-wide tree.
-// A refit keeps the topology and propagates boxes bottom-up with per-node
-// arrival counters.
+// A refit keeps the topology and recomputes the node boxes in the order of
+// the clustering iterations that made the nodes.
 // Everything is enqueued on the caller's stream: the depths, node count and
 // bounds stay in the device header, and the host waits for them only when
 // asked (eag_bvh_get_info).
@@ -179,6 +179,7 @@ constexpr int PLOC_R = 8;          // search radius
 constexpr int PLOC_ITERS = 64;     // iterations before the halving fallback
 constexpr int PLOC_GRID = 1024;    // blocks of every clustering launch
 constexpr int PLOC_TILE = 256;
+constexpr int PLOC_LEVELS = PLOC_ITERS + 24;   // iterations launched for up to 2^23 surfels, and more
 
 struct PlocState {
   int32_t n;          // clusters now
@@ -325,10 +326,14 @@ __global__ void __launch_bounds__(PLOC_TILE) k_ploc_count(Ploc P) {
 
 // One block: offsets of the blocks' kept clusters and made nodes, and the
 // state for the write step.
-__global__ void __launch_bounds__(PLOC_GRID) k_ploc_scan(Ploc P, int blocks) {
+// levels[t]: the nodes made before iteration t (iteration t makes the ids
+// n - 2 - k for k in [levels[t], levels[t + 1])), kept with the tree for
+// refits.
+__global__ void __launch_bounds__(PLOC_GRID) k_ploc_scan(Ploc P, int blocks, int t_iter, int32_t* levels) {
   __shared__ int lk[PLOC_GRID / 64], lm[PLOC_GRID / 64];
   PlocState* st = P.st;
   const int n = st->n;
+  if (threadIdx.x == 0) levels[t_iter] = st->made;
   if (n <= 1) {
     if (threadIdx.x == 0) st->active = 0;
     return;
@@ -420,6 +425,46 @@ __global__ void __launch_bounds__(PLOC_TILE) k_ploc_write(Ploc P, int64_t n_leav
   }
 }
 
+__global__ void k_ploc_done(const PlocState* st, int32_t* levels, int iters) {
+  if (threadIdx.x == 0) levels[iters] = st->made;
+}
+
+// Refit of the nodes made in clustering iteration t: their children were
+// made in earlier iterations (refitted by earlier launches) or are leaves.
+__global__ void __launch_bounds__(256) k_refit_level(int64_t n, const float* box, const int32_t* perm, Node* nodes,
+                                                    const int32_t* levels, int t) {
+  const int k0 = levels[t], k1 = levels[t + 1];
+  for (int k = k0 + (int)(blockIdx.x * blockDim.x + threadIdx.x); k < k1; k += (int)(gridDim.x * blockDim.x)) {
+    const int id = (int)(n - 2) - k;
+    Node& nd = nodes[id];
+    float lo[2][3], hi[2][3];
+    const int ch[2] = {nd.d.x, nd.d.y};
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      if (ch[c] < 0) {
+        const int64_t i = perm[~ch[c]];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          lo[c][a] = box[a * n + i];
+          hi[c][a] = box[(3 + a) * n + i];
+        }
+      } else {
+        const Node& cn = nodes[ch[c]];
+        const float4 A = cn.a, Bv = cn.b, C = cn.c;
+        lo[c][0] = fminf(A.x, Bv.z);
+        lo[c][1] = fminf(A.y, Bv.w);
+        lo[c][2] = fminf(A.z, C.x);
+        hi[c][0] = fmaxf(A.w, C.y);
+        hi[c][1] = fmaxf(Bv.x, C.z);
+        hi[c][2] = fmaxf(Bv.y, C.w);
+      }
+    }
+    nd.a = make_float4(lo[0][0], lo[0][1], lo[0][2], hi[0][0]);
+    nd.b = make_float4(hi[0][1], hi[0][2], lo[1][0], lo[1][1]);
+    nd.c = make_float4(lo[1][2], hi[1][0], hi[1][1], hi[1][2]);
+  }
+}
+
 __global__ void k_records(eag_surfels s, const int32_t* perm, Record* recs) {
   const int64_t n = s.n;
   const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -434,58 +479,6 @@ __global__ void k_records(eag_surfels s, const int32_t* perm, Record* recs) {
 __global__ void k_zero_i32(int32_t* p, int64_t n) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0;
-}
-
-__device__ __forceinline__ float aload(const float* p) {
-  return __uint_as_float(__hip_atomic_load(reinterpret_cast<const uint32_t*>(p), __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT));
-}
-
-__device__ __forceinline__ void put_box(Node* nd, int slot, const float* lo, const float* hi) {
-  float* f = reinterpret_cast<float*>(nd);
-  const int o = slot * 6;
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    __hip_atomic_store(reinterpret_cast<uint32_t*>(f + o + a), __float_as_uint(lo[a]), __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(reinterpret_cast<uint32_t*>(f + o + 3 + a), __float_as_uint(hi[a]), __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
-  }
-}
-
-// Bottom-up: each leaf writes its box into its parent's slot; the second of
-// the two children to arrive at a node forms the union and moves up.
-__global__ void k_bottom_up(int64_t n, const float* box, const int32_t* perm, Node* nodes,
-                            const int32_t* leaf_parent, const int32_t* node_parent, int32_t* visits) {
-  const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (j >= n) return;
-  const int64_t i = perm[j];
-  float lo[3], hi[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    lo[a] = box[a * n + i];
-    hi[a] = box[(3 + a) * n + i];
-  }
-  int child = ~(int)j;
-  int p = leaf_parent[j];
-  while (p >= 0) {
-    Node* nd = nodes + p;
-    const int slot = (nd->d.x == child) ? 0 : 1;
-    put_box(nd, slot, lo, hi);
-    __threadfence();
-    const int old = atomicAdd(&visits[p], 1);
-    if (old == 0) return;
-    __threadfence();
-    const float* f = reinterpret_cast<const float*>(nd);
-    const int o = (1 - slot) * 6;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      lo[a] = fminf(lo[a], aload(f + o + a));
-      hi[a] = fmaxf(hi[a], aload(f + o + 3 + a));
-    }
-    child = p;
-    p = node_parent[p];
-  }
 }
 
 __global__ void k_depth(int64_t n, const int32_t* leaf_parent, const int32_t* node_parent, BvhHeader* h) {
@@ -663,7 +656,7 @@ struct BuildWs {
   uint64_t* codes_in;
   uint64_t* codes_out;
   uint32_t* ids_in;
-  int32_t* visits;
+  int32_t* nn;
   float4* cbox[2];
   int32_t* bsum;
   int32_t* boff;
@@ -683,7 +676,7 @@ BuildWs build_ws(void* base, int64_t n) {
   w.codes_in = c.take<uint64_t>(n);
   w.codes_out = c.take<uint64_t>(n);
   w.ids_in = c.take<uint32_t>(n);
-  w.visits = c.take<int32_t>(n);
+  w.nn = c.take<int32_t>(n);
   w.cbox[0] = c.take<float4>(2 * n);
   w.cbox[1] = c.take<float4>(2 * n);
   w.bsum = c.take<int32_t>(2 * PLOC_GRID);
@@ -696,15 +689,14 @@ BuildWs build_ws(void* base, int64_t n) {
 }
 
 // The clustering's state in the build workspace. The collapse queues are
-// free while it runs and hold the two cluster orders; the bottom-up arrival
-// counters (used by refits only) hold the nearest neighbours.
+// free while it runs and hold the two cluster orders.
 Ploc ploc_ws(const BuildWs& w) {
   Ploc P;
   P.cl[0] = reinterpret_cast<int32_t*>(w.q0);
   P.cl[1] = reinterpret_cast<int32_t*>(w.q1);
   P.cb[0] = w.cbox[0];
   P.cb[1] = w.cbox[1];
-  P.nn = w.visits;
+  P.nn = w.nn;
   P.bsum = w.bsum;
   P.boff = w.boff;
   P.st = w.ploc;
@@ -717,6 +709,7 @@ Ploc ploc_ws(const BuildWs& w) {
 // find an empty queue and return at once.
 int collapse_levels(int32_t idx_bits) { return std::min(COLLAPSE_MAXL, PLOC_ITERS + idx_bits); }
 static_assert(PLOC_ITERS + 23 <= COLLAPSE_MAXL, "the collapse covers the deepest tree of 2^23 surfels");
+static_assert(PLOC_ITERS + 23 <= PLOC_LEVELS, "levels has an entry per clustering iteration of 2^23 surfels");
 
 }  // namespace
 
@@ -730,6 +723,7 @@ BvhLayout bvh_layout(void* base, int64_t n) {
   l.perm = c.take<int32_t>(n);
   l.leaf_parent = c.take<int32_t>(n);
   l.node_parent = c.take<int32_t>(n > 1 ? n - 1 : 1);
+  l.levels = c.take<int32_t>(PLOC_LEVELS + 1);
   l.bytes = c.bytes();
   return l;
 }
@@ -765,10 +759,11 @@ void build_bvh(const eag_surfels* s, eag_bvh* b, void* ws, size_t ws_bytes, hipS
     for (int t = 0; t < iters; ++t) {
       hipLaunchKernelGGL(k_ploc_nn, dim3(g), dim3(PLOC_TILE), 0, st, P, t >= PLOC_ITERS ? 1 : 0);
       hipLaunchKernelGGL(k_ploc_count, dim3(g), dim3(PLOC_TILE), 0, st, P);
-      hipLaunchKernelGGL(k_ploc_scan, dim3(1), dim3(PLOC_GRID), 0, st, P, (int)g);
+      hipLaunchKernelGGL(k_ploc_scan, dim3(1), dim3(PLOC_GRID), 0, st, P, (int)g, t, b->levels);
       hipLaunchKernelGGL(k_ploc_write, dim3(g), dim3(PLOC_TILE), 0, st, P, n, b->nodes, b->leaf_parent,
                          b->node_parent);
     }
+    hipLaunchKernelGGL(k_ploc_done, dim3(1), dim3(64), 0, st, (const PlocState*)P.st, b->levels, iters);
   } else {
     hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, b->leaf_parent, (int64_t)1);
   }
@@ -801,9 +796,12 @@ void refit_bvh(const eag_surfels* s, eag_bvh* b, void* ws, size_t ws_bytes, hipS
   hipLaunchKernelGGL(k_boxes, dim3(blocks(n)), dim3(256), 0, st, *s, 3.0f, w.box, h);
   hipLaunchKernelGGL(k_records, dim3(blocks(n)), dim3(256), 0, st, *s, b->perm, b->recs);
   if (n > 1) {
-    hipLaunchKernelGGL(k_zero_i32, dim3(blocks(n)), dim3(256), 0, st, w.visits, n);
-    hipLaunchKernelGGL(k_bottom_up, dim3(blocks(n)), dim3(256), 0, st, n, w.box, b->perm, b->nodes,
-                       b->leaf_parent, b->node_parent, w.visits);
+    // iteration by iteration of the clustering that made the tree
+    const unsigned g = std::min<unsigned>(blocks(n), 1024u);
+    const int iters = PLOC_ITERS + b->idx_bits;
+    for (int t = 0; t < iters; ++t)
+      hipLaunchKernelGGL(k_refit_level, dim3(g), dim3(256), 0, st, n, (const float*)w.box, (const int32_t*)b->perm,
+                         b->nodes, (const int32_t*)b->levels, t);
     // (the 4-wide node count is on the device: the grid covers the n - 1 it
     // can reach)
     hipLaunchKernelGGL(k_node4_boxes, dim3(blocks(n - 1)), dim3(256), 0, st, b->nodes, b->nodes4, h, w.box,

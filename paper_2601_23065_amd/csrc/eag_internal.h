@@ -76,6 +76,7 @@ struct eag_bvh {
   int32_t* perm;
   int32_t* leaf_parent;
   int32_t* node_parent;
+  int32_t* levels;        // internal nodes made before each clustering iteration
   hipEvent_t built = nullptr;   // recorded after the last build or refit
 };
 
@@ -125,6 +126,7 @@ struct BvhLayout {
   int32_t* perm;
   int32_t* leaf_parent;
   int32_t* node_parent;
+  int32_t* levels;
   size_t bytes;
 };
 BvhLayout bvh_layout(void* base, int64_t n);
