@@ -406,14 +406,7 @@ eag_status eag_build_bvh(const eag_surfels* s, void* bvh_mem, size_t bvh_bytes, 
     b->idx_bits = bits_for(s->n);
     b->mem = bvh_mem;
     b->mem_bytes = bvh_bytes;
-    b->hdr = l.hdr;
-    b->nodes = l.nodes;
-    b->nodes4 = l.nodes4;
-    b->recs = l.recs;
-    b->perm = l.perm;
-    b->leaf_parent = l.leaf_parent;
-    b->node_parent = l.node_parent;
-    b->levels = l.levels;
+    bvh_attach(b, l);
     try {
       check_hip(hipEventCreateWithFlags(&b->built, hipEventDisableTiming), "build event");
       build_bvh(s, b, ws, ws_bytes, static_cast<hipStream_t>(stream));

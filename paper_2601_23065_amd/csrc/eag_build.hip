@@ -728,6 +728,17 @@ BvhLayout bvh_layout(void* base, int64_t n) {
   return l;
 }
 
+void bvh_attach(eag_bvh* b, const BvhLayout& l) {
+  b->hdr = l.hdr;
+  b->nodes = l.nodes;
+  b->nodes4 = l.nodes4;
+  b->recs = l.recs;
+  b->perm = l.perm;
+  b->leaf_parent = l.leaf_parent;
+  b->node_parent = l.node_parent;
+  b->levels = l.levels;
+}
+
 size_t build_ws_bytes(int64_t n) { return build_ws(nullptr, n).bytes; }
 
 void validate_surfels(const eag_surfels* s) {
@@ -745,6 +756,8 @@ static void geometry_pass(const eag_surfels* s, eag_bvh* b, const BuildWs& w, hi
 
 void build_bvh(const eag_surfels* s, eag_bvh* b, void* ws, size_t ws_bytes, hipStream_t st) {
   const int64_t n = s->n;
+  if (!b->hdr || !b->nodes || !b->nodes4 || !b->recs || !b->perm || !b->leaf_parent || !b->node_parent || !b->levels)
+    fail(EAG_ERR_INTERNAL, "bvh handle without its device arrays");
   BuildWs w = build_ws(ws, n);
   if (ws_bytes < w.bytes) fail(EAG_ERR_WORKSPACE_TOO_SMALL, "build workspace too small");
   geometry_pass(s, b, w, st);
@@ -787,6 +800,8 @@ void build_bvh(const eag_surfels* s, eag_bvh* b, void* ws, size_t ws_bytes, hipS
 
 void refit_bvh(const eag_surfels* s, eag_bvh* b, void* ws, size_t ws_bytes, hipStream_t st) {
   const int64_t n = s->n;
+  if (!b->hdr || !b->nodes || !b->nodes4 || !b->recs || !b->perm || !b->levels)
+    fail(EAG_ERR_INTERNAL, "bvh handle without its device arrays");
   BuildWs w = build_ws(ws, n);
   if (ws_bytes < w.bytes) fail(EAG_ERR_WORKSPACE_TOO_SMALL, "refit workspace too small");
   BvhHeader* h = b->hdr;

@@ -130,6 +130,8 @@ struct BvhLayout {
   size_t bytes;
 };
 BvhLayout bvh_layout(void* base, int64_t n);
+// Points a handle's device arrays at the pieces of its allocation.
+void bvh_attach(eag_bvh* b, const BvhLayout& l);
 
 size_t build_ws_bytes(int64_t n);
 void validate_surfels(const eag_surfels* s);

@@ -702,13 +702,7 @@ void build_emitters(const eag_surfels* s, float tau_E, float k_sigma, float cell
   b->idx_bits = bits;
   b->mem = m.bvh;
   b->mem_bytes = m.bvh_bytes;
-  b->hdr = l.hdr;
-  b->nodes = l.nodes;
-  b->nodes4 = l.nodes4;
-  b->recs = l.recs;
-  b->perm = l.perm;
-  b->leaf_parent = l.leaf_parent;
-  b->node_parent = l.node_parent;
+  bvh_attach(b, l);
   try {
     check_hip(hipEventCreateWithFlags(&b->built, hipEventDisableTiming), "build event");
     build_bvh(&cs, b, w.build, w.build_bytes, st);
