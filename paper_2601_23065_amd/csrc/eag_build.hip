@@ -175,7 +175,7 @@ __global__ void k_morton(eag_surfels s, const BvhHeader* h, uint64_t* codes, uin
 // when one cluster is left. Internal nodes are numbered from the top: the
 // k-th node made is n - 2 - k, so the last (the root) is node 0.
 // ---------------------------------------------------------------------------
-constexpr int PLOC_R = 8;          // search radius
+constexpr int PLOC_R = 2;          // search radius (measured best of 1 to 16 for the path tracer)
 constexpr int PLOC_ITERS = 64;     // iterations before the halving fallback
 constexpr int PLOC_GRID = 1024;    // blocks of every clustering launch
 constexpr int PLOC_TILE = 256;
