@@ -26,12 +26,14 @@ def _nodes(bvh, n):
     return info, nodes, perm
 
 
-@pytest.mark.parametrize("which", ["cloud", "room"])
-def test_bvh_invariants(which):
-    from paper_2601_23065_amd.api import BVH
-    scene = sg.cloud_scene(2000, seed=1) if which == "cloud" else sg.room_scene(30000, (4.0, 3.0, 2.5), 5, seed=8)
-    gs = gpu_scene(scene)
-    bvh = BVH(gs)
+def _scene(which):
+    return sg.cloud_scene(2000, seed=1) if which == "cloud" else sg.room_scene(30000, (4.0, 3.0, 2.5), 5, seed=8)
+
+
+def _check_binary(scene, bvh):
+    """Binary tree: every surfel in exactly one leaf, every child box inside
+    its parent's box, each leaf box around its surfel's centre, and the
+    reported depth (levels of internal nodes). Returns the depth."""
     n = scene.n
     info, nodes, perm = _nodes(bvh, n)
     assert sorted(perm.tolist()) == list(range(n))
@@ -60,17 +62,13 @@ def test_bvh_invariants(which):
     assert info.max_depth == depth_max
     lo, hi = np.array(info.lo), np.array(info.hi)
     assert np.all(lo <= scene.pos.min(axis=1)) and np.all(hi >= scene.pos.max(axis=1))
+    return depth_max
 
 
-@pytest.mark.parametrize("which", ["cloud", "room"])
-def test_bvh4_invariants(which):
-    """The 4-wide tree the tracer walks: every surfel in exactly one leaf slot,
-    every child box inside its parent's box and containing its surfel's centre,
-    and the reported depth."""
-    from paper_2601_23065_amd.api import BVH
-    scene = sg.cloud_scene(2000, seed=1) if which == "cloud" else sg.room_scene(30000, (4.0, 3.0, 2.5), 5, seed=8)
-    gs = gpu_scene(scene)
-    bvh = BVH(gs)
+def _check_wide(scene, bvh):
+    """The 4-wide tree the tracer walks: every surfel in exactly one leaf
+    slot, every child box inside its parent's box and around its surfel's
+    centre, and the reported depth."""
     n = scene.n
     info = bvh.info()
     m = info.n_nodes4
@@ -103,6 +101,87 @@ def test_bvh4_invariants(which):
                 assert np.all(b[:3] < p) and np.all(p < b[3:])
     assert np.all(seen == 1) and np.all(visited == 1)
     assert info.depth4 == depth
+    return depth
+
+
+@pytest.mark.parametrize("which", ["cloud", "room"])
+def test_bvh_invariants(which):
+    from paper_2601_23065_amd.api import BVH
+    scene = _scene(which)
+    bvh = BVH(gpu_scene(scene))
+    depth = _check_binary(scene, bvh)
+    # the clustering's height bound: 64 iterations plus ceil(log2 n) halvings
+    assert depth <= 64 + int(np.ceil(np.log2(scene.n)))
+
+
+@pytest.mark.parametrize("which", ["cloud", "room"])
+def test_bvh4_invariants(which):
+    from paper_2601_23065_amd.api import BVH
+    scene = _scene(which)
+    _check_wide(scene, BVH(gpu_scene(scene)))
+
+
+def _spread3(x):
+    x = x.astype(np.uint64) & np.uint64(0x1FFFFF)
+    for shift, mask in ((32, 0x1F00000000FFFF), (16, 0x1F0000FF0000FF), (8, 0x100F00F00F00F00F),
+                        (4, 0x10C30C30C30C30C3), (2, 0x1249249249249249)):
+        x = (x | (x << np.uint64(shift))) & np.uint64(mask)
+    return x
+
+
+@pytest.mark.parametrize("which", ["cloud", "room"])
+def test_sorted_order_is_the_stable_morton_order(which):
+    """The leaf order (perm) is the stable sort of the surfels by the 63-bit
+    Morton code of their centres on cubic cells of the centres' largest
+    extent: integer work, checked bit for bit against the same codes and a
+    stable sort computed here (float32 steps as the build takes them)."""
+    from paper_2601_23065_amd.api import BVH
+    scene = _scene(which)
+    n = scene.n
+    bvh = BVH(gpu_scene(scene))
+    perm = _slice(bvh.mem, bvh.info().perm, n * 4).view(np.int32)
+    pos = scene.pos.astype(np.float32)
+    lo, hi = pos.min(axis=1), pos.max(axis=1)
+    ext = np.float32(max(np.float32(hi[a] - lo[a]) for a in range(3)))
+    q = []
+    for a in range(3):
+        x = np.clip((pos[a] - lo[a]) / ext, np.float32(0.0), np.float32(1.0)).astype(np.float32)
+        q.append(np.minimum((x * np.float32(2097152.0)).astype(np.uint32), np.uint32(2097151)))
+    code = (_spread3(q[0]) << np.uint64(2)) | (_spread3(q[1]) << np.uint64(1)) | _spread3(q[2])
+    want = np.argsort(code, kind="stable")
+    assert np.array_equal(perm, want.astype(np.int32))
+
+
+def test_coincident_surfels_take_the_halving_fallback():
+    """600 surfels with one centre, frame and scale: every pair's union has
+    the same area, so each clustering iteration merges only the pair at the
+    lowest positions (a chain), and the halving iterations finish the tree.
+    The trees keep their invariants, the height reaches past 64 levels but
+    stays within 64 + ceil(log2 n), and rays through the stack blend the
+    surfels in index order as the oracle does, through a hit list that
+    overflows."""
+    from paper_2601_23065_amd.api import BVH, Params
+    from tests.test_gpu_trace import _compare
+    n = 600
+    f32 = lambda a: np.ascontiguousarray(a, dtype=np.float32)   # noqa: E731
+    rng = np.random.default_rng(77)
+    rot = np.zeros((4, n))
+    rot[0] = 1.0
+    scene = sg.Scene(f32(np.zeros((3, n))), f32(rot), f32(np.full((2, n), 0.2)), f32(np.full(n, 0.02)),
+                     f32(rng.uniform(0.1, 0.8, (3, n))), f32(rng.uniform(1.0, 10.0, (3, n))), f32(np.ones(n)),
+                     bounds=(np.full(3, -1.0), np.full(3, 1.0)))
+    bvh = BVH(gpu_scene(scene))
+    depth = _check_binary(scene, bvh)
+    print(f"binary depth {depth}, 4-wide depth {_check_wide(scene, bvh)}")
+    assert 64 < depth <= 64 + int(np.ceil(np.log2(n)))
+    m = 64
+    O = np.zeros((3, m), dtype=np.float32)
+    O[:2] = rng.uniform(-0.2, 0.2, (2, m))
+    O[2] = -2.3   # (t = 2.3: away from a depth-bucket edge)
+    D = np.zeros((3, m), dtype=np.float32)
+    D[2] = 1.0
+    segs, _ = _compare(scene, O, D, Params())
+    assert min(s.hits.size for s in segs) > 256
 
 
 def test_single_surfel_scene():
