@@ -200,7 +200,7 @@ def test_single_surfel_scene():
 
 
 def test_refit_after_moving_surfels_traces_like_a_fresh_build():
-    """Refit (bottom-up box update over the old topology) after a transform
+    """Refit (box update over the old topology) after a transform
     edit on 10% of the surfels: the tree keeps its invariants, and tracing
     through it gives bit-identical hit lists and traced quantities to a
     tree built from scratch over the moved scene."""
