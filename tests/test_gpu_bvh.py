@@ -182,6 +182,20 @@ def test_coincident_surfels_take_the_halving_fallback():
     D[2] = 1.0
     segs, _ = _compare(scene, O, D, Params())
     assert min(s.hits.size for s in segs) > 256
+    # a refit of this tree (every node made by one clustering or halving
+    # iteration) after moving half the surfels matches a fresh build's trace
+    from paper_2601_23065_amd.api import trace_rays
+    moved = scene.copy()
+    moved.pos[0, ::2] += np.float32(0.05)
+    gs2 = gpu_scene(moved)
+    bvh.refit(gs2)
+    _check_binary(moved, bvh)
+    fresh = BVH(gs2)
+    Ot, Dt = torch.from_numpy(O).cuda(), torch.from_numpy(D).cuda()
+    a = trace_rays(bvh, gs2, Params(), Ot, Dt, max_hits=256)
+    b = trace_rays(fresh, gs2, Params(), Ot, Dt, max_hits=256)
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
 
 
 def test_single_surfel_scene():
