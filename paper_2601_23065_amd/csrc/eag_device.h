@@ -224,7 +224,10 @@ __device__ __forceinline__ float key_thi(const TraceCtx& tc, uint64_t k) {
 // quantities are evaluated in double precision: the local coordinates come
 // from a difference of nearly equal distances, and float32 there would cost
 // ~1e-5 in u at room scale, which the bounce point and direction then
-// amplify. A float32 filter with an error bound screens candidates first.
+// amplify. Every candidate takes the double-precision test, straight-line:
+// a wave nearly always holds some candidate whose decision a float32
+// evaluation could not settle, so a float screen in front of it only added
+// instructions.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ Record load_record(const Record* recs, uint32_t pos) {
   const float4* p = reinterpret_cast<const float4*>(recs + pos);
@@ -261,62 +264,6 @@ __device__ __forceinline__ Geo surfel_geo(const Record& r) {
   g.su = r.s_idx.x;
   g.sv = r.s_idx.y;
   return g;
-}
-
-// Float32 filter for the surfel test. It evaluates the same formulas in
-// float with a bound on their distance from the double-precision values
-// (unit roundoff 2^-24 times the magnitudes involved, with a safety factor
-// several times what the operations need, which also covers the 1-ulp
-// hardware reciprocal and reciprocal square root used here), and decides
-// only where the bound cannot change the outcome:
-//   REJECT  - the double test rejects (t <= t_min or outside the ellipse)
-//   ACCEPT  - the double test accepts, and t's bucket is known exactly
-//             (bucket_out), or at least bounded by [blo, bhi]
-//   EXACT   - undecided: run the double test
-enum { FILTER_REJECT = 0, FILTER_ACCEPT = 1, FILTER_EXACT = 2 };
-struct RayF {
-  V3 O, W;          // float copies of the ray
-  float Osum;       // |O.x| + |O.y| + |O.z|
-};
-
-__device__ __forceinline__ int record_filter(const Record& r, const RayF& rf, float t_min, float k2, float inv_dq,
-                                             uint32_t& blo, uint32_t& bhi) {
-  constexpr float U = 5.9604645e-08f;   // 2^-24
-  // Everything is evaluated and the decisions are combined at the end, with
-  // no branches: the wave would run both sides of each anyway. Comparisons
-  // are arranged so that a NaN (degenerate scales or quaternion) always
-  // lands in EXACT or REJECT through the paths the exact test agrees with.
-  float w = r.q.x, x = r.q.y, y = r.q.z, z = r.q.w;
-  const float iq = __builtin_amdgcn_rsqf(w * w + x * x + y * y + z * z);
-  w *= iq; x *= iq; y *= iq; z *= iq;
-  const V3 tu = v3(1.0f - 2.0f * (y * y + z * z), 2.0f * (x * y + w * z), 2.0f * (x * z - w * y));
-  const V3 tv = v3(2.0f * (x * y - w * z), 1.0f - 2.0f * (x * x + z * z), 2.0f * (y * z + w * x));
-  const V3 n = cross(tu, tv);
-  const float den = dot(rf.W, n);
-  const float aden = fabsf(den);
-  const V3 d = v3(r.p_sigma.x - rf.O.x, r.p_sigma.y - rf.O.y, r.p_sigma.z - rf.O.z);
-  const float iden = __builtin_amdgcn_rcpf(den);
-  const float t = dot(d, n) * iden;
-  const float mag = fabsf(r.p_sigma.x) + fabsf(r.p_sigma.y) + fabsf(r.p_sigma.z) + rf.Osum + fabsf(t);
-  const float et = 256.0f * U * mag * fabsf(iden);
-  const V3 yv = v3(t * rf.W.x - d.x, t * rf.W.y - d.y, t * rf.W.z - d.z);
-  const float yl = fabsf(yv.x) + fabsf(yv.y) + fabsf(yv.z);
-  const float ey = 2.0f * et + 64.0f * U * (mag + yl);
-  const float su = r.s_idx.x, sv = r.s_idx.y;
-  const float isu = __builtin_amdgcn_rcpf(su), isv = __builtin_amdgcn_rcpf(sv);
-  const float u = dot(yv, tu) * isu, v = dot(yv, tv) * isv;
-  const float eu = ey * isu + 8.0f * U * fabsf(u), ev = ey * isv + 8.0f * U * fabsf(v);
-  const float q2 = u * u + v * v;
-  const float eq = 2.0f * (fabsf(u) * eu + fabsf(v) * ev) + eu * eu + ev * ev + 16.0f * U * q2;
-  // widened by half the bound so that rounding of t -+ et cannot cross a bucket edge
-  const float lo = floorf((t - 1.5f * et) * inv_dq), hi = floorf((t + 1.5f * et) * inv_dq);
-  const bool geom = aden > 1e-3f;   // false for a NaN too
-  const bool reject = !(r.p_sigma.w > 0.0f) || (geom && (t + et <= t_min || q2 - eq > k2));
-  const bool exact = !geom || !(t - et > t_min) || !(q2 + eq <= k2) || !(inv_dq > 0.0f) || !(lo >= 0.0f) ||
-                     !(hi < 4.0e9f);
-  blo = exact ? 0u : (uint32_t)lo;
-  bhi = exact ? 0u : (uint32_t)hi;
-  return reject ? FILTER_REJECT : (exact ? FILTER_EXACT : FILTER_ACCEPT);
 }
 
 // ---------------------------------------------------------------------------
@@ -465,7 +412,7 @@ template <bool DACC>
 struct Seg {
   using Acc = typename std::conditional<DACC, double, float>::type;
   D3 O, W;            // the ray, double precision
-  RayF rf;            // float copies for the surfel filter
+  V3 Of;              // float copy of the origin for the slab tests
   V3 iW;              // float reciprocal direction for the box tests
   D3 N;
   double D, T;
@@ -503,9 +450,7 @@ __device__ __forceinline__ void seg_begin(Seg<DACC>& s, D3 O, D3 W) {
   s.O = O;
   s.W = W;
   const float wx = (float)W.x, wy = (float)W.y, wz = (float)W.z;
-  s.rf.O = v3((float)O.x, (float)O.y, (float)O.z);
-  s.rf.W = v3(wx, wy, wz);
-  s.rf.Osum = fabsf(s.rf.O.x) + fabsf(s.rf.O.y) + fabsf(s.rf.O.z);
+  s.Of = v3((float)O.x, (float)O.y, (float)O.z);
   s.iW = v3(1.0f / (fabsf(wx) > 1e-30f ? wx : copysignf(1e-30f, wx)),
             1.0f / (fabsf(wy) > 1e-30f ? wy : copysignf(1e-30f, wy)),
             1.0f / (fabsf(wz) > 1e-30f ? wz : copysignf(1e-30f, wz)));
@@ -603,7 +548,7 @@ __device__ __forceinline__ void node_visit(const TraceCtx& tc, Seg<DACC>& s, Rou
   const int4 cr = nd->ref;
   const float4* bb = nd->b;
   const float4 b0 = bb[0], b1 = bb[1], b2 = bb[2], b3 = bb[3], b4 = bb[4], b5 = bb[5];
-  const V3 Of = s.rf.O;
+  const V3 Of = s.Of;
   float e[4];
   e[0] = slab(b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, Of, s.iW, r.tlo0, r.t_cut);
   e[1] = slab(b1.z, b1.w, b2.x, b2.y, b2.z, b2.w, Of, s.iW, r.tlo0, r.t_cut);
@@ -657,26 +602,19 @@ __device__ __forceinline__ void node_visit(const TraceCtx& tc, Seg<DACC>& s, Rou
 }
 
 // The order key of a postponed leaf (its record already loaded) for the ray
-// (O, W; rf its float copies) in a round whose keys must exceed floor_key
-// (when have_floor); ~0 when the surfel is missed or its key cannot enter
-// the round. cutlim: keys whose whole bucket range lies at or above it are
-// dropped early (the k-buffer's last key, or the hit list's cut; any larger
-// value is also correct).
+// (O, W) in a round whose keys must exceed floor_key (when have_floor); ~0
+// when the surfel is missed or its key cannot enter the round. cutlim: keys
+// at or above it are dropped (the k-buffer's last key, or the hit list's
+// cut, a bucket's first key; any larger value is also correct).
 __device__ __forceinline__ uint64_t leaf_key(const TraceCtx& tc, const Record& rec, uint32_t pos, D3 O, D3 W,
-                                             const RayF& rf, bool have_floor, uint64_t floor_key,
-                                             uint64_t cutlim) {
-  uint32_t blo = 0, bhi = 0;
-  const int fr = record_filter(rec, rf, (float)tc.t_min, (float)tc.k2, (float)tc.inv_dq, blo, bhi);
-  // whole-bucket bounds drop most keys that cannot enter the round
-  const uint64_t klo = make_key_b(tc, blo, 0u, 0u), khi = make_key_b(tc, bhi + 1u, 0u, 0u);
-  const bool early_out = fr == FILTER_ACCEPT && ((have_floor && khi <= floor_key) || klo >= cutlim);
-  // Double precision for every candidate, without branches (a wave nearly
-  // always holds some candidate that needs it). The columns of the rotation
-  // of the unnormalised quaternion are |q|^2 (t_u, t_v, n): the distance
-  // t = ((p - O).n) / (W.n) needs no normalisation, and the ellipse test
-  // becomes u'^2 / s_u^2 + v'^2 / s_v^2 <= k^2 |q|^4 with u' = y.(|q|^2 t_u).
-  // Its rounding differs from the normalised evaluation by a few ulp, well
-  // inside the margins within which rim and t_min decisions are flagged.
+                                             bool have_floor, uint64_t floor_key, uint64_t cutlim) {
+  // The surfel test in double precision, straight-line. The columns of the
+  // rotation of the unnormalised quaternion are |q|^2 (t_u, t_v, n): the
+  // distance t = ((p - O).n) / (W.n) needs no normalisation, and the ellipse
+  // test becomes u'^2 / s_u^2 + v'^2 / s_v^2 <= k^2 |q|^4 with
+  // u' = y.(|q|^2 t_u). Its rounding differs from the normalised evaluation
+  // by a few ulp, well inside the margins within which rim, t_min and bucket
+  // decisions are flagged.
   const double w = rec.q.x, x = rec.q.y, y = rec.q.z, z = rec.q.w;
   const double q2n = w * w + x * x + y * y + z * z;
   const D3 cu = d3(w * w + x * x - y * y - z * z, 2.0 * (x * y + w * z), 2.0 * (x * z - w * y));
@@ -689,17 +627,15 @@ __device__ __forceinline__ uint64_t leaf_key(const TraceCtx& tc, const Record& r
   const double su2 = (double)rec.s_idx.x * rec.s_idx.x, sv2 = (double)rec.s_idx.y * rec.s_idx.y;
   const double up = dot(yv, cu), vp = dot(yv, cv);
   // (multiplied through by s_u^2 s_v^2, all positive: no division)
-  const bool exact_ok = fabs(den) > 1e-12 * q2n && rec.p_sigma.w > 0.0f && t > tc.t_min &&
-                        up * up * sv2 + vp * vp * su2 <= tc.k2 * q2n * q2n * su2 * sv2;
-  const bool hit = (fr == FILTER_ACCEPT && !early_out) || (fr == FILTER_EXACT && exact_ok);
-  const uint64_t key = fr == FILTER_ACCEPT && blo == bhi ? make_key_b(tc, blo, rec_index(rec), pos)
-                                                         : make_key(tc, t, rec_index(rec), pos);
-  const bool take = hit && !(have_floor && key <= floor_key);
+  const bool hit = fabs(den) > 1e-12 * q2n && rec.p_sigma.w > 0.0f && t > tc.t_min &&
+                   up * up * sv2 + vp * vp * su2 <= tc.k2 * q2n * q2n * su2 * sv2;
+  const uint64_t key = make_key(tc, t, rec_index(rec), pos);
+  const bool qual = hit && !(have_floor && key <= floor_key);
   // A hit in the last bucket may stand for a farther one that the key
   // saturated into it, whose order among the others is then unknown: the
   // launch reports it (a rare branch; never taken within the range).
-  if (take && tc.inv_dq > 0.0 && key_bucket(tc, key) >= tc.max_bucket) report_key_range(tc.status);
-  return take ? key : ~0ull;
+  if (qual && tc.inv_dq > 0.0 && key_bucket(tc, key) >= tc.max_bucket) report_key_range(tc.status);
+  return qual && key < cutlim ? key : ~0ull;
 }
 
 // Take a qualifying key into the round. The list needs only keys beyond the
@@ -733,7 +669,7 @@ template <bool DACC>
 __device__ __forceinline__ void leaf_eval(const TraceCtx& tc, Seg<DACC>& s, Round& r, const Record& rec,
                                           uint32_t pos) {
   ++s.tests;
-  const uint64_t key = leaf_key(tc, rec, pos, s.O, s.W, s.rf, r.have_floor, r.floor_key, round_cutlim<DACC>(tc, r));
+  const uint64_t key = leaf_key(tc, rec, pos, s.O, s.W, r.have_floor, r.floor_key, round_cutlim<DACC>(tc, r));
   if (key != ~0ull) take_key(tc, s, r, key);
 }
 
