@@ -285,11 +285,15 @@ struct SegOut {
 enum { Q_ALL = 0, Q_RADIANCE = 1 };
 
 // Slab test of a box against [tlo, thi]; returns the entry distance or +inf.
-__device__ __forceinline__ float slab(float lx, float ly, float lz, float hx, float hy, float hz, V3 O, V3 iW,
+// OiW = O * iW per component: each plane distance (l - O) / W is one fused
+// multiply-add, l * iW - OiW. Its rounding error, in space, is a few ulp of
+// |O| and |l|, far inside the pad that every leaf box carries around its
+// ellipse, so no box that a ray's hit lies in is rejected.
+__device__ __forceinline__ float slab(float lx, float ly, float lz, float hx, float hy, float hz, V3 OiW, V3 iW,
                                       float tlo, float thi) {
-  const float ax = (lx - O.x) * iW.x, bx = (hx - O.x) * iW.x;
-  const float ay = (ly - O.y) * iW.y, by = (hy - O.y) * iW.y;
-  const float az = (lz - O.z) * iW.z, bz = (hz - O.z) * iW.z;
+  const float ax = fmaf(lx, iW.x, -OiW.x), bx = fmaf(hx, iW.x, -OiW.x);
+  const float ay = fmaf(ly, iW.y, -OiW.y), by = fmaf(hy, iW.y, -OiW.y);
+  const float az = fmaf(lz, iW.z, -OiW.z), bz = fmaf(hz, iW.z, -OiW.z);
   const float tn = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), fmaxf(fminf(az, bz), tlo));
   // widen the exit so that rounding (and the float32 copy of the ray) never
   // rejects a box the ray touches
@@ -412,7 +416,7 @@ template <bool DACC>
 struct Seg {
   using Acc = typename std::conditional<DACC, double, float>::type;
   D3 O, W;            // the ray, double precision
-  V3 Of;              // float copy of the origin for the slab tests
+  V3 OiW;             // float origin times iW, for the slab tests
   V3 iW;              // float reciprocal direction for the box tests
   D3 N;
   double D, T;
@@ -450,10 +454,10 @@ __device__ __forceinline__ void seg_begin(Seg<DACC>& s, D3 O, D3 W) {
   s.O = O;
   s.W = W;
   const float wx = (float)W.x, wy = (float)W.y, wz = (float)W.z;
-  s.Of = v3((float)O.x, (float)O.y, (float)O.z);
   s.iW = v3(1.0f / (fabsf(wx) > 1e-30f ? wx : copysignf(1e-30f, wx)),
             1.0f / (fabsf(wy) > 1e-30f ? wy : copysignf(1e-30f, wy)),
             1.0f / (fabsf(wz) > 1e-30f ? wz : copysignf(1e-30f, wz)));
+  s.OiW = v3((float)O.x * s.iW.x, (float)O.y * s.iW.y, (float)O.z * s.iW.z);
   s.N = d3(0.0, 0.0, 0.0);
   s.D = 0.0;
   s.T = 1.0;
@@ -548,12 +552,11 @@ __device__ __forceinline__ void node_visit(const TraceCtx& tc, Seg<DACC>& s, Rou
   const int4 cr = nd->ref;
   const float4* bb = nd->b;
   const float4 b0 = bb[0], b1 = bb[1], b2 = bb[2], b3 = bb[3], b4 = bb[4], b5 = bb[5];
-  const V3 Of = s.Of;
   float e[4];
-  e[0] = slab(b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, Of, s.iW, r.tlo0, r.t_cut);
-  e[1] = slab(b1.z, b1.w, b2.x, b2.y, b2.z, b2.w, Of, s.iW, r.tlo0, r.t_cut);
-  e[2] = slab(b3.x, b3.y, b3.z, b3.w, b4.x, b4.y, Of, s.iW, r.tlo0, r.t_cut);
-  e[3] = slab(b4.z, b4.w, b5.x, b5.y, b5.z, b5.w, Of, s.iW, r.tlo0, r.t_cut);
+  e[0] = slab(b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, s.OiW, s.iW, r.tlo0, r.t_cut);
+  e[1] = slab(b1.z, b1.w, b2.x, b2.y, b2.z, b2.w, s.OiW, s.iW, r.tlo0, r.t_cut);
+  e[2] = slab(b3.x, b3.y, b3.z, b3.w, b4.x, b4.y, s.OiW, s.iW, r.tlo0, r.t_cut);
+  e[3] = slab(b4.z, b4.w, b5.x, b5.y, b5.z, b5.w, s.OiW, s.iW, r.tlo0, r.t_cut);
   const int c[4] = {cr.x, cr.y, cr.z, cr.w};
   float ie[4];
   int ic[4];

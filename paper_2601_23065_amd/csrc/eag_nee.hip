@@ -133,11 +133,11 @@ __device__ __forceinline__ double pdf_term(const EmitterDev& E, uint32_t pos, D3
 __device__ double light_pdf(const EmitterDev& E, D3 X, D3 W, int* lds, double S) {
   double sum = 0.0;
   if (E.n == 0) return sum;
-  const V3 Of = v3((float)X.x, (float)X.y, (float)X.z);
   const float wx = (float)W.x, wy = (float)W.y, wz = (float)W.z;
   const V3 iW = v3(1.0f / (fabsf(wx) > 1e-30f ? wx : copysignf(1e-30f, wx)),
                    1.0f / (fabsf(wy) > 1e-30f ? wy : copysignf(1e-30f, wy)),
                    1.0f / (fabsf(wz) > 1e-30f ? wz : copysignf(1e-30f, wz)));
+  const V3 OiW = v3((float)X.x * iW.x, (float)X.y * iW.y, (float)X.z * iW.z);
   const float inf = __builtin_inff();
   int ovf[STACK_OVF];
   TravStack st;
@@ -156,10 +156,10 @@ __device__ double light_pdf(const EmitterDev& E, D3 X, D3 W, int* lds, double S)
     const Node4* nd = E.nodes + ref;
     const int4 cr = nd->ref;
     const float4 b0 = nd->b[0], b1 = nd->b[1], b2 = nd->b[2], b3 = nd->b[3], b4 = nd->b[4], b5 = nd->b[5];
-    const float e0 = slab(b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, Of, iW, 0.0f, inf);
-    const float e1 = slab(b1.z, b1.w, b2.x, b2.y, b2.z, b2.w, Of, iW, 0.0f, inf);
-    const float e2 = slab(b3.x, b3.y, b3.z, b3.w, b4.x, b4.y, Of, iW, 0.0f, inf);
-    const float e3 = slab(b4.z, b4.w, b5.x, b5.y, b5.z, b5.w, Of, iW, 0.0f, inf);
+    const float e0 = slab(b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, OiW, iW, 0.0f, inf);
+    const float e1 = slab(b1.z, b1.w, b2.x, b2.y, b2.z, b2.w, OiW, iW, 0.0f, inf);
+    const float e2 = slab(b3.x, b3.y, b3.z, b3.w, b4.x, b4.y, OiW, iW, 0.0f, inf);
+    const float e3 = slab(b4.z, b4.w, b5.x, b5.y, b5.z, b5.w, OiW, iW, 0.0f, inf);
     if (cr.x != NODE4_EMPTY && e0 < inf && st.sp < STACK_SIZE) st.push(cr.x);
     if (cr.y != NODE4_EMPTY && e1 < inf && st.sp < STACK_SIZE) st.push(cr.y);
     if (cr.z != NODE4_EMPTY && e2 < inf && st.sp < STACK_SIZE) st.push(cr.z);
