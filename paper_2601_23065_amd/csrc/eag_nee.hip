@@ -233,7 +233,8 @@ struct MisPathSource {
   int depth;
   V3 beta;
   V3 lf;            // beta at the vertex of the pending light segment
-  D3 X, Wb;         // the vertex and the cosine-sampled continuation
+  D3 Wb;            // the cosine-sampled continuation (from the vertex, which is
+                    // the light segment's origin while that segment is in flight)
   double pb;        // cosine pdf of the direction of the segment in flight (or the continuation)
   double pbl;       // cosine pdf of the pending light segment's direction
   double Sx;        // selection by cells: S at the vertex the segment in flight started from
@@ -298,7 +299,7 @@ struct MisPathSource {
       light = false;
       if (hit && s.E > S.tau_E) defer(true, s.O, s.W, pbl, lf, v3(s.R0, s.R1, s.R2));
       if (!cont) return false;
-      O = X;
+      O = s.O;
       W = Wb;
       return true;
     }
@@ -318,7 +319,7 @@ struct MisPathSource {
     beta = v3(beta.x * s.P0, beta.y * s.P1, beta.z * s.P2);
     const D3 Nt = (1.0 / sqrt(dot(s.N, s.N))) * s.N;
     const double Dt = s.D / A;
-    X = d3(s.O.x + Dt * s.W.x, s.O.y + Dt * s.W.y, s.O.z + Dt * s.W.z);
+    const D3 X = d3(s.O.x + Dt * s.W.x, s.O.y + Dt * s.W.y, s.O.z + Dt * s.W.z);
     // light sample, before Russian roulette
     D3 Wl = d3(0.0, 0.0, 1.0);
     if (E->n > 0) {
@@ -378,7 +379,7 @@ k_path_trace_mis(TraceCtx tc, PtLaunch L, EmitterDev E, PdfQueue Q, unsigned lon
   src.pix = src.sample = 0;
   src.depth = 0;
   src.beta = src.lf = v3(0.f, 0.f, 0.f);
-  src.X = src.Wb = d3(0.0, 0.0, 0.0);
+  src.Wb = d3(0.0, 0.0, 0.0);
   src.pb = src.pbl = src.Sx = 0.0;
   src.light = src.cont = false;
   run_segments<Q_ALL, false>(tc, src, work_counter, L.n_work, hitlist, counters);
