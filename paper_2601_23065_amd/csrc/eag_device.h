@@ -563,8 +563,9 @@ __device__ __forceinline__ void node_visit(const TraceCtx& tc, Seg<DACC>& s, Rou
   int ni = 0;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    // a missed box reports +inf, which must not pass an infinite cut
-    const bool m = c[k] != NODE4_EMPTY && e[k] < __builtin_inff() && e[k] <= r.t_cut;
+    // a missed box reports +inf (the slab test already holds the entry to the
+    // widened cut), which must not pass while the cut is infinite
+    const bool m = c[k] != NODE4_EMPTY && e[k] < __builtin_inff();
     // leaves are queued without a branch: the slot past the queue is always
     // written (nodes are visited only while np <= PEND - 4, so it exists)
     pend[r.np * TRACE_BLOCK] = ~c[k];
