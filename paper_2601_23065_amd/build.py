@@ -23,6 +23,9 @@ HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 ARCH = os.environ.get("EAG_OFFLOAD_ARCH", "gfx950")
 CFLAGS = ["-x", "hip", f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          # the scheduler's instruction-level-parallelism strategy: the path tracer keeps its 251 registers and two
+          # waves per SIMD and runs about 1% faster than with the default strategy
+          "-mllvm", "-amdgpu-sched-strategy=max-ilp",
           "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
 
